@@ -1,0 +1,252 @@
+"""The two-level scheme end to end (paper Sec. 3, eq. modified, eqs.
+preconditioner / smw, Sec. 4.1).
+
+Setup (independent of b, done once):
+    m, Dr, Dc          max-product matching and scaling          (Sec. 2)
+    S                  least-squares skew-symmetrizer            (Sec. 2, App. A)
+    A_hat = Abar S,  D, Omega, J_tilde, N                        (Sec. 3)
+    Q_k, S_k           skew-Lanczos                              (Fig. 2)
+    X, G, C            one-time SMW data                          (Sec. 4.1)
+
+Solve: the outer Krylov method runs on the scaled system
+    A_chk x_chk = b_chk,   A_chk = Omega Abar S Omega,   b_chk = Omega P Dr b,
+    x = Dc S Omega x_chk,
+right-preconditioned with P (eq. preconditioner).
+
+Readings:
+* Outer method: flexible GMRES(m) (the paper says "a Krylov subspace method";
+  the inner solve is inexact, so the preconditioner changes from step to step
+  and the flexible variant stores the preconditioned vectors z_j).  Arnoldi
+  with classical Gram-Schmidt applied twice; Givens rotations on the
+  Hessenberg matrix.
+* Stopping: the implicit residual |g_{j+1}| <= thr only triggers a check; the
+  solve is converged when the true residual ||b - A x|| <= tol ||b|| on the
+  original system.  The true residual is also checked at every restart.  If
+  the implicit test passed but the true one failed, thr is multiplied by
+  0.5 * tol / relres_true and the method restarts.  thr starts at
+  tol * ||b_chk||.  max_outer counts Arnoldi steps over all cycles.
+* Inner solves: mrs on S_bar with tolerance inner_tol and at most inner_maxit
+  iterations (the paper uses the outer criterion for both levels).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+from .lanczos import DEFAULT_SEED, skew_lanczos, start_vector
+from .precond import Preconditioner
+from .preprocess import canonical_scaling, max_product_matching, permute_scale, validate_csr
+from .skewsym import skew_symmetrizer
+from .split import jtilde_apply, split_ahat
+
+
+@dataclass
+class SetupOptions:
+    gamma: float = 1.0
+    s_pattern: object = "tridiag"
+    k: int = 20
+    lanczos_seed: int = DEFAULT_SEED
+    x_tol: float = 1e-10
+    x_maxit: int = 2000
+    lls_dense_limit: int = 2000
+
+
+@dataclass
+class SolveOptions:
+    tol: float = 1e-8
+    restart_m: int = 64
+    max_outer: int = 2000
+    inner_tol: float = 1e-5
+    inner_maxit: int = 1000
+    fixed_inner_steps: int = 0
+
+
+@dataclass
+class OracleSetup:
+    A: sp.csr_matrix
+    m: np.ndarray
+    Dr: np.ndarray
+    Dc: np.ndarray
+    Abar: sp.csr_matrix
+    S: sp.csr_matrix
+    Ahat: sp.csr_matrix
+    D: np.ndarray
+    Omega: np.ndarray
+    Jup: sp.csr_matrix
+    N: np.ndarray
+    Q: np.ndarray
+    alpha: np.ndarray
+    prec: Preconditioner
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.A.shape[0]
+
+    # outer operator and its transpose (Sec. 3, eq. modified with the scaling)
+    def op(self, z):
+        return self.Omega * (self.Abar @ (self.S @ (self.Omega * z)))
+
+    def op_T(self, z):
+        return self.Omega * (self.S.T @ (self.Abar.T @ (self.Omega * z)))
+
+    def rhs(self, b):
+        """b_chk = Omega P Dr b."""
+        return self.Omega * (self.Dr[self.m] * b[self.m])
+
+    def back(self, x_chk):
+        """x = Dc S Omega x_chk."""
+        return self.Dc * (self.S @ (self.Omega * x_chk))
+
+    def rhs_T(self, g):
+        """g_chk = Omega S^T Dc g (adjoint)."""
+        return self.Omega * (self.S.T @ (self.Dc * g))
+
+    def back_T(self, l_chk):
+        """lambda = Dr P^T Omega l_chk (adjoint)."""
+        lam = np.empty(self.n)
+        lam[self.m] = self.Dr[self.m] * (self.Omega * l_chk)
+        return lam
+
+
+def setup(A, opts: SetupOptions | None = None) -> OracleSetup:
+    opts = opts or SetupOptions()
+    A = validate_csr(A)
+    m = max_product_matching(A)
+    Dr, Dc = canonical_scaling(A, m)
+    Abar = permute_scale(A, m, Dr, Dc)
+    S, B, v = skew_symmetrizer(Abar, opts.s_pattern, opts.gamma, dense_limit=opts.lls_dense_limit)
+    parts = split_ahat(Abar, S)
+    Jup = parts["Jup"]
+    n = A.shape[0]
+    q1 = start_vector(opts.lanczos_seed, n)
+    Q, alpha = skew_lanczos(lambda v_: jtilde_apply(Jup, v_), q1, opts.k)
+    prec = Preconditioner(Jup, parts["N"], Q, alpha, opts.x_tol, opts.x_maxit)
+    return OracleSetup(A=A, m=m, Dr=Dr, Dc=Dc, Abar=Abar, S=S, Ahat=parts["Ahat"],
+                       D=parts["D"], Omega=parts["Omega"], Jup=Jup, N=parts["N"],
+                       Q=Q, alpha=alpha, prec=prec, extra={"B_shape": B.shape, "B_nnz": B.nnz})
+
+
+def _fgmres(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
+    """Flexible GMRES(m) with the stopping rule described in the module doc."""
+    n = rhs.size
+    info = dict(converged=False, outer_its=0, inner_its_total=0, inner_its_max=0,
+                relres_true=np.nan, relres_implicit=np.nan, cycles=0, hist=[])
+    bn = np.linalg.norm(rhs)
+    x_chk = np.zeros(n)
+    if bn == 0.0:
+        info.update(converged=True, relres_true=0.0, relres_implicit=0.0)
+        return x_chk, info
+    thr = o.tol * bn
+    m = max(1, o.restart_m)
+    first = True
+    while True:
+        r = rhs.copy() if first else rhs - op(x_chk)
+        first = False
+        beta = np.linalg.norm(r)
+        info["cycles"] += 1
+        V = np.zeros((n, m + 1))
+        Z = np.zeros((n, m))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        j_used = 0
+        implicit_ok = beta <= thr
+        if beta > 0:
+            V[:, 0] = r / beta
+            for j in range(m):
+                z, its = prec_apply(V[:, j])
+                info["inner_its_total"] += its
+                info["inner_its_max"] = max(info["inner_its_max"], its)
+                Z[:, j] = z
+                w = op(z)
+                h1 = V[:, :j + 1].T @ w
+                w = w - V[:, :j + 1] @ h1
+                h2 = V[:, :j + 1].T @ w
+                w = w - V[:, :j + 1] @ h2
+                hn = np.linalg.norm(w)
+                H[:j + 1, j] = h1 + h2
+                H[j + 1, j] = hn
+                if hn != 0.0:
+                    V[:, j + 1] = w / hn
+                for i in range(j):
+                    a, b_ = H[i, j], H[i + 1, j]
+                    H[i, j] = cs[i] * a + sn[i] * b_
+                    H[i + 1, j] = -sn[i] * a + cs[i] * b_
+                rr = np.hypot(H[j, j], H[j + 1, j])
+                if rr == 0.0:
+                    cs[j], sn[j] = 1.0, 0.0
+                else:
+                    cs[j], sn[j] = H[j, j] / rr, H[j + 1, j] / rr
+                H[j, j] = rr
+                H[j + 1, j] = 0.0
+                g[j + 1] = -sn[j] * g[j]
+                g[j] = cs[j] * g[j]
+                info["outer_its"] += 1
+                j_used = j + 1
+                implicit_ok = abs(g[j + 1]) <= thr
+                info["hist"].append(abs(g[j + 1]) / bn)
+                if implicit_ok or hn == 0.0 or info["outer_its"] >= o.max_outer:
+                    break
+            y = np.zeros(j_used)
+            for i in range(j_used - 1, -1, -1):          # back substitution
+                y[i] = (g[i] - H[i, i + 1:j_used] @ y[i + 1:j_used]) / H[i, i]
+            x_chk = x_chk + Z[:, :j_used] @ y
+        info["relres_implicit"] = abs(g[j_used]) / bn
+        relres = true_relres(back(x_chk))
+        info["relres_true"] = relres
+        if relres <= o.tol:
+            info["converged"] = True
+            break
+        if info["outer_its"] >= o.max_outer:
+            break
+        if implicit_ok:
+            thr = thr * 0.5 * o.tol / relres
+    return x_chk, info
+
+
+def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None):
+    """x with A x = b (Sec. 3).  Returns (x, info)."""
+    o = o or SolveOptions()
+    b = np.asarray(b, dtype=np.float64)
+    if not np.all(np.isfinite(b)):
+        raise ValueError("b has non-finite entries")
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros(st.n), dict(converged=True, outer_its=0, inner_its_total=0,
+                                    inner_its_max=0, relres_true=0.0, relres_implicit=0.0,
+                                    cycles=0, k_eff=st.Q.shape[1], rank_r=st.N.size)
+
+    def true_relres(x):
+        return np.linalg.norm(b - st.A @ x) / bn
+
+    prec = lambda v: st.prec.apply(v, o.inner_tol, o.inner_maxit, o.fixed_inner_steps)
+    x_chk, info = _fgmres(st.op, prec, st.rhs(b), st.back, true_relres, o)
+    info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
+    return st.back(x_chk), info
+
+
+def solve_adjoint(st: OracleSetup, g: np.ndarray, o: SolveOptions | None = None):
+    """lambda with A^T lambda = g: FGMRES on A_chk^T right-preconditioned with P^T.
+    Returns (lambda, info)."""
+    o = o or SolveOptions()
+    g = np.asarray(g, dtype=np.float64)
+    if not np.all(np.isfinite(g)):
+        raise ValueError("g has non-finite entries")
+    gn = np.linalg.norm(g)
+    if gn == 0.0:
+        return np.zeros(st.n), dict(converged=True, outer_its=0, inner_its_total=0,
+                                    inner_its_max=0, relres_true=0.0, relres_implicit=0.0,
+                                    cycles=0, k_eff=st.Q.shape[1], rank_r=st.N.size)
+
+    def true_relres(lam):
+        return np.linalg.norm(g - st.A.T @ lam) / gn
+
+    prec = lambda v: st.prec.apply_T(v, o.inner_tol, o.inner_maxit, o.fixed_inner_steps)
+    l_chk, info = _fgmres(st.op_T, prec, st.rhs_T(g), st.back_T, true_relres, o)
+    info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
+    return st.back_T(l_chk), info
