@@ -12,7 +12,7 @@ permutation P and diagonal scalings Dr, Dc such that |abar_ii| = 1 and
   nonzero, gamma is the shortest-path distance from a virtual source joined to
   every node by a zero-weight edge over the edges i -> j of weight w_ij, i.e.
   the componentwise largest gamma <= 0 with gamma_j <= gamma_i + w_ij.
-  Dc = diag(exp(gamma)), the row scale of At row i is exp(-gamma_i - log|at_ii|).
+  Dc = diag(exp(gamma)), the row scale of At row i is exp(-gamma_i) / |at_ii|.
 
 Explicit zeros of the input are dropped (a stored zero is no nonzero).
 """
@@ -106,10 +106,11 @@ def canonical_scaling(A: sp.csr_matrix, m: np.ndarray):
         gamma = new
     else:
         raise ValueError("scaling relaxation did not settle (matching not optimal)")
-    rho = -gamma - np.log(at_diag)
+    # row scale exp(-gamma_i - log|at_ii|), evaluated as exp(-gamma_i)/|at_ii| so
+    # that |abar_ii| = 1 holds to rounding even when gamma_i = 0
     Dc = np.exp(gamma)
     Dr = np.empty(n)
-    Dr[m] = np.exp(rho)
+    Dr[m] = np.exp(-gamma) / at_diag
     return Dr, Dc
 
 
