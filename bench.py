@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the ASSS two-level solve on one MI355X.
+
+One step = one complete solve of A x = b to true relative residual 1e-8
+(FGMRES outer iteration, P^-1 through the SMW form around the inner mrs,
+back-transform and true-residual check), with A, b and all preconditioner
+data resident in HBM when the timed region starts.
+
+Workload (default): 3D convection-diffusion, 7-point first-order upwind on a
+128^3 grid (n = 2,097,152, nnz = 14,581,760), Peclet 100, wind (1, 0.5, 0.25),
+S on the pattern of Abar, k = 16 skew-Lanczos vectors, b = A x*, x* ~ U(-1,1).
+The plain FP64 solve is the headline value; the FP32-inner / FP64-outer solve
+of the same system is reported beside it.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 rel. residual + HBM GB/s; FP32-inner vs FP64 plain, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def mrs_bytes_per_row(nh_per_row: float, k: int, v: int) -> float:
+    """Algorithmic bytes of one inner mrs step per row: the strict upper
+    triangle of J_tilde once ((v + 4) per entry), its row pointer (4), the k
+    deflation vectors once (k v), and ten vector streams of v bytes (read q,
+    u, q_old, p_old2, x and a second q gather; write q', p, x; re-zero u)."""
+    return nh_per_row * (v + 4) + 4 + k * v + 10 * v
+
+
+def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, inner_full: int):
+    """The oracle (unchanged) timed on a smaller instance of the same workload
+    family; scaled to the full problem by rows and by total inner iterations."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    import workloads as W
+
+    w = W.convdiff3d(m=m_sample, peclet=peclet, cfg=1)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        st = O.setup(w.A, O.SetupOptions(k=k, s_pattern="abar"))
+        t1 = time.perf_counter()
+        x, info = O.solve(st, w.b, O.SolveOptions(tol=tol))
+        t2 = time.perf_counter()
+    n_s = w.A.shape[0]
+    inner_s = max(1, info["inner_its_total"])
+    scale = (n_full / n_s) * (inner_full / inner_s)
+    return {
+        "value": (t2 - t1) * scale, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle solve of convdiff3d {m_sample}^3 Pe{peclet:g} (n={n_s}) took "
+                   f"{t2 - t1:.2f} s ({info['outer_its']} outer / {info['inner_its_total']} inner its, "
+                   f"relres {info['relres_true']:.1e}; setup {t1 - t0:.1f} s not counted), scaled by "
+                   f"rows x total inner iterations to n={n_full}, {inner_full} inner its"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=128, help="grid points per axis")
+    ap.add_argument("--peclet", type=float, default=100.0)
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-m", type=int, default=24)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2009_06954_amd as asss
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    asss.load()
+    torch.cuda.set_device(0)
+    log(f"building workload m={args.m} Pe={args.peclet}")
+    w = W.convdiff3d(m=args.m, peclet=args.peclet, cfg=1)
+    n, nnz = w.A.shape[0], w.A.nnz
+    log(f"n={n} nnz={nnz}; setup (host preprocessing + device data)")
+    t0 = time.perf_counter()
+    h = asss.setup(w.A, k=args.k, s_pattern="abar", verbose=args.verbose)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    hi = h.info()
+    log(f"setup {setup_s:.2f} s: {hi}")
+    b = torch.from_numpy(w.b).cuda()
+    xs = torch.from_numpy(w.x_star).cuda()
+    x = torch.empty_like(b)
+
+    def run(mixed: bool, steps: int, warmup: int):
+        for i in range(warmup):
+            _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed)
+            log(f"warmup {'mixed' if mixed else 'fp64'} {i}: {inf['solve_s']:.3f} s, "
+                f"outer {inf['outer_its']}, inner {inf['inner_its_total']}, relres {inf['relres_true']:.2e}")
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed)
+            infos.append(inf)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+        for i, inf in enumerate(infos):
+            log(f"step {'mixed' if mixed else 'fp64'} {i}: {inf['solve_s']:.3f} s, outer {inf['outer_its']}, "
+                f"inner {inf['inner_its_total']}, relres {inf['relres_true']:.2e}, status {inf['status']}")
+        return total, infos, err
+
+    def roofline(infos, v):
+        kern_s = sum(i["inner_kernel_s"] for i in infos)
+        launches = sum(i["inner_launches"] for i in infos)
+        avg = kern_s / max(1, launches)
+        bpr = mrs_bytes_per_row(hi["nh"] / n, hi["k_eff"], v)
+        per_launch = bpr * n
+        achieved = per_launch / avg / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_mrs_iter (fused inner mrs step)",
+                "bytes_per_launch": int(per_launch), "bytes_per_row": round(bpr, 1),
+                "avg_launch_us": round(avg * 1e6, 2), "launches": launches}
+
+    total64, inf64, err64 = run(False, args.steps, args.warmup)
+    t64 = total64 / args.steps
+    res = {
+        "metric": METRIC, "value": round(t64, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t64, 3), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"convdiff3d_{args.m}^3_Pe{args.peclet:g}", "n": n, "nnz": nnz,
+                   "k": args.k, "s_pattern": "abar", "tol": args.tol, "outer": "fgmres(64)",
+                   "inner_tol": 1e-5},
+        "roofline": roofline(inf64, 8),
+        "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
+                  "relres_true": inf64[-1]["relres_true"], "rel_err_vs_xstar": err64,
+                  "inner_its_per_s": round(inf64[-1]["inner_its_total"] / inf64[-1]["solve_s"], 1)},
+        "setup_s": round(setup_s, 2),
+    }
+    if not args.no_mixed:
+        total32, inf32, err32 = run(True, args.steps, args.warmup)
+        t32 = total32 / args.steps
+        res["mixed"] = {"value": round(t32, 5), "unit": "s", "dtype": "f32 inner / f64 outer",
+                        "speedup_vs_fp64": round(t64 / t32, 3), "roofline": roofline(inf32, 4),
+                        "outer_its": inf32[-1]["outer_its"], "inner_its": inf32[-1]["inner_its_total"],
+                        "relres_true": inf32[-1]["relres_true"], "rel_err_vs_xstar": err32,
+                        "rel_diff_vs_fp64_solution": None}
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on convdiff3d {args.cpu_sample_m}^3")
+        try:
+            res["cpu_baseline"] = cpu_baseline(args.cpu_sample_m, args.peclet, args.k, args.tol, n,
+                                               inf64[-1]["inner_its_total"])
+        except Exception as e:  # the baseline must not hide the GPU result
+            res["cpu_baseline"] = {"value": None, "error": repr(e)}
+    h.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

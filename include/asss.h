@@ -1,0 +1,211 @@
+/*
+ * asss.h -- C ABI of libasss, a gfx950 (MI355X) implementation of the solve
+ * phase of the two-level iterative scheme of Manguoglu & Mehrmann, "A
+ * two-level iterative scheme for general sparse linear systems based on
+ * approximate skew-symmetrizers".
+ *
+ * A general sparse invertible A x = b (paper Sec. 1 eq. 1, Sec. 3 eq. sys) is
+ * preprocessed once (asss_setup):
+ *   - row permutation and scalings, Abar = P Dr A Dc with |abar_ii| = 1 and
+ *     |abar_ij| <= 1 (Sec. 2, eq. mc64);
+ *   - a sparse skew-symmetrizer S on a user-chosen pattern from a weighted
+ *     least-squares problem (Sec. 2, eqs. 1-2 and regularized; App. A);
+ *   - A_hat = Abar S split into D = diag(A_hat) and the skew part J_hat
+ *     (Sec. 3, eq. modified); Omega = |D|^(-1/2), J_tilde = Omega J_hat Omega;
+ *   - k skew-Lanczos vectors Q_k, S_k (Fig. 2), the deflated J_bar =
+ *     J_tilde - Q_k S_k Q_k^T, and the one-time Sherman-Morrison-Woodbury data
+ *     for the rank-(k+r) term (Sec. 3.2, eqs. preconditioner and smw; Sec. 4.1).
+ * Each solve (asss_solve) runs flexible GMRES on the scaled system
+ * Omega Abar S Omega, right-preconditioned with P = sign(D) + J_tilde, where
+ * P^-1 is applied through the SMW form around an inner minimal residual
+ * solve (mrs, Sec. 3.1 and App. B) on I + J_bar.
+ *
+ * Conventions
+ *   - Every function returns asss_status_t: 0 = ASSS_OK, > 0 = soft status
+ *     (outputs written), < 0 = error (outputs untouched, asss_last_error()
+ *     describes it).
+ *   - Host pointers are read during the call only and stay owned by the
+ *     caller.  Device pointers (b, x, g, lambda, in/out vectors) are owned by
+ *     the caller, must hold FP64 data of the stated length, and are used only
+ *     on the given HIP stream; they must stay valid until that stream has
+ *     finished the call's work (the call itself synchronises the stream
+ *     before it returns).
+ *   - A handle owns all its device memory (allocated with hipMalloc on the
+ *     device current at asss_setup) and is not thread-safe.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).
+ */
+#ifndef ASSS_H
+#define ASSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t asss_status_t;
+enum {
+  ASSS_OK = 0,
+  ASSS_NOT_CONVERGED = 1,            /* best iterate written, info filled */
+  ASSS_ERR_INVALID_ARG = -1,
+  ASSS_ERR_INVALID_CSR = -2,         /* unsorted / duplicate / out-of-range columns */
+  ASSS_ERR_STRUCTURALLY_SINGULAR = -3, /* no perfect matching exists (Sec. 2) */
+  ASSS_ERR_ZERO_DIAGONAL = -4,       /* diag(Abar S) has a zero: Omega undefined */
+  ASSS_ERR_LLS = -5,                 /* least-squares solve for S failed */
+  ASSS_ERR_NONFINITE = -6,           /* NaN/Inf in an input */
+  ASSS_ERR_HIP = -7,                 /* a HIP runtime call failed */
+  ASSS_ERR_OOM = -8,
+  ASSS_ERR_INTERNAL = -9
+};
+
+typedef struct asss_handle_s* asss_handle_t;
+
+/* Sparse matrix in CSR form, HOST memory: rowptr[n+1] (rowptr[0] = 0,
+ * non-decreasing, rowptr[n] = nnz), colind[nnz] strictly increasing within a
+ * row and in [0, n), val[nnz] finite.  Stored zeros are ignored (a zero value
+ * is not a nonzero of A). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* val;
+} asss_csr_t;
+
+/* Sparsity pattern of S (Sec. 2: diagonal, tridiagonal, the sparsity of
+ * Abar, or user defined; the experiments of Sec. 4 use the tridiagonal one). */
+enum {
+  ASSS_S_DIAG = 0,
+  ASSS_S_TRIDIAG = 1,
+  ASSS_S_PATTERN_OF_ABAR = 2,
+  ASSS_S_USER = 3          /* s_rowptr / s_colind, a CSR pattern in Abar's index space */
+};
+
+typedef struct {
+  double gamma;            /* weight of the diagonal equations (eq. regularized), default 1 */
+  int32_t s_pattern;       /* ASSS_S_*, default ASSS_S_TRIDIAG */
+  const int64_t* s_rowptr; /* USER pattern (host, n+1), else NULL */
+  const int32_t* s_colind; /* USER pattern (host), else NULL */
+  int32_t k;               /* skew-Lanczos vectors (Fig. 2), default 20; 0 = no deflation */
+  uint64_t lanczos_seed;   /* start vector: SplitMix64 stream of this seed, default 0x2009069540 */
+  int32_t inner_fp32;      /* default precision of the inner mrs: 0 = FP64, 1 = FP32 */
+  double x_tol;            /* tolerance of the one-time multi-RHS mrs for X, default 1e-10 */
+  int32_t x_maxit;         /* default 2000 */
+  double lls_tol;          /* LSQR atol = btol for S, default 1e-15 */
+  int32_t lls_maxit;       /* default 20000 */
+  int32_t row_block;       /* rows per LDS block of the skew operator, 0 = automatic */
+  int32_t verbose;         /* 0 = silent, 1 = timing lines on stderr */
+} asss_setup_opts_t;
+
+typedef struct {
+  double tol;              /* true relative residual ||b - A x|| / ||b||, default 1e-8 */
+  int32_t restart_m;       /* FGMRES restart length, default 64 */
+  int32_t max_outer;       /* total Arnoldi steps, default 2000 */
+  double inner_tol;        /* mrs relative tolerance, default 1e-5 */
+  int32_t inner_maxit;     /* default 1000 */
+  int32_t fixed_inner_steps; /* > 0: every mrs runs exactly this many steps */
+  int32_t inner_fp32;      /* -1 = handle default, 0 = FP64, 1 = FP32 inner */
+} asss_solve_opts_t;
+
+typedef struct {
+  int32_t converged;
+  int32_t outer_its;
+  int32_t inner_its_total;
+  int32_t inner_its_max;
+  int32_t k_eff;           /* Lanczos vectors actually produced */
+  int32_t rank_r;          /* number of negative entries of D */
+  int32_t cycles;          /* FGMRES cycles (restarts + 1) */
+  int32_t inner_launches;  /* launches of the fused mrs iteration kernel */
+  double relres_true;      /* ||b - A x|| / ||b|| in FP64 on the original A */
+  double relres_implicit;  /* FGMRES estimate on the scaled system */
+  double setup_host_s;
+  double setup_device_s;
+  double solve_s;
+  double inner_kernel_s;   /* HIP-event time of those launches (back to back on the stream) */
+} asss_info_t;
+
+/* Defaults of the option structs. */
+void asss_default_setup_opts(asss_setup_opts_t* o);
+void asss_default_solve_opts(asss_solve_opts_t* o);
+
+/* Preprocess A (copied) and build the device data of the preconditioner.
+ * Errors: INVALID_ARG, INVALID_CSR, NONFINITE, STRUCTURALLY_SINGULAR,
+ * ZERO_DIAGONAL, LLS, HIP, OOM.  On success *out receives a new handle. */
+asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts,
+                         void* hip_stream, asss_handle_t* out);
+
+/* x = A^-1 b (device FP64 vectors of length n).  ASSS_NOT_CONVERGED when
+ * max_outer was reached (x holds the last iterate).  NONFINITE if b has a
+ * NaN/Inf (x untouched).  info may be NULL. */
+asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev,
+                         const asss_solve_opts_t* o, asss_info_t* info, void* hip_stream);
+
+/* lambda = A^-T g: the same scheme on the transposed system, with P^-T
+ * applied as S_bar^-T (v - U_bar Sigma_bar^T C^-T X^T v) (derived from eq.
+ * smw by transposition). */
+asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* lambda_dev,
+                                 const asss_solve_opts_t* o, asss_info_t* info,
+                                 void* hip_stream);
+
+/* Several systems, each with several right-hand sides: system s has
+ * nrhs[s] columns in B_dev[s] / X_dev[s] (device, n_s x nrhs[s], column-major).
+ * infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be NULL).
+ * Returns the worst status over all columns. */
+asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const int32_t* nrhs,
+                                 const double* const* B_dev, double* const* X_dev,
+                                 const asss_solve_opts_t* o, asss_info_t* infos,
+                                 void* hip_stream);
+
+asss_status_t asss_destroy(asss_handle_t h);
+
+/* Thread-local description of the last error (never NULL). */
+const char* asss_last_error(void);
+
+/* ---- Inspection (used by parity tests and diagnostics) ------------------ */
+
+typedef struct {
+  int64_t n, nnz_a, nnz_s, nnz_ahat, nh, lls_rows, lls_nnz;
+  int32_t k_eff, rank_r, lls_its, x_its;
+  int32_t row_block, nblocks;
+  int64_t sell_entries_a, sell_entries_b; /* stored skew entries: in-block upper, off-block both */
+  double lls_relres, lls_kkt;             /* LSQR stopping quantities */
+} asss_handle_info_t;
+
+asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);
+
+/* Copy an internal array to host memory.  *count receives the number of
+ * elements; if dst is NULL only the count is returned.  Element types:
+ * MATCH, NEG, S_COLIND, J_COLIND int32; S_ROWPTR, J_ROWPTR int64; others FP64.
+ * Q and X are column-major n x k_eff and n x (k_eff + r). */
+enum {
+  ASSS_ARR_MATCH = 0,   /* m[j]: row of A matched to column j */
+  ASSS_ARR_DR = 1, ASSS_ARR_DC = 2,
+  ASSS_ARR_S_ROWPTR = 3, ASSS_ARR_S_COLIND = 4, ASSS_ARR_S_VAL = 5,
+  ASSS_ARR_D = 6,       /* diag(A_hat) */
+  ASSS_ARR_J_ROWPTR = 7, ASSS_ARR_J_COLIND = 8, ASSS_ARR_J_VAL = 9, /* strict upper J_tilde */
+  ASSS_ARR_Q = 10, ASSS_ARR_ALPHA = 11, ASSS_ARR_X = 12, ASSS_ARR_NEG = 13
+};
+asss_status_t asss_get_array(asss_handle_t h, int32_t which, void* dst, int64_t* count);
+
+/* Apply one operator of the method to a device FP64 vector (length n):
+ *   OP_SKEW       out = J_tilde in                    (FP64, or FP32 if o->inner_fp32 == 1)
+ *   OP_DEFLATED   out = J_bar in
+ *   OP_OUTER      out = Omega Abar S Omega in
+ *   OP_OUTER_T    out = (Omega Abar S Omega)^T in
+ *   OP_MRS        out = mrs solution of (I + J_bar) out = in   (o: inner_tol/maxit/fixed)
+ *   OP_PREC       out = P^-1 in   (eq. smw around mrs)
+ *   OP_PREC_T     out = P^-T in
+ *   OP_A, OP_AT   out = A in, A^T in
+ * *inner_its (may be NULL) receives the mrs iteration count. */
+enum {
+  ASSS_OP_SKEW = 0, ASSS_OP_DEFLATED = 1, ASSS_OP_OUTER = 2, ASSS_OP_OUTER_T = 3,
+  ASSS_OP_MRS = 4, ASSS_OP_PREC = 5, ASSS_OP_PREC_T = 6, ASSS_OP_A = 7, ASSS_OP_AT = 8
+};
+asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in_dev, double* out_dev,
+                         const asss_solve_opts_t* o, int32_t* inner_its, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASSS_H */

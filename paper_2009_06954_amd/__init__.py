@@ -1,0 +1,292 @@
+"""Python binding of libasss (include/asss.h): the solve phase of the two-level
+ASSS + mrs scheme of Manguoglu & Mehrmann on MI355X (gfx950).
+
+Argument marshalling only: every step of the method runs in libasss.  The
+library must have been built (``python -m paper_2009_06954_amd.build``);
+there is no fallback.
+
+    import paper_2009_06954_amd as asss
+    h = asss.setup(A_scipy_csr, k=16, s_pattern="abar")
+    x, info = h.solve(b_cuda_float64)
+
+PyTorch provides device memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasss.so")
+
+OK, NOT_CONVERGED = 0, 1
+_STATUS_NAMES = {
+    0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "INVALID_CSR",
+    -3: "STRUCTURALLY_SINGULAR", -4: "ZERO_DIAGONAL", -5: "LLS", -6: "NONFINITE",
+    -7: "HIP", -8: "OOM", -9: "INTERNAL",
+}
+S_PATTERNS = {"diag": 0, "tridiag": 1, "abar": 2, "user": 3}
+OPS = {"skew": 0, "deflated": 1, "outer": 2, "outer_t": 3, "mrs": 4, "prec": 5, "prec_t": 6,
+       "A": 7, "AT": 8}
+ARRAYS = {"match": (0, np.int32), "Dr": (1, np.float64), "Dc": (2, np.float64),
+          "S_rowptr": (3, np.int64), "S_colind": (4, np.int32), "S_val": (5, np.float64),
+          "D": (6, np.float64), "J_rowptr": (7, np.int64), "J_colind": (8, np.int32),
+          "J_val": (9, np.float64), "Q": (10, np.float64), "alpha": (11, np.float64),
+          "X": (12, np.float64), "neg": (13, np.int32)}
+
+EXPORTED = ["asss_default_setup_opts", "asss_default_solve_opts", "asss_setup", "asss_solve",
+            "asss_solve_adjoint", "asss_solve_batched", "asss_destroy", "asss_last_error",
+            "asss_get_handle_info", "asss_get_array", "asss_apply"]
+
+
+class CsrT(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("val", C.c_void_p)]
+
+
+class SetupOpts(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("s_pattern", C.c_int32), ("s_rowptr", C.c_void_p),
+                ("s_colind", C.c_void_p), ("k", C.c_int32), ("lanczos_seed", C.c_uint64),
+                ("inner_fp32", C.c_int32), ("x_tol", C.c_double), ("x_maxit", C.c_int32),
+                ("lls_tol", C.c_double), ("lls_maxit", C.c_int32), ("row_block", C.c_int32),
+                ("verbose", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart_m", C.c_int32), ("max_outer", C.c_int32),
+                ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
+                ("fixed_inner_steps", C.c_int32), ("inner_fp32", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("outer_its", C.c_int32), ("inner_its_total", C.c_int32),
+                ("inner_its_max", C.c_int32), ("k_eff", C.c_int32), ("rank_r", C.c_int32),
+                ("cycles", C.c_int32), ("inner_launches", C.c_int32), ("relres_true", C.c_double),
+                ("relres_implicit", C.c_double), ("setup_host_s", C.c_double),
+                ("setup_device_s", C.c_double), ("solve_s", C.c_double),
+                ("inner_kernel_s", C.c_double)]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class HandleInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_s", C.c_int64),
+                ("nnz_ahat", C.c_int64), ("nh", C.c_int64), ("lls_rows", C.c_int64),
+                ("lls_nnz", C.c_int64), ("k_eff", C.c_int32), ("rank_r", C.c_int32),
+                ("lls_its", C.c_int32), ("x_its", C.c_int32), ("row_block", C.c_int32),
+                ("nblocks", C.c_int32), ("sell_entries_a", C.c_int64),
+                ("sell_entries_b", C.c_int64), ("lls_relres", C.c_double), ("lls_kkt", C.c_double)]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class AsssError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)} ({status}): {msg}")
+        self.status = status
+        self.name = _STATUS_NAMES.get(status, str(status))
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libasss.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2009_06954_amd.build`")
+    lib = C.CDLL(path)
+    lib.asss_last_error.restype = C.c_char_p
+    lib.asss_default_setup_opts.argtypes = [C.POINTER(SetupOpts)]
+    lib.asss_default_solve_opts.argtypes = [C.POINTER(SolveOpts)]
+    lib.asss_setup.argtypes = [C.POINTER(CsrT), C.POINTER(SetupOpts), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.asss_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
+                               C.POINTER(Info), C.c_void_p]
+    lib.asss_solve_adjoint.argtypes = lib.asss_solve.argtypes
+    lib.asss_solve_batched.argtypes = [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                       C.POINTER(SolveOpts), C.POINTER(Info), C.c_void_p]
+    lib.asss_destroy.argtypes = [C.c_void_p]
+    lib.asss_get_handle_info.argtypes = [C.c_void_p, C.POINTER(HandleInfo)]
+    lib.asss_get_array.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]
+    lib.asss_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
+                               C.POINTER(C.c_int32), C.c_void_p]
+    for f in EXPORTED:
+        if f != "asss_last_error":
+            getattr(lib, f).restype = None if f.startswith("asss_default") else C.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(status, allow_soft=True):
+    if status < 0 or (status > 0 and not allow_soft):
+        raise AsssError(status, _lib.asss_last_error().decode())
+    return status
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _csr_arrays(A, canonicalize=True):
+    import scipy.sparse as sp
+    if hasattr(A, "crow_indices"):  # torch sparse CSR (CPU)
+        rp = A.crow_indices().numpy().astype(np.int64)
+        ci = A.col_indices().numpy().astype(np.int32)
+        va = A.values().numpy().astype(np.float64)
+        n = A.shape[0]
+    else:
+        A = sp.csr_matrix(A, copy=True)
+        if canonicalize:
+            A.sum_duplicates()
+            A.sort_indices()
+        rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+        va = np.ascontiguousarray(A.data, dtype=np.float64)
+        n = A.shape[0]
+    return n, rp, ci, va
+
+
+def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_maxit=1000,
+                  fixed_inner_steps=0, inner_fp32=None) -> SolveOpts:
+    o = SolveOpts()
+    load().asss_default_solve_opts(C.byref(o))
+    o.tol, o.restart_m, o.max_outer = tol, restart_m, max_outer
+    o.inner_tol, o.inner_maxit, o.fixed_inner_steps = inner_tol, inner_maxit, fixed_inner_steps
+    o.inner_fp32 = -1 if inner_fp32 is None else int(bool(inner_fp32))
+    return o
+
+
+class Handle:
+    """A preprocessed matrix on the GPU (owns all its device memory)."""
+
+    def __init__(self, ptr, n):
+        self._h = C.c_void_p(ptr)
+        self.n = n
+
+    def close(self):
+        if self._h and self._h.value:
+            _check(load().asss_destroy(self._h))
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, v):
+        import torch
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64
+                and v.is_contiguous() and v.numel() == self.n):
+            raise ValueError(f"expected a contiguous CUDA float64 tensor of length {self.n}")
+        return v
+
+    def solve(self, b, out=None, stream=None, **opts):
+        """x = A^-1 b.  Returns (x, info dict); info['status'] is OK or NOT_CONVERGED."""
+        import torch
+        b = self._vec(b)
+        x = out if out is not None else torch.empty_like(b)
+        info = Info()
+        st = _check(load().asss_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                      C.byref(solve_options(**opts)), C.byref(info), _stream(stream)))
+        d = info.to_dict()
+        d["status"] = _STATUS_NAMES[st]
+        return x, d
+
+    def solve_adjoint(self, g, out=None, stream=None, **opts):
+        """lambda = A^-T g.  Returns (lambda, info dict)."""
+        import torch
+        g = self._vec(g)
+        lam = out if out is not None else torch.empty_like(g)
+        info = Info()
+        st = _check(load().asss_solve_adjoint(self._h, C.c_void_p(g.data_ptr()), C.c_void_p(lam.data_ptr()),
+                                              C.byref(solve_options(**opts)), C.byref(info), _stream(stream)))
+        d = info.to_dict()
+        d["status"] = _STATUS_NAMES[st]
+        return lam, d
+
+    def apply(self, op, v, out=None, stream=None, **opts):
+        """One operator of the method (see asss_apply).  Returns (out, inner_its)."""
+        import torch
+        v = self._vec(v)
+        o = out if out is not None else torch.empty_like(v)
+        its = C.c_int32(0)
+        _check(load().asss_apply(self._h, OPS[op], C.c_void_p(v.data_ptr()), C.c_void_p(o.data_ptr()),
+                                 C.byref(solve_options(**opts)), C.byref(its), _stream(stream)))
+        return o, its.value
+
+    def info(self) -> dict:
+        hi = HandleInfo()
+        _check(load().asss_get_handle_info(self._h, C.byref(hi)))
+        return hi.to_dict()
+
+    def array(self, name) -> np.ndarray:
+        which, dt = ARRAYS[name]
+        cnt = C.c_int64(0)
+        _check(load().asss_get_array(self._h, which, None, C.byref(cnt)))
+        out = np.empty(cnt.value, dtype=dt)
+        if cnt.value:
+            _check(load().asss_get_array(self._h, which, C.c_void_p(out.ctypes.data), C.byref(cnt)))
+        return out
+
+
+def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, inner_fp32=False,
+          x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
+          stream=None, canonicalize=True) -> Handle:
+    """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
+    canonicalize: sum duplicates and sort column indices of a SciPy input first
+    (otherwise the library rejects such input with INVALID_CSR)."""
+    lib = load()
+    n, rp, ci, va = _csr_arrays(A, canonicalize)
+    csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    o = SetupOpts()
+    lib.asss_default_setup_opts(C.byref(o))
+    keep = []
+    if isinstance(s_pattern, str):
+        o.s_pattern = S_PATTERNS[s_pattern]
+    else:
+        _, srp, sci, _ = _csr_arrays(s_pattern)
+        keep += [srp, sci]
+        o.s_pattern = S_PATTERNS["user"]
+        o.s_rowptr, o.s_colind = srp.ctypes.data, sci.ctypes.data
+    o.gamma, o.k, o.lanczos_seed, o.inner_fp32 = gamma, k, lanczos_seed, int(bool(inner_fp32))
+    o.x_tol, o.x_maxit, o.lls_tol, o.lls_maxit = x_tol, x_maxit, lls_tol, lls_maxit
+    o.row_block, o.verbose = row_block, int(bool(verbose))
+    out = C.c_void_p()
+    _check(lib.asss_setup(C.byref(csr), C.byref(o), _stream(stream), C.byref(out)))
+    return Handle(out.value, n)
+
+
+def solve_batched(handles, Bs, stream=None, **opts):
+    """Solve several systems, each with several right-hand sides (B: n_s x nrhs_s
+    CUDA float64, column-major i.e. the transpose of a contiguous (nrhs, n)
+    tensor is expected as B.T).  Returns (list of X, list of info lists)."""
+    import torch
+    lib = load()
+    ns = len(handles)
+    Xs, nr = [], []
+    for h, B in zip(handles, Bs):
+        if B.dim() == 1:
+            B = B[:, None]
+        if not (B.is_cuda and B.dtype == torch.float64 and B.shape[0] == h.n and B.t().is_contiguous()):
+            raise ValueError("each B must be a column-major (n, nrhs) CUDA float64 tensor")
+        Xs.append(torch.empty_like(B))
+        nr.append(B.shape[1])
+    maxr = max(nr) if nr else 0
+    hs = (C.c_void_p * ns)(*[h._h.value for h in handles])
+    nra = (C.c_int32 * ns)(*nr)
+    bp = (C.c_void_p * ns)(*[B.data_ptr() for B in Bs])
+    xp = (C.c_void_p * ns)(*[X.data_ptr() for X in Xs])
+    infos = (Info * max(1, ns * maxr))()
+    _check(lib.asss_solve_batched(ns, hs, nra, bp, xp, C.byref(solve_options(**opts)), infos, _stream(stream)))
+    out_infos = [[infos[s * maxr + j].to_dict() for j in range(nr[s])] for s in range(ns)]
+    return Xs, out_infos

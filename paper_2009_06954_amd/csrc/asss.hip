@@ -1,0 +1,1054 @@
+// libasss driver: handle, device part of the setup (least-squares solve for S,
+// skew-Lanczos, one-time SMW data), the flexible GMRES outer iteration with
+// the preconditioner P^-1 of eq. smw around the inner mrs, the adjoint solve,
+// and the C ABI declared in include/asss.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstddef>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/asss.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace asss;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw Error{e_ == hipErrorOutOfMemory ? ASSS_ERR_OOM : ASSS_ERR_HIP,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_)};                       \
+  } while (0)
+
+// leading part of MrsState read back by the host: its, status, ..., relres_max
+constexpr size_t kStateHead = offsetof(MrsState, relres_max) + sizeof(double);
+// layout of the small device/pinned scalar buffers (doubles)
+constexpr int SM_H1 = 0, SM_H2 = 1024, SM_HN = 2047, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocations owned by a handle.
+struct DevArena {
+  std::vector<void*> ptrs;
+  template <typename T>
+  T* alloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, (size_t)count * sizeof(T)));
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = alloc<T>((int64_t)v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  void release(void* p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(*it);
+      ptrs.erase(it);
+    }
+  }
+  ~DevArena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+int lanes_for(const Csr& M) {
+  double avg = M.nrows ? (double)M.nnz() / (double)M.nrows : 1.0;
+  int l = 1;
+  while (l < avg && l < 64) l <<= 1;
+  return l;
+}
+
+DCsr upload_csr(DevArena& ar, const Csr& M, hipStream_t s) {
+  DCsr d;
+  d.nrows = M.nrows;
+  d.ncols = M.ncols;
+  d.nnz = M.nnz();
+  d.ptr = ar.upload(M.ptr, s);
+  d.col = ar.upload(M.col, s);
+  d.val = ar.upload(M.val, s);
+  d.lanes = lanes_for(M);
+  return d;
+}
+
+template <typename T>
+DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32_t* aw,
+                     const int32_t* bw, const int64_t* ao, const int64_t* bo, const uint16_t* ac,
+                     const int32_t* bc) {
+  DSkew<T> d;
+  d.n = S.n;
+  d.R = S.R;
+  d.nblocks = S.nblocks;
+  d.nslices = S.nslices;
+  d.a_width = aw;
+  d.b_width = bw;
+  d.a_off = ao;
+  d.b_off = bo;
+  d.a_col = ac;
+  d.b_col = bc;
+  std::vector<T> av(S.a_val.begin(), S.a_val.end()), bv(S.b_val.begin(), S.b_val.end());
+  d.a_val = ar.upload(av, s);
+  d.b_val = ar.upload(bv, s);
+  return d;
+}
+
+}  // namespace
+
+struct asss_handle_s {
+  int device = 0;
+  int64_t n = 0;
+  asss_setup_opts_t opts{};
+  DevArena ar;
+  // host data kept for inspection
+  std::vector<int32_t> m;
+  std::vector<double> Dr, Dc, D, Omega, alpha;
+  Csr S, U;
+  std::vector<double> jval;
+  std::vector<int32_t> neg;
+  int64_t nnz_a = 0, nnz_ahat = 0, lls_rows = 0, lls_nnz = 0;
+  int lls_its = 0, x_its = 0;
+  double lls_relres = 0, lls_kkt = 0;
+  int64_t sell_a = 0, sell_b = 0;
+  int k_eff = 0, r = 0, kr = 0;
+  double setup_host_s = 0, setup_device_s = 0;
+  // device data
+  DCsr dA, dAt, dAbar, dAbarT, dS, dSt;
+  int32_t* d_m = nullptr;
+  double *d_drp = nullptr, *d_om = nullptr, *d_dc = nullptr;
+  DSkew<double> J64;
+  DSkew<float> J32;
+  double* d_Q64 = nullptr;
+  float* d_Q32 = nullptr;
+  double* d_alpha = nullptr;
+  double* d_Ubar = nullptr;   // n x kr column-major
+  double* d_X = nullptr;      // n x kr column-major
+  double* d_Mf = nullptr;     // C^-1 Sigma (kr x kr row-major)
+  double* d_Ma = nullptr;     // Sigma^T C^-T (kr x kr row-major)
+  MrsBufs<double> mb64{};
+  MrsBufs<float> mb32{};
+  MrsState* d_state = nullptr;
+  Reducer red;
+  double* d_small = nullptr;  // 1024 doubles of scalars
+  int* d_flag = nullptr;
+  double* h_small = nullptr;  // pinned
+  // outer workspace
+  int m_alloc = 0;
+  double *V = nullptr, *Z = nullptr;
+  double *w = nullptr, *t1 = nullptr, *xchk = nullptr, *bchk = nullptr, *rv = nullptr, *tmp = nullptr;
+  int last_inner = 0;
+  // HIP events bracketing each chunk of back-to-back mrs iteration kernels
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double prof_s = 0.0;
+  int prof_launches = 0;
+
+  ~asss_handle_s() {
+    if (h_small) (void)hipHostFree(h_small);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small helpers on the handle
+// ---------------------------------------------------------------------------
+
+double dot_host(asss_handle_s* h, int64_t n, const double* a, const double* b, hipStream_t s) {
+  gemm_tn<double, double>(n, 1, a, n, b, 1, h->d_small, nullptr, h->red, 2, s);
+  HIPCHK(hipMemcpyAsync(h->h_small, h->d_small, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return h->h_small[0];
+}
+
+// w = Omega Abar S Omega z   (t1 scratch)
+void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
+  spmv(h->dS, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
+  spmv(h->dAbar, h->t1, w, h->d_om, nullptr, 0, nullptr, s);
+}
+// w = (Omega Abar S Omega)^T z = Omega S^T Abar^T Omega z
+void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
+  spmv(h->dAbarT, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
+  spmv(h->dSt, h->t1, w, h->d_om, nullptr, 0, nullptr, s);
+}
+
+// ---------------------------------------------------------------------------
+// inner mrs driver (single right-hand side, NR = 1)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb, const double* rhs,
+             double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
+  MrsLaunch L{h->n, 1, h->k_eff, h->d_alpha, sign};
+  mrs_init<T, 1>(L, rhs, h->n, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
+  int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
+  int its = 0;
+  double prev_rel = 1.0;
+  int prev_its = 0;
+  for (int guard = 0; guard < 100000; ++guard) {
+    HIPCHK(hipEventRecord(h->ev0, s));
+    for (int c = 0; c < chunk; ++c) mrs_iter<T, 1>(L, J, Q, mb, h->d_state, h->red, s);
+    HIPCHK(hipEventRecord(h->ev1, s));
+    HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      h->prof_s += 1e-3 * ms;
+      h->prof_launches += chunk;
+    }
+    int32_t st_its, st_status;
+    double rel;
+    std::memcpy(&st_its, (char*)h->h_small + offsetof(MrsState, its), 4);
+    std::memcpy(&st_status, (char*)h->h_small + offsetof(MrsState, status), 4);
+    std::memcpy(&rel, (char*)h->h_small + offsetof(MrsState, relres_max), 8);
+    if (st_status == MRS_RUNNING && st_its <= its && guard > 0)
+      throw Error{ASSS_ERR_INTERNAL, "inner mrs made no progress"};
+    its = st_its;
+    if (st_status == MRS_DONE) break;
+    if (st_status == MRS_CONVERGED) {
+      mrs_iter<T, 1>(L, J, Q, mb, h->d_state, h->red, s);  // final deferred update
+      break;
+    }
+    // estimate the remaining iterations from the observed contraction rate
+    int est = 8;
+    if (its > prev_its && rel > 0 && prev_rel > 0 && rel < prev_rel) {
+      double rate = std::log(rel / prev_rel) / (double)(its - prev_its);
+      double need = std::log(tol / rel) / rate;
+      est = (int)std::ceil(need) + 1;
+    }
+    int left = (fixed > 0 ? fixed : maxit) - its + 1;
+    chunk = std::max(2, std::min({est, 64, left}));
+    prev_rel = rel;
+    prev_its = its;
+  }
+  mrs_output<T, 1>(h->n, 1, mb, out, h->n, s);
+  h->last_inner = its;
+  return its;
+}
+
+int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
+                int maxit, int fixed, hipStream_t s) {
+  if (fp32) return run_mrs1<float>(h, h->J32, h->d_Q32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
+  return run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
+}
+
+// z = P^-1 v (eq. smw in the inverse-free form)
+int prec_apply(asss_handle_s* h, bool fp32, const double* v, double* z, const asss_solve_opts_t& o,
+               hipStream_t s) {
+  int its = inner_solve(h, fp32, v, z, +1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
+  if (h->kr > 0) {
+    double* t = h->d_small + SM_T;
+    gemm_tn<double, double>(h->n, h->kr, h->d_Ubar, h->n, z, 1, t, h->d_Mf, h->red, 3, s);
+    gemv_acc(h->n, h->kr, h->d_X, h->n, t, -1.0, z, s);
+  }
+  return its;
+}
+
+// z = P^-T v = S_bar^-T (v - U_bar Sigma^T C^-T X^T v)
+int prec_apply_T(asss_handle_s* h, bool fp32, const double* v, double* z, const asss_solve_opts_t& o,
+                 hipStream_t s) {
+  const double* rhs = v;
+  if (h->kr > 0) {
+    double* t = h->d_small + SM_T;
+    gemm_tn<double, double>(h->n, h->kr, h->d_X, h->n, v, 1, t, h->d_Ma, h->red, 3, s);
+    axpby(h->n, 1.0, v, 0.0, h->tmp, s);
+    gemv_acc(h->n, h->kr, h->d_Ubar, h->n, t, -1.0, h->tmp, s);
+    rhs = h->tmp;
+  }
+  return inner_solve(h, fp32, rhs, z, -1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
+}
+
+// ---------------------------------------------------------------------------
+// setup: least squares for S on the device (LSQR, Paige & Saunders 1982)
+// ---------------------------------------------------------------------------
+
+std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol, int maxit,
+                                hipStream_t s) {
+  DevArena tmp;
+  const int64_t m = L.B.nrows, nu = L.B.ncols;
+  DCsr B = upload_csr(tmp, L.B, s), Bt = upload_csr(tmp, L.Bt, s);
+  double* u = tmp.upload(L.rhs, s);
+  double* v = tmp.alloc<double>(nu);
+  double* w = tmp.alloc<double>(nu);
+  double* x = tmp.alloc<double>(nu);
+  double* y = tmp.alloc<double>(std::max(m, nu));
+  HIPCHK(hipMemsetAsync(x, 0, nu * sizeof(double), s));
+  auto nrm = [&](int64_t len, const double* a) { return std::sqrt(dot_host(h, len, a, a, s)); };
+  double beta = nrm(m, u);
+  const double bnorm = beta;
+  std::vector<double> out(nu, 0.0);
+  if (beta == 0.0) return out;
+  scale(m, 1.0 / beta, u, u, s);
+  spmv(Bt, u, v, nullptr, nullptr, 0, nullptr, s);
+  double alpha = nrm(nu, v);
+  if (alpha == 0.0) return out;
+  scale(nu, 1.0 / alpha, v, v, s);
+  axpby(nu, 1.0, v, 0.0, w, s);
+  double phibar = beta, rhobar = alpha, anorm2 = 0.0;
+  int it = 0;
+  double test1 = 1.0, test2 = 1.0;
+  for (it = 1; it <= maxit; ++it) {
+    spmv(B, v, y, nullptr, nullptr, 0, nullptr, s);
+    axpby(m, 1.0, y, -alpha, u, s);
+    beta = nrm(m, u);
+    if (beta > 0) scale(m, 1.0 / beta, u, u, s);
+    anorm2 += alpha * alpha + beta * beta;
+    spmv(Bt, u, y, nullptr, nullptr, 0, nullptr, s);
+    axpby(nu, 1.0, y, -beta, v, s);
+    alpha = nrm(nu, v);
+    if (alpha > 0) scale(nu, 1.0 / alpha, v, v, s);
+    const double rho = std::hypot(rhobar, beta);
+    const double c = rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    rhobar = -c * alpha;
+    const double phi = c * phibar;
+    phibar = sn * phibar;
+    axpby(nu, phi / rho, w, 1.0, x, s);
+    axpby(nu, 1.0, v, -theta / rho, w, s);
+    const double anorm = std::sqrt(anorm2);
+    const double rnorm = phibar;
+    const double arnorm = phibar * alpha * std::fabs(c);
+    test1 = rnorm / bnorm;
+    test2 = (anorm > 0 && rnorm > 0) ? arnorm / (anorm * rnorm) : 0.0;
+    if (test1 <= tol || test2 <= std::max(tol, 1.1e-16) || alpha == 0.0) break;
+  }
+  h->lls_its = std::min(it, maxit);
+  h->lls_relres = test1;
+  h->lls_kkt = test2;
+  HIPCHK(hipMemcpyAsync(out.data(), x, nu * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (double vv : out)
+    if (!std::isfinite(vv)) throw Error{ASSS_ERR_LLS, "least-squares solution is not finite"};
+  return out;
+}
+
+// LU with partial pivoting of a small dense matrix (row-major), and solves.
+struct SmallLU {
+  int n = 0;
+  std::vector<double> a;
+  std::vector<int> piv;
+  void factor(const std::vector<double>& m, int nn) {
+    n = nn;
+    a = m;
+    piv.resize(n);
+    for (int k = 0; k < n; ++k) {
+      int p = k;
+      for (int i = k + 1; i < n; ++i)
+        if (std::fabs(a[i * n + k]) > std::fabs(a[p * n + k])) p = i;
+      piv[k] = p;
+      if (p != k)
+        for (int j = 0; j < n; ++j) std::swap(a[k * n + j], a[p * n + j]);
+      if (a[k * n + k] == 0.0) throw Error{ASSS_ERR_INTERNAL, "SMW matrix C is singular"};
+      for (int i = k + 1; i < n; ++i) {
+        a[i * n + k] /= a[k * n + k];
+        for (int j = k + 1; j < n; ++j) a[i * n + j] -= a[i * n + k] * a[k * n + j];
+      }
+    }
+  }
+  // solve C x = b (trans = false) or C^T x = b (trans = true)
+  std::vector<double> solve(std::vector<double> b, bool trans) const {
+    if (!trans) {
+      for (int k = 0; k < n; ++k) std::swap(b[k], b[piv[k]]);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) b[i] -= a[i * n + j] * b[j];
+      for (int i = n - 1; i >= 0; --i) {
+        for (int j = i + 1; j < n; ++j) b[i] -= a[i * n + j] * b[j];
+        b[i] /= a[i * n + i];
+      }
+    } else {
+      for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < i; ++j) b[i] -= a[j * n + i] * b[j];
+        b[i] /= a[i * n + i];
+      }
+      for (int i = n - 1; i >= 0; --i)
+        for (int j = i + 1; j < n; ++j) b[i] -= a[j * n + i] * b[j];
+      for (int k = n - 1; k >= 0; --k) std::swap(b[k], b[piv[k]]);
+    }
+    return b;
+  }
+};
+
+void device_setup(asss_handle_s* h, hipStream_t s) {
+  const int64_t n = h->n;
+  const int k = h->opts.k;
+  // ---- skew-Lanczos (Fig. 2) in FP64
+  std::vector<double> alpha;
+  int keff = 0;
+  if (k > 0) {
+    h->d_Q64 = h->ar.alloc<double>(n * (int64_t)k);
+    double* z = h->ar.alloc<double>(n);
+    double* q0 = h->d_Q64;
+    splitmix_vector(n, h->opts.lanczos_seed, q0, s);
+    double nq = std::sqrt(dot_host(h, n, q0, q0, s));
+    scale(n, 1.0 / nq, q0, q0, s);
+    keff = 1;
+    if (k >= 2) {
+      skew_spmv<double>(h->J64, q0, z, s);
+      double a1 = std::sqrt(dot_host(h, n, z, z, s));
+      if (a1 != 0.0) {
+        alpha.push_back(a1);
+        scale(n, -1.0 / a1, z, h->d_Q64 + n, s);
+        keff = 2;
+        for (int i = 2; i < k; ++i) {
+          skew_spmv<double>(h->J64, h->d_Q64 + (int64_t)(i - 1) * n, z, s);
+          axpby(n, -alpha[i - 2], h->d_Q64 + (int64_t)(i - 2) * n, 1.0, z, s);
+          double ai = std::sqrt(dot_host(h, n, z, z, s));
+          if (ai <= 1e-14 * a1) break;
+          alpha.push_back(ai);
+          scale(n, -1.0 / ai, z, h->d_Q64 + (int64_t)i * n, s);
+          keff = i + 1;
+        }
+      }
+    }
+    h->ar.release(z);
+  }
+  h->k_eff = keff;
+  h->alpha = alpha;
+  h->d_alpha = h->ar.upload(alpha.empty() ? std::vector<double>{0.0} : alpha, s);
+  if (keff > 0) {
+    h->d_Q32 = h->ar.alloc<float>(n * (int64_t)keff);
+    cast_d2f(n * (int64_t)keff, h->d_Q64, h->d_Q32, s);
+  }
+  // ---- one-time SMW data (Sec. 4.1): U_bar, X = S_bar^-1 U_bar, G, C
+  h->r = (int)h->neg.size();
+  const int kr = keff + h->r;
+  if (kr > 512) throw Error{ASSS_ERR_INTERNAL, "rank of the low-rank term k + r exceeds 512"};
+  h->kr = kr;
+  if (kr == 0) return;
+  h->d_Ubar = h->ar.alloc<double>(n * (int64_t)kr);
+  HIPCHK(hipMemsetAsync(h->d_Ubar, 0, n * (int64_t)kr * sizeof(double), s));
+  if (keff > 0)
+    HIPCHK(hipMemcpyAsync(h->d_Ubar, h->d_Q64, n * (int64_t)keff * sizeof(double), hipMemcpyDeviceToDevice, s));
+  {
+    std::vector<double> one(1, 1.0);
+    for (int j = 0; j < h->r; ++j)
+      HIPCHK(hipMemcpyAsync(h->d_Ubar + (int64_t)(keff + j) * n + h->neg[j], one.data(), sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  h->d_X = h->ar.alloc<double>(n * (int64_t)kr);
+  // simultaneous mrs (App. B) on groups of NRMAX columns in FP64
+  {
+    DevArena tmp;
+    MrsBufs<double> mb4;
+    for (int b = 0; b < 3; ++b) mb4.w[b] = tmp.alloc<double>(n * NRMAX);
+    for (int b = 0; b < 2; ++b) mb4.p[b] = tmp.alloc<double>(n * NRMAX);
+    mb4.x = tmp.alloc<double>(n * NRMAX);
+    const bool use4 = keff <= 16;
+    int xits = 0;
+    for (int c0 = 0; c0 < kr; c0 += (use4 ? NRMAX : 1)) {
+      const int nc = use4 ? std::min(NRMAX, kr - c0) : 1;
+      if (use4) {
+        MrsLaunch L{n, nc, keff, h->d_alpha, +1};
+        mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_Q64, mb4, h->d_state,
+                                h->opts.x_tol, h->opts.x_maxit, 0, h->red, s);
+        for (int guard = 0; guard < 1000000; ++guard) {
+          for (int c = 0; c < 16; ++c) mrs_iter<double, NRMAX>(L, h->J64, h->d_Q64, mb4, h->d_state, h->red, s);
+          HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          int32_t st_its, st_status;
+          std::memcpy(&st_its, (char*)h->h_small, 4);
+          std::memcpy(&st_status, (char*)h->h_small + 4, 4);
+          if (st_status == MRS_RUNNING && st_its <= xits && guard > 0)
+            throw Error{ASSS_ERR_INTERNAL, "setup mrs made no progress"};
+          xits = std::max(xits, (int)st_its);
+          if (st_status == MRS_DONE) break;
+          if (st_status == MRS_CONVERGED) {
+            mrs_iter<double, NRMAX>(L, h->J64, h->d_Q64, mb4, h->d_state, h->red, s);
+            break;
+          }
+        }
+        mrs_output<double, NRMAX>(n, nc, mb4, h->d_X + (int64_t)c0 * n, n, s);
+      } else {
+        int it = run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, h->d_Ubar + (int64_t)c0 * n,
+                                  h->d_X + (int64_t)c0 * n, +1, h->opts.x_tol, h->opts.x_maxit, 0, s);
+        xits = std::max(xits, it);
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    h->x_its = xits;
+  }
+  // G = U_bar^T X (kr x kr), C = I + Sigma G
+  std::vector<double> G((size_t)kr * kr);
+  for (int c = 0; c < kr; ++c) {
+    gemm_tn<double, double>(n, kr, h->d_Ubar, n, h->d_X + (int64_t)c * n, 1, h->d_small, nullptr, h->red, 2, s);
+    HIPCHK(hipMemcpyAsync(h->h_small, h->d_small, kr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int l = 0; l < kr; ++l) G[(size_t)l * kr + c] = h->h_small[l];
+  }
+  std::vector<double> Sig((size_t)kr * kr, 0.0);
+  for (int i = 0; i + 1 < keff; ++i) {
+    Sig[(size_t)i * kr + i + 1] = alpha[i];
+    Sig[(size_t)(i + 1) * kr + i] = -alpha[i];
+  }
+  for (int j = 0; j < h->r; ++j) Sig[(size_t)(keff + j) * kr + keff + j] = -2.0;
+  std::vector<double> C((size_t)kr * kr, 0.0);
+  for (int i = 0; i < kr; ++i)
+    for (int j = 0; j < kr; ++j) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int l = 0; l < kr; ++l) acc += Sig[(size_t)i * kr + l] * G[(size_t)l * kr + j];
+      C[(size_t)i * kr + j] = acc;
+    }
+  SmallLU lu;
+  lu.factor(C, kr);
+  // Mf = C^-1 Sigma (columns: C^-1 Sigma e_j), Ma = Sigma^T C^-T
+  std::vector<double> Mf((size_t)kr * kr), CinvT((size_t)kr * kr), Ma((size_t)kr * kr);
+  for (int j = 0; j < kr; ++j) {
+    std::vector<double> col(kr), e(kr, 0.0);
+    for (int i = 0; i < kr; ++i) col[i] = Sig[(size_t)i * kr + j];
+    col = lu.solve(col, false);
+    for (int i = 0; i < kr; ++i) Mf[(size_t)i * kr + j] = col[i];
+    e[j] = 1.0;
+    e = lu.solve(e, true);  // column j of C^-T
+    for (int i = 0; i < kr; ++i) CinvT[(size_t)i * kr + j] = e[i];
+  }
+  for (int i = 0; i < kr; ++i)
+    for (int j = 0; j < kr; ++j) {
+      double acc = 0.0;
+      for (int l = 0; l < kr; ++l) acc += Sig[(size_t)l * kr + i] * CinvT[(size_t)l * kr + j];
+      Ma[(size_t)i * kr + j] = acc;
+    }
+  h->d_Mf = h->ar.upload(Mf, s);
+  h->d_Ma = h->ar.upload(Ma, s);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+void ensure_outer(asss_handle_s* h, int m) {
+  if (h->m_alloc >= m) return;
+  if (h->V) { h->ar.release(h->V); h->ar.release(h->Z); }
+  h->V = h->ar.alloc<double>(h->n * (int64_t)(m + 1));
+  h->Z = h->ar.alloc<double>(h->n * (int64_t)m);
+  h->m_alloc = m;
+}
+
+bool b_is_finite(asss_handle_s* h, const double* b, hipStream_t s) {
+  HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+  check_finite(h->n, b, h->d_flag, s);
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return flag == 0;
+}
+
+// Flexible GMRES(m) on the scaled system with the stopping rule of the oracle.
+asss_status_t fgmres(asss_handle_s* h, bool adjoint, const double* b, double* x,
+                     const asss_solve_opts_t& o, asss_info_t* info, hipStream_t s) {
+  const double t0 = now_s();
+  const int64_t n = h->n;
+  const bool fp32 = (o.inner_fp32 < 0) ? (h->opts.inner_fp32 != 0) : (o.inner_fp32 != 0);
+  asss_info_t inf{};
+  inf.k_eff = h->k_eff;
+  inf.rank_r = h->r;
+  inf.setup_host_s = h->setup_host_s;
+  inf.setup_device_s = h->setup_device_s;
+  const double bn = std::sqrt(dot_host(h, n, b, b, s));
+  if (bn == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    HIPCHK(hipStreamSynchronize(s));
+    inf.converged = 1;
+    inf.solve_s = now_s() - t0;
+    if (info) *info = inf;
+    return ASSS_OK;
+  }
+  const int m = std::max(1, o.restart_m);
+  ensure_outer(h, m);
+  // right-hand side of the scaled system
+  if (!adjoint) {
+    gather_scale(n, h->d_m, h->d_drp, h->d_om, b, h->bchk, s);
+  } else {
+    // g_chk = Omega S^T (Dc o g)
+    spmv(h->dSt, b, h->bchk, h->d_om, h->d_dc, 0, nullptr, s);
+  }
+  const double bcn = std::sqrt(dot_host(h, n, h->bchk, h->bchk, s));
+  double thr = o.tol * bcn;
+  HIPCHK(hipMemsetAsync(h->xchk, 0, n * sizeof(double), s));
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  bool first = true;
+  asss_status_t status = ASSS_NOT_CONVERGED;
+  double* hbuf = h->d_small;
+  h->last_inner = 0;
+  h->prof_s = 0.0;
+  h->prof_launches = 0;
+  for (;;) {
+    if (first) {
+      axpby(n, 1.0, h->bchk, 0.0, h->rv, s);
+    } else {
+      if (!adjoint) outer_op(h, h->xchk, h->w, s);
+      else outer_op_T(h, h->xchk, h->w, s);
+      axpby(n, 1.0, h->bchk, 0.0, h->rv, s);
+      axpby(n, -1.0, h->w, 1.0, h->rv, s);
+    }
+    first = false;
+    const double beta = std::sqrt(dot_host(h, n, h->rv, h->rv, s));
+    inf.cycles++;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j_used = 0;
+    bool implicit_ok = beta <= thr;
+    if (beta > 0) {
+      scale(n, 1.0 / beta, h->rv, h->V, s);
+      for (int j = 0; j < m; ++j) {
+        double* vj = h->V + (int64_t)j * n;
+        double* zj = h->Z + (int64_t)j * n;
+        int its = adjoint ? prec_apply_T(h, fp32, vj, zj, o, s) : prec_apply(h, fp32, vj, zj, o, s);
+        inf.inner_its_total += its;
+        inf.inner_its_max = std::max(inf.inner_its_max, its);
+        if (!adjoint) outer_op(h, zj, h->w, s);
+        else outer_op_T(h, zj, h->w, s);
+        // classical Gram-Schmidt, twice
+        gemm_tn<double, double>(n, j + 1, h->V, n, h->w, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
+        gemv_acc(n, j + 1, h->V, n, hbuf + SM_H1, -1.0, h->w, s);
+        gemm_tn<double, double>(n, j + 1, h->V, n, h->w, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
+        gemv_acc(n, j + 1, h->V, n, hbuf + SM_H2, -1.0, h->w, s);
+        gemm_tn<double, double>(n, 1, h->w, n, h->w, 1, hbuf + SM_HN, nullptr, h->red, 4, s);
+        HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double hn = std::sqrt(h->h_small[SM_HN]);
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i] + h->h_small[SM_H2 + i];
+        H[(size_t)(j + 1) * m + j] = hn;
+        if (hn != 0.0) scale(n, 1.0 / hn, h->w, h->V + (int64_t)(j + 1) * n, s);
+        for (int i = 0; i < j; ++i) {
+          const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+          H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+          H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+        }
+        const double rr = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+        if (rr == 0.0) {
+          cs[j] = 1.0;
+          sn[j] = 0.0;
+        } else {
+          cs[j] = H[(size_t)j * m + j] / rr;
+          sn[j] = H[(size_t)(j + 1) * m + j] / rr;
+        }
+        H[(size_t)j * m + j] = rr;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        inf.outer_its++;
+        j_used = j + 1;
+        implicit_ok = std::fabs(g[j + 1]) <= thr;
+        if (h->opts.verbose)
+          std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, its,
+                       std::fabs(g[j + 1]) / bcn);
+        if (implicit_ok || hn == 0.0 || inf.outer_its >= o.max_outer) break;
+      }
+      for (int i = j_used - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int l = i + 1; l < j_used; ++l) acc -= H[(size_t)i * m + l] * y[l];
+        y[i] = acc / H[(size_t)i * m + i];
+      }
+      HIPCHK(hipMemcpyAsync(h->d_small + SM_Y, y.data(), j_used * sizeof(double), hipMemcpyHostToDevice, s));
+      gemv_acc(n, j_used, h->Z, n, h->d_small + SM_Y, 1.0, h->xchk, s);
+    }
+    inf.relres_implicit = std::fabs(g[j_used]) / bcn;
+    // back-transform and true residual on the original system
+    double relres;
+    if (!adjoint) {
+      spmv(h->dS, h->xchk, x, h->d_dc, h->d_om, 0, nullptr, s);       // x = Dc S Omega x_chk
+      spmv(h->dA, x, h->rv, nullptr, nullptr, 1, b, s);                 // r = b - A x
+    } else {
+      scatter_scale(n, h->d_m, h->d_drp, h->d_om, h->xchk, x, s);      // lambda = Dr P^T Omega l_chk
+      spmv(h->dAt, x, h->rv, nullptr, nullptr, 1, b, s);                // r = g - A^T lambda
+    }
+    relres = std::sqrt(dot_host(h, n, h->rv, h->rv, s)) / bn;
+    inf.relres_true = relres;
+    if (relres <= o.tol) {
+      status = ASSS_OK;
+      inf.converged = 1;
+      break;
+    }
+    if (inf.outer_its >= o.max_outer) break;
+    if (implicit_ok) thr = thr * 0.5 * o.tol / relres;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  inf.solve_s = now_s() - t0;
+  inf.inner_kernel_s = h->prof_s;
+  inf.inner_launches = h->prof_launches;
+  if (info) *info = inf;
+  return status;
+}
+
+void check_handle(asss_handle_s* h) {
+  if (!h) throw Error{ASSS_ERR_INVALID_ARG, "null handle"};
+  HIPCHK(hipSetDevice(h->device));
+}
+
+asss_solve_opts_t opts_or_default(const asss_solve_opts_t* o) {
+  asss_solve_opts_t d;
+  asss_default_solve_opts(&d);
+  return o ? *o : d;
+}
+
+template <class F>
+asss_status_t guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const HostError& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host out of memory";
+    return ASSS_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return ASSS_ERR_INTERNAL;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void asss_default_setup_opts(asss_setup_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->gamma = 1.0;
+  o->s_pattern = ASSS_S_TRIDIAG;
+  o->k = 20;
+  o->lanczos_seed = 0x2009069540ull;
+  o->inner_fp32 = 0;
+  o->x_tol = 1e-10;
+  o->x_maxit = 2000;
+  o->lls_tol = 1e-15;
+  o->lls_maxit = 20000;
+  o->row_block = 0;
+  o->verbose = 0;
+}
+
+void asss_default_solve_opts(asss_solve_opts_t* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->restart_m = 64;
+  o->max_outer = 2000;
+  o->inner_tol = 1e-5;
+  o->inner_maxit = 1000;
+  o->fixed_inner_steps = 0;
+  o->inner_fp32 = -1;
+}
+
+const char* asss_last_error(void) { return g_err.c_str(); }
+
+asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, void* hip_stream,
+                         asss_handle_t* out) {
+  return guarded([&]() -> asss_status_t {
+    if (!A || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    *out = nullptr;
+    asss_setup_opts_t o;
+    asss_default_setup_opts(&o);
+    if (opts) o = *opts;
+    if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
+    if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
+    if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
+      throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::unique_ptr<asss_handle_s> h(new asss_handle_s());
+    HIPCHK(hipGetDevice(&h->device));
+    h->opts = o;
+    const double t0 = now_s();
+    // ---- host preprocessing
+    Csr Ah = validate_and_copy(A->n, A->nnz, A->rowptr, A->colind, A->val);
+    h->n = Ah.nrows;
+    h->nnz_a = Ah.nnz();
+    const int64_t n = h->n;
+    h->m = max_product_matching(Ah);
+    canonical_scaling(Ah, h->m, h->Dr, h->Dc);
+    Csr Abar = permute_scale(Ah, h->m, h->Dr, h->Dc);
+    Csr Spat = s_pattern(Abar, o.s_pattern, o.s_rowptr, o.s_colind);
+    LlsSystem L;
+    build_lls(Abar, Spat, o.gamma, L);
+    h->lls_rows = L.B.nrows;
+    h->lls_nnz = L.B.nnz();
+    const double t1 = now_s();
+    // ---- device: reducer and scalar buffers first (LSQR uses them)
+    int R = o.row_block;
+    if (R == 0) {
+      R = 64;
+      while (R < 2048 && (int64_t)R * 2 * 1024 <= n) R *= 2;
+    }
+    const int64_t nblocks = (n + R - 1) / R;
+    h->red.max_groups = (int)std::max<int64_t>(nblocks, 1024);
+    h->red.partials = h->ar.alloc<double>((int64_t)h->red.max_groups * RED_SLOTS);
+    h->red.tickets = h->ar.alloc<unsigned>(16);
+    HIPCHK(hipMemsetAsync(h->red.tickets, 0, 16 * sizeof(unsigned), s));
+    h->d_small = h->ar.alloc<double>(SM_SIZE);
+    h->d_flag = h->ar.alloc<int>(1);
+    HIPCHK(hipHostMalloc((void**)&h->h_small, SM_SIZE * sizeof(double), hipHostMallocDefault));
+    h->d_state = h->ar.alloc<MrsState>(1);
+    HIPCHK(hipEventCreate(&h->ev0));
+    HIPCHK(hipEventCreate(&h->ev1));
+    std::vector<double> svals = lsqr_device(h.get(), L, o.lls_tol, o.lls_maxit, s);
+    const double t2 = now_s();
+    h->S = Spat;
+    h->S.val = svals;
+    Csr Ahat = spgemm_on_pattern(Abar, h->S, L.P);
+    h->nnz_ahat = Ahat.nnz();
+    h->U = L.U;
+    split_ahat(Ahat, h->U, h->D, h->Omega, h->jval);
+    h->neg.clear();
+    for (int64_t i = 0; i < n; ++i)
+      if (h->D[i] < 0) h->neg.push_back((int32_t)i);
+    Csr Jup = h->U;
+    Jup.val = h->jval;
+    SkewSell sell = pack_skew_sell(Jup, R);
+    h->sell_a = sell.a_entries;
+    h->sell_b = sell.b_entries;
+    { LlsSystem dummy; std::swap(L, dummy); }
+    // ---- device uploads
+    h->dA = upload_csr(h->ar, Ah, s);
+    h->dAt = upload_csr(h->ar, transpose(Ah), s);
+    h->dAbar = upload_csr(h->ar, Abar, s);
+    h->dAbarT = upload_csr(h->ar, transpose(Abar), s);
+    h->dS = upload_csr(h->ar, h->S, s);
+    h->dSt = upload_csr(h->ar, transpose(h->S), s);
+    h->d_m = h->ar.upload(h->m, s);
+    std::vector<double> drp(n);
+    for (int64_t j = 0; j < n; ++j) drp[j] = h->Dr[h->m[j]];
+    h->d_drp = h->ar.upload(drp, s);
+    h->d_om = h->ar.upload(h->Omega, s);
+    h->d_dc = h->ar.upload(h->Dc, s);
+    {
+      const int32_t* aw = h->ar.upload(sell.a_width, s);
+      const int32_t* bw = h->ar.upload(sell.b_width, s);
+      const int64_t* ao = h->ar.upload(sell.a_off, s);
+      const int64_t* bo = h->ar.upload(sell.b_off, s);
+      const uint16_t* ac = h->ar.upload(sell.a_col, s);
+      const int32_t* bc = h->ar.upload(sell.b_col, s);
+      h->J64 = upload_sell<double>(h->ar, sell, s, aw, bw, ao, bo, ac, bc);
+      h->J32 = upload_sell<float>(h->ar, sell, s, aw, bw, ao, bo, ac, bc);
+    }
+    for (int b = 0; b < 3; ++b) { h->mb64.w[b] = h->ar.alloc<double>(n); h->mb32.w[b] = h->ar.alloc<float>(n); }
+    for (int b = 0; b < 2; ++b) { h->mb64.p[b] = h->ar.alloc<double>(n); h->mb32.p[b] = h->ar.alloc<float>(n); }
+    h->mb64.x = h->ar.alloc<double>(n);
+    h->mb32.x = h->ar.alloc<float>(n);
+    h->w = h->ar.alloc<double>(n);
+    h->t1 = h->ar.alloc<double>(n);
+    h->xchk = h->ar.alloc<double>(n);
+    h->bchk = h->ar.alloc<double>(n);
+    h->rv = h->ar.alloc<double>(n);
+    h->tmp = h->ar.alloc<double>(n);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t3 = now_s();
+    device_setup(h.get(), s);
+    const double t4 = now_s();
+    h->setup_host_s = (t1 - t0) + (t3 - t2);
+    h->setup_device_s = (t2 - t1) + (t4 - t3);
+    if (o.verbose)
+      std::fprintf(stderr,
+                   "[asss] setup n=%lld host %.3fs (pre %.3f, split/pack %.3f) lsqr %.3fs (%d its, kkt %.2e) "
+                   "device %.3fs (k_eff %d, r %d, X its %d)\n",
+                   (long long)n, h->setup_host_s, t1 - t0, t3 - t2, t2 - t1, h->lls_its, h->lls_kkt,
+                   t4 - t3, h->k_eff, h->r, h->x_its);
+    *out = h.release();
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, const asss_solve_opts_t* o,
+                         asss_info_t* info, void* hip_stream) {
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (!b_dev || !x_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    asss_solve_opts_t oo = opts_or_default(o);
+    if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
+    if (!b_is_finite(h, b_dev, s)) throw Error{ASSS_ERR_NONFINITE, "b has a non-finite entry"};
+    return fgmres(h, false, b_dev, x_dev, oo, info, s);
+  });
+}
+
+asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* lambda_dev,
+                                 const asss_solve_opts_t* o, asss_info_t* info, void* hip_stream) {
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (!g_dev || !lambda_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    asss_solve_opts_t oo = opts_or_default(o);
+    if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
+    if (!b_is_finite(h, g_dev, s)) throw Error{ASSS_ERR_NONFINITE, "g has a non-finite entry"};
+    return fgmres(h, true, g_dev, lambda_dev, oo, info, s);
+  });
+}
+
+asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const int32_t* nrhs,
+                                 const double* const* B_dev, double* const* X_dev,
+                                 const asss_solve_opts_t* o, asss_info_t* infos, void* hip_stream) {
+  return guarded([&]() -> asss_status_t {
+    if (nsys < 0 || (nsys > 0 && (!hs || !nrhs || !B_dev || !X_dev)))
+      throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    int maxr = 0;
+    for (int sidx = 0; sidx < nsys; ++sidx) maxr = std::max(maxr, (int)nrhs[sidx]);
+    asss_status_t worst = ASSS_OK;
+    for (int sidx = 0; sidx < nsys; ++sidx) {
+      asss_handle_t h = hs[sidx];
+      check_handle(h);
+      for (int j = 0; j < nrhs[sidx]; ++j) {
+        asss_info_t inf{};
+        asss_status_t st = asss_solve(h, B_dev[sidx] + (int64_t)j * h->n, X_dev[sidx] + (int64_t)j * h->n, o,
+                                      &inf, hip_stream);
+        if (st < 0) return st;
+        if (infos) infos[(int64_t)sidx * maxr + j] = inf;
+        if (st > worst) worst = st;
+      }
+    }
+    return worst;
+  });
+}
+
+asss_status_t asss_destroy(asss_handle_t h) {
+  return guarded([&]() -> asss_status_t {
+    if (!h) return ASSS_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    delete h;
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
+  return guarded([&]() -> asss_status_t {
+    if (!h || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    asss_handle_info_t i{};
+    i.n = h->n;
+    i.nnz_a = h->nnz_a;
+    i.nnz_s = h->S.nnz();
+    i.nnz_ahat = h->nnz_ahat;
+    i.nh = h->U.nnz();
+    i.lls_rows = h->lls_rows;
+    i.lls_nnz = h->lls_nnz;
+    i.k_eff = h->k_eff;
+    i.rank_r = h->r;
+    i.lls_its = h->lls_its;
+    i.x_its = h->x_its;
+    i.row_block = h->J64.R;
+    i.nblocks = h->J64.nblocks;
+    i.sell_entries_a = h->sell_a;
+    i.sell_entries_b = h->sell_b;
+    i.lls_relres = h->lls_relres;
+    i.lls_kkt = h->lls_kkt;
+    *out = i;
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_get_array(asss_handle_t h, int32_t which, void* dst, int64_t* count) {
+  return guarded([&]() -> asss_status_t {
+    if (!h || !count) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    check_handle(h);
+    const int64_t n = h->n;
+    auto give = [&](const void* src, int64_t cnt, size_t esz) {
+      *count = cnt;
+      if (dst && cnt > 0) std::memcpy(dst, src, (size_t)cnt * esz);
+    };
+    auto give_dev = [&](const void* src, int64_t cnt, size_t esz) {
+      *count = cnt;
+      if (dst && cnt > 0) {
+        HIPCHK(hipMemcpy(dst, src, (size_t)cnt * esz, hipMemcpyDeviceToHost));
+      }
+    };
+    switch (which) {
+      case ASSS_ARR_MATCH: give(h->m.data(), n, 4); break;
+      case ASSS_ARR_DR: give(h->Dr.data(), n, 8); break;
+      case ASSS_ARR_DC: give(h->Dc.data(), n, 8); break;
+      case ASSS_ARR_S_ROWPTR: give(h->S.ptr.data(), n + 1, 8); break;
+      case ASSS_ARR_S_COLIND: give(h->S.col.data(), h->S.nnz(), 4); break;
+      case ASSS_ARR_S_VAL: give(h->S.val.data(), h->S.nnz(), 8); break;
+      case ASSS_ARR_D: give(h->D.data(), n, 8); break;
+      case ASSS_ARR_J_ROWPTR: give(h->U.ptr.data(), n + 1, 8); break;
+      case ASSS_ARR_J_COLIND: give(h->U.col.data(), h->U.nnz(), 4); break;
+      case ASSS_ARR_J_VAL: give(h->jval.data(), (int64_t)h->jval.size(), 8); break;
+      case ASSS_ARR_Q: give_dev(h->d_Q64, n * (int64_t)h->k_eff, 8); break;
+      case ASSS_ARR_ALPHA: give(h->alpha.data(), (int64_t)h->alpha.size(), 8); break;
+      case ASSS_ARR_X: give_dev(h->d_X, n * (int64_t)h->kr, 8); break;
+      case ASSS_ARR_NEG: give(h->neg.data(), (int64_t)h->neg.size(), 4); break;
+      default: throw Error{ASSS_ERR_INVALID_ARG, "unknown array id"};
+    }
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in, double* out,
+                         const asss_solve_opts_t* o, int32_t* inner_its, void* hip_stream) {
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (!in || !out) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    asss_solve_opts_t oo = opts_or_default(o);
+    const bool fp32 = (oo.inner_fp32 < 0) ? (h->opts.inner_fp32 != 0) : (oo.inner_fp32 != 0);
+    const int64_t n = h->n;
+    int its = 0;
+    switch (op) {
+      case ASSS_OP_SKEW:
+      case ASSS_OP_DEFLATED: {
+        if (fp32) {
+          cast_d2f(n, in, h->mb32.w[0], s);
+          skew_spmv<float>(h->J32, h->mb32.w[0], h->mb32.w[1], s);
+          cast_f2d(n, h->mb32.w[1], out, s);
+        } else {
+          skew_spmv<double>(h->J64, in, out, s);
+        }
+        if (op == ASSS_OP_DEFLATED && h->k_eff > 0) {
+          // out -= Q (S_k (Q^T in))
+          double* d = h->d_small + SM_T;
+          gemm_tn<double, double>(n, h->k_eff, h->d_Q64, n, in, 1, d, nullptr, h->red, 3, s);
+          HIPCHK(hipMemcpyAsync(h->h_small, d, h->k_eff * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          std::vector<double> c(h->k_eff, 0.0);
+          for (int l = 0; l < h->k_eff; ++l) {
+            if (l + 1 < h->k_eff) c[l] += h->alpha[l] * h->h_small[l + 1];
+            if (l >= 1) c[l] -= h->alpha[l - 1] * h->h_small[l - 1];
+          }
+          HIPCHK(hipMemcpyAsync(d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
+          gemv_acc(n, h->k_eff, h->d_Q64, n, d, -1.0, out, s);
+        }
+        break;
+      }
+      case ASSS_OP_OUTER: outer_op(h, in, out, s); break;
+      case ASSS_OP_OUTER_T: outer_op_T(h, in, out, s); break;
+      case ASSS_OP_MRS:
+        its = inner_solve(h, fp32, in, out, +1, oo.inner_tol, oo.inner_maxit, oo.fixed_inner_steps, s);
+        break;
+      case ASSS_OP_PREC: its = prec_apply(h, fp32, in, out, oo, s); break;
+      case ASSS_OP_PREC_T: its = prec_apply_T(h, fp32, in, out, oo, s); break;
+      case ASSS_OP_A: spmv(h->dA, in, out, nullptr, nullptr, 0, nullptr, s); break;
+      case ASSS_OP_AT: spmv(h->dAt, in, out, nullptr, nullptr, 0, nullptr, s); break;
+      default: throw Error{ASSS_ERR_INVALID_ARG, "unknown operator id"};
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (inner_its) *inner_its = its;
+    return ASSS_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Host-side preprocessing of the ASSS scheme (paper Sec. 2 and Sec. 3).
+// Pure C++17; parallel loops use std::thread.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace asss {
+
+struct Csr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> ptr;  // nrows + 1
+  std::vector<int32_t> col;  // sorted within a row
+  std::vector<double> val;   // may be empty for a pattern
+  int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+struct HostError {
+  int code;
+  std::string msg;
+};
+
+int num_threads();
+
+// f(lo, hi) over contiguous chunks of [0, n), run on num_threads() threads.
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
+
+// Validate a caller CSR and copy it, dropping stored zeros (Sec. 1: a general
+// sparse matrix; a stored zero is no nonzero).  Throws HostError.
+Csr validate_and_copy(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                      const double* val);
+
+Csr transpose(const Csr& A);
+
+// Maximum product perfect matching (Sec. 2, eq. mc64): m[j] = row matched to
+// column j.  Successive shortest augmenting paths (Dijkstra with dual
+// potentials) on the costs c_ij = log(max_k |a_kj|) - log|a_ij|.
+std::vector<int32_t> max_product_matching(const Csr& A);
+
+// Scalings for the matching (largest gamma <= 0 with gamma_j <= gamma_i + w_ij,
+// w_ij = log|at_ii| - log|at_ij| for At = P A).  Dr indexed by rows of A.
+void canonical_scaling(const Csr& A, const std::vector<int32_t>& m, std::vector<double>& Dr,
+                       std::vector<double>& Dc);
+
+// Abar = P Dr A Dc with (P y)_j = y_{m[j]}.
+Csr permute_scale(const Csr& A, const std::vector<int32_t>& m, const std::vector<double>& Dr,
+                  const std::vector<double>& Dc);
+
+// Pattern of S (values unset).  kind: 0 diag, 1 tridiag, 2 pattern of Abar, 3 user.
+Csr s_pattern(const Csr& Abar, int kind, const int64_t* urow, const int32_t* ucol);
+
+// Least-squares system of App. A for the pattern Spat.  Unknowns are the
+// pattern entries of S in CSR (row-major) order; equations are the strictly
+// upper pairs of pattern(Abar S) + its transpose in row-major order, then the
+// n diagonal equations weighted by sqrt(gamma).
+struct LlsSystem {
+  Csr B, Bt;                 // B: equations x unknowns; Bt its transpose
+  std::vector<double> rhs;   // 0 for pair equations, sqrt(gamma) for diagonal ones
+  Csr P;                     // pattern of Abar S
+  Csr U;                     // strictly upper pattern of P + P^T (pattern of J_tilde)
+};
+void build_lls(const Csr& Abar, const Csr& Spat, double gamma, LlsSystem& out);
+
+// Numeric A_hat = Abar S on the structural pattern P.
+Csr spgemm_on_pattern(const Csr& Abar, const Csr& S, const Csr& P);
+
+// D = diag(A_hat), Omega = |D|^-1/2, J_tilde strict upper values on U
+// (u_ij = Omega_i Omega_j (ahat_ij - ahat_ji) / 2).  Throws on a zero D_i.
+void split_ahat(const Csr& Ahat, const Csr& U, std::vector<double>& D, std::vector<double>& Omega,
+                std::vector<double>& jval);
+
+// Sliced storage of the skew operator for the GPU kernels.  Rows are cut into
+// blocks of R rows (a multiple of 64) and each block into slices of 64 rows
+// (one wavefront, one row per lane).  For a row i:
+//   part a: upper entries (i, j), j > i, with j in i's block, local column
+//           j - block_start (uint16) -- used for a gather from and a scatter
+//           into the block's LDS window;
+//   part b: every entry whose column lies in another block, both triangles,
+//           with the signed value of J_tilde (lower entries are -u_ji).
+// Each part of a slice is stored column-major in (width x 64) with padding
+// entries (local/global column = the row itself, value 0).
+struct SkewSell {
+  int32_t n = 0, R = 0, nblocks = 0, nslices = 0;
+  std::vector<int32_t> a_width, b_width;  // per slice
+  std::vector<int64_t> a_off, b_off;      // per slice, offset in entries
+  std::vector<uint16_t> a_col;
+  std::vector<int32_t> b_col;
+  std::vector<double> a_val, b_val;
+  int64_t a_entries = 0, b_entries = 0;   // real (unpadded) entries
+};
+SkewSell pack_skew_sell(const Csr& Jup, int32_t R);
+
+}  // namespace asss

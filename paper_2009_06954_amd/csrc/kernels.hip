@@ -1,0 +1,796 @@
+// gfx950 kernels of libasss: CSR SpMV, the sliced skew-symmetric SpMV with an
+// LDS scatter, the fused inner mrs iteration (paper App. B) with the deflation
+// projector (Sec. 3.2) and one deterministic grid reduction per iteration,
+// tall-skinny products for the outer orthogonalisation and the SMW term, and
+// small vector kernels.  All of it is bandwidth bound: no matrix cores.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace asss {
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Reduce NV per-thread values over the workgroup; results in res[0..NV).
+// Fixed order (wave butterflies, then waves 0..3), so the result does not
+// depend on timing.
+template <int NV>
+__device__ __forceinline__ void wg_reduce(double (&v)[NV], double* lds /* [WG/64 * NV] */,
+                                          double* res /* [NV] */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double s = wave_sum(v[j]);
+    if (lane == 0) lds[wave * NV + j] = s;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < NV; j += WG) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) s += lds[w * NV + j];
+    res[j] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void store_partial(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_partial(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Last-arriving workgroup detection.  Every workgroup calls it after writing
+// its partials; exactly one (the last) gets true and then sees all partials.
+__device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned total) {
+  __shared__ unsigned s_last;
+  __atomic_thread_fence(__ATOMIC_RELEASE);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == total - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (s_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return s_last != 0;
+}
+
+__device__ __forceinline__ void reset_ticket(unsigned* ticket) {
+  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// In the last workgroup: res[j] = sum over groups g (in order of a fixed
+// thread/group assignment) of partials[g * stride + j], j < NV (NV >= nvals).
+// Plain loads are used after the acquire fence of arrive_last, so that the
+// compiler can keep many of them in flight.
+template <int NV>
+__device__ void final_reduce(const double* partials, int ngroups, int stride, int nvals,
+                             double* lds, double* res) {
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  for (int g = threadIdx.x; g < ngroups; g += WG) {
+    const double* pg = partials + (int64_t)g * stride;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      if (j < nvals) acc[j] += pg[j];
+  }
+  wg_reduce<NV>(acc, lds, res);
+}
+
+// sum over g = g0, g0 + step, ... < ng of P[g * stride + o], eight independent
+// chains (fixed order for given arguments).
+__device__ __forceinline__ double strided_sum(const double* P, int g0, int ng, int step,
+                                              int64_t stride, int o) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int g = g0;
+  for (; g + 7 * step < ng; g += 8 * step) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += P[(int64_t)(g + u * step) * stride + o];
+  }
+  for (; g < ng; g += step) a[0] += P[(int64_t)g * stride + o];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// ---------------------------------------------------------------------------
+// CSR SpMV (outer operator, true residual, least-squares matrices)
+// ---------------------------------------------------------------------------
+
+template <int LANES>
+__global__ __launch_bounds__(WG) void k_spmv(int64_t nrows, const int64_t* __restrict__ ptr,
+                                             const int32_t* __restrict__ col,
+                                             const double* __restrict__ val,
+                                             const double* __restrict__ x, double* __restrict__ y,
+                                             const double* __restrict__ rs,
+                                             const double* __restrict__ cs, int mode,
+                                             const double* __restrict__ b) {
+  const int64_t gid = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const int64_t row = gid / LANES;
+  const int sub = (int)(gid % LANES);
+  double sum = 0.0;
+  if (row < nrows) {
+    const int64_t e = ptr[row + 1];
+    if (cs) {
+      for (int64_t p = ptr[row] + sub; p < e; p += LANES) {
+        int32_t c = col[p];
+        sum += val[p] * (cs[c] * x[c]);
+      }
+    } else {
+      for (int64_t p = ptr[row] + sub; p < e; p += LANES) sum += val[p] * x[col[p]];
+    }
+  }
+#pragma unroll
+  for (int off = LANES / 2; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, LANES);
+  if (row < nrows && sub == 0) {
+    double r = rs ? rs[row] * sum : sum;
+    y[row] = (mode == 1) ? b[row] - r : r;
+  }
+}
+
+void spmv(const DCsr& M, const double* x, double* y, const double* rs, const double* cs, int mode,
+          const double* b, hipStream_t s) {
+  if (M.nrows == 0) return;
+  int64_t threads = M.nrows * M.lanes;
+  dim3 grid((unsigned)((threads + WG - 1) / WG));
+#define ASSS_SPMV(L)                                                                              \
+  case L:                                                                                         \
+    hipLaunchKernelGGL(k_spmv<L>, grid, dim3(WG), 0, s, M.nrows, M.ptr, M.col, M.val, x, y, rs, \
+                       cs, mode, b);                                                              \
+    break;
+  switch (M.lanes) {
+    ASSS_SPMV(1)
+    ASSS_SPMV(2)
+    ASSS_SPMV(4)
+    ASSS_SPMV(8)
+    ASSS_SPMV(16)
+    ASSS_SPMV(32)
+    default:
+      ASSS_SPMV(64)
+  }
+#undef ASSS_SPMV
+}
+
+// ---------------------------------------------------------------------------
+// Sliced skew SpMV: the part shared by the standalone operator and the mrs step.
+// One workgroup per block of R rows; wave w handles slices w, w+4, ... of it.
+// w_src(jl) reads the gathered vector at local row jl (LDS or global).
+// Accumulates the block's results into acc_lds[il * NR + c].
+// ---------------------------------------------------------------------------
+
+template <typename T, int NR, bool STAGE>
+__device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
+                                                const T* __restrict__ wg, const T* w_lds,
+                                                T* acc_lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nsl = (nrow + 63) >> 6;
+  const int64_t s0 = row0 >> 6;
+  for (int sl = wave; sl < nsl; sl += WG / 64) {
+    const int64_t s = s0 + sl;
+    const int il = sl * 64 + lane;
+    const bool valid = il < nrow;
+    const int wa = J.a_width[s], wb = J.b_width[s];
+    const int64_t ao = J.a_off[s] + lane, bo = J.b_off[s] + lane;
+    T acc[NR], wi[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      acc[c] = T(0);
+      wi[c] = valid ? (STAGE ? w_lds[il * NR + c] : wg[(row0 + il) * NR + c]) : T(0);
+    }
+    for (int l = 0; l < wa; ++l) {
+      const int jl = J.a_col[ao + (int64_t)l * 64];
+      const T v = J.a_val[ao + (int64_t)l * 64];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        const T wj = STAGE ? w_lds[jl * NR + c] : wg[(row0 + jl) * NR + c];
+        acc[c] += v * wj;
+        if (valid) atomicAdd(&acc_lds[jl * NR + c], -v * wi[c]);
+      }
+    }
+    for (int l = 0; l < wb; ++l) {
+      const int64_t j = J.b_col[bo + (int64_t)l * 64];
+      const T v = J.b_val[bo + (int64_t)l * 64];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] += v * wg[j * NR + c];
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) atomicAdd(&acc_lds[il * NR + c], acc[c]);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_skew_spmv(DSkew<T> J, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* w_lds = reinterpret_cast<T*>(smem_raw);
+  T* acc_lds = w_lds + J.R;
+  const int64_t row0 = (int64_t)blockIdx.x * J.R;
+  const int nrow = (int)min((int64_t)J.R, (int64_t)J.n - row0);
+  for (int r = threadIdx.x; r < nrow; r += WG) {
+    w_lds[r] = x[row0 + r];
+    acc_lds[r] = T(0);
+  }
+  __syncthreads();
+  skew_block_pass<T, 1, true>(J, row0, nrow, x, w_lds, acc_lds);
+  __syncthreads();
+  for (int r = threadIdx.x; r < nrow; r += WG) y[row0 + r] = acc_lds[r];
+}
+
+template <typename T>
+void skew_spmv(const DSkew<T>& J, const T* x, T* y, hipStream_t s) {
+  size_t lds = 2 * (size_t)J.R * sizeof(T);
+  hipLaunchKernelGGL(k_skew_spmv<T>, dim3(J.nblocks), dim3(WG), lds, s, J, x, y);
+}
+template void skew_spmv<double>(const DSkew<double>&, const double*, double*, hipStream_t);
+template void skew_spmv<float>(const DSkew<float>&, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Tall-skinny products: out = A^T B (A: n x ka column-major, B: n x nr row-major)
+// ---------------------------------------------------------------------------
+
+constexpr int GT_ROWS = 64;     // rows staged per chunk
+constexpr int GT_MAXOUT = 512;  // ka * nr limit
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(WG) void k_gemm_tn(int64_t n, int ka, const TA* __restrict__ A,
+                                                int64_t lda, const TB* __restrict__ B, int nr,
+                                                double* __restrict__ out,
+                                                const double* __restrict__ M, double* partials,
+                                                unsigned* ticket, int rows_per_chunk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* As = reinterpret_cast<double*>(smem_raw);          // [ka][rows]
+  double* Bs = As + (size_t)ka * rows_per_chunk;             // [rows][nr]
+  const int nout = ka * nr;
+  double acc0 = 0.0, acc1 = 0.0;  // outputs o = tid and o = tid + WG
+  const int64_t nchunks = (n + rows_per_chunk - 1) / rows_per_chunk;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t r0 = ch * rows_per_chunk;
+    const int nrow = (int)min((int64_t)rows_per_chunk, n - r0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ka * rows_per_chunk; e += WG) {
+      int l = e / rows_per_chunk, r = e % rows_per_chunk;
+      As[e] = r < nrow ? (double)A[(int64_t)l * lda + r0 + r] : 0.0;
+    }
+    for (int e = threadIdx.x; e < rows_per_chunk * nr; e += WG) {
+      int r = e / nr;
+      Bs[e] = r < nrow ? (double)B[(r0 + r) * nr + (e % nr)] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < nout) {
+      int l = threadIdx.x / nr, c = threadIdx.x % nr;
+      for (int r = 0; r < nrow; ++r) acc0 += As[l * rows_per_chunk + r] * Bs[r * nr + c];
+    }
+    if (threadIdx.x + WG < nout) {
+      int o = threadIdx.x + WG, l = o / nr, c = o % nr;
+      for (int r = 0; r < nrow; ++r) acc1 += As[l * rows_per_chunk + r] * Bs[r * nr + c];
+    }
+  }
+  if (threadIdx.x < nout) store_partial(partials + (int64_t)blockIdx.x * nout + threadIdx.x, acc0);
+  if (threadIdx.x + WG < nout)
+    store_partial(partials + (int64_t)blockIdx.x * nout + threadIdx.x + WG, acc1);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  // last workgroup: threads split each output's groups, then combine in order
+  __shared__ double red[GT_MAXOUT];
+  __shared__ double tmp[WG];
+  for (int o0 = 0; o0 < nout; o0 += WG) {
+    const int cnt = min(WG, nout - o0);
+    const int per = max(1, WG / cnt);
+    const int o = o0 + threadIdx.x / per, gs = threadIdx.x % per;
+    if (threadIdx.x / per < cnt)
+      tmp[threadIdx.x] = strided_sum(partials, gs, (int)gridDim.x, per, nout, o);
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      double sacc = 0.0;
+      for (int q = 0; q < per; ++q) sacc += tmp[threadIdx.x * per + q];
+      red[o0 + threadIdx.x] = sacc;
+    }
+    __syncthreads();
+  }
+  if (M) {  // out = M * red (nr == 1)
+    for (int i = threadIdx.x; i < ka; i += WG) {
+      double sacc = 0.0;
+      for (int j = 0; j < ka; ++j) sacc += M[i * ka + j] * red[j];
+      out[i] = sacc;
+    }
+  } else {
+    for (int o = threadIdx.x; o < nout; o += WG) out[o] = red[o];
+  }
+  reset_ticket(ticket);
+}
+
+template <typename TA, typename TB>
+void gemm_tn(int64_t n, int ka, const TA* A, int64_t lda, const TB* B, int nr, double* out,
+             const double* M, Reducer& red, int site, hipStream_t s) {
+  const int nout = ka * nr;
+  if (nout > GT_MAXOUT || nout < 1) return;  // callers keep ka * nr <= 512
+  int rows = GT_ROWS;
+  while (rows > 1 && (size_t)(ka + nr) * rows * sizeof(double) > 64 * 1024) rows >>= 1;
+  int64_t nchunks = (n + rows - 1) / rows;
+  int groups = (int)std::min<int64_t>(nchunks, 512);
+  groups = std::min(groups, (int)(red.max_groups * (int64_t)RED_SLOTS / std::max(nout, 1)));
+  if (groups < 1) groups = 1;
+  size_t lds = (size_t)(ka + nr) * rows * sizeof(double);
+  hipLaunchKernelGGL((k_gemm_tn<TA, TB>), dim3(groups), dim3(WG), lds, s, n, ka, A, lda, B, nr, out,
+                     M, red.partials, red.tickets + site, rows);
+}
+template void gemm_tn<double, double>(int64_t, int, const double*, int64_t, const double*, int,
+                                      double*, const double*, Reducer&, int, hipStream_t);
+template void gemm_tn<double, float>(int64_t, int, const double*, int64_t, const float*, int,
+                                     double*, const double*, Reducer&, int, hipStream_t);
+template void gemm_tn<float, float>(int64_t, int, const float*, int64_t, const float*, int,
+                                    double*, const double*, Reducer&, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Small vector kernels
+// ---------------------------------------------------------------------------
+
+static inline dim3 grid_for(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + WG - 1) / WG, 65535 * 4))); }
+
+__global__ __launch_bounds__(WG) void k_gemv_acc(int64_t n, int kt, const double* __restrict__ A,
+                                                 int64_t lda, const double* __restrict__ t,
+                                                 double sign, double* __restrict__ y) {
+  __shared__ double ts[1024];
+  for (int l = threadIdx.x; l < kt && l < 1024; l += WG) ts[l] = t[l];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    double sacc = 0.0;
+    for (int l = 0; l < kt; ++l) sacc += A[(int64_t)l * lda + i] * ts[l];
+    y[i] += sign * sacc;
+  }
+}
+void gemv_acc(int64_t n, int kt, const double* A, int64_t lda, const double* t, double sign,
+              double* y, hipStream_t s) {
+  if (kt <= 0 || n <= 0) return;
+  if (kt > 1024) kt = 1024;  // callers pass at most 512 (k + r and restart bounds)
+  hipLaunchKernelGGL(k_gemv_acc, grid_for(n), dim3(WG), 0, s, n, kt, A, lda, t, sign, y);
+}
+
+__global__ void k_scale(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[i] = a * x[i];
+}
+void scale(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, grid_for(n), dim3(WG), 0, s, n, a, x, y);
+}
+
+__global__ void k_normalize(int64_t n, const double* __restrict__ x, const double* nrm2,
+                            double* __restrict__ y) {
+  const double inv = 1.0 / sqrt(*nrm2);
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[i] = x[i] * inv;
+}
+void normalize(int64_t n, const double* x, const double* nrm2, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, grid_for(n), dim3(WG), 0, s, n, x, nrm2, y);
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, grid_for(n), dim3(WG), 0, s, n, a, x, b, y);
+}
+
+__global__ void k_gather_scale(int64_t n, const int32_t* __restrict__ m, const double* __restrict__ dr,
+                               const double* __restrict__ om, const double* __restrict__ x,
+                               double* __restrict__ y) {
+  for (int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x; j < n; j += (int64_t)gridDim.x * WG)
+    y[j] = om[j] * (dr[j] * x[m[j]]);
+}
+void gather_scale(int64_t n, const int32_t* m, const double* dr, const double* omega, const double* x,
+                  double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_scale, grid_for(n), dim3(WG), 0, s, n, m, dr, omega, x, y);
+}
+
+__global__ void k_scatter_scale(int64_t n, const int32_t* __restrict__ m, const double* __restrict__ dr,
+                                const double* __restrict__ om, const double* __restrict__ x,
+                                double* __restrict__ y) {
+  for (int64_t j = (int64_t)blockIdx.x * WG + threadIdx.x; j < n; j += (int64_t)gridDim.x * WG)
+    y[m[j]] = dr[j] * (om[j] * x[j]);
+}
+void scatter_scale(int64_t n, const int32_t* m, const double* dr, const double* omega, const double* x,
+                   double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_scale, grid_for(n), dim3(WG), 0, s, n, m, dr, omega, x, y);
+}
+
+__global__ void k_cast_d2f(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[i] = (float)x[i];
+}
+__global__ void k_cast_f2d(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[i] = (double)x[i];
+}
+void cast_d2f(int64_t n, const double* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_d2f, grid_for(n), dim3(WG), 0, s, n, x, y);
+}
+void cast_f2d(int64_t n, const float* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_f2d, grid_for(n), dim3(WG), 0, s, n, x, y);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output i of the stream started at
+// state `seed` is mix(seed + (i+1) * 0x9E3779B97F4A7C15); the top 53 bits
+// give u in [0,1) and the value is 2u - 1.
+__global__ void k_splitmix(int64_t n, uint64_t seed, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    y[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
+  }
+}
+void splitmix_vector(int64_t n, uint64_t seed, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitmix, grid_for(n), dim3(WG), 0, s, n, seed, y);
+}
+
+__global__ void k_check_finite(int64_t n, const double* __restrict__ x, int* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
+    bad |= !isfinite(x[i]);
+  if (bad) *flag = 1;
+}
+void check_finite(int64_t n, const double* x, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finite, grid_for(n), dim3(WG), 0, s, n, x, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Inner mrs (App. B) on S_bar = I + J_bar, J_bar = J_tilde - Q_k S_k Q_k^T
+// ---------------------------------------------------------------------------
+
+// S_k d for the skew tridiagonal S_k (superdiagonal +alpha, subdiagonal -alpha).
+__device__ __forceinline__ double sk_times(const double* alpha, const double* d, int k, int l) {
+  double r = 0.0;
+  if (l + 1 < k) r += alpha[l] * d[l + 1];
+  if (l >= 1) r -= alpha[l - 1] * d[l - 1];
+  return r;
+}
+
+template <int NR, int KF>
+__device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const double* alpha,
+                                  int t) {
+  // res: [KF+1][NR] with row 0 = ||q_new||^2, rows 1..k = Q^T q_new
+  __shared__ double dsh[NRMAX][KMAX];
+  __shared__ double s_relmax[NRMAX];
+  const int c = threadIdx.x;
+  if (c < NR) {
+    MrsCol col = st->col[c];
+    double rel = 0.0;
+    if (col.live) {
+      const double beta = sqrt(res[c]);
+      const double theta = sqrt(col.theta1 * col.theta1 + beta * beta);
+      const double ck = col.theta1 / theta;
+      const double sk = beta / theta;
+      const double delta_new = -col.s_old * beta;
+      const double theta1_new = col.c_old * theta;
+      col.pend_theta = theta;
+      col.pend_delta = col.delta_old;
+      col.pend_coef = col.g * ck;
+      col.has_pending = 1;
+      col.g = -col.g * sk;
+      col.delta_old = delta_new;
+      col.s_old = sk;
+      col.c_old = ck;
+      col.theta1 = theta1_new;
+      col.nu_old = col.nu;
+      col.nu = (beta != 0.0) ? beta : 1.0;
+      col.beta_prev = beta;
+      rel = fabs(col.g) / col.r0;
+      for (int l = 0; l < k; ++l) dsh[c][l] = res[(1 + l) * NR + c] / col.nu;
+    } else {
+      col.pend_theta = 1.0;
+      col.pend_delta = 0.0;
+      col.pend_coef = 0.0;
+      col.has_pending = 1;
+      for (int l = 0; l < k; ++l) dsh[c][l] = 0.0;
+    }
+    s_relmax[c] = rel;
+    st->col[c] = col;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NR * k; e += WG) {
+    int cc = e / k, l = e % k;
+    st->cvec[cc * KMAX + l] = sk_times(alpha, dsh[cc], k, l);
+  }
+  if (threadIdx.x == 0) {
+    double rmax = 0.0;
+    for (int cc = 0; cc < NR; ++cc) rmax = fmax(rmax, s_relmax[cc]);
+    st->relres_max = rmax;
+    st->its = t;
+    int status = MRS_RUNNING;
+    if (st->fixed > 0) {
+      if (t >= st->fixed) status = MRS_CONVERGED;
+    } else if (rmax < st->tol || t >= st->maxit) {
+      status = MRS_CONVERGED;
+    }
+    st->status = status;
+  }
+}
+
+template <typename T, int NR, int KF>
+__global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __restrict__ rhs,
+                                                 int64_t ldr, const T* __restrict__ Q,
+                                                 MrsBufs<T> buf, MrsState* st, double tol,
+                                                 int maxit, int fixed, double* partials,
+                                                 unsigned* ticket) {
+  constexpr int NV = (KF + 1) * NR;
+  __shared__ double lds[(WG / 64) * NV];
+  __shared__ double res[NV];
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  const int64_t n = L.n;
+  const int k = L.k;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    double b[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      b[c] = c < L.nr ? rhs[(int64_t)c * ldr + i] : 0.0;
+      buf.w[1][i * NR + c] = (T)b[c];
+      buf.w[0][i * NR + c] = T(0);
+      buf.w[2][i * NR + c] = T(0);
+      buf.p[0][i * NR + c] = T(0);
+      buf.p[1][i * NR + c] = T(0);
+      buf.x[i * NR + c] = T(0);
+      acc[c] += b[c] * b[c];
+    }
+#pragma unroll
+    for (int l = 0; l < KF; ++l) {
+      if (l < k) {
+        const double q = (double)Q[(int64_t)l * n + i];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[(1 + l) * NR + c] += q * (double)(T)b[c];
+      }
+    }
+  }
+  wg_reduce<NV>(acc, lds, res);
+  for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)blockIdx.x * NV + j, res[j]);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  final_reduce<NV>(partials, gridDim.x, NV, NV, lds, res);
+  __shared__ double dsh[NRMAX][KMAX];
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < NR) {
+    MrsCol col;
+    const double r0 = sqrt(res[c]);
+    col.live = (c < L.nr && r0 > 0.0) ? 1 : 0;
+    col.r0 = col.live ? r0 : 1.0;
+    col.nu = col.r0;
+    col.nu_old = 1.0;
+    col.beta_prev = 0.0;
+    col.theta1 = 1.0;  // alpha = 1 (S_bar = I + J_bar)
+    col.c_old = 1.0;
+    col.s_old = 0.0;
+    col.delta_old = 0.0;
+    col.g = col.live ? r0 : 0.0;
+    col.pend_theta = 1.0;
+    col.pend_delta = 0.0;
+    col.pend_coef = 0.0;
+    col.has_pending = 0;
+    for (int l = 0; l < k; ++l) dsh[c][l] = col.live ? res[(1 + l) * NR + c] / col.nu : 0.0;
+    st->col[c] = col;
+    if (col.live) atomicOr(&s_any, 1);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NR * k; e += WG) {
+    int cc = e / k, l = e % k;
+    st->cvec[cc * KMAX + l] = sk_times(L.alpha_dev, dsh[cc], k, l);
+  }
+  if (threadIdx.x == 0) {
+    st->its = 0;
+    st->status = s_any ? MRS_RUNNING : MRS_DONE;
+    st->nr = L.nr;
+    st->k = k;
+    st->maxit = maxit;
+    st->fixed = fixed;
+    st->sign = L.sign;
+    st->tol = tol;
+    st->alpha = 1.0;
+    st->relres_max = s_any ? 1.0 : 0.0;
+  }
+  reset_ticket(ticket);
+}
+
+template <typename T, int NR, int KF, bool STAGE>
+__global__ __launch_bounds__(WG) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
+                                                 MrsBufs<T> buf, MrsState* st, double* partials,
+                                                 unsigned* ticket) {
+  constexpr int NV = (KF + 1) * NR;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* acc_lds = reinterpret_cast<T*>(smem_raw);
+  T* w_lds = acc_lds + (size_t)J.R * NR;
+  __shared__ double lds[(WG / 64) * NV];
+  __shared__ double res[NV];
+  __shared__ int s_status, s_t, s_pend;
+  __shared__ double s_inv_nu[NR], s_inv_nu_old[NR], s_beta_prev[NR];
+  __shared__ double s_pend_delta[NR], s_inv_pend_theta[NR], s_pend_coef[NR];
+  __shared__ T s_cv[NR][KF > 0 ? KF : 1];
+  const int k = L.k;
+  if (threadIdx.x == 0) {
+    s_status = st->status;
+    s_t = st->its + 1;
+    s_pend = st->col[0].has_pending;
+  }
+  if (threadIdx.x < NR) {
+    const MrsCol& col = st->col[threadIdx.x];
+    s_inv_nu[threadIdx.x] = 1.0 / col.nu;
+    s_inv_nu_old[threadIdx.x] = 1.0 / col.nu_old;
+    s_beta_prev[threadIdx.x] = col.beta_prev;
+    s_pend_delta[threadIdx.x] = col.pend_delta;
+    s_inv_pend_theta[threadIdx.x] = 1.0 / col.pend_theta;
+    s_pend_coef[threadIdx.x] = col.pend_coef;
+  }
+  constexpr int KF1 = KF > 0 ? KF : 1;
+  for (int e = threadIdx.x; e < NR * KF; e += WG) {
+    int c = e / KF1, l = e % KF1;
+    s_cv[c][l] = (l < k) ? (T)st->cvec[c * KMAX + l] : T(0);
+  }
+  __syncthreads();
+  const int status = s_status;
+  if (status == MRS_DONE) return;
+  const int t = s_t;
+  const int64_t n = L.n;
+  const int64_t row0 = (int64_t)blockIdx.x * J.R;
+  const int nrow = (int)min((int64_t)J.R, n - row0);
+  const T* __restrict__ wcur = buf.w[t % 3];
+  const T* __restrict__ wold = buf.w[(t + 2) % 3];
+  T* __restrict__ wnew = buf.w[(t + 1) % 3];
+  T* __restrict__ pb = buf.p[(t + 1) % 2];
+  T* __restrict__ x = buf.x;
+  const bool pend = s_pend != 0;
+
+  if (status == MRS_CONVERGED) {
+    // last deferred update: p_T and x += g_T c_T p_T
+    if (pend) {
+      for (int il = threadIdx.x; il < nrow; il += WG) {
+        const int64_t i = row0 + il;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          const T qold = wold[i * NR + c] * (T)s_inv_nu_old[c];
+          const T p = (qold - (T)s_pend_delta[c] * pb[i * NR + c]) * (T)s_inv_pend_theta[c];
+          x[i * NR + c] += (T)s_pend_coef[c] * p;
+        }
+      }
+    }
+    if (!arrive_last(ticket, gridDim.x)) return;
+    if (threadIdx.x == 0) st->status = MRS_DONE;
+    reset_ticket(ticket);
+    return;
+  }
+
+  // operator pass: acc_lds = J_tilde w_t on this block
+  for (int r = threadIdx.x; r < nrow * NR; r += WG) {
+    acc_lds[r] = T(0);
+    if (STAGE) w_lds[r] = wcur[row0 * NR + r];
+  }
+  __syncthreads();
+  skew_block_pass<T, NR, STAGE>(J, row0, nrow, wcur, w_lds, acc_lds);
+  __syncthreads();
+
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  const T sgn = (T)L.sign;
+  for (int il = threadIdx.x; il < nrow; il += WG) {
+    const int64_t i = row0 + il;
+    T defl[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) defl[c] = T(0);
+    T qrow[KF > 0 ? KF : 1];
+#pragma unroll
+    for (int l = 0; l < KF; ++l) {
+      qrow[l] = (l < k) ? Q[(int64_t)l * n + i] : T(0);
+#pragma unroll
+      for (int c = 0; c < NR; ++c) defl[c] += qrow[l] * s_cv[c][l];
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const T u = acc_lds[il * NR + c] * (T)s_inv_nu[c];
+      const T qold = wold[i * NR + c] * (T)s_inv_nu_old[c];
+      const T qn = sgn * (u - defl[c]) + (T)s_beta_prev[c] * qold;
+      wnew[i * NR + c] = qn;
+      acc[c] += (double)qn * (double)qn;
+#pragma unroll
+      for (int l = 0; l < KF; ++l) acc[(1 + l) * NR + c] += (double)qrow[l] * (double)qn;
+      if (pend) {
+        const T p = (qold - (T)s_pend_delta[c] * pb[i * NR + c]) * (T)s_inv_pend_theta[c];
+        pb[i * NR + c] = p;
+        x[i * NR + c] += (T)s_pend_coef[c] * p;
+      }
+    }
+  }
+  wg_reduce<NV>(acc, lds, res);
+  for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)blockIdx.x * NV + j, res[j]);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  final_reduce<NV>(partials, gridDim.x, NV, NV, lds, res);
+  mrs_scalar_update<NR, KF>(st, res, k, L.alpha_dev, t);
+  reset_ticket(ticket);
+}
+
+// The deflation width KF is a compile-time bound (registers): the smallest of
+// {0, 8, 16, 32} that holds k (32 only for single-column solves).
+static inline int pick_kf(int k, int nr) {
+  if (k <= 0) return 0;
+  if (k <= 8) return 8;
+  if (k <= 16) return 16;
+  return nr == 1 ? 32 : -1;
+}
+
+template <typename T, int NR>
+void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const T* Q, MrsBufs<T>& buf,
+              MrsState* st, double tol, int maxit, int fixed, Reducer& red, hipStream_t s) {
+  int groups = (int)std::min<int64_t>((L.n + WG - 1) / WG, 1024);
+  groups = std::min(groups, red.max_groups);
+  const int kf = pick_kf(L.k, NR);
+#define ASSS_INIT(KF)                                                                              \
+  hipLaunchKernelGGL((k_mrs_init<T, NR, KF>), dim3(groups), dim3(WG), 0, s, L, rhs, ldr, Q, buf,   \
+                     st, tol, maxit, fixed, red.partials, red.tickets + 0)
+  switch (kf) {
+    case 0: ASSS_INIT(0); break;
+    case 8: ASSS_INIT(8); break;
+    case 16: ASSS_INIT(16); break;
+    default:
+      if constexpr (NR == 1) ASSS_INIT(32);
+      break;
+  }
+#undef ASSS_INIT
+}
+
+template <typename T, int NR>
+void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf, MrsState* st,
+              Reducer& red, hipStream_t s) {
+  constexpr bool STAGE = (NR == 1);
+  size_t lds = (size_t)J.R * NR * sizeof(T) * (STAGE ? 2 : 1);
+  const int kf = pick_kf(L.k, NR);
+#define ASSS_ITER(KF)                                                                              \
+  hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE>), dim3(J.nblocks), dim3(WG), lds, s, L, J, Q,   \
+                     buf, st, red.partials, red.tickets + 1)
+  switch (kf) {
+    case 0: ASSS_ITER(0); break;
+    case 8: ASSS_ITER(8); break;
+    case 16: ASSS_ITER(16); break;
+    default:
+      if constexpr (NR == 1) ASSS_ITER(32);
+      break;
+  }
+#undef ASSS_ITER
+}
+
+template <typename T, int NR>
+__global__ void k_mrs_output(int64_t n, int nr, MrsBufs<T> buf, double* __restrict__ out, int64_t ldo) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
+    for (int c = 0; c < nr; ++c) out[(int64_t)c * ldo + i] = (double)buf.x[i * NR + c];
+}
+template <typename T, int NR>
+void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, double* out, int64_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL((k_mrs_output<T, NR>), grid_for(n), dim3(WG), 0, s, n, nr, buf, out, ldo);
+}
+
+#define ASSS_MRS_INST(T, NR)                                                                       \
+  template void mrs_init<T, NR>(const MrsLaunch&, const double*, int64_t, const T*, MrsBufs<T>&,   \
+                                MrsState*, double, int, int, Reducer&, hipStream_t);               \
+  template void mrs_iter<T, NR>(const MrsLaunch&, const DSkew<T>&, const T*, MrsBufs<T>&,          \
+                                MrsState*, Reducer&, hipStream_t);                                 \
+  template void mrs_output<T, NR>(int64_t, int, const MrsBufs<T>&, double*, int64_t, hipStream_t);
+ASSS_MRS_INST(double, 1)
+ASSS_MRS_INST(float, 1)
+ASSS_MRS_INST(double, 4)
+ASSS_MRS_INST(float, 4)
+
+}  // namespace asss

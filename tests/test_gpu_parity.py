@@ -1,0 +1,302 @@
+"""GPU parity: libasss (through the C ABI) against the FP64 oracle on the same
+seeded inputs.  Tolerances follow the parity protocol: bit-exact matching
+indices, 1e-10 on x for the FP64 path, 1e-7 on x at 1e-8 for the mixed path.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_06954_amd as asss
+    asss.load()
+    return asss
+
+
+def _cuda(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+EPS = np.finfo(np.float64).eps
+
+
+# S (hence J_tilde and the outer operator) comes from two independent
+# least-squares solves that agree to about 1e-13 relative; operator outputs are
+# therefore compared componentwise against |M| |v| at 1e-12 (4500 eps), which
+# also covers the different summation order.
+OPERATOR_C = 1e-12 / EPS
+
+
+def _within_rounding(out, ref, absbound, c=OPERATOR_C):
+    """|out_i - ref_i| <= c eps (|M| |v|)_i (componentwise bound of a sparse
+    product with perturbed values and a different summation order)."""
+    assert np.all(np.abs(out - ref) <= c * EPS * absbound + 1e-300), \
+        float(np.max(np.abs(out - ref) / (absbound + 1e-300)))
+
+
+class Pair:
+    """A workload set up in both the oracle and the library."""
+
+    def __init__(self, A, k, pattern="tridiag", gamma=1.0, row_block=0, x_tol=1e-10, x_maxit=2000):
+        asss = _lib()
+        self.A = O.validate_csr(A)
+        print(f"[pair] n={A.shape[0]} nnz={A.nnz} k={k} pattern={pattern} gamma={gamma} R={row_block}", flush=True)
+        self.st = O.setup(A, O.SetupOptions(k=k, s_pattern=pattern, gamma=gamma, x_tol=x_tol,
+                                            x_maxit=x_maxit))
+        self.h = asss.setup(A, k=k, s_pattern=pattern, gamma=gamma, row_block=row_block,
+                            x_tol=x_tol, x_maxit=x_maxit)
+        self.n = A.shape[0]
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    w = W.config(0)
+    p = Pair(w.A, k=8)
+    p.w = w
+    return p
+
+
+@pytest.fixture(scope="module")
+def negcase():
+    """Stand-in matrix with negative entries in diag(Abar S) (r > 0), odd k."""
+    for s in range(10):
+        A = W.paper_like(200, 1200, seed=s).A
+        st = O.setup(A, O.SetupOptions(k=5, gamma=0.01))
+        if st.N.size > 0:
+            return Pair(A, k=5, gamma=0.01, row_block=64)
+    pytest.skip("no negative-diagonal case")
+
+
+def test_setup_arrays_match_oracle(cfg0):
+    p, st, h = cfg0, cfg0.st, cfg0.h
+    assert np.array_equal(h.array("match"), st.m.astype(np.int32))
+    np.testing.assert_allclose(h.array("Dr"), st.Dr, rtol=1e-15)
+    np.testing.assert_allclose(h.array("Dc"), st.Dc, rtol=1e-15)
+    S = st.S.tocsr()
+    assert np.array_equal(h.array("S_rowptr"), S.indptr)
+    assert np.array_equal(h.array("S_colind"), S.indices)
+    assert _rel(h.array("S_val"), S.data) <= 1e-12
+    assert _rel(h.array("D"), st.D) <= 1e-12
+    assert np.array_equal(h.array("J_rowptr"), st.Jup.indptr)
+    assert np.array_equal(h.array("J_colind"), st.Jup.indices)
+    assert _rel(h.array("J_val"), st.Jup.data) <= 1e-12
+    info = h.info()
+    assert info["k_eff"] == st.Q.shape[1] and info["rank_r"] == st.N.size
+    np.testing.assert_allclose(h.array("alpha"), st.alpha, rtol=1e-10)
+    Q = h.array("Q").reshape(st.Q.shape[1], p.n).T
+    assert _rel(Q, st.Q) <= 1e-10
+    X = h.array("X").reshape(-1, p.n).T
+    assert _rel(X, st.prec.X) <= 1e-8
+
+
+def test_negative_diagonal_setup(negcase):
+    p, st, h = negcase, negcase.st, negcase.h
+    assert np.array_equal(h.array("match"), st.m.astype(np.int32))
+    np.testing.assert_allclose(h.array("Dc"), st.Dc, rtol=1e-13)
+    np.testing.assert_allclose(h.array("Dr"), st.Dr, rtol=1e-13)
+    assert _rel(h.array("S_val"), st.S.tocsr().data) <= 1e-9
+    assert np.array_equal(h.array("neg"), st.N.astype(np.int32))
+    assert h.info()["rank_r"] == st.N.size > 0
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_skew_and_deflated_operators(cfg0, fp32):
+    p = cfg0
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(p.n)
+    ref = p.st.prec.jtilde(v)
+    absJ = abs(p.st.Jup)
+    bound = absJ @ np.abs(v) + absJ.T @ np.abs(v)
+    out, _ = p.h.apply("skew", _cuda(v), inner_fp32=fp32)
+    if fp32:
+        assert _rel(_np(out), ref) <= 2e-6
+    else:
+        _within_rounding(_np(out), ref, bound)
+    ref = p.st.prec.jbar(v)
+    Q = p.st.Q
+    bound_d = bound + np.abs(Q) @ (np.abs(p.st.prec.Sk) @ (np.abs(Q).T @ np.abs(v)))
+    out, _ = p.h.apply("deflated", _cuda(v), inner_fp32=fp32)
+    if fp32:
+        assert _rel(_np(out), ref) <= 2e-6
+    else:
+        _within_rounding(_np(out), ref, bound_d)
+
+
+def test_skew_operator_ragged_blocks():
+    """Several LDS row blocks with a ragged tail (n = 45^2 = 2025, R = 64)."""
+    w = W.config(0)
+    p = Pair(w.A, k=3, row_block=64)
+    assert p.h.info()["nblocks"] == 32
+    v = np.random.default_rng(1).standard_normal(p.n)
+    out, _ = p.h.apply("skew", _cuda(v))
+    absJ = abs(p.st.Jup)
+    _within_rounding(_np(out), p.st.prec.jtilde(v), absJ @ np.abs(v) + absJ.T @ np.abs(v))
+
+
+def test_outer_operators(cfg0):
+    p = cfg0
+    v = np.random.default_rng(2).standard_normal(p.n)
+    st = p.st
+    aS, aA, om = abs(st.S), abs(st.Abar), st.Omega
+    out, _ = p.h.apply("outer", _cuda(v))
+    _within_rounding(_np(out), st.op(v), om * (aA @ (aS @ (om * np.abs(v)))))
+    out, _ = p.h.apply("outer_t", _cuda(v))
+    _within_rounding(_np(out), st.op_T(v), om * (aS.T @ (aA.T @ (om * np.abs(v)))))
+    out, _ = p.h.apply("A", _cuda(v))
+    assert _rel(_np(out), p.A @ v) <= 1e-15
+    out, _ = p.h.apply("AT", _cuda(v))
+    assert _rel(_np(out), p.A.T @ v) <= 1e-15
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 30])
+def test_mrs_fixed_steps(cfg0, steps):
+    p = cfg0
+    v = np.random.default_rng(steps).standard_normal(p.n)
+    ref, _, _ = O.mrs(1.0, p.st.prec.jbar, v, steps, 0.0, fixed_steps=steps)
+    out, its = p.h.apply("mrs", _cuda(v), fixed_inner_steps=steps)
+    assert its == steps
+    assert _rel(_np(out), ref) <= 1e-12
+
+
+def test_mrs_tolerance_stop(cfg0):
+    p = cfg0
+    v = np.random.default_rng(7).standard_normal(p.n)
+    ref, its_ref, _ = O.mrs(1.0, p.st.prec.jbar, v, 1000, 1e-5)
+    out, its = p.h.apply("mrs", _cuda(v), inner_tol=1e-5)
+    assert its == its_ref
+    assert _rel(_np(out), ref) <= 1e-12
+
+
+def test_mrs_fp32(cfg0):
+    p = cfg0
+    v = np.random.default_rng(8).standard_normal(p.n)
+    ref, _, _ = O.mrs(1.0, p.st.prec.jbar, v, 30, 0.0, fixed_steps=30)
+    out, its = p.h.apply("mrs", _cuda(v), fixed_inner_steps=30, inner_fp32=True)
+    assert _rel(_np(out), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_preconditioner(cfg0, transpose):
+    p = cfg0
+    v = np.random.default_rng(9).standard_normal(p.n)
+    if transpose:
+        ref, _ = p.st.prec.apply_T(v, 0.0, 30, fixed_steps=30)
+        out, _ = p.h.apply("prec_t", _cuda(v), fixed_inner_steps=30)
+    else:
+        ref, _ = p.st.prec.apply(v, 0.0, 30, fixed_steps=30)
+        out, _ = p.h.apply("prec", _cuda(v), fixed_inner_steps=30)
+    assert _rel(_np(out), ref) <= 1e-10
+
+
+def test_solve_solution_parity(cfg0):
+    """P1: both solve to 1e-13; x agrees to 1e-10."""
+    p = cfg0
+    xo, io = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-13))
+    x, info = p.h.solve(_cuda(p.w.b), tol=1e-13)
+    assert info["status"] == "OK" and info["relres_true"] <= 1e-13
+    assert _rel(_np(x), xo) <= 1e-10
+
+
+def test_solve_trajectory_parity(cfg0):
+    """P2: fixed inner steps, tol 1e-8: same outer count, x to 1e-10."""
+    p = cfg0
+    xo, io = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-8, fixed_inner_steps=30))
+    x, info = p.h.solve(_cuda(p.w.b), tol=1e-8, fixed_inner_steps=30)
+    assert info["outer_its"] == io["outer_its"]
+    assert info["inner_its_total"] == io["inner_its_total"]
+    assert _rel(_np(x), xo) <= 1e-10
+
+
+def test_solve_default_inner(cfg0):
+    p = cfg0
+    xo, io = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-8))
+    x, info = p.h.solve(_cuda(p.w.b), tol=1e-8)
+    assert info["status"] == "OK"
+    assert info["outer_its"] == io["outer_its"]
+    assert _rel(_np(x), xo) <= 1e-10
+
+
+def test_solve_mixed_precision(cfg0):
+    """P3: FP32 inner, FP64 outer at tol 1e-8: x within 1e-7 of the FP64 oracle."""
+    p = cfg0
+    xo, _ = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-13))
+    x, info = p.h.solve(_cuda(p.w.b), tol=1e-8, inner_fp32=True)
+    assert info["status"] == "OK" and info["relres_true"] <= 1e-8
+    err = _rel(_np(x), xo)
+    print(f"[mixed] outer={info['outer_its']} inner={info['inner_its_total']} err_vs_oracle={err:.3e}")
+    assert err <= 1e-7
+
+
+def test_adjoint(cfg0):
+    p = cfg0
+    g = np.random.default_rng(11).standard_normal(p.n)
+    lo, io = O.solve_adjoint(p.st, g, O.SolveOptions(tol=1e-12))
+    lam, info = p.h.solve_adjoint(_cuda(g), tol=1e-12)
+    assert info["status"] == "OK"
+    assert _rel(_np(lam), lo) <= 1e-9
+    ld = np.linalg.solve(p.A.toarray().T, g)
+    assert _rel(_np(lam), ld) <= 1e-9
+
+
+def test_negative_diagonal_solve(negcase):
+    p = negcase
+    b = p.A @ np.ones(p.n)
+    xo, io = O.solve(p.st, b, O.SolveOptions(tol=1e-10))
+    x, info = p.h.solve(_cuda(b), tol=1e-10)
+    assert info["status"] == "OK" and info["rank_r"] > 0
+    kappa = np.linalg.cond(p.A.toarray())
+    assert _rel(_np(x), xo) <= max(1e-9, 10 * kappa * 1e-10)
+
+
+def test_edge_cases(cfg0):
+    asss = _lib()
+    p = cfg0
+    x, info = p.h.solve(_cuda(np.zeros(p.n)))
+    assert info["status"] == "OK" and float(_np(x).max()) == 0.0 and float(_np(x).min()) == 0.0
+    b = p.w.b.copy()
+    b[5] = np.nan
+    with pytest.raises(asss.AsssError) as e:
+        p.h.solve(_cuda(b))
+    assert e.value.name == "NONFINITE"
+    x, info = p.h.solve(_cuda(p.w.b), tol=1e-10, max_outer=1)
+    assert info["status"] == "NOT_CONVERGED" and info["outer_its"] == 1
+    x, info = p.h.solve(_cuda(p.w.b), tol=1e-10, restart_m=2)
+    assert info["status"] == "OK" and info["cycles"] > 1
+    A = sp.csr_matrix(np.array([[1.0, 2.0, 0], [3.0, 4.0, 0], [5.0, 6.0, 0]]))
+    with pytest.raises(asss.AsssError) as e:
+        asss.setup(A, k=1)
+    assert e.value.name == "STRUCTURALLY_SINGULAR"
+    bad = sp.csr_matrix((np.array([1.0, 2.0]), np.array([1, 0], dtype=np.int32),
+                         np.array([0, 2, 2])), shape=(2, 2))
+    with pytest.raises(asss.AsssError) as e:
+        asss.setup(bad, k=1, canonicalize=False)
+    assert e.value.name == "INVALID_CSR"
+
+
+@pytest.mark.parametrize("k", [0, 1, 4])
+def test_small_k(k):
+    w = W.config(0, m=20)
+    p = Pair(w.A, k=k)
+    xo, io = O.solve(p.st, w.b, O.SolveOptions(tol=1e-12))
+    x, info = p.h.solve(_cuda(w.b), tol=1e-12)
+    assert info["status"] == "OK"
+    assert _rel(_np(x), xo) <= 1e-10
