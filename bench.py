@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--peclet", type=float, default=100.0)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--restart", type=int, default=64, help="FGMRES restart length")
+    ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--max-outer", type=int, default=2000,
+                    help="cap on outer iterations (profiling runs only; the result then does not reach tol)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=24)
@@ -116,14 +120,16 @@ def main():
 
     def run(mixed: bool, steps: int, warmup: int):
         for i in range(warmup):
-            _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed)
+            _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed, restart_m=args.restart,
+                             inner_tol=args.inner_tol, max_outer=args.max_outer)
             log(f"warmup {'mixed' if mixed else 'fp64'} {i}: {inf['solve_s']:.3f} s, "
                 f"outer {inf['outer_its']}, inner {inf['inner_its_total']}, relres {inf['relres_true']:.2e}")
         torch.cuda.synchronize()
         infos = []
         t0 = time.perf_counter()
         for i in range(steps):
-            _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed)
+            _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed, restart_m=args.restart,
+                             inner_tol=args.inner_tol, max_outer=args.max_outer)
             infos.append(inf)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
@@ -153,8 +159,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1e3 * t64, 3), "higher_is_better": False,
         "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"convdiff3d_{args.m}^3_Pe{args.peclet:g}", "n": n, "nnz": nnz,
-                   "k": args.k, "s_pattern": "abar", "tol": args.tol, "outer": "fgmres(64)",
-                   "inner_tol": 1e-5},
+                   "k": args.k, "s_pattern": "abar", "tol": args.tol,
+                   "outer": f"fgmres({args.restart})", "inner_tol": args.inner_tol},
         "roofline": roofline(inf64, 8),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
                   "relres_true": inf64[-1]["relres_true"], "rel_err_vs_xstar": err64,

@@ -57,18 +57,23 @@ __device__ __forceinline__ double load_partial(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Last-arriving workgroup detection.  Every workgroup calls it after writing
-// its partials; exactly one (the last) gets true and then sees all partials.
+// Last-arriving workgroup detection.  Every workgroup publishes its partials
+// with agent-scope atomic stores (write-through to the device coherence point)
+// and waits for them to complete before taking a ticket; exactly one workgroup
+// (the last) gets true and then reads all partials with agent-scope atomic
+// loads.  Only the partials cross workgroups inside a kernel, so no
+// release/acquire fence (which would write back or invalidate the whole L2 of
+// the XCD) is needed; everything else reaches the next kernel at the launch
+// boundary.
 __device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned total) {
   __shared__ unsigned s_last;
-  __atomic_thread_fence(__ATOMIC_RELEASE);
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_last = (t == total - 1) ? 1u : 0u;
   }
   __syncthreads();
-  if (s_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
   return s_last != 0;
 }
 
@@ -78,8 +83,6 @@ __device__ __forceinline__ void reset_ticket(unsigned* ticket) {
 
 // In the last workgroup: res[j] = sum over groups g (in order of a fixed
 // thread/group assignment) of partials[g * stride + j], j < NV (NV >= nvals).
-// Plain loads are used after the acquire fence of arrive_last, so that the
-// compiler can keep many of them in flight.
 template <int NV>
 __device__ void final_reduce(const double* partials, int ngroups, int stride, int nvals,
                              double* lds, double* res) {
@@ -90,7 +93,7 @@ __device__ void final_reduce(const double* partials, int ngroups, int stride, in
     const double* pg = partials + (int64_t)g * stride;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
-      if (j < nvals) acc[j] += pg[j];
+      if (j < nvals) acc[j] += load_partial(pg + j);
   }
   wg_reduce<NV>(acc, lds, res);
 }
@@ -103,9 +106,9 @@ __device__ __forceinline__ double strided_sum(const double* P, int g0, int ng, i
   int g = g0;
   for (; g + 7 * step < ng; g += 8 * step) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += P[(int64_t)(g + u * step) * stride + o];
+    for (int u = 0; u < 8; ++u) a[u] += load_partial(P + (int64_t)(g + u * step) * stride + o);
   }
-  for (; g < ng; g += step) a[0] += P[(int64_t)g * stride + o];
+  for (; g < ng; g += step) a[0] += load_partial(P + (int64_t)g * stride + o);
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
@@ -178,6 +181,10 @@ template <typename T, int NR, bool STAGE>
 __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
                                                 const T* __restrict__ wg, const T* w_lds,
                                                 T* acc_lds) {
+  // Each round handles up to U in-block entries and U off-block entries of
+  // every row of the slice; all of a round's loads are issued before any of
+  // its arithmetic (the widths are wave-uniform, so the guards do not diverge).
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsl = (nrow + 63) >> 6;
   const int64_t s0 = row0 >> 6;
@@ -185,29 +192,59 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
     const int64_t s = s0 + sl;
     const int il = sl * 64 + lane;
     const bool valid = il < nrow;
-    const int wa = J.a_width[s], wb = J.b_width[s];
-    const int64_t ao = J.a_off[s] + lane, bo = J.b_off[s] + lane;
+    const int wa = __builtin_amdgcn_readfirstlane(J.a_width[s]);
+    const int wb = __builtin_amdgcn_readfirstlane(J.b_width[s]);
+    const uint16_t* __restrict__ acol = J.a_col + J.a_off[s] + lane;
+    const T* __restrict__ aval = J.a_val + J.a_off[s] + lane;
+    const int32_t* __restrict__ bcol = J.b_col + J.b_off[s] + lane;
+    const T* __restrict__ bval = J.b_val + J.b_off[s] + lane;
     T acc[NR], wi[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       acc[c] = T(0);
       wi[c] = valid ? (STAGE ? w_lds[il * NR + c] : wg[(row0 + il) * NR + c]) : T(0);
     }
-    for (int l = 0; l < wa; ++l) {
-      const int jl = J.a_col[ao + (int64_t)l * 64];
-      const T v = J.a_val[ao + (int64_t)l * 64];
+    const int rounds = (max(wa, wb) + U - 1) / U;
+    for (int r = 0; r < rounds; ++r) {
+      const int la = r * U, lb = r * U;
+      int jl[U];
+      T va[U];
+      int32_t jb[U];
+      T vb[U];
 #pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        const T wj = STAGE ? w_lds[jl * NR + c] : wg[(row0 + jl) * NR + c];
-        acc[c] += v * wj;
-        if (valid) atomicAdd(&acc_lds[jl * NR + c], -v * wi[c]);
+      for (int u = 0; u < U; ++u) {
+        if (la + u < wa) {
+          jl[u] = acol[(la + u) * 64];
+          va[u] = aval[(la + u) * 64];
+        }
+        if (lb + u < wb) {
+          jb[u] = bcol[(lb + u) * 64];
+          vb[u] = bval[(lb + u) * 64];
+        }
       }
-    }
-    for (int l = 0; l < wb; ++l) {
-      const int64_t j = J.b_col[bo + (int64_t)l * 64];
-      const T v = J.b_val[bo + (int64_t)l * 64];
+      T wj[U][NR];
 #pragma unroll
-      for (int c = 0; c < NR; ++c) acc[c] += v * wg[j * NR + c];
+      for (int u = 0; u < U; ++u)
+        if (lb + u < wb) {
+#pragma unroll
+          for (int c = 0; c < NR; ++c) wj[u][c] = wg[(int64_t)jb[u] * NR + c];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (la + u < wa) {
+#pragma unroll
+          for (int c = 0; c < NR; ++c) {
+            const T w = STAGE ? w_lds[jl[u] * NR + c] : wg[(row0 + jl[u]) * NR + c];
+            acc[c] += va[u] * w;
+            if (valid) atomicAdd(&acc_lds[jl[u] * NR + c], -va[u] * wi[c]);
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lb + u < wb) {
+#pragma unroll
+          for (int c = 0; c < NR; ++c) acc[c] += vb[u] * wj[u][c];
+        }
     }
     if (valid) {
 #pragma unroll
@@ -246,56 +283,52 @@ template void skew_spmv<float>(const DSkew<float>&, const float*, float*, hipStr
 // Tall-skinny products: out = A^T B (A: n x ka column-major, B: n x nr row-major)
 // ---------------------------------------------------------------------------
 
-constexpr int GT_ROWS = 64;     // rows staged per chunk
+constexpr int GT_COLS = 8;      // output columns of A per workgroup (blockIdx.y)
 constexpr int GT_MAXOUT = 512;  // ka * nr limit
 
-template <typename TA, typename TB>
+// Each thread streams rows (coalesced over i) and keeps GT_COLS x NR running
+// sums; workgroups write partials, the last one sums them in a fixed order.
+template <typename TA, typename TB, int NR>
 __global__ __launch_bounds__(WG) void k_gemm_tn(int64_t n, int ka, const TA* __restrict__ A,
-                                                int64_t lda, const TB* __restrict__ B, int nr,
+                                                int64_t lda, const TB* __restrict__ B,
                                                 double* __restrict__ out,
                                                 const double* __restrict__ M, double* partials,
-                                                unsigned* ticket, int rows_per_chunk) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* As = reinterpret_cast<double*>(smem_raw);          // [ka][rows]
-  double* Bs = As + (size_t)ka * rows_per_chunk;             // [rows][nr]
-  const int nout = ka * nr;
-  double acc0 = 0.0, acc1 = 0.0;  // outputs o = tid and o = tid + WG
-  const int64_t nchunks = (n + rows_per_chunk - 1) / rows_per_chunk;
-  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const int64_t r0 = ch * rows_per_chunk;
-    const int nrow = (int)min((int64_t)rows_per_chunk, n - r0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < ka * rows_per_chunk; e += WG) {
-      int l = e / rows_per_chunk, r = e % rows_per_chunk;
-      As[e] = r < nrow ? (double)A[(int64_t)l * lda + r0 + r] : 0.0;
-    }
-    for (int e = threadIdx.x; e < rows_per_chunk * nr; e += WG) {
-      int r = e / nr;
-      Bs[e] = r < nrow ? (double)B[(r0 + r) * nr + (e % nr)] : 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x < nout) {
-      int l = threadIdx.x / nr, c = threadIdx.x % nr;
-      for (int r = 0; r < nrow; ++r) acc0 += As[l * rows_per_chunk + r] * Bs[r * nr + c];
-    }
-    if (threadIdx.x + WG < nout) {
-      int o = threadIdx.x + WG, l = o / nr, c = o % nr;
-      for (int r = 0; r < nrow; ++r) acc1 += As[l * rows_per_chunk + r] * Bs[r * nr + c];
+                                                unsigned* ticket) {
+  constexpr int NV = GT_COLS * NR;
+  __shared__ double lds[(WG / 64) * NV];
+  __shared__ double res[NV];
+  const int l0 = blockIdx.y * GT_COLS;
+  const int nl = min(GT_COLS, ka - l0);
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    double b[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) b[c] = (double)B[i * NR + c];
+#pragma unroll
+    for (int q = 0; q < GT_COLS; ++q) {
+      if (q < nl) {
+        const double a = (double)A[(int64_t)(l0 + q) * lda + i];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[q * NR + c] += a * b[c];
+      }
     }
   }
-  if (threadIdx.x < nout) store_partial(partials + (int64_t)blockIdx.x * nout + threadIdx.x, acc0);
-  if (threadIdx.x + WG < nout)
-    store_partial(partials + (int64_t)blockIdx.x * nout + threadIdx.x + WG, acc1);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  // last workgroup: threads split each output's groups, then combine in order
+  wg_reduce<NV>(acc, lds, res);
+  const int nout = ka * NR;
+  const int gx = gridDim.x;
+  // partial layout: [bx][o], o = l * NR + c over all ka columns
+  for (int j = threadIdx.x; j < nl * NR; j += WG)
+    store_partial(partials + (int64_t)blockIdx.x * nout + l0 * NR + j, res[j]);
+  if (!arrive_last(ticket, gridDim.x * gridDim.y)) return;
   __shared__ double red[GT_MAXOUT];
   __shared__ double tmp[WG];
   for (int o0 = 0; o0 < nout; o0 += WG) {
     const int cnt = min(WG, nout - o0);
     const int per = max(1, WG / cnt);
     const int o = o0 + threadIdx.x / per, gs = threadIdx.x % per;
-    if (threadIdx.x / per < cnt)
-      tmp[threadIdx.x] = strided_sum(partials, gs, (int)gridDim.x, per, nout, o);
+    if (threadIdx.x / per < cnt) tmp[threadIdx.x] = strided_sum(partials, gs, gx, per, nout, o);
     __syncthreads();
     if (threadIdx.x < cnt) {
       double sacc = 0.0;
@@ -304,7 +337,7 @@ __global__ __launch_bounds__(WG) void k_gemm_tn(int64_t n, int ka, const TA* __r
     }
     __syncthreads();
   }
-  if (M) {  // out = M * red (nr == 1)
+  if (M) {  // out = M * red (NR == 1)
     for (int i = threadIdx.x; i < ka; i += WG) {
       double sacc = 0.0;
       for (int j = 0; j < ka; ++j) sacc += M[i * ka + j] * red[j];
@@ -320,16 +353,16 @@ template <typename TA, typename TB>
 void gemm_tn(int64_t n, int ka, const TA* A, int64_t lda, const TB* B, int nr, double* out,
              const double* M, Reducer& red, int site, hipStream_t s) {
   const int nout = ka * nr;
-  if (nout > GT_MAXOUT || nout < 1) return;  // callers keep ka * nr <= 512
-  int rows = GT_ROWS;
-  while (rows > 1 && (size_t)(ka + nr) * rows * sizeof(double) > 64 * 1024) rows >>= 1;
-  int64_t nchunks = (n + rows - 1) / rows;
-  int groups = (int)std::min<int64_t>(nchunks, 512);
-  groups = std::min(groups, (int)(red.max_groups * (int64_t)RED_SLOTS / std::max(nout, 1)));
-  if (groups < 1) groups = 1;
-  size_t lds = (size_t)(ka + nr) * rows * sizeof(double);
-  hipLaunchKernelGGL((k_gemm_tn<TA, TB>), dim3(groups), dim3(WG), lds, s, n, ka, A, lda, B, nr, out,
-                     M, red.partials, red.tickets + site, rows);
+  if (nout > GT_MAXOUT || nout < 1 || (nr != 1 && nr != NRMAX)) return;  // callers respect these
+  const int gy = (ka + GT_COLS - 1) / GT_COLS;
+  int gx = (int)std::min<int64_t>((n + WG - 1) / WG, 1024);
+  gx = std::max(1, std::min<int>(gx, (int)((int64_t)red.max_groups * RED_SLOTS / nout)));
+  if (nr == 1)
+    hipLaunchKernelGGL((k_gemm_tn<TA, TB, 1>), dim3(gx, gy), dim3(WG), 0, s, n, ka, A, lda, B, out, M,
+                       red.partials, red.tickets + site);
+  else
+    hipLaunchKernelGGL((k_gemm_tn<TA, TB, NRMAX>), dim3(gx, gy), dim3(WG), 0, s, n, ka, A, lda, B, out,
+                       M, red.partials, red.tickets + site);
 }
 template void gemm_tn<double, double>(int64_t, int, const double*, int64_t, const double*, int,
                                       double*, const double*, Reducer&, int, hipStream_t);
@@ -607,8 +640,10 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
   reset_ticket(ticket);
 }
 
+// Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
+// 256 threads are resident per CU (1024 on the chip).
 template <typename T, int NR, int KF, bool STAGE>
-__global__ __launch_bounds__(WG) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
+__global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
   constexpr int NV = (KF + 1) * NR;
