@@ -43,7 +43,8 @@ def mrs_bytes_per_row(nh_per_row: float, k: int, v: int) -> float:
     return nh_per_row * (v + 4) + 4 + k * v + 10 * v
 
 
-def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, inner_full: int):
+def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, inner_full: int,
+                 inner_tol: float, restart: int):
     """The oracle (unchanged) timed on a smaller instance of the same workload
     family; scaled to the full problem by rows and by total inner iterations."""
     from threadpoolctl import threadpool_limits
@@ -56,7 +57,7 @@ def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, 
         t0 = time.perf_counter()
         st = O.setup(w.A, O.SetupOptions(k=k, s_pattern="abar"))
         t1 = time.perf_counter()
-        x, info = O.solve(st, w.b, O.SolveOptions(tol=tol))
+        x, info = O.solve(st, w.b, O.SolveOptions(tol=tol, inner_tol=inner_tol, restart_m=restart))
         t2 = time.perf_counter()
     n_s = w.A.shape[0]
     inner_s = max(1, info["inner_its_total"])
@@ -79,14 +80,19 @@ def main():
     ap.add_argument("--peclet", type=float, default=100.0)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--restart", type=int, default=64, help="FGMRES restart length")
-    ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--restart", type=int, default=200, help="FGMRES restart length")
+    ap.add_argument("--inner-tol", type=float, default=0.2,
+                    help="inner mrs tolerance (0.2 minimises time-to-solution on the default workload)")
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer iterations (profiling runs only; the result then does not reach tol)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=24)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="profiling probe: setup, a 1 GiB device copy (counter calibration), then "
+                         "--probe-steps fixed inner mrs steps in FP64 and in FP32; no solve")
+    ap.add_argument("--probe-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -117,6 +123,27 @@ def main():
     b = torch.from_numpy(w.b).cuda()
     xs = torch.from_numpy(w.x_star).cuda()
     x = torch.empty_like(b)
+    if args.probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        copy_ms = []
+        for _ in range(5):
+            ev[0].record(); dst.copy_(src); ev[1].record(); torch.cuda.synchronize()
+            copy_ms.append(ev[0].elapsed_time(ev[1]))
+        out = {"probe": True, "copy_bytes": 2 * src.numel() * 4,
+               "copy_GBs": round(2 * src.numel() * 4 / (min(copy_ms) * 1e-3) / 1e9, 1)}
+        for mixed in (False, True):
+            h.apply("mrs", b, fixed_inner_steps=5, inner_fp32=mixed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.apply("mrs", b, fixed_inner_steps=args.probe_steps, inner_fp32=mixed)
+            torch.cuda.synchronize()
+            out["mrs_fp32" if mixed else "mrs_fp64"] = round((time.perf_counter() - t0) / args.probe_steps * 1e6, 1)
+        out["handle"] = hi
+        h.close()
+        print(json.dumps(out), flush=True)
+        return
 
     def run(mixed: bool, steps: int, warmup: int):
         for i in range(warmup):
@@ -179,7 +206,7 @@ def main():
         log(f"cpu baseline: oracle on convdiff3d {args.cpu_sample_m}^3")
         try:
             res["cpu_baseline"] = cpu_baseline(args.cpu_sample_m, args.peclet, args.k, args.tol, n,
-                                               inf64[-1]["inner_its_total"])
+                                               inf64[-1]["inner_its_total"], args.inner_tol, args.restart)
         except Exception as e:  # the baseline must not hide the GPU result
             res["cpu_baseline"] = {"value": None, "error": repr(e)}
     h.close()
