@@ -96,6 +96,16 @@ typedef struct {
   int32_t lls_maxit;       /* default 20000 */
   int32_t row_block;       /* rows per LDS block of the skew operator, 0 = automatic */
   int32_t verbose;         /* 0 = silent, 1 = timing lines on stderr */
+  int32_t deflation;       /* how the inner step applies Q_k S_k Q_k^T (Sec. 3.2):
+                              0 or 1 = explicitly: Q_k^T q recomputed from the k Lanczos
+                                  vectors every step (default);
+                              2 = by the Lanczos relation J_tilde Q_k = Q_k S_k + f e_k^T,
+                                  which with Q_k^T Q_k = I keeps Q_k^T q_t in
+                                  span{Q_k^T q_1, e_k} (three vectors per step instead of k).
+                                  Numerically unstable: rounding components along the
+                                  deflated directions are never re-projected and grow by
+                                  ~3x per step on the 3D convection-diffusion workload;
+                                  only accepted when max|Q_k^T Q_k - I| <= 1e-10, else 1 */
 } asss_setup_opts_t;
 
 typedef struct {
@@ -170,6 +180,9 @@ typedef struct {
   int32_t row_block, nblocks;
   int64_t sell_entries_a, sell_entries_b; /* stored skew entries: in-block upper, off-block both */
   double lls_relres, lls_kkt;             /* LSQR stopping quantities */
+  double lanczos_orth_err;                /* max |Q_k^T Q_k - I| */
+  int32_t deflation_mode;                 /* 0 none, 1 explicit, 2 recurrence */
+  int32_t reserved;
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/asss.h"
@@ -41,6 +42,9 @@ struct Error {
 constexpr size_t kStateHead = offsetof(MrsState, relres_max) + sizeof(double);
 // layout of the small device/pinned scalar buffers (doubles)
 constexpr int SM_H1 = 0, SM_H2 = 1024, SM_HN = 2047, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
+// largest max|Q^T Q - I| for which the (opt-in) recurrence form of the
+// deflation is accepted
+constexpr double kRecurrenceOrthTol = 1e-10;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -142,7 +146,13 @@ struct asss_handle_s {
   DSkew<float> J32;
   double* d_Q64 = nullptr;
   float* d_Q32 = nullptr;
+  double* d_Qs64 = nullptr;   // sliced copies for the inner iteration kernel
+  float* d_Qs32 = nullptr;
   double* d_alpha = nullptr;
+  double* d_f64 = nullptr;    // Lanczos residual f = J_tilde q_k - alpha_{k-1} q_{k-1}
+  float* d_f32 = nullptr;
+  int defl_rec = 0;           // 1: recurrence deflation in the inner iteration
+  double orth_err = 0.0;      // max |Q_k^T Q_k - I|
   double* d_Ubar = nullptr;   // n x kr column-major
   double* d_X = nullptr;      // n x kr column-major
   double* d_Mf = nullptr;     // C^-1 Sigma (kr x kr row-major)
@@ -200,10 +210,27 @@ void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb, const double* rhs,
-             double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
-  MrsLaunch L{h->n, 1, h->k_eff, h->d_alpha, sign};
+MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f, bool rec) {
+  MrsLaunch L{};
+  L.n = h->n;
+  L.nr = nr;
+  L.k = h->k_eff;
+  L.alpha_dev = h->d_alpha;
+  L.sign = sign;
+  L.rec = (rec && h->k_eff > 0) ? 1 : 0;
+  L.f = f;
+  L.qk1 = (h->k_eff >= 2) ? (const void*)(Q + (int64_t)(h->k_eff - 2) * h->n) : nullptr;
+  L.alpha_last = (h->k_eff >= 2) ? h->alpha[h->k_eff - 2] : 0.0;
+  L.Qs = std::is_same<T, float>::value ? (const void*)h->d_Qs32 : (const void*)h->d_Qs64;
+  return L;
+}
+
+template <typename T>
+int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
+  MrsLaunch L = make_launch<T>(h, 1, sign, Q, f, h->defl_rec != 0);
   mrs_init<T, 1>(L, rhs, h->n, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
+  if (L.rec) mrs_make_y1<T, 1>(L, Q, mb, h->d_state, s);
   int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
   int its = 0;
   double prev_rel = 1.0;
@@ -252,8 +279,9 @@ int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb, co
 
 int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
                 int maxit, int fixed, hipStream_t s) {
-  if (fp32) return run_mrs1<float>(h, h->J32, h->d_Q32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
-  return run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
+  if (fp32)
+    return run_mrs1<float>(h, h->J32, h->d_Q32, h->d_f32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
+  return run_mrs1<double>(h, h->J64, h->d_Q64, h->d_f64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
 }
 
 // z = P^-1 v (eq. smw in the inverse-free form)
@@ -432,6 +460,28 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   if (keff > 0) {
     h->d_Q32 = h->ar.alloc<float>(n * (int64_t)keff);
     cast_d2f(n * (int64_t)keff, h->d_Q64, h->d_Q32, s);
+    const int64_t npad = ((n + 63) / 64) * 64;
+    h->d_Qs64 = h->ar.alloc<double>(npad * keff);
+    h->d_Qs32 = h->ar.alloc<float>(npad * keff);
+    slice_columns<double>(n, keff, h->d_Q64, h->d_Qs64, s);
+    slice_columns<float>(n, keff, h->d_Q32, h->d_Qs32, s);
+    // Lanczos residual f = J_tilde q_k - alpha_{k-1} q_{k-1}: J_tilde Q_k = Q_k S_k + f e_k^T
+    h->d_f64 = h->ar.alloc<double>(n);
+    h->d_f32 = h->ar.alloc<float>(n);
+    skew_spmv<double>(h->J64, h->d_Q64 + (int64_t)(keff - 1) * n, h->d_f64, s);
+    if (keff >= 2) axpby(n, -alpha[keff - 2], h->d_Q64 + (int64_t)(keff - 2) * n, 1.0, h->d_f64, s);
+    cast_d2f(n, h->d_f64, h->d_f32, s);
+    // loss of orthogonality of Q_k decides the deflation form
+    double err = 0.0;
+    for (int c = 0; c < keff; ++c) {
+      gemm_tn<double, double>(n, keff, h->d_Q64, n, h->d_Q64 + (int64_t)c * n, 1, h->d_small, nullptr,
+                              h->red, 2, s);
+      HIPCHK(hipMemcpyAsync(h->h_small, h->d_small, keff * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int l = 0; l < keff; ++l) err = std::max(err, std::fabs(h->h_small[l] - (l == c ? 1.0 : 0.0)));
+    }
+    h->orth_err = err;
+    h->defl_rec = (h->opts.deflation == 2) && err <= kRecurrenceOrthTol;
   }
   // ---- one-time SMW data (Sec. 4.1): U_bar, X = S_bar^-1 U_bar, G, C
   h->r = (int)h->neg.size();
@@ -463,7 +513,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     for (int c0 = 0; c0 < kr; c0 += (use4 ? NRMAX : 1)) {
       const int nc = use4 ? std::min(NRMAX, kr - c0) : 1;
       if (use4) {
-        MrsLaunch L{n, nc, keff, h->d_alpha, +1};
+        MrsLaunch L = make_launch<double>(h, nc, +1, h->d_Q64, h->d_f64, false);
         mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_Q64, mb4, h->d_state,
                                 h->opts.x_tol, h->opts.x_maxit, 0, h->red, s);
         for (int guard = 0; guard < 1000000; ++guard) {
@@ -484,8 +534,11 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
         }
         mrs_output<double, NRMAX>(n, nc, mb4, h->d_X + (int64_t)c0 * n, n, s);
       } else {
-        int it = run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, h->d_Ubar + (int64_t)c0 * n,
+        const int saved = h->defl_rec;
+        h->defl_rec = 0;  // the one-time X solve uses the explicit projector
+        int it = run_mrs1<double>(h, h->J64, h->d_Q64, h->d_f64, h->mb64, h->d_Ubar + (int64_t)c0 * n,
                                   h->d_X + (int64_t)c0 * n, +1, h->opts.x_tol, h->opts.x_maxit, 0, s);
+        h->defl_rec = saved;
         xits = std::max(xits, it);
       }
     }
@@ -745,6 +798,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->lls_maxit = 20000;
   o->row_block = 0;
   o->verbose = 0;
+  o->deflation = 0;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -770,6 +824,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     if (opts) o = *opts;
     if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
     if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
+    if (o.deflation < 0 || o.deflation > 2) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1 or 2"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     hipStream_t s = (hipStream_t)hip_stream;
@@ -852,6 +907,8 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     for (int b = 0; b < 2; ++b) { h->mb64.p[b] = h->ar.alloc<double>(n); h->mb32.p[b] = h->ar.alloc<float>(n); }
     h->mb64.x = h->ar.alloc<double>(n);
     h->mb32.x = h->ar.alloc<float>(n);
+    h->mb64.y1 = h->ar.alloc<double>(n);
+    h->mb32.y1 = h->ar.alloc<float>(n);
     h->w = h->ar.alloc<double>(n);
     h->t1 = h->ar.alloc<double>(n);
     h->xchk = h->ar.alloc<double>(n);
@@ -867,9 +924,9 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     if (o.verbose)
       std::fprintf(stderr,
                    "[asss] setup n=%lld host %.3fs (pre %.3f, split/pack %.3f) lsqr %.3fs (%d its, kkt %.2e) "
-                   "device %.3fs (k_eff %d, r %d, X its %d)\n",
+                   "device %.3fs (k_eff %d, r %d, X its %d, orth %.1e, deflation %s)\n",
                    (long long)n, h->setup_host_s, t1 - t0, t3 - t2, t2 - t1, h->lls_its, h->lls_kkt,
-                   t4 - t3, h->k_eff, h->r, h->x_its);
+                   t4 - t3, h->k_eff, h->r, h->x_its, h->orth_err, h->defl_rec ? "recurrence" : "explicit");
     *out = h.release();
     return ASSS_OK;
   });
@@ -957,6 +1014,8 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.sell_entries_b = h->sell_b;
     i.lls_relres = h->lls_relres;
     i.lls_kkt = h->lls_kkt;
+    i.lanczos_orth_err = h->orth_err;
+    i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : 1);
     *out = i;
     return ASSS_OK;
   });

@@ -471,6 +471,20 @@ void splitmix_vector(int64_t n, uint64_t seed, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_splitmix, grid_for(n), dim3(WG), 0, s, n, seed, y);
 }
 
+template <typename T>
+__global__ void k_slice_columns(int64_t n, int k, const T* __restrict__ Q, T* __restrict__ Qs) {
+  const int64_t total = ((n + 63) / 64) * 64;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG)
+    for (int l = 0; l < k; ++l)
+      Qs[(i >> 6) * (int64_t)(k * 64) + l * 64 + (i & 63)] = i < n ? Q[(int64_t)l * n + i] : T(0);
+}
+template <typename T>
+void slice_columns(int64_t n, int k, const T* Q, T* Qs, hipStream_t s) {
+  hipLaunchKernelGGL(k_slice_columns<T>, grid_for(n + 64), dim3(WG), 0, s, n, k, Q, Qs);
+}
+template void slice_columns<double>(int64_t, int, const double*, double*, hipStream_t);
+template void slice_columns<float>(int64_t, int, const float*, float*, hipStream_t);
+
 __global__ void k_check_finite(int64_t n, const double* __restrict__ x, int* flag) {
   bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
@@ -493,10 +507,11 @@ __device__ __forceinline__ double sk_times(const double* alpha, const double* d,
   return r;
 }
 
-template <int NR, int KF>
+template <int NR, int KF, bool REC>
 __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const double* alpha,
-                                  int t) {
-  // res: [KF+1][NR] with row 0 = ||q_new||^2, rows 1..k = Q^T q_new
+                                  int t, int sign) {
+  // res: [KF+1][NR] with row 0 = ||q_new||^2, rows 1..k = Q^T q_new (explicit
+  // deflation), or [2][NR] with row 1 = f^T q_t (recurrence deflation)
   __shared__ double dsh[NRMAX][KMAX];
   __shared__ double s_relmax[NRMAX];
   const int c = threadIdx.x;
@@ -519,11 +534,22 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
       col.s_old = sk;
       col.c_old = ck;
       col.theta1 = theta1_new;
+      const double beta_old = col.beta_prev;
       col.nu_old = col.nu;
       col.nu = (beta != 0.0) ? beta : 1.0;
       col.beta_prev = beta;
       rel = fabs(col.g) / col.r0;
-      for (int l = 0; l < k; ++l) dsh[c][l] = res[(1 + l) * NR + c] / col.nu;
+      if (REC) {
+        const double fq = res[NR + c];
+        const double ra_new = beta_old * col.ra_old / col.nu;
+        const double rb_new = (beta_old * col.rb_old - (double)sign * fq) / col.nu;
+        col.ra_old = col.ra;
+        col.rb_old = col.rb;
+        col.ra = ra_new;
+        col.rb = rb_new;
+      } else {
+        for (int l = 0; l < k; ++l) dsh[c][l] = res[(1 + l) * NR + c] / col.nu;
+      }
     } else {
       col.pend_theta = 1.0;
       col.pend_delta = 0.0;
@@ -535,9 +561,11 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
     st->col[c] = col;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NR * k; e += WG) {
-    int cc = e / k, l = e % k;
-    st->cvec[cc * KMAX + l] = sk_times(alpha, dsh[cc], k, l);
+  if (!REC) {
+    for (int e = threadIdx.x; e < NR * k; e += WG) {
+      int cc = e / k, l = e % k;
+      st->cvec[cc * KMAX + l] = sk_times(alpha, dsh[cc], k, l);
+    }
   }
   if (threadIdx.x == 0) {
     double rmax = 0.0;
@@ -616,6 +644,10 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
     col.pend_delta = 0.0;
     col.pend_coef = 0.0;
     col.has_pending = 0;
+    col.ra = 1.0;
+    col.rb = 0.0;
+    col.ra_old = 0.0;
+    col.rb_old = 0.0;
     for (int l = 0; l < k; ++l) dsh[c][l] = col.live ? res[(1 + l) * NR + c] / col.nu : 0.0;
     st->col[c] = col;
     if (col.live) atomicOr(&s_any, 1);
@@ -642,11 +674,11 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
 
 // Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
 // 256 threads are resident per CU (1024 on the chip).
-template <typename T, int NR, int KF, bool STAGE>
+template <typename T, int NR, int KF, bool STAGE, bool REC>
 __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
-  constexpr int NV = (KF + 1) * NR;
+  constexpr int NV = REC ? 2 * NR : (KF + 1) * NR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* acc_lds = reinterpret_cast<T*>(smem_raw);
   T* w_lds = acc_lds + (size_t)J.R * NR;
@@ -656,6 +688,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   __shared__ double s_inv_nu[NR], s_inv_nu_old[NR], s_beta_prev[NR];
   __shared__ double s_pend_delta[NR], s_inv_pend_theta[NR], s_pend_coef[NR];
   __shared__ T s_cv[NR][KF > 0 ? KF : 1];
+  __shared__ double s_cy[NR], s_cq[NR];
   const int k = L.k;
   if (threadIdx.x == 0) {
     s_status = st->status;
@@ -670,6 +703,8 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     s_pend_delta[threadIdx.x] = col.pend_delta;
     s_inv_pend_theta[threadIdx.x] = 1.0 / col.pend_theta;
     s_pend_coef[threadIdx.x] = col.pend_coef;
+    s_cy[threadIdx.x] = col.ra;
+    s_cq[threadIdx.x] = col.rb * L.alpha_last;
   }
   constexpr int KF1 = KF > 0 ? KF : 1;
   for (int e = threadIdx.x; e < NR * KF; e += WG) {
@@ -722,17 +757,37 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   const T sgn = (T)L.sign;
+  const T* __restrict__ fvec = reinterpret_cast<const T*>(L.f);
+  const T* __restrict__ qk1 = reinterpret_cast<const T*>(L.qk1);
+  const T* __restrict__ y1 = buf.y1;
+  bool use_y1 = false;
+  if (REC) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) use_y1 |= (s_cy[c] != 0.0);
+  }
   for (int il = threadIdx.x; il < nrow; il += WG) {
     const int64_t i = row0 + il;
     T defl[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) defl[c] = T(0);
     T qrow[KF > 0 ? KF : 1];
+    T fi = T(0);
+    if (REC) {
+      const T qk = qk1 ? qk1[i] : T(0);
+      fi = fvec[i];
 #pragma unroll
-    for (int l = 0; l < KF; ++l) {
-      qrow[l] = (l < k) ? Q[(int64_t)l * n + i] : T(0);
+      for (int c = 0; c < NR; ++c) {
+        defl[c] = (T)s_cq[c] * qk;
+        if (use_y1) defl[c] += (T)s_cy[c] * y1[i * NR + c];
+      }
+    } else {
+      const T* __restrict__ qs = reinterpret_cast<const T*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
 #pragma unroll
-      for (int c = 0; c < NR; ++c) defl[c] += qrow[l] * s_cv[c][l];
+      for (int l = 0; l < KF; ++l) {
+        qrow[l] = (l < k) ? qs[l * 64] : T(0);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) defl[c] += qrow[l] * s_cv[c][l];
+      }
     }
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
@@ -741,8 +796,13 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
       const T qn = sgn * (u - defl[c]) + (T)s_beta_prev[c] * qold;
       wnew[i * NR + c] = qn;
       acc[c] += (double)qn * (double)qn;
+      if (REC) {
+        const T qcur = (STAGE ? w_lds[il * NR + c] : wcur[i * NR + c]) * (T)s_inv_nu[c];
+        acc[NR + c] += (double)fi * (double)qcur;
+      } else {
 #pragma unroll
-      for (int l = 0; l < KF; ++l) acc[(1 + l) * NR + c] += (double)qrow[l] * (double)qn;
+        for (int l = 0; l < KF; ++l) acc[(1 + l) * NR + c] += (double)qrow[l] * (double)qn;
+      }
       if (pend) {
         const T p = (qold - (T)s_pend_delta[c] * pb[i * NR + c]) * (T)s_inv_pend_theta[c];
         pb[i * NR + c] = p;
@@ -754,7 +814,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)blockIdx.x * NV + j, res[j]);
   if (!arrive_last(ticket, gridDim.x)) return;
   final_reduce<NV>(partials, gridDim.x, NV, NV, lds, res);
-  mrs_scalar_update<NR, KF>(st, res, k, L.alpha_dev, t);
+  mrs_scalar_update<NR, KF, REC>(st, res, k, L.alpha_dev, t, L.sign);
   reset_ticket(ticket);
 }
 
@@ -794,8 +854,13 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
   size_t lds = (size_t)J.R * NR * sizeof(T) * (STAGE ? 2 : 1);
   const int kf = pick_kf(L.k, NR);
 #define ASSS_ITER(KF)                                                                              \
-  hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE>), dim3(J.nblocks), dim3(WG), lds, s, L, J, Q,   \
-                     buf, st, red.partials, red.tickets + 1)
+  hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false>), dim3(J.nblocks), dim3(WG), lds, s, L, J, \
+                     Q, buf, st, red.partials, red.tickets + 1)
+  if (L.rec && L.k > 0) {
+    hipLaunchKernelGGL((k_mrs_iter<T, NR, 0, STAGE, true>), dim3(J.nblocks), dim3(WG), lds, s, L, J, Q,
+                       buf, st, red.partials, red.tickets + 1);
+    return;
+  }
   switch (kf) {
     case 0: ASSS_ITER(0); break;
     case 8: ASSS_ITER(8); break;
@@ -805,6 +870,30 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
       break;
   }
 #undef ASSS_ITER
+}
+
+template <typename T, int NR>
+__global__ void k_mrs_y1(int64_t n, int k, const T* __restrict__ Q, const MrsState* st,
+                         T* __restrict__ y1) {
+  __shared__ double cv[NR][KMAX];
+  for (int e = threadIdx.x; e < NR * KMAX; e += WG) cv[e / KMAX][e % KMAX] = st->cvec[e];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    for (int l = 0; l < k; ++l) {
+      const double q = (double)Q[(int64_t)l * n + i];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] += q * cv[c][l];
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) y1[i * NR + c] = (T)acc[c];
+  }
+}
+template <typename T, int NR>
+void mrs_make_y1(const MrsLaunch& L, const T* Q, MrsBufs<T>& buf, const MrsState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_mrs_y1<T, NR>), grid_for(L.n), dim3(WG), 0, s, L.n, L.k, Q, st, buf.y1);
 }
 
 template <typename T, int NR>
@@ -822,7 +911,8 @@ void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, double* out, int64_t l
                                 MrsState*, double, int, int, Reducer&, hipStream_t);               \
   template void mrs_iter<T, NR>(const MrsLaunch&, const DSkew<T>&, const T*, MrsBufs<T>&,          \
                                 MrsState*, Reducer&, hipStream_t);                                 \
-  template void mrs_output<T, NR>(int64_t, int, const MrsBufs<T>&, double*, int64_t, hipStream_t);
+  template void mrs_output<T, NR>(int64_t, int, const MrsBufs<T>&, double*, int64_t, hipStream_t); \
+  template void mrs_make_y1<T, NR>(const MrsLaunch&, const T*, MrsBufs<T>&, const MrsState*, hipStream_t);
 ASSS_MRS_INST(double, 1)
 ASSS_MRS_INST(float, 1)
 ASSS_MRS_INST(double, 4)

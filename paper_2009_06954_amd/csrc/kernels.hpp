@@ -44,6 +44,8 @@ struct MrsCol {
   double beta_prev;   // beta_{t-1}
   double theta1, c_old, s_old, delta_old, g, r0;
   double pend_theta, pend_delta, pend_coef;
+  // recurrence form of the deflation coefficients: Q_k^T q_t = ra d_1 + rb e_k
+  double ra, rb, ra_old, rb_old;
   int32_t has_pending, live;
 };
 
@@ -63,6 +65,7 @@ struct MrsBufs {
   T* w[3];
   T* p[2];
   T* x;
+  T* y1;  // Q_k S_k Q_k^T q_1 per column (recurrence deflation only)
 };
 
 struct Reducer {
@@ -107,6 +110,9 @@ void cast_f2d(int64_t n, const float* x, double* y, hipStream_t s);
 void splitmix_vector(int64_t n, uint64_t seed, double* y, hipStream_t s);
 // non-finite check: *flag = 1 if any entry of x is NaN/Inf
 void check_finite(int64_t n, const double* x, int* flag, hipStream_t s);
+// Qs (sliced, nslices * 64 * k, zero padded) from column-major Q (n x k)
+template <typename T>
+void slice_columns(int64_t n, int k, const T* Q, T* Qs, hipStream_t s);
 
 // ---- inner mrs --------------------------------------------------------------
 
@@ -116,6 +122,16 @@ struct MrsLaunch {
   int k;            // deflation vectors (0 = none)
   const double* alpha_dev;  // k-1 skew-Lanczos coefficients
   int sign;         // +1: K = J_bar,  -1: K = -J_bar
+  // Recurrence deflation (rec = 1): with J_tilde Q_k = Q_k S_k + f e_k^T and
+  // Q_k^T Q_k = I, Q_k^T (J_bar q) = -(f^T q) e_k, so Q_k^T q_t stays in
+  // span{Q_k^T q_1, e_k}; Q_k S_k Q_k^T q_t = ra y1 + rb alpha_{k-1} q_{k-1}.
+  int rec;
+  const void* f;    // Lanczos residual J_tilde q_k - alpha_{k-1} q_{k-1} (inner precision)
+  const void* qk1;  // q_{k-1} (inner precision), nullptr when k = 1
+  double alpha_last;  // alpha_{k-1} (0 when k = 1)
+  // Q_k in sliced layout for the iteration kernel: row i, column l at
+  // (i / 64) * (k * 64) + l * 64 + i % 64 (each 64-row slice contiguous)
+  const void* Qs;
 };
 
 // Initialise: w1 = rhs (col c at rhs + c * ldr), zero the other buffers,
@@ -129,6 +145,10 @@ void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const T* Q, Mr
 template <typename T, int NR>
 void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf, MrsState* st,
               Reducer& red, hipStream_t s);
+
+// y1 = Q_k (S_k d_1) per column from the state written by mrs_init (recurrence mode).
+template <typename T, int NR>
+void mrs_make_y1(const MrsLaunch& L, const T* Q, MrsBufs<T>& buf, const MrsState* st, hipStream_t s);
 
 // Copy the inner solution out: out (FP64, column c at out + c * ldo) = x.
 template <typename T, int NR>
