@@ -133,6 +133,8 @@ typedef struct {
   double setup_device_s;
   double solve_s;
   double inner_kernel_s;   /* HIP-event time of those launches (back to back on the stream) */
+  int32_t reorth;          /* Arnoldi steps that needed the second Gram-Schmidt pass */
+  int32_t reserved;
 } asss_info_t;
 
 /* Defaults of the option structs. */

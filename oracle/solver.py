@@ -17,8 +17,9 @@ Readings:
 * Outer method: flexible GMRES(m) (the paper says "a Krylov subspace method";
   the inner solve is inexact, so the preconditioner changes from step to step
   and the flexible variant stores the preconditioned vectors z_j).  Arnoldi
-  with classical Gram-Schmidt applied twice; Givens rotations on the
-  Hessenberg matrix.
+  with classical Gram-Schmidt and one reorthogonalisation pass whenever the
+  norm drops below 1/sqrt(2) of its value (Daniel-Gragg-Kaufman-Stewart
+  criterion); Givens rotations on the Hessenberg matrix.
 * Stopping: the implicit residual |g_{j+1}| <= thr only triggers a check; the
   solve is converged when the true residual ||b - A x|| <= tol ||b|| on the
   original system.  The true residual is also checked at every restart.  If
@@ -133,7 +134,7 @@ def _fgmres(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
     """Flexible GMRES(m) with the stopping rule described in the module doc."""
     n = rhs.size
     info = dict(converged=False, outer_its=0, inner_its_total=0, inner_its_max=0,
-                relres_true=np.nan, relres_implicit=np.nan, cycles=0, hist=[])
+                relres_true=np.nan, relres_implicit=np.nan, cycles=0, hist=[], reorth=0)
     bn = np.linalg.norm(rhs)
     x_chk = np.zeros(n)
     if bn == 0.0:
@@ -164,12 +165,17 @@ def _fgmres(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
                 info["inner_its_max"] = max(info["inner_its_max"], its)
                 Z[:, j] = z
                 w = op(z)
-                h1 = V[:, :j + 1].T @ w
-                w = w - V[:, :j + 1] @ h1
-                h2 = V[:, :j + 1].T @ w
-                w = w - V[:, :j + 1] @ h2
+                wn = np.linalg.norm(w)
+                h = V[:, :j + 1].T @ w
+                w = w - V[:, :j + 1] @ h
                 hn = np.linalg.norm(w)
-                H[:j + 1, j] = h1 + h2
+                if hn * hn < 0.5 * wn * wn:          # DGKS: one reorthogonalisation pass
+                    h2 = V[:, :j + 1].T @ w
+                    w = w - V[:, :j + 1] @ h2
+                    h = h + h2
+                    hn = np.linalg.norm(w)
+                    info["reorth"] += 1
+                H[:j + 1, j] = h
                 H[j + 1, j] = hn
                 if hn != 0.0:
                     V[:, j + 1] = w / hn

@@ -66,10 +66,10 @@ class Info(C.Structure):
                 ("cycles", C.c_int32), ("inner_launches", C.c_int32), ("relres_true", C.c_double),
                 ("relres_implicit", C.c_double), ("setup_host_s", C.c_double),
                 ("setup_device_s", C.c_double), ("solve_s", C.c_double),
-                ("inner_kernel_s", C.c_double)]
+                ("inner_kernel_s", C.c_double), ("reorth", C.c_int32), ("reserved", C.c_int32)]
 
     def to_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class HandleInfo(C.Structure):

@@ -671,20 +671,30 @@ asss_status_t fgmres(asss_handle_s* h, bool adjoint, const double* b, double* x,
         int its = adjoint ? prec_apply_T(h, fp32, vj, zj, o, s) : prec_apply(h, fp32, vj, zj, o, s);
         inf.inner_its_total += its;
         inf.inner_its_max = std::max(inf.inner_its_max, its);
-        if (!adjoint) outer_op(h, zj, h->w, s);
-        else outer_op_T(h, zj, h->w, s);
-        // classical Gram-Schmidt, twice
-        gemm_tn<double, double>(n, j + 1, h->V, n, h->w, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
-        gemv_acc(n, j + 1, h->V, n, hbuf + SM_H1, -1.0, h->w, s);
-        gemm_tn<double, double>(n, j + 1, h->V, n, h->w, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
-        gemv_acc(n, j + 1, h->V, n, hbuf + SM_H2, -1.0, h->w, s);
-        gemm_tn<double, double>(n, 1, h->w, n, h->w, 1, hbuf + SM_HN, nullptr, h->red, 4, s);
+        // w = A_chk z_j written straight into V[:, j+1]; classical Gram-Schmidt with
+        // one more pass when the norm drops below 1/sqrt(2) of its value (DGKS)
+        double* vn = h->V + (int64_t)(j + 1) * n;
+        if (!adjoint) outer_op(h, zj, vn, s);
+        else outer_op_T(h, zj, vn, s);
+        gemm_tn<double, double>(n, j + 2, h->V, n, vn, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
+        gemv_acc_norm(n, j + 1, h->V, n, hbuf + SM_H1, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
         HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        const double hn = std::sqrt(h->h_small[SM_HN]);
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i] + h->h_small[SM_H2 + i];
+        const double wn2 = h->h_small[SM_H1 + j + 1];
+        double hn2 = h->h_small[SM_HN];
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i];
+        if (hn2 < 0.5 * wn2) {
+          gemm_tn<double, double>(n, j + 1, h->V, n, vn, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
+          gemv_acc_norm(n, j + 1, h->V, n, hbuf + SM_H2, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
+          HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h->h_small[SM_H2 + i];
+          hn2 = h->h_small[SM_HN];
+          inf.reorth++;
+        }
+        const double hn = std::sqrt(hn2);
         H[(size_t)(j + 1) * m + j] = hn;
-        if (hn != 0.0) scale(n, 1.0 / hn, h->w, h->V + (int64_t)(j + 1) * n, s);
+        if (hn != 0.0) scale(n, 1.0 / hn, vn, vn, s);
         for (int i = 0; i < j; ++i) {
           const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
           H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;

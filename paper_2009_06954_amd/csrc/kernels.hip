@@ -396,6 +396,40 @@ void gemv_acc(int64_t n, int kt, const double* A, int64_t lda, const double* t, 
   hipLaunchKernelGGL(k_gemv_acc, grid_for(n), dim3(WG), 0, s, n, kt, A, lda, t, sign, y);
 }
 
+// y += sign * A t, then ||y||^2 reduced into *nrm2 (last workgroup, fixed order).
+__global__ __launch_bounds__(WG) void k_gemv_acc_norm(int64_t n, int kt, const double* __restrict__ A,
+                                                      int64_t lda, const double* __restrict__ t,
+                                                      double sign, double* __restrict__ y,
+                                                      double* nrm2, double* partials, unsigned* ticket) {
+  __shared__ double ts[1024];
+  __shared__ double lds[WG / 64];
+  __shared__ double res[1];
+  for (int l = threadIdx.x; l < kt && l < 1024; l += WG) ts[l] = t[l];
+  __syncthreads();
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    double sacc = 0.0;
+    for (int l = 0; l < kt; ++l) sacc += A[(int64_t)l * lda + i] * ts[l];
+    const double v = y[i] + sign * sacc;
+    y[i] = v;
+    acc[0] += v * v;
+  }
+  wg_reduce<1>(acc, lds, res);
+  if (threadIdx.x == 0) store_partial(partials + blockIdx.x, res[0]);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  final_reduce<1>(partials, gridDim.x, 1, 1, lds, res);
+  if (threadIdx.x == 0) *nrm2 = res[0];
+  reset_ticket(ticket);
+}
+void gemv_acc_norm(int64_t n, int kt, const double* A, int64_t lda, const double* t, double sign,
+                   double* y, double* nrm2, Reducer& red, int site, hipStream_t s) {
+  if (n <= 0) return;
+  if (kt > 1024) kt = 1024;
+  int groups = (int)std::min<int64_t>((n + WG - 1) / WG, 1024);
+  hipLaunchKernelGGL(k_gemv_acc_norm, dim3(groups), dim3(WG), 0, s, n, kt, A, lda, t, sign, y, nrm2,
+                     red.partials, red.tickets + site);
+}
+
 __global__ void k_scale(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[i] = a * x[i];
 }

@@ -95,6 +95,10 @@ void gemm_tn(int64_t n, int ka, const TA* A, int64_t lda, const TB* B, int nr, d
 void gemv_acc(int64_t n, int kt, const double* A, int64_t lda, const double* t, double sign,
               double* y, hipStream_t s);
 
+// y += sign * A t and *nrm2 = ||y||^2 (deterministic reduction)
+void gemv_acc_norm(int64_t n, int kt, const double* A, int64_t lda, const double* t, double sign,
+                   double* y, double* nrm2, Reducer& red, int site, hipStream_t s);
+
 // y = a * x (FP64)   and   y = x / sqrt(*nrm2) (device scalar)
 void scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
 void normalize(int64_t n, const double* x, const double* nrm2, double* y, hipStream_t s);
