@@ -51,7 +51,7 @@ class SetupOpts(C.Structure):
                 ("s_colind", C.c_void_p), ("k", C.c_int32), ("lanczos_seed", C.c_uint64),
                 ("inner_fp32", C.c_int32), ("x_tol", C.c_double), ("x_maxit", C.c_int32),
                 ("lls_tol", C.c_double), ("lls_maxit", C.c_int32), ("row_block", C.c_int32),
-                ("verbose", C.c_int32), ("deflation", C.c_int32)]
+                ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -79,7 +79,8 @@ class HandleInfo(C.Structure):
                 ("lls_its", C.c_int32), ("x_its", C.c_int32), ("row_block", C.c_int32),
                 ("nblocks", C.c_int32), ("sell_entries_a", C.c_int64),
                 ("sell_entries_b", C.c_int64), ("lls_relres", C.c_double), ("lls_kkt", C.c_double),
-                ("lanczos_orth_err", C.c_double), ("deflation_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("lanczos_orth_err", C.c_double), ("deflation_mode", C.c_int32), ("reordered", C.c_int32),
+                ("cross_pairs_natural", C.c_int64), ("cross_pairs_used", C.c_int64)]
 
     def to_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -242,7 +243,7 @@ class Handle:
 
 def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, inner_fp32=False,
           x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
-          stream=None, canonicalize=True, deflation="auto") -> Handle:
+          stream=None, canonicalize=True, deflation="auto", reorder="auto") -> Handle:
     """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
     canonicalize: sum duplicates and sort column indices of a SciPy input first
     (otherwise the library rejects such input with INVALID_CSR)."""
@@ -263,6 +264,7 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.x_tol, o.x_maxit, o.lls_tol, o.lls_maxit = x_tol, x_maxit, lls_tol, lls_maxit
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2}[deflation]
+    o.reorder = {"auto": 0, "none": 1, "blocks": 2}[reorder]
     out = C.c_void_p()
     _check(lib.asss_setup(C.byref(csr), C.byref(o), _stream(stream), C.byref(out)))
     return Handle(out.value, n)

@@ -144,7 +144,12 @@ struct asss_handle_s {
   double *d_drp = nullptr, *d_om = nullptr, *d_dc = nullptr;
   DSkew<double> J64;
   DSkew<float> J32;
-  double* d_Q64 = nullptr;
+  // inner system in block order: row i of the inner system is row perm[i]
+  std::vector<int32_t> perm;
+  int32_t* d_perm = nullptr;  // null when the natural order is kept
+  int64_t cross_natural = 0, cross_used = 0;
+  double* d_Qorig = nullptr;  // Q_k in the original order (U_bar, export)
+  double* d_Q64 = nullptr;    // Q_k in the inner (block) order
   float* d_Q32 = nullptr;
   double* d_Qs64 = nullptr;   // sliced copies for the inner iteration kernel
   float* d_Qs32 = nullptr;
@@ -229,7 +234,7 @@ template <typename T>
 int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
              const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
   MrsLaunch L = make_launch<T>(h, 1, sign, Q, f, h->defl_rec != 0);
-  mrs_init<T, 1>(L, rhs, h->n, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
+  mrs_init<T, 1>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
   if (L.rec) mrs_make_y1<T, 1>(L, Q, mb, h->d_state, s);
   int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
   int its = 0;
@@ -272,7 +277,7 @@ int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBuf
     prev_rel = rel;
     prev_its = its;
   }
-  mrs_output<T, 1>(h->n, 1, mb, out, h->n, s);
+  mrs_output<T, 1>(h->n, 1, mb, h->d_perm, out, h->n, s);
   h->last_inner = its;
   return its;
 }
@@ -430,7 +435,12 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     h->d_Q64 = h->ar.alloc<double>(n * (int64_t)k);
     double* z = h->ar.alloc<double>(n);
     double* q0 = h->d_Q64;
-    splitmix_vector(n, h->opts.lanczos_seed, q0, s);
+    if (h->d_perm) {  // the start vector is defined in the original order
+      splitmix_vector(n, h->opts.lanczos_seed, z, s);
+      permute_gather(n, h->d_perm, z, q0, s);
+    } else {
+      splitmix_vector(n, h->opts.lanczos_seed, q0, s);
+    }
     double nq = std::sqrt(dot_host(h, n, q0, q0, s));
     scale(n, 1.0 / nq, q0, q0, s);
     keff = 1;
@@ -456,6 +466,13 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   }
   h->k_eff = keff;
   h->alpha = alpha;
+  if (keff > 0 && h->d_perm) {
+    h->d_Qorig = h->ar.alloc<double>(n * (int64_t)keff);
+    for (int c = 0; c < keff; ++c)
+      permute_scatter(n, h->d_perm, h->d_Q64 + (int64_t)c * n, h->d_Qorig + (int64_t)c * n, s);
+  } else {
+    h->d_Qorig = h->d_Q64;
+  }
   h->d_alpha = h->ar.upload(alpha.empty() ? std::vector<double>{0.0} : alpha, s);
   if (keff > 0) {
     h->d_Q32 = h->ar.alloc<float>(n * (int64_t)keff);
@@ -492,7 +509,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   h->d_Ubar = h->ar.alloc<double>(n * (int64_t)kr);
   HIPCHK(hipMemsetAsync(h->d_Ubar, 0, n * (int64_t)kr * sizeof(double), s));
   if (keff > 0)
-    HIPCHK(hipMemcpyAsync(h->d_Ubar, h->d_Q64, n * (int64_t)keff * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->d_Ubar, h->d_Qorig, n * (int64_t)keff * sizeof(double), hipMemcpyDeviceToDevice, s));
   {
     std::vector<double> one(1, 1.0);
     for (int j = 0; j < h->r; ++j)
@@ -514,7 +531,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
       const int nc = use4 ? std::min(NRMAX, kr - c0) : 1;
       if (use4) {
         MrsLaunch L = make_launch<double>(h, nc, +1, h->d_Q64, h->d_f64, false);
-        mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_Q64, mb4, h->d_state,
+        mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_perm, h->d_Q64, mb4, h->d_state,
                                 h->opts.x_tol, h->opts.x_maxit, 0, h->red, s);
         for (int guard = 0; guard < 1000000; ++guard) {
           for (int c = 0; c < 16; ++c) mrs_iter<double, NRMAX>(L, h->J64, h->d_Q64, mb4, h->d_state, h->red, s);
@@ -532,7 +549,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
             break;
           }
         }
-        mrs_output<double, NRMAX>(n, nc, mb4, h->d_X + (int64_t)c0 * n, n, s);
+        mrs_output<double, NRMAX>(n, nc, mb4, h->d_perm, h->d_X + (int64_t)c0 * n, n, s);
       } else {
         const int saved = h->defl_rec;
         h->defl_rec = 0;  // the one-time X solve uses the explicit projector
@@ -809,6 +826,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->row_block = 0;
   o->verbose = 0;
   o->deflation = 0;
+  o->reorder = 0;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -835,6 +853,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
     if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
     if (o.deflation < 0 || o.deflation > 2) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1 or 2"};
+    if (o.reorder < 0 || o.reorder > 2) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1 or 2"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     hipStream_t s = (hipStream_t)hip_stream;
@@ -886,6 +905,21 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
       if (h->D[i] < 0) h->neg.push_back((int32_t)i);
     Csr Jup = h->U;
     Jup.val = h->jval;
+    // block order of the inner system (fewer pairs stored twice in the sliced layout)
+    h->cross_natural = count_cross_pairs(Jup, R);
+    h->cross_used = h->cross_natural;
+    bool reordered = false;
+    if (o.reorder == 2 && n >= 2 * (int64_t)R) {
+      std::vector<int32_t> perm = block_partition(Jup, R);
+      Csr Jp = permute_skew_upper(Jup, perm);
+      const int64_t cross = count_cross_pairs(Jp, R);
+      {
+        Jup = std::move(Jp);
+        h->perm = std::move(perm);
+        h->cross_used = cross;
+        reordered = true;
+      }
+    }
     SkewSell sell = pack_skew_sell(Jup, R);
     h->sell_a = sell.a_entries;
     h->sell_b = sell.b_entries;
@@ -898,6 +932,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->dS = upload_csr(h->ar, h->S, s);
     h->dSt = upload_csr(h->ar, transpose(h->S), s);
     h->d_m = h->ar.upload(h->m, s);
+    if (reordered) h->d_perm = h->ar.upload(h->perm, s);
     std::vector<double> drp(n);
     for (int64_t j = 0; j < n; ++j) drp[j] = h->Dr[h->m[j]];
     h->d_drp = h->ar.upload(drp, s);
@@ -1026,6 +1061,9 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.lls_kkt = h->lls_kkt;
     i.lanczos_orth_err = h->orth_err;
     i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : 1);
+    i.reordered = h->d_perm ? 1 : 0;
+    i.cross_pairs_natural = h->cross_natural;
+    i.cross_pairs_used = h->cross_used;
     *out = i;
     return ASSS_OK;
   });
@@ -1057,7 +1095,7 @@ asss_status_t asss_get_array(asss_handle_t h, int32_t which, void* dst, int64_t*
       case ASSS_ARR_J_ROWPTR: give(h->U.ptr.data(), n + 1, 8); break;
       case ASSS_ARR_J_COLIND: give(h->U.col.data(), h->U.nnz(), 4); break;
       case ASSS_ARR_J_VAL: give(h->jval.data(), (int64_t)h->jval.size(), 8); break;
-      case ASSS_ARR_Q: give_dev(h->d_Q64, n * (int64_t)h->k_eff, 8); break;
+      case ASSS_ARR_Q: give_dev(h->d_Qorig, n * (int64_t)h->k_eff, 8); break;
       case ASSS_ARR_ALPHA: give(h->alpha.data(), (int64_t)h->alpha.size(), 8); break;
       case ASSS_ARR_X: give_dev(h->d_X, n * (int64_t)h->kr, 8); break;
       case ASSS_ARR_NEG: give(h->neg.data(), (int64_t)h->neg.size(), 4); break;
@@ -1080,17 +1118,25 @@ asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in, double* 
     switch (op) {
       case ASSS_OP_SKEW:
       case ASSS_OP_DEFLATED: {
+        // the operators act in the inner (block) order: gather, apply, scatter
+        const double* vin = in;
+        double* vout = out;
+        if (h->d_perm) {
+          permute_gather(n, h->d_perm, in, h->tmp, s);
+          vin = h->tmp;
+          vout = h->w;
+        }
         if (fp32) {
-          cast_d2f(n, in, h->mb32.w[0], s);
+          cast_d2f(n, vin, h->mb32.w[0], s);
           skew_spmv<float>(h->J32, h->mb32.w[0], h->mb32.w[1], s);
-          cast_f2d(n, h->mb32.w[1], out, s);
+          cast_f2d(n, h->mb32.w[1], vout, s);
         } else {
-          skew_spmv<double>(h->J64, in, out, s);
+          skew_spmv<double>(h->J64, vin, vout, s);
         }
         if (op == ASSS_OP_DEFLATED && h->k_eff > 0) {
           // out -= Q (S_k (Q^T in))
           double* d = h->d_small + SM_T;
-          gemm_tn<double, double>(n, h->k_eff, h->d_Q64, n, in, 1, d, nullptr, h->red, 3, s);
+          gemm_tn<double, double>(n, h->k_eff, h->d_Q64, n, vin, 1, d, nullptr, h->red, 3, s);
           HIPCHK(hipMemcpyAsync(h->h_small, d, h->k_eff * sizeof(double), hipMemcpyDeviceToHost, s));
           HIPCHK(hipStreamSynchronize(s));
           std::vector<double> c(h->k_eff, 0.0);
@@ -1099,8 +1145,9 @@ asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in, double* 
             if (l >= 1) c[l] -= h->alpha[l - 1] * h->h_small[l - 1];
           }
           HIPCHK(hipMemcpyAsync(d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
-          gemv_acc(n, h->k_eff, h->d_Q64, n, d, -1.0, out, s);
+          gemv_acc(n, h->k_eff, h->d_Q64, n, d, -1.0, vout, s);
         }
+        if (h->d_perm) permute_scatter(n, h->d_perm, vout, out, s);
         break;
       }
       case ASSS_OP_OUTER: outer_op(h, in, out, s); break;

@@ -92,4 +92,18 @@ struct SkewSell {
 };
 SkewSell pack_skew_sell(const Csr& Jup, int32_t R);
 
+// Symmetric reordering of the inner system into compact blocks of R rows:
+// recursive bisection of the graph of J_tilde (pattern of U + U^T), each cut
+// by BFS distances from two pseudo-peripheral vertices (the half closer to
+// the first one goes left).  Every leaf but the last holds exactly R vertices,
+// in increasing original index.  Returns perm (new -> old).
+std::vector<int32_t> block_partition(const Csr& U, int32_t R);
+
+// Strict upper triangle of P J P^T for the permutation perm (new -> old) of
+// the skew matrix whose strict upper triangle is U (values u_ij, lower -u_ij).
+Csr permute_skew_upper(const Csr& U, const std::vector<int32_t>& perm);
+
+// Number of upper pairs (i, j) of U with i and j in different R-blocks.
+int64_t count_cross_pairs(const Csr& U, int32_t R);
+
 }  // namespace asss

@@ -618,7 +618,8 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
 
 template <typename T, int NR, int KF>
 __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __restrict__ rhs,
-                                                 int64_t ldr, const T* __restrict__ Q,
+                                                 int64_t ldr, const int32_t* __restrict__ perm,
+                                                 const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double tol,
                                                  int maxit, int fixed, double* partials,
                                                  unsigned* ticket) {
@@ -632,9 +633,10 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
   const int k = L.k;
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
     double b[NR];
+    const int64_t src = perm ? (int64_t)perm[i] : i;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-      b[c] = c < L.nr ? rhs[(int64_t)c * ldr + i] : 0.0;
+      b[c] = c < L.nr ? rhs[(int64_t)c * ldr + src] : 0.0;
       buf.w[1][i * NR + c] = (T)b[c];
       buf.w[0][i * NR + c] = T(0);
       buf.w[2][i * NR + c] = T(0);
@@ -862,14 +864,15 @@ static inline int pick_kf(int k, int nr) {
 }
 
 template <typename T, int NR>
-void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const T* Q, MrsBufs<T>& buf,
-              MrsState* st, double tol, int maxit, int fixed, Reducer& red, hipStream_t s) {
+void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const int32_t* perm, const T* Q,
+              MrsBufs<T>& buf, MrsState* st, double tol, int maxit, int fixed, Reducer& red,
+              hipStream_t s) {
   int groups = (int)std::min<int64_t>((L.n + WG - 1) / WG, 1024);
   groups = std::min(groups, red.max_groups);
   const int kf = pick_kf(L.k, NR);
 #define ASSS_INIT(KF)                                                                              \
-  hipLaunchKernelGGL((k_mrs_init<T, NR, KF>), dim3(groups), dim3(WG), 0, s, L, rhs, ldr, Q, buf,   \
-                     st, tol, maxit, fixed, red.partials, red.tickets + 0)
+  hipLaunchKernelGGL((k_mrs_init<T, NR, KF>), dim3(groups), dim3(WG), 0, s, L, rhs, ldr, perm, Q,   \
+                     buf, st, tol, maxit, fixed, red.partials, red.tickets + 0)
   switch (kf) {
     case 0: ASSS_INIT(0); break;
     case 8: ASSS_INIT(8); break;
@@ -931,21 +934,41 @@ void mrs_make_y1(const MrsLaunch& L, const T* Q, MrsBufs<T>& buf, const MrsState
 }
 
 template <typename T, int NR>
-__global__ void k_mrs_output(int64_t n, int nr, MrsBufs<T> buf, double* __restrict__ out, int64_t ldo) {
-  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
-    for (int c = 0; c < nr; ++c) out[(int64_t)c * ldo + i] = (double)buf.x[i * NR + c];
+__global__ void k_mrs_output(int64_t n, int nr, MrsBufs<T> buf, const int32_t* __restrict__ perm,
+                             double* __restrict__ out, int64_t ldo) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    const int64_t dst = perm ? (int64_t)perm[i] : i;
+    for (int c = 0; c < nr; ++c) out[(int64_t)c * ldo + dst] = (double)buf.x[i * NR + c];
+  }
 }
 template <typename T, int NR>
-void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, double* out, int64_t ldo, hipStream_t s) {
-  hipLaunchKernelGGL((k_mrs_output<T, NR>), grid_for(n), dim3(WG), 0, s, n, nr, buf, out, ldo);
+void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, const int32_t* perm, double* out, int64_t ldo,
+                hipStream_t s) {
+  hipLaunchKernelGGL((k_mrs_output<T, NR>), grid_for(n), dim3(WG), 0, s, n, nr, buf, perm, out, ldo);
+}
+
+__global__ void k_permute_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
+                                 double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[i] = x[perm[i]];
+}
+__global__ void k_permute_scatter(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
+                                  double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[perm[i]] = x[i];
+}
+void permute_gather(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_gather, grid_for(n), dim3(WG), 0, s, n, perm, x, y);
+}
+void permute_scatter(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_scatter, grid_for(n), dim3(WG), 0, s, n, perm, x, y);
 }
 
 #define ASSS_MRS_INST(T, NR)                                                                       \
-  template void mrs_init<T, NR>(const MrsLaunch&, const double*, int64_t, const T*, MrsBufs<T>&,   \
-                                MrsState*, double, int, int, Reducer&, hipStream_t);               \
+  template void mrs_init<T, NR>(const MrsLaunch&, const double*, int64_t, const int32_t*, const T*, \
+                                MrsBufs<T>&, MrsState*, double, int, int, Reducer&, hipStream_t);  \
   template void mrs_iter<T, NR>(const MrsLaunch&, const DSkew<T>&, const T*, MrsBufs<T>&,          \
                                 MrsState*, Reducer&, hipStream_t);                                 \
-  template void mrs_output<T, NR>(int64_t, int, const MrsBufs<T>&, double*, int64_t, hipStream_t); \
+  template void mrs_output<T, NR>(int64_t, int, const MrsBufs<T>&, const int32_t*, double*, int64_t, \
+                                  hipStream_t);                                                    \
   template void mrs_make_y1<T, NR>(const MrsLaunch&, const T*, MrsBufs<T>&, const MrsState*, hipStream_t);
 ASSS_MRS_INST(double, 1)
 ASSS_MRS_INST(float, 1)

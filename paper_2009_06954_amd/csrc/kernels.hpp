@@ -140,9 +140,11 @@ struct MrsLaunch {
 
 // Initialise: w1 = rhs (col c at rhs + c * ldr), zero the other buffers,
 // r0 = ||rhs_c||, d = Q^T q_1, c = S_k d.
+// perm (new -> old, may be null): row i of the inner system is row perm[i] of rhs.
 template <typename T, int NR>
-void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const T* Q, MrsBufs<T>& buf,
-              MrsState* st, double tol, int maxit, int fixed, Reducer& red, hipStream_t s);
+void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const int32_t* perm, const T* Q,
+              MrsBufs<T>& buf, MrsState* st, double tol, int maxit, int fixed, Reducer& red,
+              hipStream_t s);
 
 // One iteration of App. B (or the final deferred update once converged, or
 // nothing once done), fused with the skew operator and the deflation.
@@ -156,6 +158,11 @@ void mrs_make_y1(const MrsLaunch& L, const T* Q, MrsBufs<T>& buf, const MrsState
 
 // Copy the inner solution out: out (FP64, column c at out + c * ldo) = x.
 template <typename T, int NR>
-void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, double* out, int64_t ldo, hipStream_t s);
+void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, const int32_t* perm, double* out, int64_t ldo,
+                hipStream_t s);
+
+// y[i] = x[perm[i]] (gather) and y[perm[i]] = x[i] (scatter), FP64
+void permute_gather(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s);
+void permute_scatter(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s);
 
 }  // namespace asss

@@ -342,3 +342,30 @@ def test_deflation_forms(mode):
     lo, _ = O.solve_adjoint(st, g, O.SolveOptions(tol=1e-12))
     lam, inf = h.solve_adjoint(_cuda(g), tol=1e-12)
     assert inf["status"] == "OK" and _rel(_np(lam), lo) <= 1e-9
+
+
+def test_block_reordering_is_invisible():
+    """The inner system may run in a block order (a symmetric permutation of
+    J_tilde); inner solves, P^-1, the exported Q and full solves must not
+    depend on it beyond rounding."""
+    asss = _lib()
+    w = W.config(0, m=40)
+    st = O.setup(w.A, O.SetupOptions(k=6))
+    hn = asss.setup(w.A, k=6, reorder="none", row_block=64)
+    hb = asss.setup(w.A, k=6, reorder="blocks", row_block=64)
+    ib, inn = hb.info(), hn.info()
+    assert ib["reordered"] == 1 and inn["reordered"] == 0
+    assert ib["cross_pairs_used"] < inn["cross_pairs_used"]
+    print(f"[reorder] cross pairs {inn['cross_pairs_used']} -> {ib['cross_pairs_used']}, "
+          f"part-a {inn['sell_entries_a']} -> {ib['sell_entries_a']}, part-b {inn['sell_entries_b']} -> {ib['sell_entries_b']}")
+    assert _rel(hb.array("Q").reshape(6, -1).T, st.Q) <= 1e-10
+    v = np.random.default_rng(31).standard_normal(w.A.shape[0])
+    for op, ref in (("skew", st.prec.jtilde(v)), ("mrs", O.mrs(1.0, st.prec.jbar, v, 20, 0.0, 20)[0])):
+        kw = {"fixed_inner_steps": 20} if op == "mrs" else {}
+        ob, _ = hb.apply(op, _cuda(v), **kw)
+        on, _ = hn.apply(op, _cuda(v), **kw)
+        assert _rel(_np(ob), _np(on)) <= 1e-12
+        assert _rel(_np(ob), ref) <= 1e-10
+    xo, _ = O.solve(st, w.b, O.SolveOptions(tol=1e-12))
+    xb, ib2 = hb.solve(_cuda(w.b), tol=1e-12)
+    assert ib2["status"] == "OK" and _rel(_np(xb), xo) <= 1e-10
