@@ -533,15 +533,17 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
         MrsLaunch L = make_launch<double>(h, nc, +1, h->d_Q64, h->d_f64, false);
         mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_perm, h->d_Q64, mb4, h->d_state,
                                 h->opts.x_tol, h->opts.x_maxit, 0, h->red, s);
+        int group_its = -1;
         for (int guard = 0; guard < 1000000; ++guard) {
           for (int c = 0; c < 16; ++c) mrs_iter<double, NRMAX>(L, h->J64, h->d_Q64, mb4, h->d_state, h->red, s);
           HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
           HIPCHK(hipStreamSynchronize(s));
           int32_t st_its, st_status;
-          std::memcpy(&st_its, (char*)h->h_small, 4);
-          std::memcpy(&st_status, (char*)h->h_small + 4, 4);
-          if (st_status == MRS_RUNNING && st_its <= xits && guard > 0)
+          std::memcpy(&st_its, (char*)h->h_small + offsetof(MrsState, its), 4);
+          std::memcpy(&st_status, (char*)h->h_small + offsetof(MrsState, status), 4);
+          if (st_status == MRS_RUNNING && st_its <= group_its)
             throw Error{ASSS_ERR_INTERNAL, "setup mrs made no progress"};
+          group_its = st_its;
           xits = std::max(xits, (int)st_its);
           if (st_status == MRS_DONE) break;
           if (st_status == MRS_CONVERGED) {
