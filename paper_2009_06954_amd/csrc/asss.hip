@@ -153,6 +153,8 @@ struct asss_handle_s {
   float* d_Q32 = nullptr;
   double* d_Qs64 = nullptr;   // sliced copies for the inner iteration kernel
   float* d_Qs32 = nullptr;
+  double* d_G64 = nullptr;    // Q_k^T Q_k of the FP64 and of the FP32 copy (k x k)
+  double* d_G32 = nullptr;
   double* d_alpha = nullptr;
   double* d_f64 = nullptr;    // Lanczos residual f = J_tilde q_k - alpha_{k-1} q_{k-1}
   float* d_f32 = nullptr;
@@ -227,6 +229,7 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f
   L.qk1 = (h->k_eff >= 2) ? (const void*)(Q + (int64_t)(h->k_eff - 2) * h->n) : nullptr;
   L.alpha_last = (h->k_eff >= 2) ? h->alpha[h->k_eff - 2] : 0.0;
   L.Qs = std::is_same<T, float>::value ? (const void*)h->d_Qs32 : (const void*)h->d_Qs64;
+  L.gram = std::is_same<T, float>::value ? h->d_G32 : h->d_G64;
   return L;
 }
 
@@ -488,15 +491,23 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     skew_spmv<double>(h->J64, h->d_Q64 + (int64_t)(keff - 1) * n, h->d_f64, s);
     if (keff >= 2) axpby(n, -alpha[keff - 2], h->d_Q64 + (int64_t)(keff - 2) * n, 1.0, h->d_f64, s);
     cast_d2f(n, h->d_f64, h->d_f32, s);
-    // loss of orthogonality of Q_k decides the deflation form
-    double err = 0.0;
+    // Gram matrices G = Q_k^T Q_k of both stored copies (column c of G at
+    // G + c k; G is symmetric bit for bit, the products and their order being
+    // the same); the FP64 one's distance from I decides the deflation form
+    h->d_G64 = h->ar.alloc<double>((int64_t)keff * keff);
+    h->d_G32 = h->ar.alloc<double>((int64_t)keff * keff);
     for (int c = 0; c < keff; ++c) {
-      gemm_tn<double, double>(n, keff, h->d_Q64, n, h->d_Q64 + (int64_t)c * n, 1, h->d_small, nullptr,
-                              h->red, 2, s);
-      HIPCHK(hipMemcpyAsync(h->h_small, h->d_small, keff * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int l = 0; l < keff; ++l) err = std::max(err, std::fabs(h->h_small[l] - (l == c ? 1.0 : 0.0)));
+      gemm_tn<double, double>(n, keff, h->d_Q64, n, h->d_Q64 + (int64_t)c * n, 1, h->d_G64 + (int64_t)c * keff,
+                              nullptr, h->red, 2, s);
+      gemm_tn<float, float>(n, keff, h->d_Q32, n, h->d_Q32 + (int64_t)c * n, 1, h->d_G32 + (int64_t)c * keff,
+                            nullptr, h->red, 2, s);
     }
+    std::vector<double> g64((size_t)keff * keff);
+    HIPCHK(hipMemcpyAsync(g64.data(), h->d_G64, g64.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double err = 0.0;
+    for (int c = 0; c < keff; ++c)
+      for (int l = 0; l < keff; ++l) err = std::max(err, std::fabs(g64[(size_t)c * keff + l] - (l == c ? 1.0 : 0.0)));
     h->orth_err = err;
     h->defl_rec = (h->opts.deflation == 2) && err <= kRecurrenceOrthTol;
   }

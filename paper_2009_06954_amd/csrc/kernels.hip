@@ -81,19 +81,45 @@ __device__ __forceinline__ void reset_ticket(unsigned* ticket) {
   if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// In the last workgroup: res[j] = sum over groups g (in order of a fixed
-// thread/group assignment) of partials[g * stride + j], j < NV (NV >= nvals).
+// Partials in column layout: value j of workgroup g at partials[j * ngroups + g],
+// so that the last workgroup reads each value's partials with coalesced loads.
 template <int NV>
-__device__ void final_reduce(const double* partials, int ngroups, int stride, int nvals,
-                             double* lds, double* res) {
+__device__ __forceinline__ void publish_partials(double* partials, const double* res) {
+  for (int j = threadIdx.x; j < NV; j += WG)
+    store_partial(partials + (int64_t)j * gridDim.x + blockIdx.x, res[j]);
+}
+
+// In the last workgroup: res[j] = sum over groups g of partials[j * ngroups + g].
+// Thread t adds groups t, t + WG, t + 2 WG, ... in that order, then the
+// workgroup reduction runs in its fixed order, so the result does not depend
+// on timing.  The atomic loads stay in program order, so all loads of a batch
+// of B groups are written before any of their sums: one memory round trip per
+// batch instead of one per value.
+template <int NV>
+__device__ __forceinline__ void final_reduce(const double* partials, int ngroups, double* lds,
+                                             double* res) {
+  constexpr int B = NV <= 20 ? 2 : 1;
   double acc[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-  for (int g = threadIdx.x; g < ngroups; g += WG) {
-    const double* pg = partials + (int64_t)g * stride;
+  int g = threadIdx.x;
+  for (; g + (B - 1) * WG < ngroups; g += B * WG) {
+    double v[B][NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j)
-      if (j < nvals) acc[j] += load_partial(pg + j);
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) v[b][j] = load_partial(partials + (int64_t)j * ngroups + g + b * WG);
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) acc[j] += v[b][j];
+  }
+  for (; g < ngroups; g += WG) {
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = load_partial(partials + (int64_t)j * ngroups + g);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] += v[j];
   }
   wg_reduce<NV>(acc, lds, res);
 }
@@ -105,8 +131,11 @@ __device__ __forceinline__ double strided_sum(const double* P, int g0, int ng, i
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int g = g0;
   for (; g + 7 * step < ng; g += 8 * step) {
+    double v[8];  // all eight loads in flight before the sums (see final_reduce)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += load_partial(P + (int64_t)(g + u * step) * stride + o);
+    for (int u = 0; u < 8; ++u) v[u] = load_partial(P + (int64_t)(g + u * step) * stride + o);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
   for (; g < ng; g += step) a[0] += load_partial(P + (int64_t)g * stride + o);
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
@@ -172,7 +201,8 @@ void spmv(const DCsr& M, const double* x, double* y, const double* rs, const dou
 
 // ---------------------------------------------------------------------------
 // Sliced skew SpMV: the part shared by the standalone operator and the mrs step.
-// One workgroup per block of R rows; wave w handles slices w, w+4, ... of it.
+// One workgroup per block of R rows; wave w handles slices w, w + 4, ... of it,
+// P slices at a time (P = 2 for one column: twice the loads in flight per wave).
 // w_src(jl) reads the gathered vector at local row jl (LDS or global).
 // Accumulates the block's results into acc_lds[il * NR + c].
 // ---------------------------------------------------------------------------
@@ -182,74 +212,99 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
                                                 const T* __restrict__ wg, const T* w_lds,
                                                 T* acc_lds) {
   // Each round handles up to U in-block entries and U off-block entries of
-  // every row of the slice; all of a round's loads are issued before any of
+  // every row of the P slices; all of a round's loads are issued before any of
   // its arithmetic (the widths are wave-uniform, so the guards do not diverge).
-  constexpr int U = 8;
+  constexpr int P = (NR == 1) ? 2 : 1;
+  constexpr int U = (NR == 1) ? 4 : 8;
+  constexpr int NW = WG / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nsl = (nrow + 63) >> 6;
   const int64_t s0 = row0 >> 6;
-  for (int sl = wave; sl < nsl; sl += WG / 64) {
-    const int64_t s = s0 + sl;
-    const int il = sl * 64 + lane;
-    const bool valid = il < nrow;
-    const int wa = __builtin_amdgcn_readfirstlane(J.a_width[s]);
-    const int wb = __builtin_amdgcn_readfirstlane(J.b_width[s]);
-    const uint16_t* __restrict__ acol = J.a_col + J.a_off[s] + lane;
-    const T* __restrict__ aval = J.a_val + J.a_off[s] + lane;
-    const int32_t* __restrict__ bcol = J.b_col + J.b_off[s] + lane;
-    const T* __restrict__ bval = J.b_val + J.b_off[s] + lane;
-    T acc[NR], wi[NR];
+  for (int sl0 = wave; sl0 < nsl; sl0 += P * NW) {
+    int wa[P], wb[P], il[P];
+    bool valid[P];
+    const uint16_t* __restrict__ acol[P];
+    const T* __restrict__ aval[P];
+    const int32_t* __restrict__ bcol[P];
+    const T* __restrict__ bval[P];
+    T acc[P][NR], wi[P][NR];
+    int wmax = 0;
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-      acc[c] = T(0);
-      wi[c] = valid ? (STAGE ? w_lds[il * NR + c] : wg[(row0 + il) * NR + c]) : T(0);
-    }
-    const int rounds = (max(wa, wb) + U - 1) / U;
-    for (int r = 0; r < rounds; ++r) {
-      const int la = r * U, lb = r * U;
-      int jl[U];
-      T va[U];
-      int32_t jb[U];
-      T vb[U];
+    for (int p = 0; p < P; ++p) {
+      const int sl = sl0 + p * NW;
+      const bool has = sl < nsl;  // wave-uniform
+      const int64_t s = s0 + (has ? sl : 0);
+      wa[p] = has ? __builtin_amdgcn_readfirstlane(J.a_width[s]) : 0;
+      wb[p] = has ? __builtin_amdgcn_readfirstlane(J.b_width[s]) : 0;
+      wmax = max(wmax, max(wa[p], wb[p]));
+      il[p] = sl * 64 + lane;
+      valid[p] = has && il[p] < nrow;
+      acol[p] = J.a_col + J.a_off[s] + lane;
+      aval[p] = J.a_val + J.a_off[s] + lane;
+      bcol[p] = J.b_col + J.b_off[s] + lane;
+      bval[p] = J.b_val + J.b_off[s] + lane;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (la + u < wa) {
-          jl[u] = acol[(la + u) * 64];
-          va[u] = aval[(la + u) * 64];
-        }
-        if (lb + u < wb) {
-          jb[u] = bcol[(lb + u) * 64];
-          vb[u] = bval[(lb + u) * 64];
-        }
+      for (int c = 0; c < NR; ++c) {
+        acc[p][c] = T(0);
+        wi[p][c] = valid[p] ? (STAGE ? w_lds[il[p] * NR + c] : wg[(row0 + il[p]) * NR + c]) : T(0);
       }
-      T wj[U][NR];
+    }
+    const int rounds = (wmax + U - 1) / U;
+    for (int r = 0; r < rounds; ++r) {
+      const int l0 = r * U;
+      int jl[P][U];
+      T va[P][U];
+      int32_t jb[P][U];
+      T vb[P][U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (lb + u < wb) {
+      for (int p = 0; p < P; ++p)
 #pragma unroll
-          for (int c = 0; c < NR; ++c) wj[u][c] = wg[(int64_t)jb[u] * NR + c];
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (la + u < wa) {
-#pragma unroll
-          for (int c = 0; c < NR; ++c) {
-            const T w = STAGE ? w_lds[jl[u] * NR + c] : wg[(row0 + jl[u]) * NR + c];
-            acc[c] += va[u] * w;
-            if (valid) atomicAdd(&acc_lds[jl[u] * NR + c], -va[u] * wi[c]);
+        for (int u = 0; u < U; ++u) {
+          if (l0 + u < wa[p]) {
+            jl[p][u] = acol[p][(l0 + u) * 64];
+            va[p][u] = aval[p][(l0 + u) * 64];
+          }
+          if (l0 + u < wb[p]) {
+            jb[p][u] = bcol[p][(l0 + u) * 64];
+            vb[p][u] = bval[p][(l0 + u) * 64];
           }
         }
+      T wj[P][U][NR];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (lb + u < wb) {
+      for (int p = 0; p < P; ++p)
 #pragma unroll
-          for (int c = 0; c < NR; ++c) acc[c] += vb[u] * wj[u][c];
-        }
+        for (int u = 0; u < U; ++u)
+          if (l0 + u < wb[p]) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) wj[p][u][c] = wg[(int64_t)jb[p][u] * NR + c];
+          }
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (l0 + u < wa[p]) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+              const T w = STAGE ? w_lds[jl[p][u] * NR + c] : wg[(row0 + jl[p][u]) * NR + c];
+              acc[p][c] += va[p][u] * w;
+              if (valid[p]) atomicAdd(&acc_lds[jl[p][u] * NR + c], -va[p][u] * wi[p][c]);
+            }
+          }
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (l0 + u < wb[p]) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[p][c] += vb[p][u] * wj[p][u][c];
+          }
     }
-    if (valid) {
 #pragma unroll
-      for (int c = 0; c < NR; ++c) atomicAdd(&acc_lds[il * NR + c], acc[c]);
-    }
+    for (int p = 0; p < P; ++p)
+      if (valid[p]) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) atomicAdd(&acc_lds[il[p] * NR + c], acc[p][c]);
+      }
   }
 }
 
@@ -415,9 +470,9 @@ __global__ __launch_bounds__(WG) void k_gemv_acc_norm(int64_t n, int kt, const d
     acc[0] += v * v;
   }
   wg_reduce<1>(acc, lds, res);
-  if (threadIdx.x == 0) store_partial(partials + blockIdx.x, res[0]);
+  publish_partials<1>(partials, res);
   if (!arrive_last(ticket, gridDim.x)) return;
-  final_reduce<1>(partials, gridDim.x, 1, 1, lds, res);
+  final_reduce<1>(partials, gridDim.x, lds, res);
   if (threadIdx.x == 0) *nrm2 = res[0];
   reset_ticket(ticket);
 }
@@ -541,16 +596,49 @@ __device__ __forceinline__ double sk_times(const double* alpha, const double* d,
   return r;
 }
 
-template <int NR, int KF, bool REC>
-__device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const double* alpha,
-                                  int t, int sign) {
-  // res: [KF+1][NR] with row 0 = ||q_new||^2, rows 1..k = Q^T q_new (explicit
-  // deflation), or [2][NR] with row 1 = f^T q_t (recurrence deflation)
+// What the last workgroup of an iteration needs besides the reduced values,
+// copied to LDS by every workgroup at the start of the launch (the copies'
+// latency hides behind the launch's main work instead of adding to the serial
+// tail of the last workgroup).
+template <int NR, int KF>
+struct MrsTail {
+  static constexpr int KF1 = KF > 0 ? KF : 1;
+  MrsCol col[NR];
+  double cvt[NR][KF1];   // deflation coefficients c as applied (rounded to T)
+  double alpha[KF1];     // skew-Lanczos coefficients
+  double gram[KF1 * KF1];
+};
+
+template <typename T, int NR, int KF>
+__device__ __forceinline__ void mrs_tail_prefetch(MrsTail<NR, KF>& tl, const MrsState* st, const MrsLaunch& L,
+                                                  bool rec) {
+  const int k = L.k;
+  for (int e = threadIdx.x; e < NR * (int)sizeof(MrsCol) / 8; e += WG)
+    reinterpret_cast<double*>(tl.col)[e] = reinterpret_cast<const double*>(st->col)[e];
+  if (KF > 0 && !rec) {
+    for (int e = threadIdx.x; e < NR * k; e += WG) {
+      const int cc = e / k, l = e % k;
+      tl.cvt[cc][l] = (double)(T)st->cvec[cc * KMAX + l];
+    }
+    for (int e = threadIdx.x; e < k - 1; e += WG) tl.alpha[e] = L.alpha_dev[e];
+    for (int e = threadIdx.x; e < k * k; e += WG) tl.gram[e] = L.gram[e];
+  }
+}
+
+template <typename T, int NR, int KF, bool REC>
+__device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const MrsTail<NR, KF>& tl,
+                                  int fixed, int maxit, double tol, int t, int sign) {
+  // res: [KF+1][NR] with row 0 = ||w_new||^2 and rows 1..k = Q^T a, where
+  // a = sign u + beta q_old is w_new before the deflation term (explicit
+  // deflation), or [2][NR] with row 1 = f^T q_t (recurrence deflation).
+  // Explicit: w_new = a - sign Q c with c the deflation coefficients as applied
+  // (rounded to T), so Q^T w_new = Q^T a - sign G c, G = Q^T Q.
   __shared__ double dsh[NRMAX][KMAX];
-  __shared__ double s_relmax[NRMAX];
+  __shared__ double s_relmax[NRMAX], s_nu[NRMAX];
+  __shared__ int s_live[NRMAX];
   const int c = threadIdx.x;
   if (c < NR) {
-    MrsCol col = st->col[c];
+    MrsCol col = tl.col[c];
     double rel = 0.0;
     if (col.live) {
       const double beta = sqrt(res[c]);
@@ -581,24 +669,31 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
         col.rb_old = col.rb;
         col.ra = ra_new;
         col.rb = rb_new;
-      } else {
-        for (int l = 0; l < k; ++l) dsh[c][l] = res[(1 + l) * NR + c] / col.nu;
       }
     } else {
       col.pend_theta = 1.0;
       col.pend_delta = 0.0;
       col.pend_coef = 0.0;
       col.has_pending = 1;
-      for (int l = 0; l < k; ++l) dsh[c][l] = 0.0;
     }
     s_relmax[c] = rel;
+    s_nu[c] = col.nu;
+    s_live[c] = col.live;
     st->col[c] = col;
   }
   __syncthreads();
   if (!REC) {
+    // d = Q^T q_new = (Q^T a - sign G c) / nu_new
+    for (int e = threadIdx.x; e < NR * k; e += WG) {
+      const int cc = e / k, l = e % k;
+      double gc = 0.0;
+      for (int m = 0; m < k; ++m) gc += tl.gram[l * k + m] * tl.cvt[cc][m];
+      dsh[cc][l] = s_live[cc] ? (res[(1 + l) * NR + cc] - (double)sign * gc) / s_nu[cc] : 0.0;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < NR * k; e += WG) {
       int cc = e / k, l = e % k;
-      st->cvec[cc * KMAX + l] = sk_times(alpha, dsh[cc], k, l);
+      st->cvec[cc * KMAX + l] = sk_times(tl.alpha, dsh[cc], k, l);
     }
   }
   if (threadIdx.x == 0) {
@@ -607,9 +702,9 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
     st->relres_max = rmax;
     st->its = t;
     int status = MRS_RUNNING;
-    if (st->fixed > 0) {
-      if (t >= st->fixed) status = MRS_CONVERGED;
-    } else if (rmax < st->tol || t >= st->maxit) {
+    if (fixed > 0) {
+      if (t >= fixed) status = MRS_CONVERGED;
+    } else if (rmax < tol || t >= maxit) {
       status = MRS_CONVERGED;
     }
     st->status = status;
@@ -655,9 +750,9 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
     }
   }
   wg_reduce<NV>(acc, lds, res);
-  for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)blockIdx.x * NV + j, res[j]);
+  publish_partials<NV>(partials, res);
   if (!arrive_last(ticket, gridDim.x)) return;
-  final_reduce<NV>(partials, gridDim.x, NV, NV, lds, res);
+  final_reduce<NV>(partials, gridDim.x, lds, res);
   __shared__ double dsh[NRMAX][KMAX];
   __shared__ int s_any;
   if (threadIdx.x == 0) s_any = 0;
@@ -720,37 +815,37 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   T* w_lds = acc_lds + (size_t)J.R * NR;
   __shared__ double lds[(WG / 64) * NV];
   __shared__ double res[NV];
-  __shared__ int s_status, s_t, s_pend;
-  __shared__ double s_inv_nu[NR], s_inv_nu_old[NR], s_beta_prev[NR];
-  __shared__ double s_pend_delta[NR], s_inv_pend_theta[NR], s_pend_coef[NR];
-  __shared__ T s_cv[NR][KF > 0 ? KF : 1];
-  __shared__ double s_cy[NR], s_cq[NR];
+  // The state was written by the previous launch and is not written before
+  // the end of this one: every thread reads it with uniform (scalar) loads, so
+  // the per-column coefficients and the deflation coefficients c live in
+  // scalar registers rather than in LDS or vector registers.
   const int k = L.k;
-  if (threadIdx.x == 0) {
-    s_status = st->status;
-    s_t = st->its + 1;
-    s_pend = st->col[0].has_pending;
-  }
-  if (threadIdx.x < NR) {
-    const MrsCol& col = st->col[threadIdx.x];
-    s_inv_nu[threadIdx.x] = 1.0 / col.nu;
-    s_inv_nu_old[threadIdx.x] = 1.0 / col.nu_old;
-    s_beta_prev[threadIdx.x] = col.beta_prev;
-    s_pend_delta[threadIdx.x] = col.pend_delta;
-    s_inv_pend_theta[threadIdx.x] = 1.0 / col.pend_theta;
-    s_pend_coef[threadIdx.x] = col.pend_coef;
-    s_cy[threadIdx.x] = col.ra;
-    s_cq[threadIdx.x] = col.rb * L.alpha_last;
-  }
-  constexpr int KF1 = KF > 0 ? KF : 1;
-  for (int e = threadIdx.x; e < NR * KF; e += WG) {
-    int c = e / KF1, l = e % KF1;
-    s_cv[c][l] = (l < k) ? (T)st->cvec[c * KMAX + l] : T(0);
-  }
-  __syncthreads();
-  const int status = s_status;
+  const int status = st->status;
   if (status == MRS_DONE) return;
-  const int t = s_t;
+  const int t = st->its + 1;
+  const bool pend = st->col[0].has_pending != 0;
+  constexpr int KF1 = KF > 0 ? KF : 1;
+  T inv_nu[NR], inv_nu_old[NR], beta_prev[NR], pend_delta[NR], inv_pend_theta[NR], pend_coef[NR];
+  T cy[NR], cq[NR];
+  T cv[NR][KF1];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    const MrsCol& col = st->col[c];
+    inv_nu[c] = (T)(1.0 / col.nu);
+    inv_nu_old[c] = (T)(1.0 / col.nu_old);
+    beta_prev[c] = (T)col.beta_prev;
+    pend_delta[c] = (T)col.pend_delta;
+    inv_pend_theta[c] = (T)(1.0 / col.pend_theta);
+    pend_coef[c] = (T)col.pend_coef;
+    cy[c] = (T)col.ra;
+    cq[c] = (T)(col.rb * L.alpha_last);
+#pragma unroll
+    for (int l = 0; l < KF1; ++l) cv[c][l] = (KF > 0 && l < k) ? (T)st->cvec[c * KMAX + l] : T(0);
+  }
+  const int st_fixed = st->fixed, st_maxit = st->maxit;
+  const double st_tol = st->tol;
+  __shared__ MrsTail<NR, KF> tail;
+  if (status == MRS_RUNNING) mrs_tail_prefetch<T, NR, KF>(tail, st, L, REC);
   const int64_t n = L.n;
   const int64_t row0 = (int64_t)blockIdx.x * J.R;
   const int nrow = (int)min((int64_t)J.R, n - row0);
@@ -759,7 +854,6 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   T* __restrict__ wnew = buf.w[(t + 1) % 3];
   T* __restrict__ pb = buf.p[(t + 1) % 2];
   T* __restrict__ x = buf.x;
-  const bool pend = s_pend != 0;
 
   if (status == MRS_CONVERGED) {
     // last deferred update: p_T and x += g_T c_T p_T
@@ -768,9 +862,9 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
         const int64_t i = row0 + il;
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-          const T qold = wold[i * NR + c] * (T)s_inv_nu_old[c];
-          const T p = (qold - (T)s_pend_delta[c] * pb[i * NR + c]) * (T)s_inv_pend_theta[c];
-          x[i * NR + c] += (T)s_pend_coef[c] * p;
+          const T qold = wold[i * NR + c] * inv_nu_old[c];
+          const T p = (qold - pend_delta[c] * pb[i * NR + c]) * inv_pend_theta[c];
+          x[i * NR + c] += pend_coef[c] * p;
         }
       }
     }
@@ -799,58 +893,64 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   bool use_y1 = false;
   if (REC) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) use_y1 |= (s_cy[c] != 0.0);
+    for (int c = 0; c < NR; ++c) use_y1 |= (cy[c] != T(0));
   }
   for (int il = threadIdx.x; il < nrow; il += WG) {
     const int64_t i = row0 + il;
     T defl[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) defl[c] = T(0);
-    T qrow[KF > 0 ? KF : 1];
     T fi = T(0);
     if (REC) {
       const T qk = qk1 ? qk1[i] : T(0);
       fi = fvec[i];
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
-        defl[c] = (T)s_cq[c] * qk;
-        if (use_y1) defl[c] += (T)s_cy[c] * y1[i * NR + c];
+        defl[c] = cq[c] * qk;
+        if (use_y1) defl[c] += cy[c] * y1[i * NR + c];
       }
-    } else {
+    }
+    T u[NR], qold[NR], a[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      u[c] = acc_lds[il * NR + c] * inv_nu[c];
+      qold[c] = wold[i * NR + c] * inv_nu_old[c];
+      a[c] = sgn * u[c] + beta_prev[c] * qold[c];
+    }
+    if (!REC) {
+      // Q row i streams once: deflation term and Q^T a together
       const T* __restrict__ qs = reinterpret_cast<const T*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
 #pragma unroll
       for (int l = 0; l < KF; ++l) {
-        qrow[l] = (l < k) ? qs[l * 64] : T(0);
+        const T q = (l < k) ? qs[l * 64] : T(0);
 #pragma unroll
-        for (int c = 0; c < NR; ++c) defl[c] += qrow[l] * s_cv[c][l];
+        for (int c = 0; c < NR; ++c) {
+          defl[c] += q * cv[c][l];
+          acc[(1 + l) * NR + c] += (double)q * (double)a[c];
+        }
       }
     }
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-      const T u = acc_lds[il * NR + c] * (T)s_inv_nu[c];
-      const T qold = wold[i * NR + c] * (T)s_inv_nu_old[c];
-      const T qn = sgn * (u - defl[c]) + (T)s_beta_prev[c] * qold;
+      const T qn = sgn * (u[c] - defl[c]) + beta_prev[c] * qold[c];
       wnew[i * NR + c] = qn;
       acc[c] += (double)qn * (double)qn;
       if (REC) {
-        const T qcur = (STAGE ? w_lds[il * NR + c] : wcur[i * NR + c]) * (T)s_inv_nu[c];
+        const T qcur = (STAGE ? w_lds[il * NR + c] : wcur[i * NR + c]) * inv_nu[c];
         acc[NR + c] += (double)fi * (double)qcur;
-      } else {
-#pragma unroll
-        for (int l = 0; l < KF; ++l) acc[(1 + l) * NR + c] += (double)qrow[l] * (double)qn;
       }
       if (pend) {
-        const T p = (qold - (T)s_pend_delta[c] * pb[i * NR + c]) * (T)s_inv_pend_theta[c];
+        const T p = (qold[c] - pend_delta[c] * pb[i * NR + c]) * inv_pend_theta[c];
         pb[i * NR + c] = p;
-        x[i * NR + c] += (T)s_pend_coef[c] * p;
+        x[i * NR + c] += pend_coef[c] * p;
       }
     }
   }
   wg_reduce<NV>(acc, lds, res);
-  for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)blockIdx.x * NV + j, res[j]);
+  publish_partials<NV>(partials, res);
   if (!arrive_last(ticket, gridDim.x)) return;
-  final_reduce<NV>(partials, gridDim.x, NV, NV, lds, res);
-  mrs_scalar_update<NR, KF, REC>(st, res, k, L.alpha_dev, t, L.sign);
+  final_reduce<NV>(partials, gridDim.x, lds, res);
+  mrs_scalar_update<T, NR, KF, REC>(st, res, k, tail, st_fixed, st_maxit, st_tol, t, L.sign);
   reset_ticket(ticket);
 }
 

@@ -49,6 +49,8 @@ struct MrsCol {
   int32_t has_pending, live;
 };
 
+static_assert(sizeof(MrsCol) % 8 == 0, "MrsCol is copied as doubles");
+
 enum { MRS_RUNNING = 0, MRS_CONVERGED = 1, MRS_DONE = 2 };
 
 struct MrsState {
@@ -136,6 +138,9 @@ struct MrsLaunch {
   // Q_k in sliced layout for the iteration kernel: row i, column l at
   // (i / 64) * (k * 64) + l * 64 + i % 64 (each 64-row slice contiguous)
   const void* Qs;
+  // G = Q_k^T Q_k (k x k, FP64) of Q_k as stored in the inner precision: the
+  // iteration kernel forms Q_k^T q_new as Q_k^T a - sign G c (see k_mrs_iter)
+  const double* gram;
 };
 
 // Initialise: w1 = rhs (col c at rhs + c * ldr), zero the other buffers,
