@@ -17,6 +17,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -41,6 +42,22 @@ def mrs_bytes_per_row(nh_per_row: float, k: int, v: int) -> float:
     deflation vectors once (k v), and ten vector streams of v bytes (read q,
     u, q_old, p_old2, x and a second q gather; write q', p, x; re-zero u)."""
     return nh_per_row * (v + 4) + 4 + k * v + 10 * v
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per full inner step from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if it was taken on the kernel source as it is now."""
+    path = os.path.join(ROOT, "profiles", "k_mrs_iter_convdiff3d_128_Pe100_k16_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_2009_06954_amd", "csrc", "kernels.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_src_sha256") != sha or precision not in rec.get("kernels", {}):
+        return None  # counters predate the current kernel
+    return rec["kernels"][precision]["hbm_bytes"]
 
 
 def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, inner_full: int,
@@ -167,17 +184,24 @@ def main():
         return total, infos, err
 
     def roofline(infos, v):
+        # kernel time of every launch (HIP events around each chunk of back-to-back
+        # launches on the solve's stream); bytes only for the full steps (a solve
+        # also launches one deferred-update step and, when its chunk overshoots,
+        # launches that return at once)
         kern_s = sum(i["inner_kernel_s"] for i in infos)
         launches = sum(i["inner_launches"] for i in infos)
+        steps = sum(i["inner_its_total"] for i in infos)
         avg = kern_s / max(1, launches)
         bpr = mrs_bytes_per_row(hi["nh"] / n, hi["k_eff"], v)
-        per_launch = bpr * n
-        achieved = per_launch / avg / 1e9
+        per_step = bpr * n
+        achieved = per_step * steps / kern_s / 1e9
+        traffic = measured_traffic("fp64" if v == 8 else "fp32")
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per full step (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_mrs_iter (fused inner mrs step)",
-                "bytes_per_launch": int(per_launch), "bytes_per_row": round(bpr, 1),
-                "avg_launch_us": round(avg * 1e6, 2), "launches": launches}
+                "bytes_per_step": int(per_step), "bytes_per_row": round(bpr, 1),
+                "avg_launch_us": round(avg * 1e6, 2), "launches": launches, "full_steps": steps}
 
     total64, inf64, err64 = run(False, args.steps, args.warmup)
     t64 = total64 / args.steps
