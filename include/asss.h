@@ -169,6 +169,34 @@ asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* l
                                  const asss_solve_opts_t* o, asss_info_t* info,
                                  void* hip_stream);
 
+/* ---- Differentiation ----------------------------------------------------
+ * For x = A^-1 b and a scalar loss L(x): dL/db = lambda with A^T lambda =
+ * dL/dx (asss_solve_adjoint), and dL/da_ij = -lambda_i x_j on the stored
+ * entries of A (differentiating A x = b; the transposed solve is the adjoint
+ * of the scheme, Sec. 3 eqs. modified and smw taken by transposition). */
+
+/* Replace the values of A (host CSR, n as at setup) while keeping everything
+ * built from the old values: matching, scaling, S, Omega, J_tilde, Q_k, X, C,
+ * i.e. the preconditioner is frozen and only the outer operator, the true
+ * residual and the adjoint use the new values.  Solves then return
+ * A_new^-1 b to their tolerance (convergence may degrade as A_new drifts from
+ * the matrix the preconditioner was built for).  The caller's entries must
+ * lie in the pattern given at setup (explicit zeros there were dropped; a
+ * zero outside the pattern is ignored, a nonzero outside it is INVALID_ARG;
+ * stored entries the caller omits become zero).  INVALID_CSR / NONFINITE as
+ * for asss_setup.  Synchronizes hip_stream. */
+asss_status_t asss_update_values(asss_handle_t h, const asss_csr_t* A, void* hip_stream);
+
+/* grad_dev[e] = -lambda_dev[i] * x_dev[colind_dev[e]] for every entry e of
+ * row i of the caller's CSR pattern (device arrays: rowptr n+1 int64, colind
+ * nnz int32, lambda, x length n FP64, grad nnz FP64, all owned by the caller).
+ * Row pointers outside [0, nnz] or decreasing, and columns outside [0, n),
+ * are skipped and reported as INVALID_CSR after the kernel (other entries are
+ * written).  Synchronizes hip_stream. */
+asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* rowptr_dev,
+                                  const int32_t* colind_dev, const double* lambda_dev,
+                                  const double* x_dev, double* grad_dev, void* hip_stream);
+
 /* Several systems, each with several right-hand sides: system s has
  * nrhs[s] columns in B_dev[s] / X_dev[s] (device, n_s x nrhs[s], column-major).
  * infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be NULL).

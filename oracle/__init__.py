@@ -18,7 +18,8 @@ split       A_hat = Abar S, D, Omega, J_tilde, negative-diagonal set (Sec. 3)
 lanczos     counter-based start vector and the skew-Lanczos process (Fig. 2)
 mrs         simultaneous minimal residual iterations for (alpha I + K) x = b (App. B)
 precond     deflated operator, combined low-rank term and its SMW application (Sec. 3.2)
-solver      flexible GMRES outer iteration, back-transform, adjoint (Sec. 3, Sec. 4.1)
+solver      flexible GMRES outer iteration, back-transform, adjoint, value
+            gradient of a solve (Sec. 3, Sec. 4.1)
 """
 from .preprocess import (StructurallySingular, ZeroDiagonal, validate_csr,
                          max_product_matching, canonical_scaling, permute_scale)
@@ -27,12 +28,13 @@ from .split import split_ahat
 from .lanczos import splitmix64_uniform, start_vector, skew_lanczos
 from .mrs import mrs
 from .precond import Preconditioner
-from .solver import SolveOptions, SetupOptions, OracleSetup, setup, solve, solve_adjoint
+from .solver import (SolveOptions, SetupOptions, OracleSetup, setup, solve, solve_adjoint,
+                     value_gradient)
 
 __all__ = [
     "StructurallySingular", "ZeroDiagonal", "validate_csr", "max_product_matching",
     "canonical_scaling", "permute_scale", "s_pattern", "build_lls", "solve_lls",
     "skew_symmetrizer", "lls_gradient", "split_ahat", "splitmix64_uniform",
     "start_vector", "skew_lanczos", "mrs", "Preconditioner", "SolveOptions",
-    "SetupOptions", "OracleSetup", "setup", "solve", "solve_adjoint",
+    "SetupOptions", "OracleSetup", "setup", "solve", "solve_adjoint", "value_gradient",
 ]

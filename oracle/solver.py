@@ -256,3 +256,20 @@ def solve_adjoint(st: OracleSetup, g: np.ndarray, o: SolveOptions | None = None)
     l_chk, info = _fgmres(st.op_T, prec, st.rhs_T(g), st.back_T, true_relres, o)
     info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
     return st.back_T(l_chk), info
+
+
+def value_gradient(A, lam: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Derivative of a loss L(x) with respect to the stored values of A, for
+    x = A^-1 b and lam = A^-T dL/dx.
+
+    Differentiating A x = b gives A dx = -dA x, so dL = lam^T dx =
+    -sum_ij lam_i dA_ij x_j: the entry (i, j) gets -lam_i x_j.  Returned in
+    the order of A's CSR storage (the adjoint is the transposed two-level
+    scheme, Sec. 3 eqs. modified and smw taken by transposition)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(A)
+    out = np.empty(A.nnz)
+    for i in range(A.shape[0]):
+        for e in range(A.indptr[i], A.indptr[i + 1]):
+            out[e] = -lam[i] * x[A.indices[e]]
+    return out

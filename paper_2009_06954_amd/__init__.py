@@ -38,7 +38,8 @@ ARRAYS = {"match": (0, np.int32), "Dr": (1, np.float64), "Dc": (2, np.float64),
 
 EXPORTED = ["asss_default_setup_opts", "asss_default_solve_opts", "asss_setup", "asss_solve",
             "asss_solve_adjoint", "asss_solve_batched", "asss_destroy", "asss_last_error",
-            "asss_get_handle_info", "asss_get_array", "asss_apply"]
+            "asss_get_handle_info", "asss_get_array", "asss_apply", "asss_update_values",
+            "asss_value_gradient"]
 
 
 class CsrT(C.Structure):
@@ -114,6 +115,9 @@ def load(path: str = LIB_PATH):
     lib.asss_solve_batched.argtypes = [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                        C.POINTER(SolveOpts), C.POINTER(Info), C.c_void_p]
+    lib.asss_update_values.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_void_p]
+    lib.asss_value_gradient.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
     lib.asss_destroy.argtypes = [C.c_void_p]
     lib.asss_get_handle_info.argtypes = [C.c_void_p, C.POINTER(HandleInfo)]
     lib.asss_get_array.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]
@@ -225,6 +229,32 @@ class Handle:
         _check(load().asss_apply(self._h, OPS[op], C.c_void_p(v.data_ptr()), C.c_void_p(o.data_ptr()),
                                  C.byref(solve_options(**opts)), C.byref(its), _stream(stream)))
         return o, its.value
+
+    def update_values(self, A, stream=None):
+        """Give A new values on the pattern used at setup; the preconditioner
+        stays as built (see asss_update_values)."""
+        n, rp, ci, va = _csr_arrays(A)
+        if n != self.n:
+            raise ValueError(f"expected an n = {self.n} matrix")
+        csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+        _check(load().asss_update_values(self._h, C.byref(csr), _stream(stream)))
+
+    def value_gradient(self, rowptr, colind, lam, x, out=None, stream=None):
+        """grad[e] = -lam[i] x[colind[e]] over the CSR pattern (rowptr int64 and
+        colind int32 CUDA tensors), i.e. dL/dA for x = A^-1 b, A^T lam = dL/dx."""
+        import torch
+        lam, x = self._vec(lam), self._vec(x)
+        if not (rowptr.is_cuda and rowptr.dtype == torch.int64 and rowptr.is_contiguous()
+                and rowptr.numel() == self.n + 1 and colind.is_cuda and colind.dtype == torch.int32
+                and colind.is_contiguous()):
+            raise ValueError("rowptr must be CUDA int64 (n + 1), colind CUDA int32")
+        nnz = colind.numel()
+        g = out if out is not None else torch.empty(nnz, dtype=torch.float64, device=x.device)
+        _check(load().asss_value_gradient(self._h, nnz, C.c_void_p(rowptr.data_ptr()),
+                                          C.c_void_p(colind.data_ptr()), C.c_void_p(lam.data_ptr()),
+                                          C.c_void_p(x.data_ptr()), C.c_void_p(g.data_ptr()),
+                                          _stream(stream)))
+        return g
 
     def info(self) -> dict:
         hi = HandleInfo()

@@ -140,6 +140,7 @@ struct asss_handle_s {
   double setup_host_s = 0, setup_device_s = 0;
   // device data
   DCsr dA, dAt, dAbar, dAbarT, dS, dSt;
+  Csr Apat;  // pattern of A as stored (explicit zeros dropped), for value updates
   int32_t* d_m = nullptr;
   double *d_drp = nullptr, *d_om = nullptr, *d_dc = nullptr;
   DSkew<double> J64;
@@ -938,6 +939,9 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->sell_b = sell.b_entries;
     { LlsSystem dummy; std::swap(L, dummy); }
     // ---- device uploads
+    h->Apat.nrows = h->Apat.ncols = n;
+    h->Apat.ptr = Ah.ptr;
+    h->Apat.col = Ah.col;
     h->dA = upload_csr(h->ar, Ah, s);
     h->dAt = upload_csr(h->ar, transpose(Ah), s);
     h->dAbar = upload_csr(h->ar, Abar, s);
@@ -1013,6 +1017,45 @@ asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* l
     if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
     if (!b_is_finite(h, g_dev, s)) throw Error{ASSS_ERR_NONFINITE, "g has a non-finite entry"};
     return fgmres(h, true, g_dev, lambda_dev, oo, info, s);
+  });
+}
+
+asss_status_t asss_update_values(asss_handle_t h, const asss_csr_t* A, void* hip_stream) {
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (!A) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    Csr Ah = map_values_onto(h->Apat, A->n, A->nnz, A->rowptr, A->colind, A->val);
+    Csr Abar = permute_scale(Ah, h->m, h->Dr, h->Dc);
+    Csr At = transpose(Ah), AbarT = transpose(Abar);
+    const DCsr* dst[4] = {&h->dA, &h->dAt, &h->dAbar, &h->dAbarT};
+    const Csr* src[4] = {&Ah, &At, &Abar, &AbarT};
+    for (int q = 0; q < 4; ++q) {
+      if (src[q]->nnz() != dst[q]->nnz) throw Error{ASSS_ERR_INTERNAL, "stored pattern changed"};
+      HIPCHK(hipMemcpyAsync(dst[q]->val, src[q]->val.data(), src[q]->nnz() * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));  // the host arrays go out of scope
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* rowptr_dev,
+                                  const int32_t* colind_dev, const double* lambda_dev, const double* x_dev,
+                                  double* grad_dev, void* hip_stream) {
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (nnz < 0) throw Error{ASSS_ERR_INVALID_ARG, "nnz must be >= 0"};
+    if (!rowptr_dev || !lambda_dev || !x_dev || (nnz > 0 && (!colind_dev || !grad_dev)))
+      throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+    csr_value_grad(h->n, nnz, rowptr_dev, colind_dev, lambda_dev, x_dev, grad_dev, h->d_flag, s);
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) throw Error{ASSS_ERR_INVALID_CSR, "invalid row pointer or column index in the gradient pattern"};
+    return ASSS_OK;
   });
 }
 

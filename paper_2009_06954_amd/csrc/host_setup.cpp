@@ -95,6 +95,45 @@ Csr validate_and_copy(int64_t n, int64_t nnz, const int64_t* rowptr, const int32
   return A;
 }
 
+Csr map_values_onto(const Csr& pat, int64_t n, int64_t nnz, const int64_t* rowptr,
+                    const int32_t* colind, const double* val) {
+  if (n != pat.nrows) fail(ASSS_ERR_INVALID_ARG, "n differs from the matrix given at setup");
+  if (!rowptr || (nnz > 0 && (!colind || !val))) fail(ASSS_ERR_INVALID_ARG, "null CSR array");
+  if (rowptr[0] != 0 || rowptr[n] != nnz) fail(ASSS_ERR_INVALID_CSR, "rowptr[0] != 0 or rowptr[n] != nnz");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) fail(ASSS_ERR_INVALID_CSR, "rowptr decreases");
+  Csr A;
+  A.nrows = A.ncols = n;
+  A.ptr = pat.ptr;
+  A.col = pat.col;
+  A.val.assign(pat.col.size(), 0.0);
+  std::atomic<int> bad(0);
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi && !bad; ++i) {
+      int64_t q = pat.ptr[i];
+      const int64_t qe = pat.ptr[i + 1];
+      for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        const int32_t c = colind[p];
+        if (c < 0 || c >= n) { bad = 1; return; }
+        if (p > rowptr[i] && colind[p - 1] >= c) { bad = 2; return; }
+        if (!std::isfinite(val[p])) { bad = 3; return; }
+        while (q < qe && pat.col[q] < c) ++q;
+        if (q < qe && pat.col[q] == c) {
+          A.val[q] = val[p];
+        } else if (val[p] != 0.0) {
+          bad = 4;
+          return;
+        }
+      }
+    }
+  });
+  if (bad == 1) fail(ASSS_ERR_INVALID_CSR, "column index out of range");
+  if (bad == 2) fail(ASSS_ERR_INVALID_CSR, "columns not strictly increasing within a row");
+  if (bad == 3) fail(ASSS_ERR_NONFINITE, "A has a non-finite value");
+  if (bad == 4) fail(ASSS_ERR_INVALID_ARG, "a nonzero outside the pattern given at setup");
+  return A;
+}
+
 Csr transpose(const Csr& A) {
   Csr T;
   T.nrows = A.ncols;

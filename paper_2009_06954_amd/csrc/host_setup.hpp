@@ -32,6 +32,14 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
 Csr validate_and_copy(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
                       const double* val);
 
+// New values for the stored pattern `pat` (the pattern kept at setup, explicit
+// zeros dropped) from a caller CSR with the same checks as validate_and_copy:
+// an entry of the caller inside the pattern sets that value, a zero outside it
+// is ignored, a nonzero outside it is an INVALID_ARG error, and pattern entries
+// the caller does not list become zero.
+Csr map_values_onto(const Csr& pat, int64_t n, int64_t nnz, const int64_t* rowptr,
+                    const int32_t* colind, const double* val);
+
 Csr transpose(const Csr& A);
 
 // Maximum product perfect matching (Sec. 2, eq. mc64): m[j] = row matched to

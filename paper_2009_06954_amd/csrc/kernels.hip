@@ -1055,6 +1055,40 @@ __global__ void k_permute_scatter(int64_t n, const int32_t* __restrict__ perm, c
                                   double* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) y[perm[i]] = x[i];
 }
+// ---------------------------------------------------------------------------
+// Value gradient of a linear solve: for x = A^-1 b and lambda = A^-T dL/dx,
+// dL/da_ij = -lambda_i x_j on every stored entry (i, j) of A.  The caller's
+// CSR arrays are checked as they are read: an entry range outside [0, nnz) or
+// a column outside [0, n) is not used and raises *bad.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(WG) void k_csr_value_grad(int64_t n, int64_t nnz, const int64_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ lam,
+                                                       const double* __restrict__ x, double* __restrict__ g,
+                                                       int* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+    const int64_t lo = ptr[i], hi = ptr[i + 1];
+    if (lo < 0 || hi < lo || hi > nnz) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    const double li = lam[i];
+    for (int64_t e = lo; e < hi; ++e) {
+      const int32_t c = col[e];
+      if (c < 0 || c >= n) {
+        atomicOr(bad, 1);
+        continue;
+      }
+      g[e] = -li * x[c];
+    }
+  }
+}
+void csr_value_grad(int64_t n, int64_t nnz, const int64_t* ptr, const int32_t* col, const double* lam,
+                    const double* x, double* g, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_value_grad, grid_for(n), dim3(WG), 0, s, n, nnz, ptr, col, lam, x, g, bad);
+}
+
 void permute_gather(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_permute_gather, grid_for(n), dim3(WG), 0, s, n, perm, x, y);
 }

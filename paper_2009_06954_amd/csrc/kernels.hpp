@@ -166,6 +166,11 @@ template <typename T, int NR>
 void mrs_output(int64_t n, int nr, const MrsBufs<T>& buf, const int32_t* perm, double* out, int64_t ldo,
                 hipStream_t s);
 
+// g[e] = -lam[i] x[col[e]] over the entries e of every row i of a CSR pattern
+// (device arrays, checked while read: *bad = 1 on an invalid entry range or column)
+void csr_value_grad(int64_t n, int64_t nnz, const int64_t* ptr, const int32_t* col, const double* lam,
+                    const double* x, double* g, int* bad, hipStream_t s);
+
 // y[i] = x[perm[i]] (gather) and y[perm[i]] = x[i] (scatter), FP64
 void permute_gather(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s);
 void permute_scatter(int64_t n, const int32_t* perm, const double* x, double* y, hipStream_t s);
