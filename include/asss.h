@@ -119,13 +119,17 @@ typedef struct {
 
 typedef struct {
   double tol;              /* true relative residual ||b - A x|| / ||b||, default 1e-8 */
-  int32_t restart_m;       /* FGMRES restart length, default 64 */
-  int32_t max_outer;       /* total Arnoldi steps, default 2000 */
+  int32_t restart_m;       /* FGMRES restart length, default 64 (TFQMR: unused) */
+  int32_t max_outer;       /* total Arnoldi steps (TFQMR: half steps), default 2000 */
   double inner_tol;        /* mrs relative tolerance, default 1e-5 */
   int32_t inner_maxit;     /* default 1000 */
   int32_t fixed_inner_steps; /* > 0: every mrs runs exactly this many steps */
   int32_t inner_fp32;      /* -1 = handle default, 0 = FP64, 1 = FP32 inner */
+  int32_t outer;           /* ASSS_OUTER_FGMRES (default) or ASSS_OUTER_TFQMR, the
+                              transpose-free QMR of the paper's experiments (Sec. 4.1) */
 } asss_solve_opts_t;
+
+enum { ASSS_OUTER_FGMRES = 0, ASSS_OUTER_TFQMR = 1 };
 
 typedef struct {
   int32_t converged;

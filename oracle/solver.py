@@ -62,6 +62,9 @@ class SolveOptions:
     inner_tol: float = 1e-5
     inner_maxit: int = 1000
     fixed_inner_steps: int = 0
+    outer: str = "fgmres"  # or "tfqmr"
+    record: bool = False   # tfqmr: keep x_chk and ||w|| after every half step
+                           # (info["x_hist"], info["w_norms"])
 
 
 @dataclass
@@ -215,6 +218,121 @@ def _fgmres(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
     return x_chk, info
 
 
+def _tfqmr(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
+    """Transpose-free QMR (Freund 1993) on A_chk P^-1 y = rhs, x_chk = P^-1 y:
+    the outer method of the paper's experiments (Sec. 4.1).
+
+    Right preconditioning with the iterate kept in x_chk coordinates: every
+    vector u that enters a product gets z = P^-1 u once, the product is
+    A_chk z, and the direction d (a combination of the u's) is carried as
+    P^-1 d, built from the same z's.  With an exact preconditioner this is
+    the textbook method; with the inexact inner solve the update of x_chk
+    stays consistent with the products actually formed.  Two half steps per
+    iteration (m even: new alpha, u_{m+1} = u_m - alpha v_m; m odd: new rho,
+    beta, u_{m+1} = w_{m+1} + beta u_m, v_{m+1}); quasi-minimal residual
+    bound ||r_{m+1}|| <= tau_{m+1} sqrt(m + 2).  Stopping as for FGMRES: the
+    bound only triggers the true-residual check; a failed check restarts the
+    method from x_chk with the threshold tightened; a breakdown ((v, r*) = 0
+    or rho = 0) also restarts.  outer_its counts half steps."""
+    n = rhs.size
+    info = dict(converged=False, outer_its=0, inner_its_total=0, inner_its_max=0,
+                relres_true=np.nan, relres_implicit=np.nan, cycles=0, hist=[], reorth=0)
+    bn = np.linalg.norm(rhs)
+    x_chk = np.zeros(n)
+    if bn == 0.0:
+        info.update(converged=True, relres_true=0.0, relres_implicit=0.0)
+        return x_chk, info
+    thr = o.tol * bn
+
+    def pre(u):
+        z, its = prec_apply(u)
+        info["inner_its_total"] += its
+        info["inner_its_max"] = max(info["inner_its_max"], its)
+        return z
+
+    first = True
+    while True:
+        r = rhs.copy() if first else rhs - op(x_chk)
+        first = False
+        info["cycles"] += 1
+        tau = np.linalg.norm(r)
+        implicit_ok = tau <= thr
+        bound = tau
+        if not implicit_ok:
+            rstar = r.copy()
+            rho = rstar @ r
+            w = r.copy()
+            u = r.copy()
+            z = pre(u)          # P^-1 u_0
+            Au = op(z)          # A_chk P^-1 u_0
+            v = Au.copy()
+            dz = np.zeros(n)
+            theta = eta = 0.0
+            alpha = 0.0
+            m = 0
+            while True:
+                if m % 2 == 0:
+                    sigma = v @ rstar
+                    if sigma == 0.0 or rho == 0.0:
+                        break                       # breakdown: restart
+                    alpha = rho / sigma
+                    u_next = u - alpha * v
+                    zm, Aum = z, Au                 # u_m = u (product known)
+                else:
+                    zm = pre(u)                     # u_m = u_next of the even step
+                    Aum = op(zm)
+                w = w - alpha * Aum
+                dz = zm + (theta * theta / alpha) * eta * dz
+                theta = np.linalg.norm(w) / tau
+                if o.record:
+                    info.setdefault("w_norms", []).append(np.linalg.norm(w))
+                c = 1.0 / np.sqrt(1.0 + theta * theta)
+                tau = tau * theta * c
+                eta = c * c * alpha
+                x_chk = x_chk + eta * dz
+                info["outer_its"] += 1
+                bound = tau * np.sqrt(m + 2.0)
+                info["hist"].append(bound / bn)
+                if o.record:
+                    info.setdefault("x_hist", []).append(x_chk.copy())
+                implicit_ok = bound <= thr
+                if implicit_ok or info["outer_its"] >= o.max_outer:
+                    break
+                if m % 2 == 1:
+                    rho_new = w @ rstar
+                    if rho_new == 0.0:
+                        break                       # breakdown: restart
+                    beta = rho_new / rho
+                    rho = rho_new
+                    u_new = w + beta * u
+                    z = pre(u_new)
+                    Au_new = op(z)
+                    v = Au_new + beta * (Aum + beta * v)
+                    u, Au = u_new, Au_new
+                else:
+                    u = u_next
+                m += 1
+        info["relres_implicit"] = bound / bn
+        relres = true_relres(back(x_chk))
+        info["relres_true"] = relres
+        if relres <= o.tol:
+            info["converged"] = True
+            break
+        if info["outer_its"] >= o.max_outer:
+            break
+        if implicit_ok:
+            thr = thr * 0.5 * o.tol / relres
+    return x_chk, info
+
+
+def _outer(o: SolveOptions):
+    if o.outer == "fgmres":
+        return _fgmres
+    if o.outer == "tfqmr":
+        return _tfqmr
+    raise ValueError(f"unknown outer method {o.outer!r}")
+
+
 def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None):
     """x with A x = b (Sec. 3).  Returns (x, info)."""
     o = o or SolveOptions()
@@ -231,7 +349,7 @@ def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None):
         return np.linalg.norm(b - st.A @ x) / bn
 
     prec = lambda v: st.prec.apply(v, o.inner_tol, o.inner_maxit, o.fixed_inner_steps)
-    x_chk, info = _fgmres(st.op, prec, st.rhs(b), st.back, true_relres, o)
+    x_chk, info = _outer(o)(st.op, prec, st.rhs(b), st.back, true_relres, o)
     info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
     return st.back(x_chk), info
 
@@ -253,7 +371,7 @@ def solve_adjoint(st: OracleSetup, g: np.ndarray, o: SolveOptions | None = None)
         return np.linalg.norm(g - st.A.T @ lam) / gn
 
     prec = lambda v: st.prec.apply_T(v, o.inner_tol, o.inner_maxit, o.fixed_inner_steps)
-    l_chk, info = _fgmres(st.op_T, prec, st.rhs_T(g), st.back_T, true_relres, o)
+    l_chk, info = _outer(o)(st.op_T, prec, st.rhs_T(g), st.back_T, true_relres, o)
     info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
     return st.back_T(l_chk), info
 

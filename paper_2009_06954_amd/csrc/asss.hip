@@ -787,6 +787,162 @@ asss_status_t fgmres(asss_handle_s* h, bool adjoint, const double* b, double* x,
   return status;
 }
 
+// Transpose-free QMR (Freund) on A_chk P^-1 y = b_chk with the iterate kept as
+// x_chk = P^-1 y: every vector u that enters a product gets z = P^-1 u once,
+// the product is A_chk z, and the direction is carried as P^-1 d built from
+// the same z's (consistent with the products even though the inner solve is
+// inexact).  Half steps m = 0, 1, ...: even m takes alpha = rho / (v, r*) and
+// u_{m+1} = u_m - alpha v_m; odd m takes beta from rho = (w, r*) and forms
+// u_{m+1} = w_{m+1} + beta u_m, v_{m+1} = A u_{m+1} + beta (A u_m + beta v_m).
+// The quasi-residual bound tau sqrt(m + 2) triggers the true-residual check;
+// a failed check or a breakdown restarts from x_chk (threshold as in fgmres).
+asss_status_t tfqmr(asss_handle_s* h, bool adjoint, const double* b, double* x,
+                    const asss_solve_opts_t& o, asss_info_t* info, hipStream_t s) {
+  const double t0 = now_s();
+  const int64_t n = h->n;
+  const bool fp32 = (o.inner_fp32 < 0) ? (h->opts.inner_fp32 != 0) : (o.inner_fp32 != 0);
+  asss_info_t inf{};
+  inf.k_eff = h->k_eff;
+  inf.rank_r = h->r;
+  inf.setup_host_s = h->setup_host_s;
+  inf.setup_device_s = h->setup_device_s;
+  const double bn = std::sqrt(dot_host(h, n, b, b, s));
+  if (bn == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    HIPCHK(hipStreamSynchronize(s));
+    inf.converged = 1;
+    inf.solve_s = now_s() - t0;
+    if (info) *info = inf;
+    return ASSS_OK;
+  }
+  ensure_outer(h, 6);  // 7 + 6 work vectors
+  double* w = h->V;
+  double* u = h->V + n;
+  double* un = h->V + 2 * n;
+  double* v = h->V + 3 * n;
+  double* Au = h->V + 4 * n;
+  double* Aum_buf = h->V + 5 * n;
+  double* rstar = h->V + 6 * n;
+  double* z = h->Z;
+  double* zm_buf = h->Z + n;
+  double* dz = h->Z + 2 * n;
+  if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, h->bchk, s);
+  else spmv(h->dSt, b, h->bchk, h->d_om, h->d_dc, 0, nullptr, s);
+  const double bcn = std::sqrt(dot_host(h, n, h->bchk, h->bchk, s));
+  double thr = o.tol * bcn;
+  HIPCHK(hipMemsetAsync(h->xchk, 0, n * sizeof(double), s));
+  auto op = [&](const double* in, double* out) {
+    if (!adjoint) outer_op(h, in, out, s);
+    else outer_op_T(h, in, out, s);
+  };
+  auto pre = [&](const double* in, double* out) {
+    const int its = adjoint ? prec_apply_T(h, fp32, in, out, o, s) : prec_apply(h, fp32, in, out, o, s);
+    inf.inner_its_total += its;
+    inf.inner_its_max = std::max(inf.inner_its_max, its);
+  };
+  asss_status_t status = ASSS_NOT_CONVERGED;
+  h->last_inner = 0;
+  h->prof_s = 0.0;
+  h->prof_launches = 0;
+  bool first = true;
+  for (;;) {
+    axpby(n, 1.0, h->bchk, 0.0, w, s);  // w = r = b_chk - A_chk x_chk
+    if (!first) {
+      op(h->xchk, h->rv);
+      axpby(n, -1.0, h->rv, 1.0, w, s);
+    }
+    first = false;
+    inf.cycles++;
+    double tau = std::sqrt(dot_host(h, n, w, w, s));
+    double bound = tau;
+    bool implicit_ok = tau <= thr;
+    if (!implicit_ok) {
+      axpby(n, 1.0, w, 0.0, rstar, s);
+      axpby(n, 1.0, w, 0.0, u, s);
+      double rho = tau * tau;
+      pre(u, z);
+      op(z, Au);
+      axpby(n, 1.0, Au, 0.0, v, s);
+      HIPCHK(hipMemsetAsync(dz, 0, n * sizeof(double), s));
+      double theta = 0.0, eta = 0.0, alpha = 0.0;
+      for (int m = 0;; ++m) {
+        const double* zm;
+        const double* Aum;
+        if (m % 2 == 0) {
+          const double sigma = dot_host(h, n, v, rstar, s);
+          if (sigma == 0.0 || rho == 0.0) break;  // breakdown: restart
+          alpha = rho / sigma;
+          axpby(n, 1.0, u, 0.0, un, s);
+          axpby(n, -alpha, v, 1.0, un, s);  // u_{m+1} = u_m - alpha v_m
+          zm = z;
+          Aum = Au;
+        } else {
+          pre(u, zm_buf);
+          op(zm_buf, Aum_buf);
+          zm = zm_buf;
+          Aum = Aum_buf;
+        }
+        axpby(n, -alpha, Aum, 1.0, w, s);                                   // w -= alpha A u_m
+        axpby(n, 1.0, zm, (theta * theta / alpha) * eta, dz, s);            // P^-1 d
+        theta = std::sqrt(dot_host(h, n, w, w, s)) / tau;
+        const double c = 1.0 / std::sqrt(1.0 + theta * theta);
+        tau = tau * theta * c;
+        eta = c * c * alpha;
+        axpby(n, eta, dz, 1.0, h->xchk, s);
+        inf.outer_its++;
+        bound = tau * std::sqrt(m + 2.0);
+        implicit_ok = bound <= thr;
+        if (h->opts.verbose)
+          std::fprintf(stderr, "[asss] tfqmr half step %d bound %.3e\n", inf.outer_its, bound / bcn);
+        if (implicit_ok || inf.outer_its >= o.max_outer) break;
+        if (m % 2 == 1) {
+          const double rho_new = dot_host(h, n, w, rstar, s);
+          if (rho_new == 0.0) break;  // breakdown: restart
+          const double beta = rho_new / rho;
+          rho = rho_new;
+          axpby(n, 1.0, w, 0.0, un, s);
+          axpby(n, beta, u, 1.0, un, s);  // u_{m+1} = w_{m+1} + beta u_m
+          pre(un, z);
+          op(z, Au);                      // A u_{m+1}
+          axpby(n, 1.0, Aum, beta, v, s);  // v = A u_m + beta v_m
+          axpby(n, 1.0, Au, beta, v, s);   // v = A u_{m+1} + beta (A u_m + beta v_m)
+        }
+        std::swap(u, un);
+      }
+    }
+    inf.relres_implicit = bound / bcn;
+    double relres;
+    if (!adjoint) {
+      spmv(h->dS, h->xchk, x, h->d_dc, h->d_om, 0, nullptr, s);
+      spmv(h->dA, x, h->rv, nullptr, nullptr, 1, b, s);
+    } else {
+      scatter_scale(n, h->d_m, h->d_drp, h->d_om, h->xchk, x, s);
+      spmv(h->dAt, x, h->rv, nullptr, nullptr, 1, b, s);
+    }
+    relres = std::sqrt(dot_host(h, n, h->rv, h->rv, s)) / bn;
+    inf.relres_true = relres;
+    if (relres <= o.tol) {
+      status = ASSS_OK;
+      inf.converged = 1;
+      break;
+    }
+    if (inf.outer_its >= o.max_outer) break;
+    if (implicit_ok) thr = thr * 0.5 * o.tol / relres;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  inf.solve_s = now_s() - t0;
+  inf.inner_kernel_s = h->prof_s;
+  inf.inner_launches = h->prof_launches;
+  if (info) *info = inf;
+  return status;
+}
+
+asss_status_t outer_solve(asss_handle_s* h, bool adjoint, const double* b, double* x,
+                          const asss_solve_opts_t& o, asss_info_t* info, hipStream_t s) {
+  if (o.outer == ASSS_OUTER_TFQMR) return tfqmr(h, adjoint, b, x, o, info, s);
+  return fgmres(h, adjoint, b, x, o, info, s);
+}
+
 void check_handle(asss_handle_s* h) {
   if (!h) throw Error{ASSS_ERR_INVALID_ARG, "null handle"};
   HIPCHK(hipSetDevice(h->device));
@@ -852,6 +1008,7 @@ void asss_default_solve_opts(asss_solve_opts_t* o) {
   o->inner_maxit = 1000;
   o->fixed_inner_steps = 0;
   o->inner_fp32 = -1;
+  o->outer = ASSS_OUTER_FGMRES;
 }
 
 const char* asss_last_error(void) { return g_err.c_str(); }
@@ -1002,8 +1159,10 @@ asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, co
     hipStream_t s = (hipStream_t)hip_stream;
     asss_solve_opts_t oo = opts_or_default(o);
     if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
+    if (oo.outer != ASSS_OUTER_FGMRES && oo.outer != ASSS_OUTER_TFQMR)
+      throw Error{ASSS_ERR_INVALID_ARG, "outer must be ASSS_OUTER_FGMRES or ASSS_OUTER_TFQMR"};
     if (!b_is_finite(h, b_dev, s)) throw Error{ASSS_ERR_NONFINITE, "b has a non-finite entry"};
-    return fgmres(h, false, b_dev, x_dev, oo, info, s);
+    return outer_solve(h, false, b_dev, x_dev, oo, info, s);
   });
 }
 
@@ -1015,8 +1174,10 @@ asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* l
     hipStream_t s = (hipStream_t)hip_stream;
     asss_solve_opts_t oo = opts_or_default(o);
     if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
+    if (oo.outer != ASSS_OUTER_FGMRES && oo.outer != ASSS_OUTER_TFQMR)
+      throw Error{ASSS_ERR_INVALID_ARG, "outer must be ASSS_OUTER_FGMRES or ASSS_OUTER_TFQMR"};
     if (!b_is_finite(h, g_dev, s)) throw Error{ASSS_ERR_NONFINITE, "g has a non-finite entry"};
-    return fgmres(h, true, g_dev, lambda_dev, oo, info, s);
+    return outer_solve(h, true, g_dev, lambda_dev, oo, info, s);
   });
 }
 
