@@ -1,0 +1,133 @@
+"""The benchmark workload at full size (3D convection-diffusion, 128^3,
+n = 2,097,152, Peclet 100, S on the pattern of Abar, k = 16), in the launch
+configuration the benchmark times (row blocks of 2048, one workgroup each).
+
+The oracle cannot build S at this size in seconds (its LLS is a 27M x 15M
+least-squares problem), so these tests check what holds at any size:
+the true residual recomputed on the host with SciPy, exact skew-symmetry of
+the GPU operator and its agreement with the CSR form of J_tilde exported by
+the handle (which pins the sliced storage, both parts and the block split),
+the Lanczos relations, the mrs residual identity, P z = v for the
+preconditioner, and the adjoint residual."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+M = 128
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _cuda(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_06954_amd as asss
+    asss.load()
+    print(f"[full] building convdiff3d {M}^3", flush=True)
+    w = W.convdiff3d(m=M, peclet=100.0, cfg=1)
+    h = asss.setup(w.A, k=16, s_pattern="abar")
+    info = h.info()
+    print(f"[full] setup done: {info}", flush=True)
+    U = sp.csr_matrix((h.array("J_val"), h.array("J_colind"), h.array("J_rowptr")), shape=w.A.shape)
+    J = (U - U.T).tocsr()
+    yield dict(w=w, h=h, info=info, J=J, absJ=abs(J).tocsr(), Q=h.array("Q").reshape(-1, w.A.shape[0]).T,
+               alpha=h.array("alpha"), D=h.array("D"))
+    h.close()
+
+
+def test_fullsize_launch_configuration(full):
+    i = full["info"]
+    assert i["n"] == M ** 3 and i["row_block"] == 2048 and i["nblocks"] == M ** 3 // 2048
+    assert i["k_eff"] == 16 and i["nh"] == full["J"].nnz // 2
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fullsize_solve_true_residual(full, fp32):
+    w, h = full["w"], full["h"]
+    x, info = h.solve(_cuda(w.b), tol=1e-8, restart_m=200, inner_tol=0.2, inner_fp32=fp32)
+    xs = _np(x)
+    rel = np.linalg.norm(w.b - w.A @ xs) / np.linalg.norm(w.b)
+    err = np.linalg.norm(xs - w.x_star) / np.linalg.norm(w.x_star)
+    print(f"[full] fp32={fp32} outer={info['outer_its']} inner={info['inner_its_total']} "
+          f"relres(host)={rel:.3e} err_vs_xstar={err:.3e}", flush=True)
+    assert info["status"] == "OK"
+    assert rel <= 1e-8 * (1 + 1e-6)
+    assert abs(rel - info["relres_true"]) <= 1e-3 * rel
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fullsize_skew_operator(full, fp32):
+    h, J, absJ = full["h"], full["J"], full["absJ"]
+    rng = np.random.default_rng(21)
+    n = J.shape[0]
+    v = rng.uniform(-1, 1, n)
+    out, _ = h.apply("skew", _cuda(v), inner_fp32=fp32)
+    y = _np(out)
+    ref = J @ v
+    bound = absJ @ np.abs(v)
+    c = 2e-6 if fp32 else 1e-12
+    assert np.all(np.abs(y - ref) <= c * bound + 1e-300), float(np.max(np.abs(y - ref) / (bound + 1e-300)))
+    # exact skew-symmetry of the GPU operator: v^T (J v) = 0, w^T J v = -v^T J w
+    wv = rng.uniform(-1, 1, n)
+    out2, _ = h.apply("skew", _cuda(wv), inner_fp32=fp32)
+    y2 = _np(out2)
+    scale = np.abs(v) @ bound
+    assert abs(v @ y) <= (1e-5 if fp32 else 1e-12) * scale
+    assert abs(wv @ y + v @ y2) <= (1e-5 if fp32 else 1e-12) * scale
+
+
+def test_fullsize_deflation_and_lanczos(full):
+    h, J, Q, alpha = full["h"], full["J"], full["Q"], full["alpha"]
+    k = Q.shape[1]
+    Sk = np.diag(alpha, 1) - np.diag(alpha, -1)
+    # Lanczos relations (Fig. 2): Q^T Q = I and Q^T J Q = S_k up to the loss of
+    # orthogonality of the unreorthogonalised process
+    assert np.max(np.abs(Q.T @ Q - np.eye(k))) <= 1e-8
+    assert np.max(np.abs(Q.T @ (J @ Q) - Sk)) <= 1e-8 * np.max(np.abs(alpha))
+    rng = np.random.default_rng(22)
+    v = rng.uniform(-1, 1, J.shape[0])
+    out, _ = h.apply("deflated", _cuda(v))
+    ref = J @ v - Q @ (Sk @ (Q.T @ v))
+    assert np.linalg.norm(_np(out) - ref) <= 1e-12 * np.linalg.norm(ref) * 1e2
+
+
+def test_fullsize_mrs_and_preconditioner(full):
+    h, J, Q, alpha, D = full["h"], full["J"], full["Q"], full["alpha"], full["D"]
+    Sk = np.diag(alpha, 1) - np.diag(alpha, -1)
+    rng = np.random.default_rng(23)
+    v = rng.uniform(-1, 1, J.shape[0])
+    for fp32, tol, slack in ((False, 1e-8, 10.0), (True, 1e-4, 10.0)):
+        out, its = h.apply("mrs", _cuda(v), inner_tol=tol, inner_maxit=2000, inner_fp32=fp32)
+        x = _np(out)
+        r = v - x - (J @ x - Q @ (Sk @ (Q.T @ x)))  # (I + J_bar) x = v
+        rel = np.linalg.norm(r) / np.linalg.norm(v)
+        print(f"[full] mrs fp32={fp32} its={its} true relres={rel:.3e}", flush=True)
+        assert 0 < its < 2000 and rel <= slack * tol
+    z, its = h.apply("prec", _cuda(v), inner_tol=1e-10, inner_maxit=4000)
+    zz = _np(z)
+    Pz = np.sign(D) * zz + J @ zz  # P = sign(D) + J_tilde
+    assert np.linalg.norm(Pz - v) <= 1e-8 * np.linalg.norm(v)
+
+
+def test_fullsize_adjoint_true_residual(full):
+    w, h = full["w"], full["h"]
+    g = np.random.default_rng(24).standard_normal(w.A.shape[0])
+    lam, info = h.solve_adjoint(_cuda(g), tol=1e-8, restart_m=200, inner_tol=0.2)
+    rel = np.linalg.norm(g - w.A.T @ _np(lam)) / np.linalg.norm(g)
+    print(f"[full] adjoint outer={info['outer_its']} relres(host)={rel:.3e}", flush=True)
+    assert info["status"] == "OK" and rel <= 1e-8 * (1 + 1e-6)
