@@ -203,7 +203,14 @@ asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* r
 
 /* Several systems, each with several right-hand sides: system s has
  * nrhs[s] columns in B_dev[s] / X_dev[s] (device, n_s x nrhs[s], column-major).
- * infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be NULL).
+ * With FGMRES the columns of a system advance in lockstep in groups of up to
+ * 4: one simultaneous mrs solve (App. B) per outer step serves the group, so
+ * each inner step reads J_tilde and Q_k once for all its columns; the inner
+ * stop rule is the maximum over the group.  Each column restarts and stops on
+ * its own true residual.  With TFQMR the columns are solved one at a time.
+ * All right-hand sides are checked for NaN/Inf first (NONFINITE, nothing
+ * solved).  infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be
+ * NULL); inner_kernel_s / inner_launches are those of the column's group.
  * Returns the worst status over all columns. */
 asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const int32_t* nrhs,
                                  const double* const* B_dev, double* const* X_dev,

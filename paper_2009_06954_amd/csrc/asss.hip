@@ -175,6 +175,14 @@ struct asss_handle_s {
   // outer workspace
   int m_alloc = 0;
   double *V = nullptr, *Z = nullptr;
+  // lockstep columns of a batched solve (up to NRMAX) and the 4-column inner buffers
+  struct MultiCol {
+    double *V = nullptr, *Z = nullptr, *bchk = nullptr, *xchk = nullptr, *rv = nullptr;
+  } mcol[NRMAX];
+  int m_alloc_multi = 0;
+  double *pin = nullptr, *pout = nullptr;
+  MrsBufs<double> mb4_64{};
+  MrsBufs<float> mb4_32{};
   double *w = nullptr, *t1 = nullptr, *xchk = nullptr, *bchk = nullptr, *rv = nullptr, *tmp = nullptr;
   int last_inner = 0;
   // HIP events bracketing each chunk of back-to-back mrs iteration kernels
@@ -234,19 +242,25 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f
   return L;
 }
 
-template <typename T>
-int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
-             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
-  MrsLaunch L = make_launch<T>(h, 1, sign, Q, f, h->defl_rec != 0);
-  mrs_init<T, 1>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
-  if (L.rec) mrs_make_y1<T, 1>(L, Q, mb, h->d_state, s);
+// Inner mrs solve of nc <= NR right-hand sides (columns of rhs / out with
+// leading dimension n; NR = 4: App. B's simultaneous form, one matrix pass per
+// step for all columns, shared stop rule).
+template <typename T, int NR = 1>
+int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+            const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s,
+            int nc = 1) {
+  MrsLaunch L = make_launch<T>(h, nc, sign, Q, f, NR == 1 && h->defl_rec != 0);
+  mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
+  if constexpr (NR == 1) {
+    if (L.rec) mrs_make_y1<T, 1>(L, Q, mb, h->d_state, s);
+  }
   int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
   int its = 0;
   double prev_rel = 1.0;
   int prev_its = 0;
   for (int guard = 0; guard < 100000; ++guard) {
     HIPCHK(hipEventRecord(h->ev0, s));
-    for (int c = 0; c < chunk; ++c) mrs_iter<T, 1>(L, J, Q, mb, h->d_state, h->red, s);
+    for (int c = 0; c < chunk; ++c) mrs_iter<T, NR>(L, J, Q, mb, h->d_state, h->red, s);
     HIPCHK(hipEventRecord(h->ev1, s));
     HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -266,7 +280,7 @@ int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBuf
     its = st_its;
     if (st_status == MRS_DONE) break;
     if (st_status == MRS_CONVERGED) {
-      mrs_iter<T, 1>(L, J, Q, mb, h->d_state, h->red, s);  // final deferred update
+      mrs_iter<T, NR>(L, J, Q, mb, h->d_state, h->red, s);  // final deferred update
       break;
     }
     // estimate the remaining iterations from the observed contraction rate
@@ -281,9 +295,15 @@ int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBuf
     prev_rel = rel;
     prev_its = its;
   }
-  mrs_output<T, 1>(h->n, 1, mb, h->d_perm, out, h->n, s);
+  mrs_output<T, NR>(h->n, nc, mb, h->d_perm, out, h->n, s);
   h->last_inner = its;
   return its;
+}
+
+template <typename T>
+int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
+  return run_mrs<T, 1>(h, J, Q, f, mb, rhs, out, sign, tol, maxit, fixed, s);
 }
 
 int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
@@ -293,16 +313,53 @@ int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int
   return run_mrs1<double>(h, h->J64, h->d_Q64, h->d_f64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
 }
 
-// z = P^-1 v (eq. smw in the inverse-free form)
-int prec_apply(asss_handle_s* h, bool fp32, const double* v, double* z, const asss_solve_opts_t& o,
-               hipStream_t s) {
-  int its = inner_solve(h, fp32, v, z, +1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
+// z <- z - X (C^-1 Sigma) (U_bar^T z): the low-rank part of eq. smw (inverse-free form)
+void smw_correct(asss_handle_s* h, double* z, hipStream_t s) {
   if (h->kr > 0) {
     double* t = h->d_small + SM_T;
     gemm_tn<double, double>(h->n, h->kr, h->d_Ubar, h->n, z, 1, t, h->d_Mf, h->red, 3, s);
     gemv_acc(h->n, h->kr, h->d_X, h->n, t, -1.0, z, s);
   }
+}
+
+// z = P^-1 v (eq. smw in the inverse-free form)
+int prec_apply(asss_handle_s* h, bool fp32, const double* v, double* z, const asss_solve_opts_t& o,
+               hipStream_t s) {
+  int its = inner_solve(h, fp32, v, z, +1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
+  smw_correct(h, z, s);
   return its;
+}
+
+// Buffers of the 4-column inner solve and of up to 4 lockstep outer columns.
+void ensure_multi(asss_handle_s* h, int m, bool fp32) {
+  const int64_t n = h->n;
+  if (fp32 && !h->mb4_32.x) {
+    for (int b = 0; b < 3; ++b) h->mb4_32.w[b] = h->ar.alloc<float>(n * NRMAX);
+    for (int b = 0; b < 2; ++b) h->mb4_32.p[b] = h->ar.alloc<float>(n * NRMAX);
+    h->mb4_32.x = h->ar.alloc<float>(n * NRMAX);
+  }
+  if (!fp32 && !h->mb4_64.x) {
+    for (int b = 0; b < 3; ++b) h->mb4_64.w[b] = h->ar.alloc<double>(n * NRMAX);
+    for (int b = 0; b < 2; ++b) h->mb4_64.p[b] = h->ar.alloc<double>(n * NRMAX);
+    h->mb4_64.x = h->ar.alloc<double>(n * NRMAX);
+  }
+  if (!h->pin) {
+    h->pin = h->ar.alloc<double>(n * NRMAX);
+    h->pout = h->ar.alloc<double>(n * NRMAX);
+    for (int c = 0; c < NRMAX; ++c) {
+      h->mcol[c].bchk = h->ar.alloc<double>(n);
+      h->mcol[c].xchk = h->ar.alloc<double>(n);
+      h->mcol[c].rv = h->ar.alloc<double>(n);
+    }
+  }
+  if (h->m_alloc_multi < m) {
+    for (int c = 0; c < NRMAX; ++c) {
+      if (h->mcol[c].V) { h->ar.release(h->mcol[c].V); h->ar.release(h->mcol[c].Z); }
+      h->mcol[c].V = h->ar.alloc<double>(n * (int64_t)(m + 1));
+      h->mcol[c].Z = h->ar.alloc<double>(n * (int64_t)m);
+    }
+    h->m_alloc_multi = m;
+  }
 }
 
 // z = P^-T v = S_bar^-T (v - U_bar Sigma^T C^-T X^T v)
@@ -638,153 +695,258 @@ bool b_is_finite(asss_handle_s* h, const double* b, hipStream_t s) {
   return flag == 0;
 }
 
-// Flexible GMRES(m) on the scaled system with the stopping rule of the oracle.
-asss_status_t fgmres(asss_handle_s* h, bool adjoint, const double* b, double* x,
-                     const asss_solve_opts_t& o, asss_info_t* info, hipStream_t s) {
-  const double t0 = now_s();
-  const int64_t n = h->n;
-  const bool fp32 = (o.inner_fp32 < 0) ? (h->opts.inner_fp32 != 0) : (o.inner_fp32 != 0);
+// One column of flexible GMRES(m) on the scaled system, with the stopping rule
+// of the oracle, as a state machine: the caller applies the preconditioner to
+// v_next() into z_next() and calls after_prec(); the column restarts and
+// finishes by itself.  Several columns can so share one preconditioner call.
+struct FgmresCol {
+  asss_handle_s* h = nullptr;
+  bool adjoint = false;
+  const double* b = nullptr;
+  double* x = nullptr;
+  asss_solve_opts_t o{};
+  hipStream_t s = nullptr;
+  int64_t n = 0;
+  int m = 1;
+  double *V = nullptr, *Z = nullptr, *bchk = nullptr, *xchk = nullptr, *rv = nullptr;
+  std::vector<double> H, cs, sn, g, y;
+  double bn = 0.0, bcn = 0.0, thr = 0.0, t0 = 0.0;
+  int j = 0;
+  bool first = true, done = false, implicit_ok = false;
   asss_info_t inf{};
-  inf.k_eff = h->k_eff;
-  inf.rank_r = h->r;
-  inf.setup_host_s = h->setup_host_s;
-  inf.setup_device_s = h->setup_device_s;
-  const double bn = std::sqrt(dot_host(h, n, b, b, s));
-  if (bn == 0.0) {
-    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    HIPCHK(hipStreamSynchronize(s));
-    inf.converged = 1;
-    inf.solve_s = now_s() - t0;
-    if (info) *info = inf;
-    return ASSS_OK;
-  }
-  const int m = std::max(1, o.restart_m);
-  ensure_outer(h, m);
-  // right-hand side of the scaled system
-  if (!adjoint) {
-    gather_scale(n, h->d_m, h->d_drp, h->d_om, b, h->bchk, s);
-  } else {
-    // g_chk = Omega S^T (Dc o g)
-    spmv(h->dSt, b, h->bchk, h->d_om, h->d_dc, 0, nullptr, s);
-  }
-  const double bcn = std::sqrt(dot_host(h, n, h->bchk, h->bchk, s));
-  double thr = o.tol * bcn;
-  HIPCHK(hipMemsetAsync(h->xchk, 0, n * sizeof(double), s));
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  bool first = true;
   asss_status_t status = ASSS_NOT_CONVERGED;
-  double* hbuf = h->d_small;
-  h->last_inner = 0;
-  h->prof_s = 0.0;
-  h->prof_launches = 0;
-  for (;;) {
+
+  void op(const double* in, double* out) {
+    if (!adjoint) outer_op(h, in, out, s);
+    else outer_op_T(h, in, out, s);
+  }
+  const double* v_next() const { return V + (int64_t)j * n; }
+  double* z_next() { return Z + (int64_t)j * n; }
+
+  void begin(asss_handle_s* h_, bool adj, const double* b_, double* x_, const asss_solve_opts_t& o_,
+             double* V_, double* Z_, double* bchk_, double* xchk_, double* rv_, hipStream_t s_) {
+    h = h_; adjoint = adj; b = b_; x = x_; o = o_; s = s_;
+    V = V_; Z = Z_; bchk = bchk_; xchk = xchk_; rv = rv_;
+    t0 = now_s();
+    n = h->n;
+    m = std::max(1, o.restart_m);
+    inf = asss_info_t{};
+    inf.k_eff = h->k_eff;
+    inf.rank_r = h->r;
+    inf.setup_host_s = h->setup_host_s;
+    inf.setup_device_s = h->setup_device_s;
+    bn = std::sqrt(dot_host(h, n, b, b, s));
+    if (bn == 0.0) {
+      HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+      inf.converged = 1;
+      status = ASSS_OK;
+      done = true;
+      return;
+    }
+    if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, bchk, s);
+    else spmv(h->dSt, b, bchk, h->d_om, h->d_dc, 0, nullptr, s);  // g_chk = Omega S^T (Dc o g)
+    bcn = std::sqrt(dot_host(h, n, bchk, bchk, s));
+    thr = o.tol * bcn;
+    HIPCHK(hipMemsetAsync(xchk, 0, n * sizeof(double), s));
+    H.assign((size_t)(m + 1) * m, 0.0);
+    cs.assign(m, 0.0);
+    sn.assign(m, 0.0);
+    g.assign(m + 1, 0.0);
+    y.assign(m, 0.0);
+    first = true;
+    start_cycle();
+  }
+
+  void start_cycle() {
     if (first) {
-      axpby(n, 1.0, h->bchk, 0.0, h->rv, s);
+      axpby(n, 1.0, bchk, 0.0, rv, s);
     } else {
-      if (!adjoint) outer_op(h, h->xchk, h->w, s);
-      else outer_op_T(h, h->xchk, h->w, s);
-      axpby(n, 1.0, h->bchk, 0.0, h->rv, s);
-      axpby(n, -1.0, h->w, 1.0, h->rv, s);
+      op(xchk, h->w);
+      axpby(n, 1.0, bchk, 0.0, rv, s);
+      axpby(n, -1.0, h->w, 1.0, rv, s);
     }
     first = false;
-    const double beta = std::sqrt(dot_host(h, n, h->rv, h->rv, s));
+    const double beta = std::sqrt(dot_host(h, n, rv, rv, s));
     inf.cycles++;
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int j_used = 0;
-    bool implicit_ok = beta <= thr;
+    j = 0;
+    implicit_ok = beta <= thr;
     if (beta > 0) {
-      scale(n, 1.0 / beta, h->rv, h->V, s);
-      for (int j = 0; j < m; ++j) {
-        double* vj = h->V + (int64_t)j * n;
-        double* zj = h->Z + (int64_t)j * n;
-        int its = adjoint ? prec_apply_T(h, fp32, vj, zj, o, s) : prec_apply(h, fp32, vj, zj, o, s);
-        inf.inner_its_total += its;
-        inf.inner_its_max = std::max(inf.inner_its_max, its);
-        // w = A_chk z_j written straight into V[:, j+1]; classical Gram-Schmidt with
-        // one more pass when the norm drops below 1/sqrt(2) of its value (DGKS)
-        double* vn = h->V + (int64_t)(j + 1) * n;
-        if (!adjoint) outer_op(h, zj, vn, s);
-        else outer_op_T(h, zj, vn, s);
-        gemm_tn<double, double>(n, j + 2, h->V, n, vn, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
-        gemv_acc_norm(n, j + 1, h->V, n, hbuf + SM_H1, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
-        HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        const double wn2 = h->h_small[SM_H1 + j + 1];
-        double hn2 = h->h_small[SM_HN];
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i];
-        if (hn2 < 0.5 * wn2) {
-          gemm_tn<double, double>(n, j + 1, h->V, n, vn, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
-          gemv_acc_norm(n, j + 1, h->V, n, hbuf + SM_H2, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
-          HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
-          HIPCHK(hipStreamSynchronize(s));
-          for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h->h_small[SM_H2 + i];
-          hn2 = h->h_small[SM_HN];
-          inf.reorth++;
-        }
-        const double hn = std::sqrt(hn2);
-        H[(size_t)(j + 1) * m + j] = hn;
-        if (hn != 0.0) scale(n, 1.0 / hn, vn, vn, s);
-        for (int i = 0; i < j; ++i) {
-          const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-          H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-          H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-        }
-        const double rr = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
-        if (rr == 0.0) {
-          cs[j] = 1.0;
-          sn[j] = 0.0;
-        } else {
-          cs[j] = H[(size_t)j * m + j] / rr;
-          sn[j] = H[(size_t)(j + 1) * m + j] / rr;
-        }
-        H[(size_t)j * m + j] = rr;
-        H[(size_t)(j + 1) * m + j] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        inf.outer_its++;
-        j_used = j + 1;
-        implicit_ok = std::fabs(g[j + 1]) <= thr;
-        if (h->opts.verbose)
-          std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, its,
-                       std::fabs(g[j + 1]) / bcn);
-        if (implicit_ok || hn == 0.0 || inf.outer_its >= o.max_outer) break;
-      }
+      scale(n, 1.0 / beta, rv, V, s);
+    } else {
+      end_cycle();
+    }
+  }
+
+  // Arnoldi step j with z_j = Z[:, j] just written by the preconditioner.
+  void after_prec(int its) {
+    inf.inner_its_total += its;
+    inf.inner_its_max = std::max(inf.inner_its_max, its);
+    double* hbuf = h->d_small;
+    double* zj = Z + (int64_t)j * n;
+    // w = A_chk z_j written straight into V[:, j+1]; classical Gram-Schmidt with
+    // one more pass when the norm drops below 1/sqrt(2) of its value (DGKS)
+    double* vn = V + (int64_t)(j + 1) * n;
+    op(zj, vn);
+    gemm_tn<double, double>(n, j + 2, V, n, vn, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
+    gemv_acc_norm(n, j + 1, V, n, hbuf + SM_H1, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
+    HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double wn2 = h->h_small[SM_H1 + j + 1];
+    double hn2 = h->h_small[SM_HN];
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i];
+    if (hn2 < 0.5 * wn2) {
+      gemm_tn<double, double>(n, j + 1, V, n, vn, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
+      gemv_acc_norm(n, j + 1, V, n, hbuf + SM_H2, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
+      HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h->h_small[SM_H2 + i];
+      hn2 = h->h_small[SM_HN];
+      inf.reorth++;
+    }
+    const double hn = std::sqrt(hn2);
+    H[(size_t)(j + 1) * m + j] = hn;
+    if (hn != 0.0) scale(n, 1.0 / hn, vn, vn, s);
+    for (int i = 0; i < j; ++i) {
+      const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+      H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+      H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+    }
+    const double rr = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+    if (rr == 0.0) {
+      cs[j] = 1.0;
+      sn[j] = 0.0;
+    } else {
+      cs[j] = H[(size_t)j * m + j] / rr;
+      sn[j] = H[(size_t)(j + 1) * m + j] / rr;
+    }
+    H[(size_t)j * m + j] = rr;
+    H[(size_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    inf.outer_its++;
+    implicit_ok = std::fabs(g[j + 1]) <= thr;
+    if (h->opts.verbose)
+      std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, its,
+                   std::fabs(g[j + 1]) / bcn);
+    ++j;
+    if (implicit_ok || hn == 0.0 || inf.outer_its >= o.max_outer || j == m) end_cycle();
+  }
+
+  // x_chk += Z y, back-transform, true residual; then finish or restart.
+  void end_cycle() {
+    const int j_used = j;
+    if (j_used > 0) {
       for (int i = j_used - 1; i >= 0; --i) {
         double acc = g[i];
         for (int l = i + 1; l < j_used; ++l) acc -= H[(size_t)i * m + l] * y[l];
         y[i] = acc / H[(size_t)i * m + i];
       }
       HIPCHK(hipMemcpyAsync(h->d_small + SM_Y, y.data(), j_used * sizeof(double), hipMemcpyHostToDevice, s));
-      gemv_acc(n, j_used, h->Z, n, h->d_small + SM_Y, 1.0, h->xchk, s);
+      gemv_acc(n, j_used, Z, n, h->d_small + SM_Y, 1.0, xchk, s);
     }
     inf.relres_implicit = std::fabs(g[j_used]) / bcn;
-    // back-transform and true residual on the original system
-    double relres;
     if (!adjoint) {
-      spmv(h->dS, h->xchk, x, h->d_dc, h->d_om, 0, nullptr, s);       // x = Dc S Omega x_chk
-      spmv(h->dA, x, h->rv, nullptr, nullptr, 1, b, s);                 // r = b - A x
+      spmv(h->dS, xchk, x, h->d_dc, h->d_om, 0, nullptr, s);       // x = Dc S Omega x_chk
+      spmv(h->dA, x, rv, nullptr, nullptr, 1, b, s);                 // r = b - A x
     } else {
-      scatter_scale(n, h->d_m, h->d_drp, h->d_om, h->xchk, x, s);      // lambda = Dr P^T Omega l_chk
-      spmv(h->dAt, x, h->rv, nullptr, nullptr, 1, b, s);                // r = g - A^T lambda
+      scatter_scale(n, h->d_m, h->d_drp, h->d_om, xchk, x, s);      // lambda = Dr P^T Omega l_chk
+      spmv(h->dAt, x, rv, nullptr, nullptr, 1, b, s);                // r = g - A^T lambda
     }
-    relres = std::sqrt(dot_host(h, n, h->rv, h->rv, s)) / bn;
+    const double relres = std::sqrt(dot_host(h, n, rv, rv, s)) / bn;
     inf.relres_true = relres;
     if (relres <= o.tol) {
       status = ASSS_OK;
       inf.converged = 1;
-      break;
+      done = true;
+      return;
     }
-    if (inf.outer_its >= o.max_outer) break;
+    if (inf.outer_its >= o.max_outer) {
+      done = true;
+      return;
+    }
     if (implicit_ok) thr = thr * 0.5 * o.tol / relres;
+    start_cycle();
   }
-  HIPCHK(hipStreamSynchronize(s));
-  inf.solve_s = now_s() - t0;
-  inf.inner_kernel_s = h->prof_s;
-  inf.inner_launches = h->prof_launches;
-  if (info) *info = inf;
-  return status;
+
+  asss_status_t finish(asss_info_t* info) {
+    HIPCHK(hipStreamSynchronize(s));
+    inf.solve_s = now_s() - t0;
+    inf.inner_kernel_s = h->prof_s;
+    inf.inner_launches = h->prof_launches;
+    if (info) *info = inf;
+    return status;
+  }
+};
+
+asss_status_t fgmres(asss_handle_s* h, bool adjoint, const double* b, double* x,
+                     const asss_solve_opts_t& o, asss_info_t* info, hipStream_t s) {
+  const bool fp32 = (o.inner_fp32 < 0) ? (h->opts.inner_fp32 != 0) : (o.inner_fp32 != 0);
+  ensure_outer(h, std::max(1, o.restart_m));
+  h->last_inner = 0;
+  h->prof_s = 0.0;
+  h->prof_launches = 0;
+  FgmresCol c;
+  c.begin(h, adjoint, b, x, o, h->V, h->Z, h->bchk, h->xchk, h->rv, s);
+  while (!c.done) {
+    const int its = adjoint ? prec_apply_T(h, fp32, c.v_next(), c.z_next(), o, s)
+                            : prec_apply(h, fp32, c.v_next(), c.z_next(), o, s);
+    c.after_prec(its);
+  }
+  return c.finish(info);
+}
+
+// Up to NRMAX right-hand sides of one system (columns of B and X, leading
+// dimension n) as FGMRES columns in lockstep: each step gathers the active
+// columns' v_j into one block, solves the inner system for all of them with
+// the simultaneous mrs of App. B (one pass over J_tilde and Q_k per inner
+// step; the stop rule is the maximum over the block, so a column may iterate
+// past its own tolerance), applies the SMW correction per column and lets each
+// column take its Arnoldi step.  Columns restart and finish independently.
+asss_status_t fgmres_block(asss_handle_s* h, int nc, const double* const* B, double* const* X,
+                           const asss_solve_opts_t& o, asss_info_t* infos, hipStream_t s) {
+  const int64_t n = h->n;
+  const bool fp32 = (o.inner_fp32 < 0) ? (h->opts.inner_fp32 != 0) : (o.inner_fp32 != 0);
+  const int m = std::max(1, o.restart_m);
+  ensure_multi(h, m, fp32);
+  h->last_inner = 0;
+  h->prof_s = 0.0;
+  h->prof_launches = 0;
+  FgmresCol cols[NRMAX];
+  for (int c = 0; c < nc; ++c)
+    cols[c].begin(h, false, B[c], X[c], o, h->mcol[c].V, h->mcol[c].Z, h->mcol[c].bchk, h->mcol[c].xchk,
+                  h->mcol[c].rv, s);
+  for (;;) {
+    int act[NRMAX], na = 0;
+    for (int c = 0; c < nc; ++c)
+      if (!cols[c].done) act[na++] = c;
+    if (na == 0) break;
+    for (int i = 0; i < na; ++i)
+      HIPCHK(hipMemcpyAsync(h->pin + (int64_t)i * n, cols[act[i]].v_next(), n * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    int its;
+    if (fp32)
+      its = run_mrs<float, NRMAX>(h, h->J32, h->d_Q32, h->d_f32, h->mb4_32, h->pin, h->pout, +1, o.inner_tol,
+                                  o.inner_maxit, o.fixed_inner_steps, s, na);
+    else
+      its = run_mrs<double, NRMAX>(h, h->J64, h->d_Q64, h->d_f64, h->mb4_64, h->pin, h->pout, +1, o.inner_tol,
+                                   o.inner_maxit, o.fixed_inner_steps, s, na);
+    for (int i = 0; i < na; ++i) {
+      FgmresCol& c = cols[act[i]];
+      double* z = c.z_next();
+      HIPCHK(hipMemcpyAsync(z, h->pout + (int64_t)i * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      smw_correct(h, z, s);
+      c.after_prec(its);
+    }
+  }
+  asss_status_t worst = ASSS_OK;
+  for (int c = 0; c < nc; ++c) {
+    asss_status_t st = cols[c].finish(infos ? &infos[c] : nullptr);
+    if (st > worst) worst = st;
+  }
+  return worst;
 }
 
 // Transpose-free QMR (Freund) on A_chk P^-1 y = b_chk with the iterate kept as
@@ -1226,18 +1388,50 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
   return guarded([&]() -> asss_status_t {
     if (nsys < 0 || (nsys > 0 && (!hs || !nrhs || !B_dev || !X_dev)))
       throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    asss_solve_opts_t oo = opts_or_default(o);
+    if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
+    if (oo.outer != ASSS_OUTER_FGMRES && oo.outer != ASSS_OUTER_TFQMR)
+      throw Error{ASSS_ERR_INVALID_ARG, "outer must be ASSS_OUTER_FGMRES or ASSS_OUTER_TFQMR"};
     int maxr = 0;
-    for (int sidx = 0; sidx < nsys; ++sidx) maxr = std::max(maxr, (int)nrhs[sidx]);
+    for (int sidx = 0; sidx < nsys; ++sidx) {
+      if (nrhs[sidx] < 0 || (nrhs[sidx] > 0 && (!B_dev[sidx] || !X_dev[sidx])))
+        throw Error{ASSS_ERR_INVALID_ARG, "bad nrhs or null block"};
+      check_handle(hs[sidx]);
+      maxr = std::max(maxr, (int)nrhs[sidx]);
+    }
+    // every right-hand side is checked before any is solved
+    for (int sidx = 0; sidx < nsys; ++sidx)
+      for (int j = 0; j < nrhs[sidx]; ++j)
+        if (!b_is_finite(hs[sidx], B_dev[sidx] + (int64_t)j * hs[sidx]->n, s))
+          throw Error{ASSS_ERR_NONFINITE, "a right-hand side has a non-finite entry"};
     asss_status_t worst = ASSS_OK;
     for (int sidx = 0; sidx < nsys; ++sidx) {
       asss_handle_t h = hs[sidx];
       check_handle(h);
-      for (int j = 0; j < nrhs[sidx]; ++j) {
-        asss_info_t inf{};
-        asss_status_t st = asss_solve(h, B_dev[sidx] + (int64_t)j * h->n, X_dev[sidx] + (int64_t)j * h->n, o,
-                                      &inf, hip_stream);
-        if (st < 0) return st;
-        if (infos) infos[(int64_t)sidx * maxr + j] = inf;
+      const int64_t n = h->n;
+      for (int j0 = 0; j0 < nrhs[sidx]; j0 += NRMAX) {
+        const int nc = std::min(NRMAX, (int)nrhs[sidx] - j0);
+        asss_info_t inf[NRMAX] = {};
+        asss_status_t st;
+        if (nc >= 2 && oo.outer == ASSS_OUTER_FGMRES) {
+          const double* bs[NRMAX];
+          double* xs[NRMAX];
+          for (int c = 0; c < nc; ++c) {
+            bs[c] = B_dev[sidx] + (int64_t)(j0 + c) * n;
+            xs[c] = X_dev[sidx] + (int64_t)(j0 + c) * n;
+          }
+          st = fgmres_block(h, nc, bs, xs, oo, inf, s);
+        } else {
+          st = ASSS_OK;
+          for (int c = 0; c < nc; ++c) {
+            asss_status_t sc = outer_solve(h, false, B_dev[sidx] + (int64_t)(j0 + c) * n,
+                                           X_dev[sidx] + (int64_t)(j0 + c) * n, oo, &inf[c], s);
+            if (sc > st) st = sc;
+          }
+        }
+        if (infos)
+          for (int c = 0; c < nc; ++c) infos[(int64_t)sidx * maxr + j0 + c] = inf[c];
         if (st > worst) worst = st;
       }
     }

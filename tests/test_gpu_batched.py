@@ -1,0 +1,100 @@
+"""Batched solves (several uneven systems, several right-hand sides each)
+through asss_solve_batched: FGMRES columns of a system advance in lockstep
+with one simultaneous inner mrs (App. B) per step.  Checked against the oracle
+(per-system solves) and dense solves, against column-by-column solves, and on
+the error path."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_06954_amd as asss
+    asss.load()
+    return asss
+
+
+def _colmajor(B):
+    """(n, nrhs) float64 CUDA tensor with column-major storage."""
+    return torch.from_numpy(np.ascontiguousarray(B.T)).cuda().t()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def batch():
+    asss = _lib()
+    ws = W.batched_implicit_euler(nsys=4, n_lo=400, n_hi=3000, nrhs=4, cfg=3)
+    nr = [4, 3, 1, 2]
+    hs = [asss.setup(w.A, k=8, s_pattern="tridiag") for w in ws]
+    print("[batch] sizes", [w.A.shape[0] for w in ws], "h", [round(w.meta["h"], 3) for w in ws], flush=True)
+    yield asss, ws, nr, hs
+    for h in hs:
+        h.close()
+
+
+def test_batched_against_oracle_and_dense(batch):
+    asss, ws, nr, hs = batch
+    Bs = [_colmajor(w.b[:, :r]) for w, r in zip(ws, nr)]
+    Xs, infos = asss.solve_batched(hs, Bs, tol=1e-10)
+    for s, (w, r) in enumerate(zip(ws, nr)):
+        X = Xs[s].detach().cpu().numpy()
+        st = O.setup(w.A, O.SetupOptions(k=8, s_pattern="tridiag"))
+        Ad = w.A.toarray()
+        kappa = np.linalg.cond(Ad)
+        for j in range(r):
+            inf = infos[s][j]
+            assert inf["converged"] == 1 and inf["relres_true"] <= 1e-10, inf
+            xo, io = O.solve(st, w.b[:, j], O.SolveOptions(tol=1e-12))
+            xd = np.linalg.solve(Ad, w.b[:, j])
+            bound = max(1e-9, 10 * kappa * 1e-10)
+            assert _rel(X[:, j], xd) <= bound and _rel(X[:, j], xo) <= bound, (s, j, kappa)
+
+
+def test_batched_block_matches_single_columns(batch):
+    asss, ws, nr, hs = batch
+    w, h = ws[0], hs[0]
+    B = w.b[:, :4]
+    Xs, infos = asss.solve_batched([h], [_colmajor(B)], tol=1e-12)
+    X = Xs[0].detach().cpu().numpy()
+    for j in range(4):
+        x, info = h.solve(torch.from_numpy(B[:, j].copy()).cuda(), tol=1e-12)
+        assert info["status"] == "OK"
+        assert _rel(X[:, j], x.cpu().numpy()) <= 1e-9
+    # the block shares one inner solve per outer step: its inner count is the
+    # same for every column of the block
+    assert len({i["inner_its_total"] for i in infos[0]}) <= 4
+
+
+def test_batched_mixed_precision_and_tfqmr(batch):
+    asss, ws, nr, hs = batch
+    Bs = [_colmajor(w.b[:, :r]) for w, r in zip(ws, nr)]
+    for kw in (dict(inner_fp32=True), dict(outer="tfqmr")):
+        Xs, infos = asss.solve_batched(hs, Bs, tol=1e-8, **kw)
+        for s, (w, r) in enumerate(zip(ws, nr)):
+            X = Xs[s].detach().cpu().numpy()
+            Ad = w.A.toarray()
+            kappa = np.linalg.cond(Ad)
+            for j in range(r):
+                assert infos[s][j]["relres_true"] <= 1e-8, (kw, s, j)
+                xd = np.linalg.solve(Ad, w.b[:, j])
+                assert _rel(X[:, j], xd) <= max(1e-7, 10 * kappa * 1e-8), (kw, s, j)
+
+
+def test_batched_rejects_nonfinite(batch):
+    asss, ws, nr, hs = batch
+    B = ws[1].b[:, :3].copy()
+    B[7, 2] = np.nan
+    with pytest.raises(asss.AsssError, match="NONFINITE"):
+        asss.solve_batched([hs[0], hs[1]], [_colmajor(ws[0].b[:, :2]), _colmajor(B)], tol=1e-8)
