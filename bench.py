@@ -88,6 +88,49 @@ def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, 
     }
 
 
+def batched(args, asss, torch, np, W):
+    """64 uneven systems x 4 right-hand sides: the lockstep block solve against
+    solving the same columns one at a time (same handles, same options)."""
+    ws = W.batched_implicit_euler(nsys=args.nsys, nrhs=4, cfg=3)
+    log(f"batched: {len(ws)} systems, n from {min(w.A.shape[0] for w in ws)} to "
+        f"{max(w.A.shape[0] for w in ws)}, total {sum(w.A.shape[0] for w in ws)}")
+    t0 = time.perf_counter()
+    hs = [asss.setup(w.A, k=8, s_pattern="tridiag") for w in ws]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup {setup_s:.1f} s")
+    Bs = [torch.from_numpy(np.ascontiguousarray(w.b.T)).cuda().t() for w in ws]
+    kw = dict(tol=args.tol, inner_fp32=not args.no_mixed, restart_m=64, inner_tol=1e-2)
+    asss.solve_batched(hs[:2], Bs[:2], **kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xs, infos = asss.solve_batched(hs, Bs, **kw)
+    torch.cuda.synchronize()
+    t_block = time.perf_counter() - t0
+    nrhs = sum(B.shape[1] for B in Bs)
+    worst = max(i["relres_true"] for row in infos for i in row)
+    t0 = time.perf_counter()
+    worst1 = 0.0
+    for h, B in zip(hs, Bs):
+        for j in range(B.shape[1]):
+            _, inf = h.solve(B[:, j].contiguous(), **kw)
+            worst1 = max(worst1, inf["relres_true"])
+    torch.cuda.synchronize()
+    t_cols = time.perf_counter() - t0
+    for h in hs:
+        h.close()
+    res = {"metric": "batched solve throughput (right-hand sides to 1e-8 per second)",
+           "value": round(nrhs / t_block, 3), "unit": "rhs/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32 inner / f64 outer" if not args.no_mixed else "f64", "data": "synthetic",
+           "config": {"workload": f"implicit_euler_batched_{len(ws)}x4", "systems": len(ws),
+                      "total_n": int(sum(w.A.shape[0] for w in ws)), "rhs": nrhs, "k": 8, "s_pattern": "tridiag",
+                      "tol": args.tol, "outer": "fgmres(64)", "inner_tol": 1e-2},
+           "block_s": round(t_block, 3), "column_by_column_s": round(t_cols, 3),
+           "speedup_block_vs_columns": round(t_cols / t_block, 3),
+           "worst_relres_block": worst, "worst_relres_columns": worst1, "setup_s": round(setup_s, 1)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +153,13 @@ def main():
                     help="profiling probe: setup, a 1 GiB device copy (counter calibration), then "
                          "--probe-steps fixed inner mrs steps in FP64 and in FP32; no solve")
     ap.add_argument("--probe-steps", type=int, default=50)
+    ap.add_argument("--batched", action="store_true",
+                    help="batched workload instead: 64 uneven implicit-Euler systems (n log-uniform in "
+                         "[1e4, 5e5]), 4 right-hand sides each, FP32 inner / FP64 outer, tol 1e-8; "
+                         "reports right-hand sides per second for the lockstep block solve and for "
+                         "column-by-column solves")
+    ap.add_argument("--nsys", type=int, default=64)
+    ap.add_argument("--outer", default="fgmres", choices=["fgmres", "tfqmr"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -127,6 +177,8 @@ def main():
         sys.exit(1)
     asss.load()
     torch.cuda.set_device(0)
+    if args.batched:
+        return batched(args, asss, torch, np, W)
     log(f"building workload m={args.m} Pe={args.peclet}")
     w = W.convdiff3d(m=args.m, peclet=args.peclet, cfg=1)
     n, nnz = w.A.shape[0], w.A.nnz
@@ -165,7 +217,7 @@ def main():
     def run(mixed: bool, steps: int, warmup: int):
         for i in range(warmup):
             _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed, restart_m=args.restart,
-                             inner_tol=args.inner_tol, max_outer=args.max_outer)
+                             inner_tol=args.inner_tol, max_outer=args.max_outer, outer=args.outer)
             log(f"warmup {'mixed' if mixed else 'fp64'} {i}: {inf['solve_s']:.3f} s, "
                 f"outer {inf['outer_its']}, inner {inf['inner_its_total']}, relres {inf['relres_true']:.2e}")
         torch.cuda.synchronize()
@@ -173,7 +225,7 @@ def main():
         t0 = time.perf_counter()
         for i in range(steps):
             _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed, restart_m=args.restart,
-                             inner_tol=args.inner_tol, max_outer=args.max_outer)
+                             inner_tol=args.inner_tol, max_outer=args.max_outer, outer=args.outer)
             infos.append(inf)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
@@ -211,7 +263,8 @@ def main():
         "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"convdiff3d_{args.m}^3_Pe{args.peclet:g}", "n": n, "nnz": nnz,
                    "k": args.k, "s_pattern": "abar", "tol": args.tol,
-                   "outer": f"fgmres({args.restart})", "inner_tol": args.inner_tol},
+                   "outer": f"fgmres({args.restart})" if args.outer == "fgmres" else "tfqmr",
+                   "inner_tol": args.inner_tol},
         "roofline": roofline(inf64, 8),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
                   "relres_true": inf64[-1]["relres_true"], "rel_err_vs_xstar": err64,

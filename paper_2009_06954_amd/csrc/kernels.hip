@@ -217,7 +217,9 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
   constexpr int P = (NR == 1) ? 2 : 1;
   constexpr int U = (NR == 1) ? 4 : 8;
   constexpr int NW = WG / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is uniform: said so, the slice metadata below comes in
+  // through scalar loads instead of a vector round trip per slice
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nsl = (nrow + 63) >> 6;
   const int64_t s0 = row0 >> 6;
   for (int sl0 = wave; sl0 < nsl; sl0 += P * NW) {
