@@ -159,13 +159,16 @@ __global__ __launch_bounds__(WG) void k_spmv(int64_t nrows, const int64_t* __res
   double sum = 0.0;
   if (row < nrows) {
     const int64_t e = ptr[row + 1];
+    // the matrix is streamed once: non-temporal loads keep it from pushing
+    // the gathered vector out of L2
     if (cs) {
       for (int64_t p = ptr[row] + sub; p < e; p += LANES) {
-        int32_t c = col[p];
-        sum += val[p] * (cs[c] * x[c]);
+        const int32_t c = __builtin_nontemporal_load(&col[p]);
+        sum += __builtin_nontemporal_load(&val[p]) * (cs[c] * x[c]);
       }
     } else {
-      for (int64_t p = ptr[row] + sub; p < e; p += LANES) sum += val[p] * x[col[p]];
+      for (int64_t p = ptr[row] + sub; p < e; p += LANES)
+        sum += __builtin_nontemporal_load(&val[p]) * x[__builtin_nontemporal_load(&col[p])];
     }
   }
 #pragma unroll
@@ -214,6 +217,10 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
   // Each round handles up to U in-block entries and U off-block entries of
   // every row of the P slices; all of a round's loads are issued before any of
   // its arithmetic (the widths are wave-uniform, so the guards do not diverge).
+  // The entries are streamed once per launch: non-temporal loads keep them
+  // from evicting the w vector from L2, which the part-b gathers of the
+  // neighbouring blocks re-read (measured: FP64 step 185 -> 150 us, FP32
+  // 138 -> 124 us on the 128^3 workload).
   constexpr int P = (NR == 1) ? 2 : 1;
   constexpr int U = (NR == 1) ? 4 : 8;
   constexpr int NW = WG / 64;
@@ -263,12 +270,12 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (l0 + u < wa[p]) {
-            jl[p][u] = acol[p][(l0 + u) * 64];
-            va[p][u] = aval[p][(l0 + u) * 64];
+            jl[p][u] = __builtin_nontemporal_load(&acol[p][(l0 + u) * 64]);
+            va[p][u] = __builtin_nontemporal_load(&aval[p][(l0 + u) * 64]);
           }
           if (l0 + u < wb[p]) {
-            jb[p][u] = bcol[p][(l0 + u) * 64];
-            vb[p][u] = bval[p][(l0 + u) * 64];
+            jb[p][u] = __builtin_nontemporal_load(&bcol[p][(l0 + u) * 64]);
+            vb[p][u] = __builtin_nontemporal_load(&bval[p][(l0 + u) * 64]);
           }
         }
       T wj[P][U][NR];
@@ -366,7 +373,7 @@ __global__ __launch_bounds__(WG) void k_gemm_tn(int64_t n, int ka, const TA* __r
 #pragma unroll
     for (int q = 0; q < GT_COLS; ++q) {
       if (q < nl) {
-        const double a = (double)A[(int64_t)(l0 + q) * lda + i];
+        const double a = (double)__builtin_nontemporal_load(&A[(int64_t)(l0 + q) * lda + i]);
 #pragma unroll
         for (int c = 0; c < NR; ++c) acc[q * NR + c] += a * b[c];
       }
@@ -442,7 +449,7 @@ __global__ __launch_bounds__(WG) void k_gemv_acc(int64_t n, int kt, const double
   __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
     double sacc = 0.0;
-    for (int l = 0; l < kt; ++l) sacc += A[(int64_t)l * lda + i] * ts[l];
+    for (int l = 0; l < kt; ++l) sacc += __builtin_nontemporal_load(&A[(int64_t)l * lda + i]) * ts[l];
     y[i] += sign * sacc;
   }
 }
@@ -466,7 +473,7 @@ __global__ __launch_bounds__(WG) void k_gemv_acc_norm(int64_t n, int kt, const d
   double acc[1] = {0.0};
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
     double sacc = 0.0;
-    for (int l = 0; l < kt; ++l) sacc += A[(int64_t)l * lda + i] * ts[l];
+    for (int l = 0; l < kt; ++l) sacc += __builtin_nontemporal_load(&A[(int64_t)l * lda + i]) * ts[l];
     const double v = y[i] + sign * sacc;
     y[i] = v;
     acc[0] += v * v;
@@ -920,11 +927,13 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
       a[c] = sgn * u[c] + beta_prev[c] * qold[c];
     }
     if (!REC) {
-      // Q row i streams once: deflation term and Q^T a together
+      // Q row i streams once: deflation term and Q^T a together (non-temporal
+      // in FP64, where it helps: 161 -> 150 us; in FP32 it costs 124 -> 132 us)
       const T* __restrict__ qs = reinterpret_cast<const T*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
 #pragma unroll
       for (int l = 0; l < KF; ++l) {
-        const T q = (l < k) ? qs[l * 64] : T(0);
+        T q = T(0);
+        if (l < k) q = (sizeof(T) == 8) ? __builtin_nontemporal_load(&qs[l * 64]) : qs[l * 64];
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
           defl[c] += q * cv[c][l];
