@@ -15,17 +15,30 @@ namespace asss {
 // Reductions
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// v moved across lanes by one DPP pattern (the two 32-bit halves separately);
+// lanes outside ROW_MASK get 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum_t(T v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Sum over the 64 lanes of a wave in a fixed order, with DPP lane moves (VALU)
+// instead of LDS permutes: pairs and quads (quad_perm), rows of 16 (row_ror 4
+// and 8: every lane then holds its row's sum), then row 1 += row 0 and row 3
+// += row 2 (row_bcast:15), rows 2-3 += rows 0-1 (row_bcast:31); lane 63 holds
+// the total, which is returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124, 0xf>(v);  // row_ror:4
+  v += dpp_move<0x128, 0xf>(v);  // row_ror:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Reduce NV per-thread values over the workgroup; results in res[0..NV).
