@@ -220,13 +220,16 @@ void spmv(const DCsr& M, const double* x, double* y, const double* rs, const dou
 // One workgroup per block of R rows; wave w handles slices w, w + 4, ... of it,
 // P slices at a time (P = 2 for one column: twice the loads in flight per wave).
 // w_src(jl) reads the gathered vector at local row jl (LDS or global).
-// Accumulates the block's results into acc_lds[il * NR + c].
+// Accumulates the block's results into acc_lds[il * NR + c], which is FP64 in
+// both precisions: LDS float atomics (ds_add_f32) are slow on this chip (the
+// FP32 step spent about 24 of its 120 us in them), ds_add_f64 is not, and the
+// FP64 sums round to T once when read.
 // ---------------------------------------------------------------------------
 
 template <typename T, int NR, bool STAGE>
 __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
                                                 const T* __restrict__ wg, const T* w_lds,
-                                                T* acc_lds) {
+                                                double* acc_lds) {
   // Each round handles up to U in-block entries and U off-block entries of
   // every row of the P slices; all of a round's loads are issued before any of
   // its arithmetic (the widths are wave-uniform, so the guards do not diverge).
@@ -309,7 +312,7 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
             for (int c = 0; c < NR; ++c) {
               const T w = STAGE ? w_lds[jl[p][u] * NR + c] : wg[(row0 + jl[p][u]) * NR + c];
               acc[p][c] += va[p][u] * w;
-              if (valid[p]) atomicAdd(&acc_lds[jl[p][u] * NR + c], -va[p][u] * wi[p][c]);
+              if (valid[p]) atomicAdd(&acc_lds[jl[p][u] * NR + c], (double)(-va[p][u] * wi[p][c]));
             }
           }
 #pragma unroll
@@ -325,7 +328,7 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
     for (int p = 0; p < P; ++p)
       if (valid[p]) {
 #pragma unroll
-        for (int c = 0; c < NR; ++c) atomicAdd(&acc_lds[il[p] * NR + c], acc[p][c]);
+        for (int c = 0; c < NR; ++c) atomicAdd(&acc_lds[il[p] * NR + c], (double)acc[p][c]);
       }
   }
 }
@@ -334,23 +337,23 @@ template <typename T>
 __global__ __launch_bounds__(WG) void k_skew_spmv(DSkew<T> J, const T* __restrict__ x,
                                                   T* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* w_lds = reinterpret_cast<T*>(smem_raw);
-  T* acc_lds = w_lds + J.R;
+  double* acc_lds = reinterpret_cast<double*>(smem_raw);
+  T* w_lds = reinterpret_cast<T*>(acc_lds + J.R);
   const int64_t row0 = (int64_t)blockIdx.x * J.R;
   const int nrow = (int)min((int64_t)J.R, (int64_t)J.n - row0);
   for (int r = threadIdx.x; r < nrow; r += WG) {
     w_lds[r] = x[row0 + r];
-    acc_lds[r] = T(0);
+    acc_lds[r] = 0.0;
   }
   __syncthreads();
   skew_block_pass<T, 1, true>(J, row0, nrow, x, w_lds, acc_lds);
   __syncthreads();
-  for (int r = threadIdx.x; r < nrow; r += WG) y[row0 + r] = acc_lds[r];
+  for (int r = threadIdx.x; r < nrow; r += WG) y[row0 + r] = (T)acc_lds[r];
 }
 
 template <typename T>
 void skew_spmv(const DSkew<T>& J, const T* x, T* y, hipStream_t s) {
-  size_t lds = 2 * (size_t)J.R * sizeof(T);
+  size_t lds = (size_t)J.R * (sizeof(double) + sizeof(T));
   hipLaunchKernelGGL(k_skew_spmv<T>, dim3(J.nblocks), dim3(WG), lds, s, J, x, y);
 }
 template void skew_spmv<double>(const DSkew<double>&, const double*, double*, hipStream_t);
@@ -833,8 +836,8 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
                                                  unsigned* ticket) {
   constexpr int NV = REC ? 2 * NR : (KF + 1) * NR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* acc_lds = reinterpret_cast<T*>(smem_raw);
-  T* w_lds = acc_lds + (size_t)J.R * NR;
+  double* acc_lds = reinterpret_cast<double*>(smem_raw);
+  T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
   __shared__ double lds[(WG / 64) * NV];
   __shared__ double res[NV];
   // The state was written by the previous launch and is not written before
@@ -898,7 +901,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
 
   // operator pass: acc_lds = J_tilde w_t on this block
   for (int r = threadIdx.x; r < nrow * NR; r += WG) {
-    acc_lds[r] = T(0);
+    acc_lds[r] = 0.0;
     if (STAGE) w_lds[r] = wcur[row0 * NR + r];
   }
   __syncthreads();
@@ -935,7 +938,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     T u[NR], qold[NR], a[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-      u[c] = acc_lds[il * NR + c] * inv_nu[c];
+      u[c] = (T)acc_lds[il * NR + c] * inv_nu[c];
       qold[c] = wold[i * NR + c] * inv_nu_old[c];
       a[c] = sgn * u[c] + beta_prev[c] * qold[c];
     }
@@ -1012,7 +1015,7 @@ template <typename T, int NR>
 void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf, MrsState* st,
               Reducer& red, hipStream_t s) {
   constexpr bool STAGE = (NR == 1);
-  size_t lds = (size_t)J.R * NR * sizeof(T) * (STAGE ? 2 : 1);
+  size_t lds = (size_t)J.R * NR * (sizeof(double) + (STAGE ? sizeof(T) : 0));
   const int kf = pick_kf(L.k, NR);
 #define ASSS_ITER(KF)                                                                              \
   hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false>), dim3(J.nblocks), dim3(WG), lds, s, L, J, \
