@@ -235,6 +235,8 @@ typedef struct {
   int32_t reordered;                      /* 1 if the inner system uses block order */
   int64_t cross_pairs_natural;            /* strictly upper pairs straddling two row blocks */
   int64_t cross_pairs_used;               /* the same in the order used */
+  int32_t narrow_b_columns;               /* 1: off-block columns stored as 16-bit deltas
+                                             from per-slot bases (grid-like patterns) */
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);

@@ -18,8 +18,8 @@ split       A_hat = Abar S, D, Omega, J_tilde, negative-diagonal set (Sec. 3)
 lanczos     counter-based start vector and the skew-Lanczos process (Fig. 2)
 mrs         simultaneous minimal residual iterations for (alpha I + K) x = b (App. B)
 precond     deflated operator, combined low-rank term and its SMW application (Sec. 3.2)
-solver      flexible GMRES outer iteration, back-transform, adjoint, value
-            gradient of a solve (Sec. 3, Sec. 4.1)
+solver      outer iterations (flexible GMRES; TFQMR as in the experiments),
+            back-transform, adjoint, value gradient of a solve (Sec. 3, Sec. 4.1)
 """
 from .preprocess import (StructurallySingular, ZeroDiagonal, validate_csr,
                          max_product_matching, canonical_scaling, permute_scale)

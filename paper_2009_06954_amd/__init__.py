@@ -81,7 +81,8 @@ class HandleInfo(C.Structure):
                 ("nblocks", C.c_int32), ("sell_entries_a", C.c_int64),
                 ("sell_entries_b", C.c_int64), ("lls_relres", C.c_double), ("lls_kkt", C.c_double),
                 ("lanczos_orth_err", C.c_double), ("deflation_mode", C.c_int32), ("reordered", C.c_int32),
-                ("cross_pairs_natural", C.c_int64), ("cross_pairs_used", C.c_int64)]
+                ("cross_pairs_natural", C.c_int64), ("cross_pairs_used", C.c_int64),
+                ("narrow_b_columns", C.c_int32)]
 
     def to_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

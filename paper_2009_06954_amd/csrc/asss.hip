@@ -101,7 +101,7 @@ DCsr upload_csr(DevArena& ar, const Csr& M, hipStream_t s) {
 template <typename T>
 DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32_t* aw,
                      const int32_t* bw, const int64_t* ao, const int64_t* bo, const uint16_t* ac,
-                     const int32_t* bc) {
+                     const int32_t* bc, const uint16_t* bcd, const int32_t* bbase) {
   DSkew<T> d;
   d.n = S.n;
   d.R = S.R;
@@ -113,6 +113,9 @@ DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32
   d.b_off = bo;
   d.a_col = ac;
   d.b_col = bc;
+  d.b_cd = bcd;
+  d.b_base = bbase;
+  d.b_narrow = S.b_narrow ? 1 : 0;
   std::vector<T> av(S.a_val.begin(), S.a_val.end()), bv(S.b_val.begin(), S.b_val.end());
   d.a_val = ar.upload(av, s);
   d.b_val = ar.upload(bv, s);
@@ -149,6 +152,7 @@ struct asss_handle_s {
   std::vector<int32_t> perm;
   int32_t* d_perm = nullptr;  // null when the natural order is kept
   int64_t cross_natural = 0, cross_used = 0;
+  int narrow_b = 0;  // part-b columns stored as 16-bit deltas
   double* d_Qorig = nullptr;  // Q_k in the original order (U_bar, export)
   double* d_Q64 = nullptr;    // Q_k in the inner (block) order
   float* d_Q32 = nullptr;
@@ -1280,9 +1284,14 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
       const int64_t* ao = h->ar.upload(sell.a_off, s);
       const int64_t* bo = h->ar.upload(sell.b_off, s);
       const uint16_t* ac = h->ar.upload(sell.a_col, s);
-      const int32_t* bc = h->ar.upload(sell.b_col, s);
-      h->J64 = upload_sell<double>(h->ar, sell, s, aw, bw, ao, bo, ac, bc);
-      h->J32 = upload_sell<float>(h->ar, sell, s, aw, bw, ao, bo, ac, bc);
+      // part-b columns: 16-bit deltas from per-slot bases when every slot fits
+      // (2 bytes per entry instead of 4), else global 32-bit columns
+      const int32_t* bc = sell.b_narrow ? nullptr : h->ar.upload(sell.b_col, s);
+      const uint16_t* bcd = sell.b_narrow ? h->ar.upload(sell.b_cd, s) : nullptr;
+      const int32_t* bbase = sell.b_narrow ? h->ar.upload(sell.b_base, s) : nullptr;
+      h->narrow_b = sell.b_narrow ? 1 : 0;
+      h->J64 = upload_sell<double>(h->ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
+      h->J32 = upload_sell<float>(h->ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
     }
     for (int b = 0; b < 3; ++b) { h->mb64.w[b] = h->ar.alloc<double>(n); h->mb32.w[b] = h->ar.alloc<float>(n); }
     for (int b = 0; b < 2; ++b) { h->mb64.p[b] = h->ar.alloc<double>(n); h->mb32.p[b] = h->ar.alloc<float>(n); }
@@ -1471,6 +1480,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.lls_relres = h->lls_relres;
     i.lls_kkt = h->lls_kkt;
     i.lanczos_orth_err = h->orth_err;
+    i.narrow_b_columns = h->narrow_b;
     i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : 1);
     i.reordered = h->d_perm ? 1 : 0;
     i.cross_pairs_natural = h->cross_natural;

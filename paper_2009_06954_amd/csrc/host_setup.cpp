@@ -661,6 +661,43 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
   for (int64_t i = 0; i < n; ++i) { ta += na[i]; tb += nb[i]; }
   S.a_entries = ta;
   S.b_entries = tb;
+  // narrow part-b columns: per slot, base = smallest real column; padding
+  // entries (value 0) take the base so that they do not widen the span
+  const int64_t nslots = S.b_off[S.nslices] / 64;
+  S.b_base.assign(nslots, 0);
+  std::atomic<int> wide(0);
+  parallel_for(S.nslices, [&](int64_t lo, int64_t hi) {
+    for (int64_t s = lo; s < hi; ++s) {
+      for (int32_t l = 0; l < S.b_width[s]; ++l) {
+        const int64_t q0 = S.b_off[s] + (int64_t)l * 64;
+        int64_t mn = INT64_MAX, mx = INT64_MIN;
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t i = s * 64 + lane;
+          const bool real = i < n && l < nb[i];
+          if (real) {
+            mn = std::min<int64_t>(mn, S.b_col[q0 + lane]);
+            mx = std::max<int64_t>(mx, S.b_col[q0 + lane]);
+          }
+        }
+        if (mn == INT64_MAX) mn = mx = S.b_col[q0];  // cannot happen: l < width
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t i = s * 64 + lane;
+          if (!(i < n && l < nb[i])) S.b_col[q0 + lane] = (int32_t)mn;
+        }
+        S.b_base[q0 / 64] = (int32_t)mn;
+        if (mx - mn > 65535) wide = 1;
+      }
+    }
+  });
+  S.b_narrow = (wide == 0);
+  if (S.b_narrow) {
+    S.b_cd.resize(S.b_col.size());
+    parallel_for(nslots, [&](int64_t lo, int64_t hi) {
+      for (int64_t t = lo; t < hi; ++t)
+        for (int lane = 0; lane < 64; ++lane)
+          S.b_cd[t * 64 + lane] = (uint16_t)(S.b_col[t * 64 + lane] - S.b_base[t]);
+    });
+  }
   return S;
 }
 

@@ -94,7 +94,13 @@ struct SkewSell {
   std::vector<int32_t> a_width, b_width;  // per slice
   std::vector<int64_t> a_off, b_off;      // per slice, offset in entries
   std::vector<uint16_t> a_col;
-  std::vector<int32_t> b_col;
+  std::vector<int32_t> b_col;             // global column (wide form)
+  // narrow form of the part-b columns, used when every (slice, slot) of part
+  // b spans fewer than 2^16 columns (grid-like matrices): column = base of the
+  // slot + 16-bit delta; b_base has one entry per slot (b_off[s] / 64 + l)
+  bool b_narrow = false;
+  std::vector<int32_t> b_base;
+  std::vector<uint16_t> b_cd;
   std::vector<double> a_val, b_val;
   int64_t a_entries = 0, b_entries = 0;   // real (unpadded) entries
 };

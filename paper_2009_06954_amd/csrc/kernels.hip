@@ -226,10 +226,10 @@ void spmv(const DCsr& M, const double* x, double* y, const double* rs, const dou
 // FP64 sums round to T once when read.
 // ---------------------------------------------------------------------------
 
-template <typename T, int NR, bool STAGE>
-__device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
-                                                const T* __restrict__ wg, const T* w_lds,
-                                                double* acc_lds) {
+template <typename T, int NR, bool STAGE, bool NARROW>
+__device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t row0, int nrow,
+                                                     const T* __restrict__ wg, const T* w_lds,
+                                                     double* acc_lds) {
   // Each round handles up to U in-block entries and U off-block entries of
   // every row of the P slices; all of a round's loads are issued before any of
   // its arithmetic (the widths are wave-uniform, so the guards do not diverge).
@@ -251,6 +251,8 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
     const uint16_t* __restrict__ acol[P];
     const T* __restrict__ aval[P];
     const int32_t* __restrict__ bcol[P];
+    const uint16_t* __restrict__ bcd[P];
+    const int32_t* __restrict__ bbase[P];
     const T* __restrict__ bval[P];
     T acc[P][NR], wi[P][NR];
     int wmax = 0;
@@ -267,6 +269,8 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
       acol[p] = J.a_col + J.a_off[s] + lane;
       aval[p] = J.a_val + J.a_off[s] + lane;
       bcol[p] = J.b_col + J.b_off[s] + lane;
+      bcd[p] = J.b_cd + J.b_off[s] + lane;
+      bbase[p] = J.b_base + (J.b_off[s] >> 6);
       bval[p] = J.b_val + J.b_off[s] + lane;
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
@@ -290,7 +294,11 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
             va[p][u] = __builtin_nontemporal_load(&aval[p][(l0 + u) * 64]);
           }
           if (l0 + u < wb[p]) {
-            jb[p][u] = __builtin_nontemporal_load(&bcol[p][(l0 + u) * 64]);
+            // narrow: the 16-bit delta now, its slot base (uniform) at the gather
+            if (NARROW)
+              jb[p][u] = (int32_t)__builtin_nontemporal_load(&bcd[p][(l0 + u) * 64]);
+            else
+              jb[p][u] = __builtin_nontemporal_load(&bcol[p][(l0 + u) * 64]);
             vb[p][u] = __builtin_nontemporal_load(&bval[p][(l0 + u) * 64]);
           }
         }
@@ -300,8 +308,9 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
 #pragma unroll
         for (int u = 0; u < U; ++u)
           if (l0 + u < wb[p]) {
+            const int32_t col = NARROW ? bbase[p][l0 + u] + jb[p][u] : jb[p][u];
 #pragma unroll
-            for (int c = 0; c < NR; ++c) wj[p][u][c] = wg[(int64_t)jb[p][u] * NR + c];
+            for (int c = 0; c < NR; ++c) wj[p][u][c] = wg[(int64_t)col * NR + c];
           }
 #pragma unroll
       for (int p = 0; p < P; ++p)
@@ -331,6 +340,17 @@ __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0,
         for (int c = 0; c < NR; ++c) atomicAdd(&acc_lds[il[p] * NR + c], (double)acc[p][c]);
       }
   }
+}
+
+// The column form of part b is fixed per matrix: one uniform branch per launch.
+template <typename T, int NR, bool STAGE>
+__device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
+                                                const T* __restrict__ wg, const T* w_lds,
+                                                double* acc_lds) {
+  if (J.b_narrow)
+    skew_block_pass_form<T, NR, STAGE, true>(J, row0, nrow, wg, w_lds, acc_lds);
+  else
+    skew_block_pass_form<T, NR, STAGE, false>(J, row0, nrow, wg, w_lds, acc_lds);
 }
 
 template <typename T>

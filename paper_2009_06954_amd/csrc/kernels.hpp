@@ -30,7 +30,10 @@ struct DSkew {
   const int64_t* a_off = nullptr;
   const int64_t* b_off = nullptr;
   const uint16_t* a_col = nullptr;
-  const int32_t* b_col = nullptr;
+  const int32_t* b_col = nullptr;   // wide part-b columns (b_narrow == 0)
+  const uint16_t* b_cd = nullptr;   // narrow: column = b_base[b_off / 64 + slot] + b_cd
+  const int32_t* b_base = nullptr;
+  int32_t b_narrow = 0;
   const T* a_val = nullptr;
   const T* b_val = nullptr;
 };

@@ -53,6 +53,7 @@ def test_fullsize_launch_configuration(full):
     i = full["info"]
     assert i["n"] == M ** 3 and i["row_block"] == 2048 and i["nblocks"] == M ** 3 // 2048
     assert i["k_eff"] == 16 and i["nh"] == full["J"].nnz // 2
+    assert i["narrow_b_columns"] == 1  # off-block columns as 16-bit deltas
 
 
 @pytest.mark.parametrize("fp32", [False, True])

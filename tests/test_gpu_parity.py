@@ -428,3 +428,27 @@ def test_outer_method_must_be_known(cfg0):
     st = asss.load().asss_solve(cfg0.h._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                 C.byref(o), None, asss._stream())
     assert st == -1
+
+
+def test_column_storage_forms(cfg0):
+    """Grid matrices store their off-block columns as 16-bit deltas from
+    per-slot bases (the operator tests above run on that form); a random
+    pattern with n = 120,000 spans more than 2^16 columns per slot and keeps
+    global 32-bit columns: its skew operator is checked against the exported
+    CSR of J_tilde, componentwise and for exact skewness."""
+    asss = _lib()
+    assert cfg0.h.info()["narrow_b_columns"] == 1
+    w = W.paper_like(120000, 600000, seed=3)
+    print(f"[wide] n={w.A.shape[0]} nnz={w.A.nnz}", flush=True)
+    h = asss.setup(w.A, k=4, s_pattern="tridiag")
+    assert h.info()["narrow_b_columns"] == 0
+    U = sp.csr_matrix((h.array("J_val"), h.array("J_colind"), h.array("J_rowptr")), shape=w.A.shape)
+    J = (U - U.T).tocsr()
+    v = np.random.default_rng(9).uniform(-1, 1, w.A.shape[0])
+    for fp32, c in ((False, 1e-12), (True, 2e-6)):
+        out, _ = h.apply("skew", _cuda(v), inner_fp32=fp32)
+        y = _np(out)
+        bound = abs(J) @ np.abs(v)
+        assert np.all(np.abs(y - J @ v) <= c * bound + 1e-300)
+        assert abs(v @ y) <= (1e-5 if fp32 else 1e-12) * (np.abs(v) @ bound)
+    h.close()
