@@ -79,8 +79,15 @@ def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, 
     n_s = w.A.shape[0]
     inner_s = max(1, info["inner_its_total"])
     scale = (n_full / n_s) * (inner_full / inner_s)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
         "value": (t2 - t1) * scale, "unit": "s", "cores": 1, "kind": "oracle",
+        "cpu_model": cpu, "host_cpu_count": os.cpu_count(), "setup_s_sample": round(t1 - t0, 2),
         "sample": (f"oracle solve of convdiff3d {m_sample}^3 Pe{peclet:g} (n={n_s}) took "
                    f"{t2 - t1:.2f} s ({info['outer_its']} outer / {info['inner_its_total']} inner its, "
                    f"relres {info['relres_true']:.1e}; setup {t1 - t0:.1f} s not counted), scaled by "
@@ -131,6 +138,46 @@ def batched(args, asss, torch, np, W):
     print(json.dumps(res), flush=True)
 
 
+def grad_bench(args, asss, torch, np, W):
+    """Forward + backward of L = ||A^-1 b - x_t||^2 at n = 1e6 (A's values and b
+    require gradients); the preconditioner is built once from A."""
+    from paper_2009_06954_amd.autograd import LinearSolve
+    w = W.implicit_euler_grid(m=1000, h=0.1, cfg=4)
+    rng = np.random.default_rng(4)
+    xt = torch.from_numpy(rng.standard_normal(w.A.shape[0])).cuda()
+    t0 = time.perf_counter()
+    op = LinearSolve(w.A, k=8, s_pattern="tridiag", tol=1e-10)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    times = []
+    for it in range(args.warmup + args.steps):
+        vals = torch.tensor(op.values0, requires_grad=True)
+        b = torch.from_numpy(w.b.copy()).cuda().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = op(vals, b)
+        L = ((x - xt) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it >= args.warmup:
+            times.append((t1 - t0, t2 - t1))
+    fwd = sum(t[0] for t in times) / len(times)
+    bwd = sum(t[1] for t in times) / len(times)
+    res = {"metric": "forward + backward time of a differentiable solve (s)", "value": round(fwd + bwd, 4),
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "steps": args.steps, "warmup": args.warmup,
+           "config": {"workload": "implicit_euler_1000x1000_h0.1", "n": int(w.A.shape[0]), "nnz": int(w.A.nnz),
+                      "k": 8, "s_pattern": "tridiag", "tol": 1e-10, "outer": "fgmres(64)"},
+           "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "setup_s": round(setup_s, 2),
+           "forward_info": {k: op.last_info[k] for k in ("outer_its", "inner_its_total", "relres_true")},
+           "grad_norm_values": float(vals.grad.norm()), "grad_norm_b": float(b.grad.norm())}
+    op.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +206,10 @@ def main():
                          "reports right-hand sides per second for the lockstep block solve and for "
                          "column-by-column solves")
     ap.add_argument("--nsys", type=int, default=64)
+    ap.add_argument("--grad", action="store_true",
+                    help="differentiation workload instead: 1000 x 1000 implicit-Euler grid (n = 1e6), "
+                         "loss ||x - x_t||^2, forward solve + backward (adjoint solve and dL/dA, dL/db) "
+                         "through the autograd function, FP64, tol 1e-10")
     ap.add_argument("--outer", default="fgmres", choices=["fgmres", "tfqmr"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -179,6 +230,8 @@ def main():
     torch.cuda.set_device(0)
     if args.batched:
         return batched(args, asss, torch, np, W)
+    if args.grad:
+        return grad_bench(args, asss, torch, np, W)
     log(f"building workload m={args.m} Pe={args.peclet}")
     w = W.convdiff3d(m=args.m, peclet=args.peclet, cfg=1)
     n, nnz = w.A.shape[0], w.A.nnz
@@ -257,6 +310,7 @@ def main():
 
     total64, inf64, err64 = run(False, args.steps, args.warmup)
     t64 = total64 / args.steps
+    x64 = x.clone()
     res = {
         "metric": METRIC, "value": round(t64, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * t64, 3), "higher_is_better": False,
@@ -270,6 +324,9 @@ def main():
                   "relres_true": inf64[-1]["relres_true"], "rel_err_vs_xstar": err64,
                   "inner_its_per_s": round(inf64[-1]["inner_its_total"] / inf64[-1]["solve_s"], 1)},
         "setup_s": round(setup_s, 2),
+        "setup_host_s": round(inf64[-1]["setup_host_s"], 2),
+        "setup_device_s": round(inf64[-1]["setup_device_s"], 2),
+        "solve_s_per_step": [round(i["solve_s"], 4) for i in inf64],
     }
     if not args.no_mixed:
         total32, inf32, err32 = run(True, args.steps, args.warmup)
@@ -278,7 +335,8 @@ def main():
                         "speedup_vs_fp64": round(t64 / t32, 3), "roofline": roofline(inf32, 4),
                         "outer_its": inf32[-1]["outer_its"], "inner_its": inf32[-1]["inner_its_total"],
                         "relres_true": inf32[-1]["relres_true"], "rel_err_vs_xstar": err32,
-                        "rel_diff_vs_fp64_solution": None}
+                        "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
+                        "solve_s_per_step": [round(i["solve_s"], 4) for i in inf32]}
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on convdiff3d {args.cpu_sample_m}^3")
         try:
