@@ -211,8 +211,8 @@ def _fgmres(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
         if relres <= o.tol:
             info["converged"] = True
             break
-        if info["outer_its"] >= o.max_outer:
-            break
+        if info["outer_its"] >= o.max_outer or j_used == 0:
+            break          # j_used == 0: zero scaled residual, a restart cannot move
         if implicit_ok:
             thr = thr * 0.5 * o.tol / relres
     return x_chk, info
@@ -256,6 +256,7 @@ def _tfqmr(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
         first = False
         info["cycles"] += 1
         tau = np.linalg.norm(r)
+        tau0 = tau
         implicit_ok = tau <= thr
         bound = tau
         if not implicit_ok:
@@ -318,8 +319,8 @@ def _tfqmr(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
         if relres <= o.tol:
             info["converged"] = True
             break
-        if info["outer_its"] >= o.max_outer:
-            break
+        if info["outer_its"] >= o.max_outer or tau0 == 0.0:
+            break          # zero scaled residual: a restart cannot move
         if implicit_ok:
             thr = thr * 0.5 * o.tol / relres
     return x_chk, info

@@ -867,7 +867,9 @@ struct FgmresCol {
       done = true;
       return;
     }
-    if (inf.outer_its >= o.max_outer) {
+    if (inf.outer_its >= o.max_outer || j_used == 0) {
+      // j_used == 0: the scaled residual was exactly zero while the true one is
+      // not below tol; a restart would start from the same point
       done = true;
       return;
     }
@@ -1022,6 +1024,7 @@ asss_status_t tfqmr(asss_handle_s* h, bool adjoint, const double* b, double* x,
     double tau = std::sqrt(dot_host(h, n, w, w, s));
     double bound = tau;
     bool implicit_ok = tau <= thr;
+    int cycle_steps = tau > 0.0 ? 1 : 0;  // 0: nothing to iterate on
     if (!implicit_ok) {
       axpby(n, 1.0, w, 0.0, rstar, s);
       axpby(n, 1.0, w, 0.0, u, s);
@@ -1092,7 +1095,8 @@ asss_status_t tfqmr(asss_handle_s* h, bool adjoint, const double* b, double* x,
       inf.converged = 1;
       break;
     }
-    if (inf.outer_its >= o.max_outer) break;
+    // a zero scaled residual with the true one above tol: no step can be taken
+    if (inf.outer_its >= o.max_outer || cycle_steps == 0) break;
     if (implicit_ok) thr = thr * 0.5 * o.tol / relres;
   }
   HIPCHK(hipStreamSynchronize(s));
