@@ -321,6 +321,7 @@ def main():
                    "inner_tol": args.inner_tol},
         "roofline": roofline(inf64, 8),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
+                  "reorth_passes": inf64[-1]["reorth"],
                   "relres_true": inf64[-1]["relres_true"], "rel_err_vs_xstar": err64,
                   "inner_its_per_s": round(inf64[-1]["inner_its_total"] / inf64[-1]["solve_s"], 1)},
         "setup_s": round(setup_s, 2),

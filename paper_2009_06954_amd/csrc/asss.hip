@@ -791,7 +791,7 @@ struct FgmresCol {
     double* hbuf = h->d_small;
     double* zj = Z + (int64_t)j * n;
     // w = A_chk z_j written straight into V[:, j+1]; classical Gram-Schmidt with
-    // one more pass when the norm drops below 1/sqrt(2) of its value (DGKS)
+    // one more pass when the norm drops below 1/sqrt(10) of its value (DGKS)
     double* vn = V + (int64_t)(j + 1) * n;
     op(zj, vn);
     gemm_tn<double, double>(n, j + 2, V, n, vn, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
@@ -801,7 +801,7 @@ struct FgmresCol {
     const double wn2 = h->h_small[SM_H1 + j + 1];
     double hn2 = h->h_small[SM_HN];
     for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i];
-    if (hn2 < 0.5 * wn2) {
+    if (hn2 < 0.1 * wn2) {
       gemm_tn<double, double>(n, j + 1, V, n, vn, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
       gemv_acc_norm(n, j + 1, V, n, hbuf + SM_H2, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
       HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
