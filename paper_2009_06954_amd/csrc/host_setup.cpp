@@ -581,7 +581,10 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
   S.nslices = (int32_t)((n + 63) / 64);
   // lower part: for row i, entries (i, j) with j < i come from upper row j
   Csr Lo = transpose(Jup);  // row i of Lo: columns j < i with value u_ji
-  std::vector<int32_t> na(n, 0), nb(n, 0);
+  // part b of a row: nbl entries in earlier blocks, then nbu in later blocks;
+  // each group gets its own slot range in the slice (below), so that one slot
+  // never mixes a neighbour before the block with one after it
+  std::vector<int32_t> na(n, 0), nb(n, 0), nbl(n, 0);
   parallel_for(n, [&](int64_t lo, int64_t hi) {
     for (int64_t i = lo; i < hi; ++i) {
       int64_t blk = i / R;
@@ -590,19 +593,23 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
         else nb[i]++;
       }
       for (int64_t p = Lo.ptr[i]; p < Lo.ptr[i + 1]; ++p)
-        if (Lo.col[p] / R != blk) nb[i]++;
+        if (Lo.col[p] / R != blk) { nb[i]++; nbl[i]++; }
     }
   });
   S.a_width.assign(S.nslices, 0);
   S.b_width.assign(S.nslices, 0);
   S.a_off.assign(S.nslices + 1, 0);
   S.b_off.assign(S.nslices + 1, 0);
+  std::vector<int32_t> wlo(S.nslices, 0);
   for (int64_t s = 0; s < S.nslices; ++s) {
-    int32_t wa = 0, wb = 0;
+    int32_t wa = 0, wl = 0, wu = 0;
     for (int64_t i = s * 64; i < std::min<int64_t>(n, s * 64 + 64); ++i) {
       wa = std::max(wa, na[i]);
-      wb = std::max(wb, nb[i]);
+      wl = std::max(wl, nbl[i]);
+      wu = std::max(wu, nb[i] - nbl[i]);
     }
+    const int32_t wb = wl + wu;
+    wlo[s] = wl;
     S.a_width[s] = wa;
     S.b_width[s] = wb;
     S.a_off[s + 1] = S.a_off[s] + (int64_t)wa * 64;
@@ -619,7 +626,8 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
         int64_t blk = i / R, b0 = blk * R;
         int32_t la = 0, lb = 0;
         if (i < n) {
-          // part b, lower entries first (ascending columns overall)
+          // part b: entries before the block in slots [0, wlo), entries after
+          // it from slot wlo on (ascending columns within each group)
           for (int64_t p = Lo.ptr[i]; p < Lo.ptr[i + 1]; ++p)
             if (Lo.col[p] / R != blk) {
               int64_t q = S.b_off[s] + (int64_t)lb * 64 + lane;
@@ -627,6 +635,11 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
               S.b_val[q] = -Lo.val[p];
               ++lb;
             }
+          for (; lb < wlo[s]; ++lb) {  // padding up to the upper group
+            int64_t q = S.b_off[s] + (int64_t)lb * 64 + lane;
+            S.b_col[q] = -1;  // placeholder: set to the slot's base below
+            S.b_val[q] = 0.0;
+          }
           for (int64_t p = Jup.ptr[i]; p < Jup.ptr[i + 1]; ++p) {
             int32_t j = Jup.col[p];
             if (j / R == blk) {
@@ -671,19 +684,20 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
       for (int32_t l = 0; l < S.b_width[s]; ++l) {
         const int64_t q0 = S.b_off[s] + (int64_t)l * 64;
         int64_t mn = INT64_MAX, mx = INT64_MIN;
-        for (int lane = 0; lane < 64; ++lane) {
+        auto real = [&](int lane) {
           const int64_t i = s * 64 + lane;
-          const bool real = i < n && l < nb[i];
-          if (real) {
+          if (i >= n) return false;
+          return l < nbl[i] || (l >= wlo[s] && l - wlo[s] < nb[i] - nbl[i]);
+        };
+        for (int lane = 0; lane < 64; ++lane) {
+          if (real(lane)) {
             mn = std::min<int64_t>(mn, S.b_col[q0 + lane]);
             mx = std::max<int64_t>(mx, S.b_col[q0 + lane]);
           }
         }
         if (mn == INT64_MAX) mn = mx = S.b_col[q0];  // cannot happen: l < width
-        for (int lane = 0; lane < 64; ++lane) {
-          const int64_t i = s * 64 + lane;
-          if (!(i < n && l < nb[i])) S.b_col[q0 + lane] = (int32_t)mn;
-        }
+        for (int lane = 0; lane < 64; ++lane)
+          if (!real(lane)) S.b_col[q0 + lane] = (int32_t)mn;
         S.b_base[q0 / 64] = (int32_t)mn;
         if (mx - mn > 65535) wide = 1;
       }

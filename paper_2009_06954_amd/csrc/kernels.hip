@@ -215,6 +215,25 @@ void spmv(const DCsr& M, const double* x, double* y, const double* rs, const dou
 #undef ASSS_SPMV
 }
 
+// Row block of this workgroup.  Workgroups are dispatched to the 8 XCDs round
+// robin (workgroup b on XCD b mod 8), and each XCD has its own L2.  In FP32 XCD
+// x gets one contiguous eighth of the row blocks, so blocks that are
+// neighbours in index space -- whose w entries the part-b gathers read --
+// share an L2 at any grid size (in natural order a block's z neighbours are a
+// plane of rows away: 8 blocks at 128^3, 18 at 192^3).  The FP32 step is
+// latency bound and gains (128^3: 87.6 -> 83.7 us, 192^3: 358.7 -> 350.7 us);
+// the bandwidth-bound FP64 step loses (142.9 -> 149.7 us, 523.5 -> 533.9 us)
+// and keeps the natural order, where all XCDs stream neighbouring blocks.
+template <typename T>
+__device__ __forceinline__ int xcd_block() {
+  constexpr int NXCD = 8;
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (sizeof(T) != 4) return b;
+  const int q = nb / NXCD, r = nb % NXCD;
+  const int x = b % NXCD, k = b / NXCD;
+  return x * q + min(x, r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Sliced skew SpMV: the part shared by the standalone operator and the mrs step.
 // One workgroup per block of R rows; wave w handles slices w, w + 4, ... of it,
@@ -359,7 +378,7 @@ __global__ __launch_bounds__(WG) void k_skew_spmv(DSkew<T> J, const T* __restric
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc_lds = reinterpret_cast<double*>(smem_raw);
   T* w_lds = reinterpret_cast<T*>(acc_lds + J.R);
-  const int64_t row0 = (int64_t)blockIdx.x * J.R;
+  const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, (int64_t)J.n - row0);
   for (int r = threadIdx.x; r < nrow; r += WG) {
     w_lds[r] = x[row0 + r];
@@ -892,7 +911,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   __shared__ MrsTail<NR, KF> tail;
   if (status == MRS_RUNNING) mrs_tail_prefetch<T, NR, KF>(tail, st, L, REC);
   const int64_t n = L.n;
-  const int64_t row0 = (int64_t)blockIdx.x * J.R;
+  const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, n - row0);
   const T* __restrict__ wcur = buf.w[t % 3];
   const T* __restrict__ wold = buf.w[(t + 2) % 3];
