@@ -207,7 +207,8 @@ asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* r
  * 4: one simultaneous mrs solve (App. B) per outer step serves the group, so
  * each inner step reads J_tilde and Q_k once for all its columns; the inner
  * stop rule is the maximum over the group.  Each column restarts and stops on
- * its own true residual.  With TFQMR the columns are solved one at a time.
+ * its own true residual.  With TFQMR, or with more than 16 deflation vectors,
+ * the columns are solved one at a time.
  * All right-hand sides are checked for NaN/Inf first (NONFINITE, nothing
  * solved).  infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be
  * NULL); inner_kernel_s / inner_launches are those of the column's group.

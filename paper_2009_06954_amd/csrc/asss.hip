@@ -1427,7 +1427,8 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
         const int nc = std::min(NRMAX, (int)nrhs[sidx] - j0);
         asss_info_t inf[NRMAX] = {};
         asss_status_t st;
-        if (nc >= 2 && oo.outer == ASSS_OUTER_FGMRES) {
+        // the 4-column inner kernels hold at most 16 deflation vectors
+        if (nc >= 2 && oo.outer == ASSS_OUTER_FGMRES && h->k_eff <= 16) {
           const double* bs[NRMAX];
           double* xs[NRMAX];
           for (int c = 0; c < nc; ++c) {

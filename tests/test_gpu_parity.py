@@ -300,8 +300,10 @@ def test_edge_cases(cfg0):
     assert e.value.name == "INVALID_CSR"
 
 
-@pytest.mark.parametrize("k", [0, 1, 4])
+@pytest.mark.parametrize("k", [0, 1, 4, 9, 20, 32])
 def test_small_k(k):
+    """k = 0 (no deflation), widths 8 / 16 / 32 of the deflation kernels, and
+    k > 16 where the one-time X solve runs column by column."""
     w = W.config(0, m=20)
     p = Pair(w.A, k=k)
     xo, io = O.solve(p.st, w.b, O.SolveOptions(tol=1e-12))
