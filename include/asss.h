@@ -82,6 +82,19 @@ enum {
   ASSS_S_USER = 3          /* s_rowptr / s_colind, a CSR pattern in Abar's index space */
 };
 
+/* Device memory provider for a handle, e.g. a framework's caching allocator.
+ * alloc returns at least `bytes` bytes of device memory (256-byte aligned)
+ * usable on the handle's device, or NULL (the entry point then fails with
+ * ASSS_ERR_OOM); free gives it back.  Both are called from the calling thread
+ * of asss_setup, of the solve entry points (workspaces are grown on first use)
+ * and of asss_destroy, with ctx passed through.  The functions and ctx must
+ * stay valid until the handle is destroyed (the structure itself is copied). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} asss_allocator_t;
+
 typedef struct {
   double gamma;            /* weight of the diagonal equations (eq. regularized), default 1 */
   int32_t s_pattern;       /* ASSS_S_*, default ASSS_S_TRIDIAG */
@@ -115,6 +128,7 @@ typedef struct {
                                   convection-diffusion workload this stores 22 % fewer
                                   skew entries but is slower, because neighbours no
                                   longer sit at a common offset across a wavefront */
+  const asss_allocator_t* allocator; /* device memory of the handle; NULL = hipMalloc / hipFree */
 } asss_setup_opts_t;
 
 typedef struct {

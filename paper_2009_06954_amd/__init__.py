@@ -52,7 +52,36 @@ class SetupOpts(C.Structure):
                 ("s_colind", C.c_void_p), ("k", C.c_int32), ("lanczos_seed", C.c_uint64),
                 ("inner_fp32", C.c_int32), ("x_tol", C.c_double), ("x_maxit", C.c_int32),
                 ("lls_tol", C.c_double), ("lls_maxit", C.c_int32), ("row_block", C.c_int32),
-                ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32)]
+                ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32),
+                ("allocator", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class AllocatorT(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+def torch_allocator():
+    """asss_allocator_t backed by torch's caching allocator on the current
+    device (the returned object must outlive the handle; Handle keeps it)."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+        except RuntimeError:  # out of memory: the library reports ASSS_ERR_OOM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = AllocatorT(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    a._keep = (_alloc, _free)
+    return a
 
 
 class SolveOpts(C.Structure):
@@ -179,9 +208,10 @@ def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_
 class Handle:
     """A preprocessed matrix on the GPU (owns all its device memory)."""
 
-    def __init__(self, ptr, n):
+    def __init__(self, ptr, n, keep=None):
         self._h = C.c_void_p(ptr)
         self.n = n
+        self._keep = keep  # the allocator callbacks must outlive the handle
 
     def close(self):
         if self._h and self._h.value:
@@ -278,10 +308,12 @@ class Handle:
 
 def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, inner_fp32=False,
           x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
-          stream=None, canonicalize=True, deflation="auto", reorder="auto") -> Handle:
+          stream=None, canonicalize=True, deflation="auto", reorder="auto", allocator=None) -> Handle:
     """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
     canonicalize: sum duplicates and sort column indices of a SciPy input first
-    (otherwise the library rejects such input with INVALID_CSR)."""
+    (otherwise the library rejects such input with INVALID_CSR).
+    allocator: None (the library's hipMalloc) or "torch" (torch's caching
+    allocator holds all device memory of the handle)."""
     lib = load()
     n, rp, ci, va = _csr_arrays(A, canonicalize)
     csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
@@ -300,9 +332,15 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2}[deflation]
     o.reorder = {"auto": 0, "none": 1, "blocks": 2}[reorder]
+    alloc = None
+    if allocator == "torch":
+        alloc = torch_allocator()
+        o.allocator = C.cast(C.pointer(alloc), C.c_void_p)
+    elif allocator is not None:
+        raise ValueError("allocator must be None or 'torch'")
     out = C.c_void_p()
     _check(lib.asss_setup(C.byref(csr), C.byref(o), _stream(stream), C.byref(out)))
-    return Handle(out.value, n)
+    return Handle(out.value, n, keep=alloc)
 
 
 def solve_batched(handles, Bs, stream=None, **opts):

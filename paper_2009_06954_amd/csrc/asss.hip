@@ -53,11 +53,24 @@ double now_s() {
 // Device allocations owned by a handle.
 struct DevArena {
   std::vector<void*> ptrs;
+  asss_allocator_t al{};  // al.alloc == nullptr: hipMalloc / hipFree
+  DevArena() = default;
+  explicit DevArena(const asss_allocator_t& a) : al(a) {}
+  DevArena(const DevArena&) = delete;
+  DevArena& operator=(const DevArena&) = delete;
   template <typename T>
   T* alloc(int64_t count) {
     if (count <= 0) count = 1;
+    const size_t bytes = (size_t)count * sizeof(T);
     void* p = nullptr;
-    HIPCHK(hipMalloc(&p, (size_t)count * sizeof(T)));
+    if (al.alloc) {
+      p = al.alloc(bytes, al.ctx);
+      if (!p) throw Error{ASSS_ERR_OOM, "the caller's allocator returned no memory"};
+    } else {
+      const hipError_t e = hipMalloc(&p, bytes);
+      if (e == hipErrorOutOfMemory) throw Error{ASSS_ERR_OOM, "hipMalloc: out of device memory"};
+      HIPCHK(e);
+    }
     ptrs.push_back(p);
     return (T*)p;
   }
@@ -67,15 +80,19 @@ struct DevArena {
     if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return p;
   }
+  void give_back(void* p) {
+    if (al.alloc) al.free(p, al.ctx);
+    else (void)hipFree(p);
+  }
   void release(void* p) {
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
     if (it != ptrs.end()) {
-      (void)hipFree(*it);
+      give_back(*it);
       ptrs.erase(it);
     }
   }
   ~DevArena() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) give_back(p);
   }
 };
 
@@ -128,7 +145,7 @@ struct asss_handle_s {
   int device = 0;
   int64_t n = 0;
   asss_setup_opts_t opts{};
-  DevArena ar;
+  DevArena ar;  // every device buffer of the handle (caller's allocator if given)
   // host data kept for inspection
   std::vector<int32_t> m;
   std::vector<double> Dr, Dc, D, Omega, alpha;
@@ -386,7 +403,7 @@ int prec_apply_T(asss_handle_s* h, bool fp32, const double* v, double* z, const 
 
 std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol, int maxit,
                                 hipStream_t s) {
-  DevArena tmp;
+  DevArena tmp(h->ar.al);
   const int64_t m = L.B.nrows, nu = L.B.ncols;
   DCsr B = upload_csr(tmp, L.B, s), Bt = upload_csr(tmp, L.Bt, s);
   double* u = tmp.upload(L.rhs, s);
@@ -593,7 +610,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   h->d_X = h->ar.alloc<double>(n * (int64_t)kr);
   // simultaneous mrs (App. B) on groups of NRMAX columns in FP64
   {
-    DevArena tmp;
+    DevArena tmp(h->ar.al);
     MrsBufs<double> mb4;
     for (int b = 0; b < 3; ++b) mb4.w[b] = tmp.alloc<double>(n * NRMAX);
     for (int b = 0; b < 2; ++b) mb4.p[b] = tmp.alloc<double>(n * NRMAX);
@@ -1200,7 +1217,13 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<asss_handle_s> h(new asss_handle_s());
     HIPCHK(hipGetDevice(&h->device));
+    if (o.allocator) {
+      if (!o.allocator->alloc || !o.allocator->free)
+        throw Error{ASSS_ERR_INVALID_ARG, "allocator needs both alloc and free"};
+      h->ar.al = *o.allocator;  // copied: the caller's structure may go away
+    }
     h->opts = o;
+    h->opts.allocator = nullptr;
     const double t0 = now_s();
     // ---- host preprocessing
     Csr Ah = validate_and_copy(A->n, A->nnz, A->rowptr, A->colind, A->val);

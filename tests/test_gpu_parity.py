@@ -454,3 +454,26 @@ def test_column_storage_forms(cfg0):
         assert np.all(np.abs(y - J @ v) <= c * bound + 1e-300)
         assert abs(v @ y) <= (1e-5 if fp32 else 1e-12) * (np.abs(v) @ bound)
     h.close()
+
+
+def test_torch_allocator():
+    """With allocator="torch" every device buffer of the handle comes from
+    torch's caching allocator (setup and the workspace grown by the first
+    solve) and goes back to it at destroy."""
+    asss = _lib()
+    w = W.config(0)
+    b = _cuda(w.b)
+    x = torch.empty_like(b)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    h = asss.setup(w.A, k=8, s_pattern="tridiag", allocator="torch")
+    after_setup = torch.cuda.memory_allocated()
+    assert after_setup - before > 1 << 20
+    _, info = h.solve(b, out=x, tol=1e-12)
+    assert info["status"] == "OK"
+    assert torch.cuda.memory_allocated() > after_setup  # Krylov workspace
+    xd = np.linalg.solve(w.A.toarray(), w.b)
+    assert _rel(_np(x), xd) <= 1e-10
+    h.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
