@@ -222,7 +222,9 @@ asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* r
  * each inner step reads J_tilde and Q_k once for all its columns; the inner
  * stop rule is the maximum over the group.  Each column restarts and stops on
  * its own true residual.  With TFQMR, or with more than 16 deflation vectors,
- * the columns are solved one at a time.
+ * the columns are solved one at a time.  Systems run concurrently on up to 4
+ * internal streams (one host thread each; all work on one handle stays on one
+ * of them), ordered after hip_stream; the call returns when all are done.
  * All right-hand sides are checked for NaN/Inf first (NONFINITE, nothing
  * solved).  infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be
  * NULL); inner_kernel_s / inner_launches are those of the column's group.

@@ -11,7 +11,9 @@
 #include <cstddef>
 #include <cstring>
 #include <memory>
+#include <map>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -1431,25 +1433,50 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
       throw Error{ASSS_ERR_INVALID_ARG, "outer must be ASSS_OUTER_FGMRES or ASSS_OUTER_TFQMR"};
     int maxr = 0;
     for (int sidx = 0; sidx < nsys; ++sidx) {
+      if (!hs[sidx]) throw Error{ASSS_ERR_INVALID_ARG, "null handle"};
       if (nrhs[sidx] < 0 || (nrhs[sidx] > 0 && (!B_dev[sidx] || !X_dev[sidx])))
         throw Error{ASSS_ERR_INVALID_ARG, "bad nrhs or null block"};
-      check_handle(hs[sidx]);
       maxr = std::max(maxr, (int)nrhs[sidx]);
     }
     // every right-hand side is checked before any is solved
-    for (int sidx = 0; sidx < nsys; ++sidx)
+    for (int sidx = 0; sidx < nsys; ++sidx) {
+      check_handle(hs[sidx]);
       for (int j = 0; j < nrhs[sidx]; ++j)
         if (!b_is_finite(hs[sidx], B_dev[sidx] + (int64_t)j * hs[sidx]->n, s))
           throw Error{ASSS_ERR_NONFINITE, "a right-hand side has a non-finite entry"};
-    asss_status_t worst = ASSS_OK;
-    for (int sidx = 0; sidx < nsys; ++sidx) {
+    }
+    // Work list: systems (all right-hand sides of one handle stay together, a
+    // handle is not used from two threads), largest first, dealt to up to
+    // four workers -- one host thread and one stream each -- so that small,
+    // latency-bound systems run side by side on the GPU.
+    std::map<asss_handle_t, std::vector<int>> by_handle;
+    for (int sidx = 0; sidx < nsys; ++sidx)
+      if (nrhs[sidx] > 0) by_handle[hs[sidx]].push_back(sidx);
+    std::vector<std::pair<int64_t, std::vector<int>>> groups;
+    for (auto& kv : by_handle) {
+      int64_t work = 0;
+      for (int sidx : kv.second) work += kv.first->n * (int64_t)nrhs[sidx];
+      groups.push_back({work, kv.second});
+    }
+    std::sort(groups.begin(), groups.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    bool one_device = true;
+    for (int sidx = 0; sidx < nsys; ++sidx) one_device &= hs[sidx]->device == hs[0]->device;
+    const int nworkers = one_device ? std::min<int>(4, (int)groups.size()) : 1;
+    std::vector<std::vector<int>> assign(std::max(1, nworkers));
+    std::vector<int64_t> load(std::max(1, nworkers), 0);
+    for (auto& g : groups) {
+      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[w] += g.first;
+      assign[w].insert(assign[w].end(), g.second.begin(), g.second.end());
+    }
+    auto solve_system = [&](int sidx, hipStream_t st) -> asss_status_t {
       asss_handle_t h = hs[sidx];
-      check_handle(h);
       const int64_t n = h->n;
+      asss_status_t worst_s = ASSS_OK;
       for (int j0 = 0; j0 < nrhs[sidx]; j0 += NRMAX) {
         const int nc = std::min(NRMAX, (int)nrhs[sidx] - j0);
         asss_info_t inf[NRMAX] = {};
-        asss_status_t st;
+        asss_status_t stt;
         // the 4-column inner kernels hold at most 16 deflation vectors
         if (nc >= 2 && oo.outer == ASSS_OUTER_FGMRES && h->k_eff <= 16) {
           const double* bs[NRMAX];
@@ -1458,19 +1485,77 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
             bs[c] = B_dev[sidx] + (int64_t)(j0 + c) * n;
             xs[c] = X_dev[sidx] + (int64_t)(j0 + c) * n;
           }
-          st = fgmres_block(h, nc, bs, xs, oo, inf, s);
+          stt = fgmres_block(h, nc, bs, xs, oo, inf, st);
         } else {
-          st = ASSS_OK;
+          stt = ASSS_OK;
           for (int c = 0; c < nc; ++c) {
             asss_status_t sc = outer_solve(h, false, B_dev[sidx] + (int64_t)(j0 + c) * n,
-                                           X_dev[sidx] + (int64_t)(j0 + c) * n, oo, &inf[c], s);
-            if (sc > st) st = sc;
+                                           X_dev[sidx] + (int64_t)(j0 + c) * n, oo, &inf[c], st);
+            if (sc > stt) stt = sc;
           }
         }
         if (infos)
           for (int c = 0; c < nc; ++c) infos[(int64_t)sidx * maxr + j0 + c] = inf[c];
-        if (st > worst) worst = st;
+        if (stt > worst_s) worst_s = stt;
       }
+      return worst_s;
+    };
+    if (nworkers <= 1) {
+      asss_status_t worst = ASSS_OK;
+      for (auto& list : assign)
+        for (int sidx : list) {
+          check_handle(hs[sidx]);
+          worst = std::max(worst, solve_system(sidx, s));
+        }
+      return worst;
+    }
+    // worker streams (default priority) start after the caller's stream
+    HIPCHK(hipSetDevice(hs[0]->device));
+    hipEvent_t ready = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    std::vector<hipStream_t> streams(nworkers, nullptr);
+    struct Outcome { asss_status_t status = ASSS_OK; int code = 0; std::string msg; };
+    std::vector<Outcome> out(nworkers);
+    try {
+      HIPCHK(hipEventRecord(ready, s));
+      for (int w = 0; w < nworkers; ++w) {
+        HIPCHK(hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking));
+        HIPCHK(hipStreamWaitEvent(streams[w], ready, 0));
+      }
+      std::vector<std::thread> threads;
+      for (int w = 0; w < nworkers; ++w)
+        threads.emplace_back([&, w]() {
+          try {
+            HIPCHK(hipSetDevice(hs[0]->device));
+            for (int sidx : assign[w]) out[w].status = std::max(out[w].status, solve_system(sidx, streams[w]));
+            HIPCHK(hipStreamSynchronize(streams[w]));
+          } catch (const Error& e) {
+            out[w].code = e.code;
+            out[w].msg = e.msg;
+          } catch (const HostError& e) {
+            out[w].code = e.code;
+            out[w].msg = e.msg;
+          } catch (const std::bad_alloc&) {
+            out[w].code = ASSS_ERR_OOM;
+            out[w].msg = "host out of memory";
+          } catch (const std::exception& e) {
+            out[w].code = ASSS_ERR_INTERNAL;
+            out[w].msg = e.what();
+          }
+        });
+      for (auto& t : threads) t.join();
+    } catch (...) {
+      for (hipStream_t st : streams)
+        if (st) { (void)hipStreamSynchronize(st); (void)hipStreamDestroy(st); }
+      (void)hipEventDestroy(ready);
+      throw;
+    }
+    for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+    (void)hipEventDestroy(ready);
+    asss_status_t worst = ASSS_OK;
+    for (auto& r : out) {
+      if (r.code != 0) throw Error{r.code, r.msg};
+      worst = std::max(worst, r.status);
     }
     return worst;
   });

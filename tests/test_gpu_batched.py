@@ -113,3 +113,18 @@ def test_batched_many_deflation_vectors():
         assert infos[0][j]["converged"] == 1
         assert _rel(X[:, j], np.linalg.solve(Ad, w.b[:, j])) <= max(1e-8, 10 * np.linalg.cond(Ad) * 1e-10)
     h.close()
+
+
+def test_batched_same_handle_twice_and_many_systems(batch):
+    """Systems run concurrently on worker streams; a handle listed twice stays
+    on one worker.  Every column matches its own single solve."""
+    asss, ws, nr, hs = batch
+    order = [0, 1, 0, 2, 3, 1]
+    Bs = [_colmajor(ws[i].b[:, :2]) for i in order]
+    Xs, infos = asss.solve_batched([hs[i] for i in order], Bs, tol=1e-11)
+    for t, i in enumerate(order):
+        X = Xs[t].detach().cpu().numpy()
+        for j in range(2):
+            assert infos[t][j]["converged"] == 1
+            x, _ = hs[i].solve(torch.from_numpy(ws[i].b[:, j].copy()).cuda(), tol=1e-11)
+            assert _rel(X[:, j], x.cpu().numpy()) <= 1e-8
