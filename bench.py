@@ -102,7 +102,8 @@ def batched(args, asss, torch, np, W):
     log(f"batched: {len(ws)} systems, n from {min(w.A.shape[0] for w in ws)} to "
         f"{max(w.A.shape[0] for w in ws)}, total {sum(w.A.shape[0] for w in ws)}")
     t0 = time.perf_counter()
-    hs = [asss.setup(w.A, k=8, s_pattern="tridiag") for w in ws]
+    hs = [asss.setup(w.A, k=8, s_pattern="tridiag", inner_fp32=not args.no_mixed, autotune=args.autotune)
+          for w in ws]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"setup {setup_s:.1f} s")
@@ -124,7 +125,10 @@ def batched(args, asss, torch, np, W):
             worst1 = max(worst1, inf["relres_true"])
     torch.cuda.synchronize()
     t_cols = time.perf_counter() - t0
+    row_blocks = {}
     for h in hs:
+        rb = h.info()["row_block"]
+        row_blocks[rb] = row_blocks.get(rb, 0) + 1
         h.close()
     res = {"metric": "batched solve throughput (right-hand sides to 1e-8 per second)",
            "value": round(nrhs / t_block, 3), "unit": "rhs/s", "n_gpus": 1, "higher_is_better": True,
@@ -134,7 +138,8 @@ def batched(args, asss, torch, np, W):
                       "tol": args.tol, "outer": "fgmres(64)", "inner_tol": 1e-2},
            "block_s": round(t_block, 3), "column_by_column_s": round(t_cols, 3),
            "speedup_block_vs_columns": round(t_cols / t_block, 3),
-           "worst_relres_block": worst, "worst_relres_columns": worst1, "setup_s": round(setup_s, 1)}
+           "worst_relres_block": worst, "worst_relres_columns": worst1, "setup_s": round(setup_s, 1),
+           "autotune": bool(args.autotune), "row_blocks": row_blocks}
     print(json.dumps(res), flush=True)
 
 
@@ -211,7 +216,13 @@ def main():
                          "loss ||x - x_t||^2, forward solve + backward (adjoint solve and dL/dA, dL/db) "
                          "through the autograd function, FP64, tol 1e-10")
     ap.add_argument("--outer", default="fgmres", choices=["fgmres", "tfqmr"])
+    ap.add_argument("--autotune", choices=["on", "off"], default=None,
+                    help="row-block autotuner at setup (times the inner step for several row-block "
+                         "sizes and keeps the fastest).  Default: on for --batched (it picks larger "
+                         "blocks than the automatic size for most of the small systems), off for the "
+                         "128^3 workload (where it keeps the automatic 2048)")
     args = ap.parse_args()
+    args.autotune = (args.autotune == "on") if args.autotune else bool(args.batched)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -237,7 +248,7 @@ def main():
     n, nnz = w.A.shape[0], w.A.nnz
     log(f"n={n} nnz={nnz}; setup (host preprocessing + device data)")
     t0 = time.perf_counter()
-    h = asss.setup(w.A, k=args.k, s_pattern="abar", verbose=args.verbose)
+    h = asss.setup(w.A, k=args.k, s_pattern="abar", verbose=args.verbose, autotune=args.autotune)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     hi = h.info()
@@ -318,7 +329,7 @@ def main():
         "config": {"workload": f"convdiff3d_{args.m}^3_Pe{args.peclet:g}", "n": n, "nnz": nnz,
                    "k": args.k, "s_pattern": "abar", "tol": args.tol,
                    "outer": f"fgmres({args.restart})" if args.outer == "fgmres" else "tfqmr",
-                   "inner_tol": args.inner_tol},
+                   "inner_tol": args.inner_tol, "row_block": hi["row_block"]},
         "roofline": roofline(inf64, 8),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
                   "reorth_passes": inf64[-1]["reorth"],
@@ -329,6 +340,9 @@ def main():
         "setup_device_s": round(inf64[-1]["setup_device_s"], 2),
         "solve_s_per_step": [round(i["solve_s"], 4) for i in inf64],
     }
+    if args.autotune:
+        res["autotune"] = {"row_blocks": hi["tune_rows"], "inner_step_us": [round(t, 1) for t in hi["tune_us"]],
+                           "tune_s": round(hi["tune_s"], 2)}
     if not args.no_mixed:
         total32, inf32, err32 = run(True, args.steps, args.warmup)
         t32 = total32 / args.steps

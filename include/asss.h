@@ -129,6 +129,16 @@ typedef struct {
                                   skew entries but is slower, because neighbours no
                                   longer sit at a common offset across a wavefront */
   const asss_allocator_t* allocator; /* device memory of the handle; NULL = hipMalloc / hipFree */
+  int32_t autotune;        /* row-block autotuner (only with row_block = 0 and the natural
+                              order; reorder = 2 is rejected):
+                              0 = the automatic size (default);
+                              1 = at the end of setup, pack J_tilde for the automatic size
+                                  and up to two halvings and doublings of it within
+                                  [64, 2048], time the fused inner step on each (HIP events,
+                                  the handle's deflation and default inner precision, one
+                                  right-hand side) and keep the fastest layout.  Costs one
+                                  host packing and a few ms of GPU time per candidate;
+                                  the result is in asss_handle_info_t.tune_* */
 } asss_setup_opts_t;
 
 typedef struct {
@@ -254,6 +264,10 @@ typedef struct {
   int64_t cross_pairs_used;               /* the same in the order used */
   int32_t narrow_b_columns;               /* 1: off-block columns stored as 16-bit deltas
                                              from per-slot bases (grid-like patterns) */
+  int32_t tune_n;                         /* row-block candidates timed (0: no autotune) */
+  int32_t tune_rows[8];                   /* their row_block values, ascending */
+  double tune_us[8];                      /* their inner-step times (microseconds) */
+  double tune_s;                          /* wall time of the autotuner */
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);

@@ -141,6 +141,49 @@ DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32
   return d;
 }
 
+// One sliced layout of J_tilde on the device, in both precisions (the index
+// arrays are shared), with the list of its buffers so that it can be replaced.
+struct SkewLayout {
+  DSkew<double> J64;
+  DSkew<float> J32;
+  std::vector<const void*> bufs;
+  int64_t a_entries = 0, b_entries = 0;
+  int narrow = 0;
+};
+
+SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s) {
+  SkewLayout L;
+  auto keep = [&](const void* p) { if (p) L.bufs.push_back(p); };
+  const int32_t* aw = ar.upload(sell.a_width, s);
+  const int32_t* bw = ar.upload(sell.b_width, s);
+  const int64_t* ao = ar.upload(sell.a_off, s);
+  const int64_t* bo = ar.upload(sell.b_off, s);
+  const uint16_t* ac = ar.upload(sell.a_col, s);
+  // part-b columns: 16-bit deltas from per-slot bases when every slot fits
+  // (2 bytes per entry instead of 4), else global 32-bit columns
+  const int32_t* bc = sell.b_narrow ? nullptr : ar.upload(sell.b_col, s);
+  const uint16_t* bcd = sell.b_narrow ? ar.upload(sell.b_cd, s) : nullptr;
+  const int32_t* bbase = sell.b_narrow ? ar.upload(sell.b_base, s) : nullptr;
+  for (const void* p : {(const void*)aw, (const void*)bw, (const void*)ao, (const void*)bo, (const void*)ac,
+                        (const void*)bc, (const void*)bcd, (const void*)bbase})
+    keep(p);
+  L.J64 = upload_sell<double>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
+  L.J32 = upload_sell<float>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
+  for (const void* p : {(const void*)L.J64.a_val, (const void*)L.J64.b_val, (const void*)L.J32.a_val,
+                        (const void*)L.J32.b_val})
+    keep(p);
+  L.a_entries = sell.a_entries;
+  L.b_entries = sell.b_entries;
+  L.narrow = sell.b_narrow ? 1 : 0;
+  return L;
+}
+
+void release_layout(DevArena& ar, SkewLayout& L, hipStream_t s) {
+  HIPCHK(hipStreamSynchronize(s));  // no kernel may still read it
+  for (const void* p : L.bufs) ar.release(const_cast<void*>(p));
+  L = SkewLayout{};
+}
+
 }  // namespace
 
 struct asss_handle_s {
@@ -167,6 +210,10 @@ struct asss_handle_s {
   double *d_drp = nullptr, *d_om = nullptr, *d_dc = nullptr;
   DSkew<double> J64;
   DSkew<float> J32;
+  std::vector<const void*> lay_bufs;  // buffers of the J64 / J32 layout
+  // row-block autotuner: candidates timed at setup (row_block, us per inner step)
+  std::vector<std::pair<int, double>> tuned;
+  double tune_s = 0.0;
   // inner system in block order: row i of the inner system is row perm[i]
   std::vector<int32_t> perm;
   int32_t* d_perm = nullptr;  // null when the natural order is kept
@@ -273,6 +320,7 @@ int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs
             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s,
             int nc = 1) {
   MrsLaunch L = make_launch<T>(h, nc, sign, Q, f, NR == 1 && h->defl_rec != 0);
+  if (J.nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
   mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
   if constexpr (NR == 1) {
     if (L.rec) mrs_make_y1<T, 1>(L, Q, mb, h->d_state, s);
@@ -397,6 +445,91 @@ int prec_apply_T(asss_handle_s* h, bool fp32, const double* v, double* z, const 
     rhs = h->tmp;
   }
   return inner_solve(h, fp32, rhs, z, -1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
+}
+
+// ---------------------------------------------------------------------------
+// row-block autotuner
+// ---------------------------------------------------------------------------
+
+// Average duration of one fused inner step (k_mrs_iter, the handle's
+// deflation, one column) on layout J, timed with HIP events over a fixed
+// number of steps from the right-hand side in h->tmp.  Leaves no trace in
+// the handle's counters.
+template <typename T>
+double time_inner_step(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+                       int steps, hipStream_t s) {
+  const double ps = h->prof_s;
+  const int pl = h->prof_launches, li = h->last_inner;
+  h->prof_s = 0.0;
+  h->prof_launches = 0;
+  run_mrs1<T>(h, J, Q, f, mb, h->tmp, h->w, +1, 1e-300, steps, steps, s);
+  const double t = h->prof_launches > 0 ? h->prof_s / h->prof_launches : 0.0;
+  h->prof_s = ps;
+  h->prof_launches = pl;
+  h->last_inner = li;
+  return t;
+}
+
+double time_layout(asss_handle_s* h, const SkewLayout& L, bool fp32, hipStream_t s) {
+  auto run = [&](int steps) {
+    return fp32 ? time_inner_step<float>(h, L.J32, h->d_Q32, h->d_f32, h->mb32, steps, s)
+                : time_inner_step<double>(h, L.J64, h->d_Q64, h->d_f64, h->mb64, steps, s);
+  };
+  const double warm = run(4);
+  // about 4 ms of timed steps per repeat, best of two repeats
+  const int steps = (int)std::min(256.0, std::max(8.0, 4e-3 / std::max(warm, 1e-7)));
+  return std::min(run(steps), run(steps));
+}
+
+// Packs the sliced layout of J_tilde (strict upper part Jup, natural order)
+// for every candidate row-block size, times the inner step on each in the
+// handle's default inner precision and keeps the fastest in the handle.  All
+// layouts hold the same operator, so the deflation and SMW data stay valid.
+void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& cands, hipStream_t s) {
+  const int64_t n = h->n;
+  {  // a fixed pseudo-random right-hand side in (-1, 1)
+    std::vector<double> r(n);
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    for (int64_t i = 0; i < n; ++i) {
+      x ^= x << 13; x ^= x >> 7; x ^= x << 17;  // xorshift64
+      r[i] = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    HIPCHK(hipMemcpyAsync(h->tmp, r.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  const bool fp32 = h->opts.inner_fp32 != 0;
+  SkewLayout best;
+  best.J64 = h->J64;
+  best.J32 = h->J32;
+  best.bufs = h->lay_bufs;
+  best.a_entries = h->sell_a;
+  best.b_entries = h->sell_b;
+  best.narrow = h->narrow_b;
+  double t_best = time_layout(h, best, fp32, s);
+  h->tuned.assign(1, {h->J64.R, 1e6 * t_best});
+  for (int R : cands) {
+    if (R == best.J64.R) continue;
+    SkewSell sell = pack_skew_sell(Jup, R);
+    SkewLayout cand = upload_layout(h->ar, sell, s);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t = time_layout(h, cand, fp32, s);
+    h->tuned.push_back({R, 1e6 * t});
+    if (t < t_best) {
+      release_layout(h->ar, best, s);
+      best = std::move(cand);
+      t_best = t;
+    } else {
+      release_layout(h->ar, cand, s);
+    }
+  }
+  std::sort(h->tuned.begin(), h->tuned.end());
+  h->J64 = best.J64;
+  h->J32 = best.J32;
+  h->lay_bufs = best.bufs;
+  h->sell_a = best.a_entries;
+  h->sell_b = best.b_entries;
+  h->narrow_b = best.narrow;
+  h->cross_natural = h->cross_used = count_cross_pairs(Jup, h->J64.R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1186,6 +1319,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->verbose = 0;
   o->deflation = 0;
   o->reorder = 0;
+  o->autotune = 0;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -1216,6 +1350,9 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     if (o.reorder < 0 || o.reorder > 2) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1 or 2"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
+    if (o.autotune < 0 || o.autotune > 1) throw Error{ASSS_ERR_INVALID_ARG, "autotune must be 0 or 1"};
+    if (o.autotune && o.reorder == 2)
+      throw Error{ASSS_ERR_INVALID_ARG, "autotune needs the natural order (reorder 0 or 1)"};
     hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<asss_handle_s> h(new asss_handle_s());
     HIPCHK(hipGetDevice(&h->device));
@@ -1247,7 +1384,13 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
       R = 64;
       while (R < 2048 && (int64_t)R * 2 * 1024 <= n) R *= 2;
     }
-    const int64_t nblocks = (n + R - 1) / R;
+    // autotuner candidates: the automatic size and up to two doublings and
+    // halvings of it within [64, 2048]
+    std::vector<int> cands;
+    if (o.autotune && o.row_block == 0)
+      for (int c = std::max(64, R / 4); c <= std::min(2048, R * 4); c *= 2) cands.push_back(c);
+    const int Rmin = cands.empty() ? R : cands.front();
+    const int64_t nblocks = (n + Rmin - 1) / Rmin;
     h->red.max_groups = (int)std::max<int64_t>(nblocks, 1024);
     h->red.partials = h->ar.alloc<double>((int64_t)h->red.max_groups * RED_SLOTS);
     h->red.tickets = h->ar.alloc<unsigned>(16);
@@ -1308,19 +1451,11 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->d_om = h->ar.upload(h->Omega, s);
     h->d_dc = h->ar.upload(h->Dc, s);
     {
-      const int32_t* aw = h->ar.upload(sell.a_width, s);
-      const int32_t* bw = h->ar.upload(sell.b_width, s);
-      const int64_t* ao = h->ar.upload(sell.a_off, s);
-      const int64_t* bo = h->ar.upload(sell.b_off, s);
-      const uint16_t* ac = h->ar.upload(sell.a_col, s);
-      // part-b columns: 16-bit deltas from per-slot bases when every slot fits
-      // (2 bytes per entry instead of 4), else global 32-bit columns
-      const int32_t* bc = sell.b_narrow ? nullptr : h->ar.upload(sell.b_col, s);
-      const uint16_t* bcd = sell.b_narrow ? h->ar.upload(sell.b_cd, s) : nullptr;
-      const int32_t* bbase = sell.b_narrow ? h->ar.upload(sell.b_base, s) : nullptr;
-      h->narrow_b = sell.b_narrow ? 1 : 0;
-      h->J64 = upload_sell<double>(h->ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
-      h->J32 = upload_sell<float>(h->ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
+      SkewLayout lay = upload_layout(h->ar, sell, s);
+      h->narrow_b = lay.narrow;
+      h->J64 = lay.J64;
+      h->J32 = lay.J32;
+      h->lay_bufs = std::move(lay.bufs);
     }
     for (int b = 0; b < 3; ++b) { h->mb64.w[b] = h->ar.alloc<double>(n); h->mb32.w[b] = h->ar.alloc<float>(n); }
     for (int b = 0; b < 2; ++b) { h->mb64.p[b] = h->ar.alloc<double>(n); h->mb32.p[b] = h->ar.alloc<float>(n); }
@@ -1338,6 +1473,15 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     const double t3 = now_s();
     device_setup(h.get(), s);
     const double t4 = now_s();
+    if (cands.size() > 1) {
+      tune_row_block(h.get(), Jup, cands, s);
+      h->tune_s = now_s() - t4;
+      if (o.verbose) {
+        std::fprintf(stderr, "[asss] row-block autotune %.3fs:", h->tune_s);
+        for (auto& c : h->tuned) std::fprintf(stderr, " %d:%.1fus", c.first, c.second);
+        std::fprintf(stderr, " -> %d\n", h->J64.R);
+      }
+    }
     h->setup_host_s = (t1 - t0) + (t3 - t2);
     h->setup_device_s = (t2 - t1) + (t4 - t3);
     if (o.verbose)
@@ -1598,6 +1742,12 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.reordered = h->d_perm ? 1 : 0;
     i.cross_pairs_natural = h->cross_natural;
     i.cross_pairs_used = h->cross_used;
+    i.tune_n = (int32_t)std::min<size_t>(h->tuned.size(), 8);
+    for (int c = 0; c < i.tune_n; ++c) {
+      i.tune_rows[c] = h->tuned[c].first;
+      i.tune_us[c] = h->tuned[c].second;
+    }
+    i.tune_s = h->tune_s;
     *out = i;
     return ASSS_OK;
   });

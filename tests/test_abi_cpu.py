@@ -46,7 +46,7 @@ def _header_struct_fields(name):
         names = " ".join(parts[1:]).replace(",", " ").split()
         if parts[0] == "const":
             names = " ".join(parts[2:]).replace(",", " ").split()
-        fields += names
+        fields += [re.sub(r"\[\d+\]$", "", f) for f in names]
     return fields
 
 
@@ -64,7 +64,7 @@ def test_defaults():
     o = asss.SetupOpts()
     lib.asss_default_setup_opts(ctypes.byref(o))
     assert o.gamma == 1.0 and o.s_pattern == 1 and o.k == 20 and o.lanczos_seed == 0x2009069540
-    assert o.x_tol == 1e-10 and o.inner_fp32 == 0
+    assert o.x_tol == 1e-10 and o.inner_fp32 == 0 and o.row_block == 0 and o.autotune == 0
     s = asss.SolveOpts()
     lib.asss_default_solve_opts(ctypes.byref(s))
     assert s.tol == 1e-8 and s.restart_m == 64 and s.inner_fp32 == -1
