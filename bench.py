@@ -44,10 +44,14 @@ def mrs_bytes_per_row(nh_per_row: float, k: int, v: int) -> float:
     return nh_per_row * (v + 4) + 4 + k * v + 10 * v
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, order: str, m: int):
     """HBM bytes per full inner step from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, if it was taken on the kernel source as it is now."""
-    path = os.path.join(ROOT, "profiles", "k_mrs_iter_convdiff3d_128_Pe100_k16_traffic.json")
+    WRITE_SIZE summary for this order of the inner system, if it was taken on
+    the kernel source as it is now (the 128^3 workload only)."""
+    if m != 128:
+        return None
+    suffix = "_linetiles4x4" if order == "x-line tiles 4x4" else ""
+    path = os.path.join(ROOT, "profiles", f"k_mrs_iter_convdiff3d_128_Pe100_k16{suffix}_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -57,6 +61,8 @@ def measured_traffic(precision: str):
         return None
     if rec.get("kernel_src_sha256") != sha or precision not in rec.get("kernels", {}):
         return None  # counters predate the current kernel
+    if rec.get("inner_order", "natural") != order:
+        return None
     return rec["kernels"][precision]["hbm_bytes"]
 
 
@@ -216,6 +222,13 @@ def main():
                          "loss ||x - x_t||^2, forward solve + backward (adjoint solve and dL/dA, dL/db) "
                          "through the autograd function, FP64, tol 1e-10")
     ap.add_argument("--outer", default="fgmres", choices=["fgmres", "tfqmr"])
+    ap.add_argument("--inner-order", choices=["natural", "tiles"], default="tiles",
+                    help="order of the inner system (a symmetric permutation of J_tilde that the "
+                         "solution does not depend on): tiles of whole x-lines (--tile TYxTZ lines per "
+                         "tile, one tile per row block; default) or the grid's natural order")
+    ap.add_argument("--tile", default="4x4")
+    ap.add_argument("--no-natural", action="store_true",
+                    help="with tiles: skip the comparison solves in the natural order")
     ap.add_argument("--autotune", choices=["on", "off"], default=None,
                     help="row-block autotuner at setup (times the inner step for several row-block "
                          "sizes and keeps the fastest).  Default: on for --batched (it picks larger "
@@ -248,7 +261,14 @@ def main():
     n, nnz = w.A.shape[0], w.A.nnz
     log(f"n={n} nnz={nnz}; setup (host preprocessing + device data)")
     t0 = time.perf_counter()
-    h = asss.setup(w.A, k=args.k, s_pattern="abar", verbose=args.verbose, autotune=args.autotune)
+    order_kw = {}
+    order_name = "natural" if args.inner_order == "natural" else f"x-line tiles {args.tile}"
+    if args.inner_order == "tiles":
+        ty, tz = (int(v) for v in args.tile.split("x"))
+        order_kw["reorder"] = W.grid_line_tiles(args.m, ty, tz)
+        if not args.autotune:
+            order_kw["row_block"] = args.m * ty * tz  # one tile per row block
+    h = asss.setup(w.A, k=args.k, s_pattern="abar", verbose=args.verbose, autotune=args.autotune, **order_kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     hi = h.info()
@@ -278,7 +298,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    def run(mixed: bool, steps: int, warmup: int):
+    def run(mixed: bool, steps: int, warmup: int, h=h):
         for i in range(warmup):
             _, inf = h.solve(b, out=x, tol=args.tol, inner_fp32=mixed, restart_m=args.restart,
                              inner_tol=args.inner_tol, max_outer=args.max_outer, outer=args.outer)
@@ -311,7 +331,7 @@ def main():
         bpr = mrs_bytes_per_row(hi["nh"] / n, hi["k_eff"], v)
         per_step = bpr * n
         achieved = per_step * steps / kern_s / 1e9
-        traffic = measured_traffic("fp64" if v == 8 else "fp32")
+        traffic = measured_traffic("fp64" if v == 8 else "fp32", order_name, args.m)
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per full step (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -329,7 +349,8 @@ def main():
         "config": {"workload": f"convdiff3d_{args.m}^3_Pe{args.peclet:g}", "n": n, "nnz": nnz,
                    "k": args.k, "s_pattern": "abar", "tol": args.tol,
                    "outer": f"fgmres({args.restart})" if args.outer == "fgmres" else "tfqmr",
-                   "inner_tol": args.inner_tol, "row_block": hi["row_block"]},
+                   "inner_tol": args.inner_tol, "row_block": hi["row_block"],
+                   "inner_order": order_name},
         "roofline": roofline(inf64, 8),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
                   "reorth_passes": inf64[-1]["reorth"],
@@ -352,6 +373,20 @@ def main():
                         "relres_true": inf32[-1]["relres_true"], "rel_err_vs_xstar": err32,
                         "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
                         "solve_s_per_step": [round(i["solve_s"], 4) for i in inf32]}
+    if args.inner_order == "tiles" and not args.no_natural:
+        # the same solves with the inner system in the grid's natural order
+        log("natural order of the inner system: setup and one solve per precision")
+        hn = asss.setup(w.A, k=args.k, s_pattern="abar")
+        nat = {"row_block": hn.info()["row_block"]}
+        for mixed in ([False] if args.no_mixed else [False, True]):
+            tn, infn, _ = run(mixed, 1, 1, h=hn)
+            key = "mixed" if mixed else "fp64"
+            nat[key + "_s"] = round(tn, 5)
+            nat[key + "_avg_launch_us"] = round(1e6 * infn[-1]["inner_kernel_s"] / max(1, infn[-1]["inner_launches"]), 2)
+            nat[key + "_inner_its"] = infn[-1]["inner_its_total"]
+        hn.close()
+        nat["speedup_of_tiles_fp64"] = round(nat["fp64_s"] / t64, 3)
+        res["natural_order"] = nat
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on convdiff3d {args.cpu_sample_m}^3")
         try:

@@ -127,10 +127,15 @@ typedef struct {
                                   pairs (i,j) straddle two blocks.  On the 3D
                                   convection-diffusion workload this stores 22 % fewer
                                   skew entries but is slower, because neighbours no
-                                  longer sit at a common offset across a wavefront */
+                                  longer sit at a common offset across a wavefront;
+                              3 = the caller's order in inner_perm.  For a grid, an
+                                  order in which each block of row_block rows is a
+                                  compact tile of whole grid lines keeps more pairs
+                                  inside a block than the natural order and keeps
+                                  the neighbours of a wavefront at common offsets */
   const asss_allocator_t* allocator; /* device memory of the handle; NULL = hipMalloc / hipFree */
-  int32_t autotune;        /* row-block autotuner (only with row_block = 0 and the natural
-                              order; reorder = 2 is rejected):
+  int32_t autotune;        /* row-block autotuner (only with row_block = 0; reorder = 2 is
+                              rejected):
                               0 = the automatic size (default);
                               1 = at the end of setup, pack J_tilde for the automatic size
                                   and up to two halvings and doublings of it within
@@ -139,6 +144,10 @@ typedef struct {
                                   right-hand side) and keep the fastest layout.  Costs one
                                   host packing and a few ms of GPU time per candidate;
                                   the result is in asss_handle_info_t.tune_* */
+  const int32_t* inner_perm; /* reorder = 3: host array of n entries, inner row i is row
+                              inner_perm[i] of J_tilde (new -> old); read during setup
+                              only; must be a permutation of 0..n-1 (INVALID_ARG else).
+                              Solutions do not depend on it beyond rounding */
 } asss_setup_opts_t;
 
 typedef struct {

@@ -53,7 +53,7 @@ class SetupOpts(C.Structure):
                 ("inner_fp32", C.c_int32), ("x_tol", C.c_double), ("x_maxit", C.c_int32),
                 ("lls_tol", C.c_double), ("lls_maxit", C.c_int32), ("row_block", C.c_int32),
                 ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32),
-                ("allocator", C.c_void_p), ("autotune", C.c_int32)]
+                ("allocator", C.c_void_p), ("autotune", C.c_int32), ("inner_perm", C.c_void_p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -321,7 +321,10 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     allocator: None (the library's hipMalloc) or "torch" (torch's caching
     allocator holds all device memory of the handle).
     autotune: time the inner step for several row-block sizes at setup and keep
-    the fastest (row_block must be 0; see info()["tune_rows"], ["tune_us"])."""
+    the fastest (row_block must be 0; see info()["tune_rows"], ["tune_us"]).
+    reorder: "auto"/"none" (natural order of the inner system), "blocks" (BFS
+    bisection into row blocks) or an integer array perm of length n (inner row
+    i is row perm[i])."""
     lib = load()
     n, rp, ci, va = _csr_arrays(A, canonicalize)
     csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
@@ -340,7 +343,14 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.autotune = int(bool(autotune))
     o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2}[deflation]
-    o.reorder = {"auto": 0, "none": 1, "blocks": 2}[reorder]
+    if isinstance(reorder, str):
+        o.reorder = {"auto": 0, "none": 1, "blocks": 2}[reorder]
+    else:  # the caller's order of the inner system: inner row i is row reorder[i]
+        perm = np.ascontiguousarray(reorder, dtype=np.int32)
+        if perm.shape != (n,):
+            raise ValueError("reorder must be 'auto', 'none', 'blocks' or a permutation of length n")
+        keep.append(perm)
+        o.reorder, o.inner_perm = 3, perm.ctypes.data
     alloc = None
     if allocator == "torch":
         alloc = torch_allocator()

@@ -481,8 +481,8 @@ double time_layout(asss_handle_s* h, const SkewLayout& L, bool fp32, hipStream_t
   return std::min(run(steps), run(steps));
 }
 
-// Packs the sliced layout of J_tilde (strict upper part Jup, natural order)
-// for every candidate row-block size, times the inner step on each in the
+// Packs the sliced layout of J_tilde (strict upper part Jup, in the order of
+// the inner system) for every candidate row-block size, times the inner step on each in the
 // handle's default inner precision and keeps the fastest in the handle.  All
 // layouts hold the same operator, so the deflation and SMW data stay valid.
 void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& cands, hipStream_t s) {
@@ -529,7 +529,8 @@ void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& ca
   h->sell_a = best.a_entries;
   h->sell_b = best.b_entries;
   h->narrow_b = best.narrow;
-  h->cross_natural = h->cross_used = count_cross_pairs(Jup, h->J64.R);
+  h->cross_natural = count_cross_pairs(h->U, h->J64.R);
+  h->cross_used = count_cross_pairs(Jup, h->J64.R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1320,6 +1321,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->deflation = 0;
   o->reorder = 0;
   o->autotune = 0;
+  o->inner_perm = nullptr;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -1347,12 +1349,13 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
     if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
     if (o.deflation < 0 || o.deflation > 2) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1 or 2"};
-    if (o.reorder < 0 || o.reorder > 2) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1 or 2"};
+    if (o.reorder < 0 || o.reorder > 3) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1, 2 or 3"};
+    if (o.reorder == 3 && !o.inner_perm) throw Error{ASSS_ERR_INVALID_ARG, "reorder 3 needs inner_perm"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     if (o.autotune < 0 || o.autotune > 1) throw Error{ASSS_ERR_INVALID_ARG, "autotune must be 0 or 1"};
     if (o.autotune && o.reorder == 2)
-      throw Error{ASSS_ERR_INVALID_ARG, "autotune needs the natural order (reorder 0 or 1)"};
+      throw Error{ASSS_ERR_INVALID_ARG, "autotune does not combine with reorder 2 (its blocks depend on row_block)"};
     hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<asss_handle_s> h(new asss_handle_s());
     HIPCHK(hipGetDevice(&h->device));
@@ -1428,6 +1431,18 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
         h->cross_used = cross;
         reordered = true;
       }
+    } else if (o.reorder == 3) {  // the caller's order, validated as a permutation
+      std::vector<int32_t> perm(o.inner_perm, o.inner_perm + n);
+      std::vector<char> seen(n, 0);
+      for (int64_t i = 0; i < n; ++i) {
+        if (perm[i] < 0 || perm[i] >= n || seen[perm[i]])
+          throw Error{ASSS_ERR_INVALID_ARG, "inner_perm is not a permutation of 0..n-1"};
+        seen[perm[i]] = 1;
+      }
+      Jup = permute_skew_upper(Jup, perm);
+      h->cross_used = count_cross_pairs(Jup, R);
+      h->perm = std::move(perm);
+      reordered = true;
     }
     SkewSell sell = pack_skew_sell(Jup, R);
     h->sell_a = sell.a_entries;

@@ -112,3 +112,18 @@ def test_validate_rejects_nonfinite():
     A = sp.csr_matrix(np.array([[1.0, np.nan], [0.0, 1.0]]))
     with pytest.raises(ValueError):
         O.validate_csr(A)
+
+
+def test_grid_line_tiles_is_a_tiling_permutation():
+    """The input-side ordering helper: a permutation whose consecutive runs of
+    m*ty*tz entries are ty x tz blocks of whole x-lines."""
+    m, ty, tz = 8, 2, 4
+    p = W.grid_line_tiles(m, ty, tz)
+    assert p.dtype == np.int32 and np.array_equal(np.sort(p), np.arange(m ** 3))
+    run = m * ty * tz
+    for t in range(m ** 3 // run):
+        q = p[t * run:(t + 1) * run]
+        x, y, z = q % m, (q // m) % m, q // (m * m)
+        assert np.array_equal(x, np.tile(np.arange(m), ty * tz))
+        assert len(set(y)) == ty and len(set(z)) == tz
+        assert y.max() - y.min() == ty - 1 and z.max() - z.min() == tz - 1

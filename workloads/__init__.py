@@ -181,6 +181,22 @@ def convdiff3d(m: int = 128, peclet: float = 100.0, cfg: int = 1,
                     meta={"m": m, "peclet": peclet, "wind": wind, "s_pattern": "abar", "k": 16})
 
 
+def grid_line_tiles(m: int, ty: int = 4, tz: int = 4) -> np.ndarray:
+    """An order of the m^3 grid (node x + m y + m^2 z) in which each run of
+    m*ty*tz consecutive positions is one tile of ty x tz whole x-lines: tiles in
+    lexicographic (y, z) order, inside a tile lines y-fastest, points x-fastest.
+    Returns perm with perm[new] = old (int32)."""
+    if m % ty or m % tz:
+        raise ValueError("ty and tz must divide m")
+    TZ = np.arange(m // tz)[:, None, None, None, None]
+    TY = np.arange(m // ty)[None, :, None, None, None]
+    z = np.arange(tz)[None, None, :, None, None]
+    y = np.arange(ty)[None, None, None, :, None]
+    x = np.arange(m)[None, None, None, None, :]
+    perm = x + m * ((TY * ty + y) + m * (TZ * tz + z))
+    return np.ascontiguousarray(perm.reshape(-1), dtype=np.int32)
+
+
 # ---------------------------------------------------------------------------
 # Batched uneven implicit Euler systems
 # ---------------------------------------------------------------------------
