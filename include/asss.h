@@ -148,6 +148,17 @@ typedef struct {
                               inner_perm[i] of J_tilde (new -> old); read during setup
                               only; must be a permutation of 0..n-1 (INVALID_ARG else).
                               Solutions do not depend on it beyond rounding */
+  int32_t skew_form;       /* column form of the sliced J_tilde storage:
+                              0 = automatic (default): offset slots when they store at
+                                  most 1.2x the entries of the per-entry forms (grid
+                                  patterns), else 16-bit off-block deltas when they fit,
+                                  else 32-bit columns;
+                              1 = 32-bit off-block columns;
+                              2 = 16-bit off-block column deltas (INVALID_ARG if a slot
+                                  spans 2^16 columns or more);
+                              3 = offset slots: every slot of a 64-row slice is one offset
+                                  d (column = row + d), no per-entry columns; INVALID_ARG
+                                  if that stores more than 16x the entries */
 } asss_setup_opts_t;
 
 typedef struct {
@@ -273,6 +284,8 @@ typedef struct {
   int64_t cross_pairs_used;               /* the same in the order used */
   int32_t narrow_b_columns;               /* 1: off-block columns stored as 16-bit deltas
                                              from per-slot bases (grid-like patterns) */
+  int32_t skew_form;                      /* column form used: 1 32-bit, 2 16-bit deltas,
+                                             3 offset slots (see asss_setup_opts_t) */
   int32_t tune_n;                         /* row-block candidates timed (0: no autotune) */
   int32_t tune_rows[8];                   /* their row_block values, ascending */
   double tune_us[8];                      /* their inner-step times (microseconds) */

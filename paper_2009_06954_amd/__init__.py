@@ -53,7 +53,8 @@ class SetupOpts(C.Structure):
                 ("inner_fp32", C.c_int32), ("x_tol", C.c_double), ("x_maxit", C.c_int32),
                 ("lls_tol", C.c_double), ("lls_maxit", C.c_int32), ("row_block", C.c_int32),
                 ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32),
-                ("allocator", C.c_void_p), ("autotune", C.c_int32), ("inner_perm", C.c_void_p)]
+                ("allocator", C.c_void_p), ("autotune", C.c_int32), ("inner_perm", C.c_void_p),
+                ("skew_form", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -111,7 +112,7 @@ class HandleInfo(C.Structure):
                 ("sell_entries_b", C.c_int64), ("lls_relres", C.c_double), ("lls_kkt", C.c_double),
                 ("lanczos_orth_err", C.c_double), ("deflation_mode", C.c_int32), ("reordered", C.c_int32),
                 ("cross_pairs_natural", C.c_int64), ("cross_pairs_used", C.c_int64),
-                ("narrow_b_columns", C.c_int32), ("tune_n", C.c_int32),
+                ("narrow_b_columns", C.c_int32), ("skew_form", C.c_int32), ("tune_n", C.c_int32),
                 ("tune_rows", C.c_int32 * 8), ("tune_us", C.c_double * 8), ("tune_s", C.c_double)]
 
     def to_dict(self):
@@ -311,10 +312,13 @@ class Handle:
         return out
 
 
+SKEW_FORMS = {"auto": 0, "wide": 1, "narrow": 2, "slots": 3}
+
+
 def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, inner_fp32=False,
           x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
           stream=None, canonicalize=True, deflation="auto", reorder="auto", allocator=None,
-          autotune=False) -> Handle:
+          autotune=False, skew_form="auto") -> Handle:
     """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
     canonicalize: sum duplicates and sort column indices of a SciPy input first
     (otherwise the library rejects such input with INVALID_CSR).
@@ -324,7 +328,9 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     the fastest (row_block must be 0; see info()["tune_rows"], ["tune_us"]).
     reorder: "auto"/"none" (natural order of the inner system), "blocks" (BFS
     bisection into row blocks) or an integer array perm of length n (inner row
-    i is row perm[i])."""
+    i is row perm[i]).
+    skew_form: storage of J_tilde's columns: "auto", "wide" (32-bit), "narrow"
+    (16-bit deltas) or "slots" (one offset per slot, no per-entry columns)."""
     lib = load()
     n, rp, ci, va = _csr_arrays(A, canonicalize)
     csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
@@ -342,6 +348,7 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.x_tol, o.x_maxit, o.lls_tol, o.lls_maxit = x_tol, x_maxit, lls_tol, lls_maxit
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.autotune = int(bool(autotune))
+    o.skew_form = SKEW_FORMS[skew_form]
     o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2}[deflation]
     if isinstance(reorder, str):
         o.reorder = {"auto": 0, "none": 1, "blocks": 2}[reorder]

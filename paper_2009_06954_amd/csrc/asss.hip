@@ -120,7 +120,7 @@ DCsr upload_csr(DevArena& ar, const Csr& M, hipStream_t s) {
 template <typename T>
 DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32_t* aw,
                      const int32_t* bw, const int64_t* ao, const int64_t* bo, const uint16_t* ac,
-                     const int32_t* bc, const uint16_t* bcd, const int32_t* bbase) {
+                     const int32_t* bc, const uint16_t* bcd, const int32_t* bbase, const int32_t* adoff) {
   DSkew<T> d;
   d.n = S.n;
   d.R = S.R;
@@ -135,6 +135,8 @@ DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32
   d.b_cd = bcd;
   d.b_base = bbase;
   d.b_narrow = S.b_narrow ? 1 : 0;
+  d.a_doff = adoff;
+  d.form = S.form;
   std::vector<T> av(S.a_val.begin(), S.a_val.end()), bv(S.b_val.begin(), S.b_val.end());
   d.a_val = ar.upload(av, s);
   d.b_val = ar.upload(bv, s);
@@ -149,6 +151,7 @@ struct SkewLayout {
   std::vector<const void*> bufs;
   int64_t a_entries = 0, b_entries = 0;
   int narrow = 0;
+  int form = SKEW_WIDE;
 };
 
 SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s) {
@@ -158,23 +161,28 @@ SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s) {
   const int32_t* bw = ar.upload(sell.b_width, s);
   const int64_t* ao = ar.upload(sell.a_off, s);
   const int64_t* bo = ar.upload(sell.b_off, s);
-  const uint16_t* ac = ar.upload(sell.a_col, s);
-  // part-b columns: 16-bit deltas from per-slot bases when every slot fits
-  // (2 bytes per entry instead of 4), else global 32-bit columns
-  const int32_t* bc = sell.b_narrow ? nullptr : ar.upload(sell.b_col, s);
-  const uint16_t* bcd = sell.b_narrow ? ar.upload(sell.b_cd, s) : nullptr;
-  const int32_t* bbase = sell.b_narrow ? ar.upload(sell.b_base, s) : nullptr;
+  // per-entry columns: part a 16-bit local; part b 16-bit deltas from per-slot
+  // bases when every slot fits (2 bytes per entry instead of 4), else global
+  // 32-bit columns.  Offset slots store no per-entry columns, only one offset
+  // per slot (part a) and one base per slot (part b).
+  const bool slots = sell.form == SKEW_SLOTS;
+  const uint16_t* ac = slots ? nullptr : ar.upload(sell.a_col, s);
+  const int32_t* bc = (sell.form == SKEW_WIDE) ? ar.upload(sell.b_col, s) : nullptr;
+  const uint16_t* bcd = (sell.form == SKEW_NARROW) ? ar.upload(sell.b_cd, s) : nullptr;
+  const int32_t* bbase = (sell.form != SKEW_WIDE) ? ar.upload(sell.b_base, s) : nullptr;
+  const int32_t* adoff = slots ? ar.upload(sell.a_doff, s) : nullptr;
   for (const void* p : {(const void*)aw, (const void*)bw, (const void*)ao, (const void*)bo, (const void*)ac,
-                        (const void*)bc, (const void*)bcd, (const void*)bbase})
+                        (const void*)bc, (const void*)bcd, (const void*)bbase, (const void*)adoff})
     keep(p);
-  L.J64 = upload_sell<double>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
-  L.J32 = upload_sell<float>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase);
+  L.J64 = upload_sell<double>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase, adoff);
+  L.J32 = upload_sell<float>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase, adoff);
   for (const void* p : {(const void*)L.J64.a_val, (const void*)L.J64.b_val, (const void*)L.J32.a_val,
                         (const void*)L.J32.b_val})
     keep(p);
   L.a_entries = sell.a_entries;
   L.b_entries = sell.b_entries;
   L.narrow = sell.b_narrow ? 1 : 0;
+  L.form = sell.form;
   return L;
 }
 
@@ -219,6 +227,7 @@ struct asss_handle_s {
   int32_t* d_perm = nullptr;  // null when the natural order is kept
   int64_t cross_natural = 0, cross_used = 0;
   int narrow_b = 0;  // part-b columns stored as 16-bit deltas
+  int skew_form = 0; // column form of the sliced J_tilde (SKEW_*)
   double* d_Qorig = nullptr;  // Q_k in the original order (U_bar, export)
   double* d_Q64 = nullptr;    // Q_k in the inner (block) order
   float* d_Q32 = nullptr;
@@ -505,11 +514,12 @@ void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& ca
   best.a_entries = h->sell_a;
   best.b_entries = h->sell_b;
   best.narrow = h->narrow_b;
+  best.form = h->skew_form;
   double t_best = time_layout(h, best, fp32, s);
   h->tuned.assign(1, {h->J64.R, 1e6 * t_best});
   for (int R : cands) {
     if (R == best.J64.R) continue;
-    SkewSell sell = pack_skew_sell(Jup, R);
+    SkewSell sell = pack_skew_sell(Jup, R, h->opts.skew_form);
     SkewLayout cand = upload_layout(h->ar, sell, s);
     HIPCHK(hipStreamSynchronize(s));
     const double t = time_layout(h, cand, fp32, s);
@@ -529,6 +539,7 @@ void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& ca
   h->sell_a = best.a_entries;
   h->sell_b = best.b_entries;
   h->narrow_b = best.narrow;
+  h->skew_form = best.form;
   h->cross_natural = count_cross_pairs(h->U, h->J64.R);
   h->cross_used = count_cross_pairs(Jup, h->J64.R);
 }
@@ -1322,6 +1333,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->reorder = 0;
   o->autotune = 0;
   o->inner_perm = nullptr;
+  o->skew_form = 0;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -1354,6 +1366,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     if (o.autotune < 0 || o.autotune > 1) throw Error{ASSS_ERR_INVALID_ARG, "autotune must be 0 or 1"};
+    if (o.skew_form < 0 || o.skew_form > 3) throw Error{ASSS_ERR_INVALID_ARG, "skew_form must be 0, 1, 2 or 3"};
     if (o.autotune && o.reorder == 2)
       throw Error{ASSS_ERR_INVALID_ARG, "autotune does not combine with reorder 2 (its blocks depend on row_block)"};
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1444,7 +1457,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
       h->perm = std::move(perm);
       reordered = true;
     }
-    SkewSell sell = pack_skew_sell(Jup, R);
+    SkewSell sell = pack_skew_sell(Jup, R, o.skew_form);
     h->sell_a = sell.a_entries;
     h->sell_b = sell.b_entries;
     { LlsSystem dummy; std::swap(L, dummy); }
@@ -1468,6 +1481,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     {
       SkewLayout lay = upload_layout(h->ar, sell, s);
       h->narrow_b = lay.narrow;
+      h->skew_form = lay.form;
       h->J64 = lay.J64;
       h->J32 = lay.J32;
       h->lay_bufs = std::move(lay.bufs);
@@ -1753,6 +1767,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.lls_kkt = h->lls_kkt;
     i.lanczos_orth_err = h->orth_err;
     i.narrow_b_columns = h->narrow_b;
+    i.skew_form = h->skew_form;
     i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : 1);
     i.reordered = h->d_perm ? 1 : 0;
     i.cross_pairs_natural = h->cross_natural;

@@ -572,15 +572,118 @@ void split_ahat(const Csr& Ahat, const Csr& U, std::vector<double>& D, std::vect
 // Sliced layout of J_tilde
 // ---------------------------------------------------------------------------
 
-SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
+// Slot form: per slice, the sorted distinct offsets d = j - i of its rows'
+// in-block upper entries (part a) and of its off-block entries of both
+// triangles (part b); one slot per offset.
+static SkewSell pack_skew_slots(const Csr& Jup, const Csr& Lo, int32_t R,
+                                const std::vector<std::vector<int32_t>>& aoffs,
+                                const std::vector<std::vector<int32_t>>& boffs) {
   SkewSell S;
   const int64_t n = Jup.nrows;
   S.n = (int32_t)n;
   S.R = R;
   S.nblocks = (int32_t)((n + R - 1) / R);
   S.nslices = (int32_t)((n + 63) / 64);
+  S.form = SKEW_SLOTS;
+  S.a_width.assign(S.nslices, 0);
+  S.b_width.assign(S.nslices, 0);
+  S.a_off.assign(S.nslices + 1, 0);
+  S.b_off.assign(S.nslices + 1, 0);
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    S.a_width[s] = (int32_t)aoffs[s].size();
+    S.b_width[s] = (int32_t)boffs[s].size();
+    S.a_off[s + 1] = S.a_off[s] + (int64_t)S.a_width[s] * 64;
+    S.b_off[s + 1] = S.b_off[s] + (int64_t)S.b_width[s] * 64;
+  }
+  S.a_val.assign(S.a_off[S.nslices], 0.0);
+  S.b_val.assign(S.b_off[S.nslices], 0.0);
+  S.a_doff.assign(S.a_off[S.nslices] / 64, 0);
+  S.b_base.assign(S.b_off[S.nslices] / 64, 0);
+  std::vector<int64_t> na(S.nslices, 0), nb(S.nslices, 0);
+  parallel_for(S.nslices, [&](int64_t lo, int64_t hi) {
+    for (int64_t s = lo; s < hi; ++s) {
+      const auto& ao = aoffs[s];
+      const auto& bo = boffs[s];
+      for (size_t t = 0; t < ao.size(); ++t) S.a_doff[S.a_off[s] / 64 + t] = ao[t];
+      for (size_t t = 0; t < bo.size(); ++t) S.b_base[S.b_off[s] / 64 + t] = (int32_t)(s * 64 + bo[t]);
+      auto slot = [](const std::vector<int32_t>& v, int64_t d) {
+        return (int64_t)(std::lower_bound(v.begin(), v.end(), (int32_t)d) - v.begin());
+      };
+      for (int lane = 0; lane < 64; ++lane) {
+        const int64_t i = s * 64 + lane;
+        if (i >= n) break;
+        const int64_t blk = i / R;
+        for (int64_t p = Lo.ptr[i]; p < Lo.ptr[i + 1]; ++p)
+          if (Lo.col[p] / R != blk) {
+            S.b_val[S.b_off[s] + slot(bo, Lo.col[p] - i) * 64 + lane] = -Lo.val[p];
+            ++nb[s];
+          }
+        for (int64_t p = Jup.ptr[i]; p < Jup.ptr[i + 1]; ++p) {
+          const int64_t j = Jup.col[p];
+          if (j / R == blk) {
+            S.a_val[S.a_off[s] + slot(ao, j - i) * 64 + lane] = Jup.val[p];
+            ++na[s];
+          } else {
+            S.b_val[S.b_off[s] + slot(bo, j - i) * 64 + lane] = Jup.val[p];
+            ++nb[s];
+          }
+        }
+      }
+    }
+  });
+  for (int64_t s = 0; s < S.nslices; ++s) {
+    S.a_entries += na[s];
+    S.b_entries += nb[s];
+  }
+  return S;
+}
+
+SkewSell pack_skew_sell(const Csr& Jup, int32_t R, int32_t form) {
+  const int64_t n = Jup.nrows;
+  const int64_t nslices = (n + 63) / 64;
   // lower part: for row i, entries (i, j) with j < i come from upper row j
   Csr Lo = transpose(Jup);  // row i of Lo: columns j < i with value u_ji
+  if (form == SKEW_AUTO || form == SKEW_SLOTS) {
+    std::vector<std::vector<int32_t>> aoffs(nslices), boffs(nslices);
+    std::vector<int64_t> per_std(nslices, 0), per_slots(nslices, 0);
+    parallel_for(nslices, [&](int64_t lo, int64_t hi) {
+      for (int64_t s = lo; s < hi; ++s) {
+        auto& ao = aoffs[s];
+        auto& bo = boffs[s];
+        int32_t wa = 0, wl = 0, wu = 0;
+        for (int64_t i = s * 64; i < std::min<int64_t>(n, s * 64 + 64); ++i) {
+          const int64_t blk = i / R;
+          int32_t ra = 0, rl = 0, ru = 0;
+          for (int64_t p = Lo.ptr[i]; p < Lo.ptr[i + 1]; ++p)
+            if (Lo.col[p] / R != blk) { bo.push_back((int32_t)(Lo.col[p] - i)); ++rl; }
+          for (int64_t p = Jup.ptr[i]; p < Jup.ptr[i + 1]; ++p) {
+            if (Jup.col[p] / R == blk) { ao.push_back((int32_t)(Jup.col[p] - i)); ++ra; }
+            else { bo.push_back((int32_t)(Jup.col[p] - i)); ++ru; }
+          }
+          wa = std::max(wa, ra);
+          wl = std::max(wl, rl);
+          wu = std::max(wu, ru);
+        }
+        std::sort(ao.begin(), ao.end());
+        ao.erase(std::unique(ao.begin(), ao.end()), ao.end());
+        std::sort(bo.begin(), bo.end());
+        bo.erase(std::unique(bo.begin(), bo.end()), bo.end());
+        per_std[s] = (int64_t)wa + wl + wu;
+        per_slots[s] = (int64_t)ao.size() + bo.size();
+      }
+    });
+    int64_t tot_std = 0, tot_slots = 0;
+    for (int64_t s = 0; s < nslices; ++s) { tot_std += per_std[s]; tot_slots += per_slots[s]; }
+    if (form == SKEW_SLOTS && tot_slots > 16 * std::max<int64_t>(tot_std, 1))
+      fail(ASSS_ERR_INVALID_ARG, "the slot form of this matrix would store more than 16x the entries");
+    if (form == SKEW_SLOTS || tot_slots * 10 <= tot_std * 12)
+      return pack_skew_slots(Jup, Lo, R, aoffs, boffs);
+  }
+  SkewSell S;
+  S.n = (int32_t)n;
+  S.R = R;
+  S.nblocks = (int32_t)((n + R - 1) / R);
+  S.nslices = (int32_t)nslices;
   // part b of a row: nbl entries in earlier blocks, then nbu in later blocks;
   // each group gets its own slot range in the slice (below), so that one slot
   // never mixes a neighbour before the block with one after it
@@ -703,7 +806,10 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R) {
       }
     }
   });
-  S.b_narrow = (wide == 0);
+  if (form == SKEW_NARROW && wide != 0)
+    fail(ASSS_ERR_INVALID_ARG, "16-bit off-block columns do not fit this matrix");
+  S.b_narrow = (wide == 0) && form != SKEW_WIDE;
+  S.form = S.b_narrow ? SKEW_NARROW : SKEW_WIDE;
   if (S.b_narrow) {
     S.b_cd.resize(S.b_col.size());
     parallel_for(nslots, [&](int64_t lo, int64_t hi) {

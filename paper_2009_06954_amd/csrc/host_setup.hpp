@@ -89,6 +89,20 @@ void split_ahat(const Csr& Ahat, const Csr& U, std::vector<double>& D, std::vect
 //           with the signed value of J_tilde (lower entries are -u_ji).
 // Each part of a slice is stored column-major in (width x 64) with padding
 // entries (local/global column = the row itself, value 0).
+//
+// Column forms (form):
+//   SKEW_WIDE    part a: 16-bit local columns; part b: 32-bit global columns;
+//   SKEW_NARROW  part b as a 16-bit delta from a per-(slice, slot) base, when
+//                every slot spans fewer than 2^16 columns;
+//   SKEW_SLOTS   no per-entry columns: each slot of a slice holds one offset d
+//                (column = row + d) for all 64 lanes, lanes without that entry
+//                hold value 0.  Part a keeps d per slot (a_doff, d > 0), part b
+//                the column of lane 0 (b_base = first row of the slice + d); the
+//                reader clamps a padding lane's column into the block (part a)
+//                or into [0, n) (part b).  Slots are the sorted distinct offsets
+//                of the slice's entries in each part, so a grid pattern needs
+//                about as many slots as it has entries per row.
+enum { SKEW_AUTO = 0, SKEW_WIDE = 1, SKEW_NARROW = 2, SKEW_SLOTS = 3 };
 struct SkewSell {
   int32_t n = 0, R = 0, nblocks = 0, nslices = 0;
   std::vector<int32_t> a_width, b_width;  // per slice
@@ -101,10 +115,17 @@ struct SkewSell {
   bool b_narrow = false;
   std::vector<int32_t> b_base;
   std::vector<uint16_t> b_cd;
+  std::vector<int32_t> a_doff;            // SKEW_SLOTS: offset d per part-a slot
   std::vector<double> a_val, b_val;
   int64_t a_entries = 0, b_entries = 0;   // real (unpadded) entries
+  int32_t form = SKEW_WIDE;
 };
-SkewSell pack_skew_sell(const Csr& Jup, int32_t R);
+// form: SKEW_AUTO picks SKEW_SLOTS when it stores at most 1.2 times the
+// entries (padding included) of the per-entry-column forms, else SKEW_NARROW
+// when it fits, else SKEW_WIDE.  A forced SKEW_NARROW that does not fit, or a
+// forced SKEW_SLOTS that would store more than 16 times as many entries,
+// throws HostError(ASSS_ERR_INVALID_ARG).
+SkewSell pack_skew_sell(const Csr& Jup, int32_t R, int32_t form = SKEW_AUTO);
 
 // Symmetric reordering of the inner system into compact blocks of R rows:
 // recursive bisection of the graph of J_tilde (pattern of U + U^T), each cut

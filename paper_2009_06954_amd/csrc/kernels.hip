@@ -245,7 +245,11 @@ __device__ __forceinline__ int xcd_block() {
 // FP64 sums round to T once when read.
 // ---------------------------------------------------------------------------
 
-template <typename T, int NR, bool STAGE, bool NARROW>
+// FORM: 1 = 32-bit part-b columns, 2 = 16-bit part-b deltas from a per-slot
+// base, 3 = offset slots (no per-entry columns: every lane of a slot reads
+// column row + d; padding lanes, whose value is 0, are clamped into the block
+// for part a and into [0, n) for part b).
+template <typename T, int NR, bool STAGE, int FORM>
 __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t row0, int nrow,
                                                      const T* __restrict__ wg, const T* w_lds,
                                                      double* acc_lds) {
@@ -259,6 +263,7 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
   constexpr int P = (NR == 1) ? 2 : 1;
   constexpr int U = (NR == 1) ? 4 : 8;
   constexpr int NW = WG / 64;
+  constexpr bool NARROW = FORM == 2, SLOTS = FORM == 3;
   // the wave index is uniform: said so, the slice metadata below comes in
   // through scalar loads instead of a vector round trip per slice
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -272,6 +277,7 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
     const int32_t* __restrict__ bcol[P];
     const uint16_t* __restrict__ bcd[P];
     const int32_t* __restrict__ bbase[P];
+    const int32_t* __restrict__ adoff[P];
     const T* __restrict__ bval[P];
     T acc[P][NR], wi[P][NR];
     int wmax = 0;
@@ -290,6 +296,7 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
       bcol[p] = J.b_col + J.b_off[s] + lane;
       bcd[p] = J.b_cd + J.b_off[s] + lane;
       bbase[p] = J.b_base + (J.b_off[s] >> 6);
+      adoff[p] = J.a_doff + (J.a_off[s] >> 6);
       bval[p] = J.b_val + J.b_off[s] + lane;
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
@@ -309,14 +316,18 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (l0 + u < wa[p]) {
-            jl[p][u] = __builtin_nontemporal_load(&acol[p][(l0 + u) * 64]);
+            if (SLOTS)  // d > 0 (uniform); padding lanes past the block end clamp to its last row
+              jl[p][u] = min(il[p] + adoff[p][l0 + u], nrow - 1);
+            else
+              jl[p][u] = __builtin_nontemporal_load(&acol[p][(l0 + u) * 64]);
             va[p][u] = __builtin_nontemporal_load(&aval[p][(l0 + u) * 64]);
           }
           if (l0 + u < wb[p]) {
-            // narrow: the 16-bit delta now, its slot base (uniform) at the gather
+            // narrow: the 16-bit delta now, its slot base (uniform) at the gather;
+            // slots: no column load at all
             if (NARROW)
               jb[p][u] = (int32_t)__builtin_nontemporal_load(&bcd[p][(l0 + u) * 64]);
-            else
+            else if (!SLOTS)
               jb[p][u] = __builtin_nontemporal_load(&bcol[p][(l0 + u) * 64]);
             vb[p][u] = __builtin_nontemporal_load(&bval[p][(l0 + u) * 64]);
           }
@@ -327,7 +338,9 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
 #pragma unroll
         for (int u = 0; u < U; ++u)
           if (l0 + u < wb[p]) {
-            const int32_t col = NARROW ? bbase[p][l0 + u] + jb[p][u] : jb[p][u];
+            const int32_t col = SLOTS    ? min(max(bbase[p][l0 + u] + lane, 0), J.n - 1)
+                                : NARROW ? bbase[p][l0 + u] + jb[p][u]
+                                         : jb[p][u];
 #pragma unroll
             for (int c = 0; c < NR; ++c) wj[p][u][c] = wg[(int64_t)col * NR + c];
           }
@@ -361,15 +374,17 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
   }
 }
 
-// The column form of part b is fixed per matrix: one uniform branch per launch.
+// The column form is fixed per matrix: one uniform branch per launch.
 template <typename T, int NR, bool STAGE>
 __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
                                                 const T* __restrict__ wg, const T* w_lds,
                                                 double* acc_lds) {
-  if (J.b_narrow)
-    skew_block_pass_form<T, NR, STAGE, true>(J, row0, nrow, wg, w_lds, acc_lds);
+  if (J.form == 3)
+    skew_block_pass_form<T, NR, STAGE, 3>(J, row0, nrow, wg, w_lds, acc_lds);
+  else if (J.form == 2)
+    skew_block_pass_form<T, NR, STAGE, 2>(J, row0, nrow, wg, w_lds, acc_lds);
   else
-    skew_block_pass_form<T, NR, STAGE, false>(J, row0, nrow, wg, w_lds, acc_lds);
+    skew_block_pass_form<T, NR, STAGE, 1>(J, row0, nrow, wg, w_lds, acc_lds);
 }
 
 template <typename T>

@@ -32,8 +32,10 @@ struct DSkew {
   const uint16_t* a_col = nullptr;
   const int32_t* b_col = nullptr;   // wide part-b columns (b_narrow == 0)
   const uint16_t* b_cd = nullptr;   // narrow: column = b_base[b_off / 64 + slot] + b_cd
-  const int32_t* b_base = nullptr;
+  const int32_t* b_base = nullptr;  // slots: column of lane 0 = first row of the slice + d
+  const int32_t* a_doff = nullptr;  // slots: part-a offset d > 0 per slot (a_off / 64 + slot)
   int32_t b_narrow = 0;
+  int32_t form = 1;                 // 1: 32-bit part-b columns, 2: 16-bit deltas, 3: offset slots
   const T* a_val = nullptr;
   const T* b_val = nullptr;
 };

@@ -49,7 +49,7 @@ def test_autotune_keeps_the_fastest_candidate(handles):
 
 def test_autotuned_layout_equals_explicit_row_block(handles):
     it, ir = handles["ht"].info(), handles["hr"].info()
-    for key in ("row_block", "nblocks", "sell_entries_a", "sell_entries_b", "narrow_b_columns",
+    for key in ("row_block", "nblocks", "sell_entries_a", "sell_entries_b", "narrow_b_columns", "skew_form",
                 "cross_pairs_natural", "k_eff"):
         assert it[key] == ir[key], key
 

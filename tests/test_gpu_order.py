@@ -96,7 +96,7 @@ def test_line_tiles_on_a_3d_grid():
           f"b {i_n['sell_entries_b']} -> {it['sell_entries_b']}", flush=True)
     assert it["cross_pairs_used"] < 0.7 * i_n["cross_pairs_used"]
     assert it["sell_entries_a"] + it["sell_entries_b"] < i_n["sell_entries_a"] + i_n["sell_entries_b"]
-    assert it["narrow_b_columns"] == 1
+    assert it["skew_form"] == 3  # offset slots
     v = np.random.default_rng(3).uniform(-1, 1, m ** 3)
     yt, _ = ht.apply("skew", _cuda(v))
     yn, _ = hn.apply("skew", _cuda(v))

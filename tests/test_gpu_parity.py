@@ -433,17 +433,39 @@ def test_outer_method_must_be_known(cfg0):
 
 
 def test_column_storage_forms(cfg0):
-    """Grid matrices store their off-block columns as 16-bit deltas from
-    per-slot bases (the operator tests above run on that form); a random
-    pattern with n = 120,000 spans more than 2^16 columns per slot and keeps
-    global 32-bit columns: its skew operator is checked against the exported
-    CSR of J_tilde, componentwise and for exact skewness."""
+    """Grid matrices store J_tilde in offset slots by default (no per-entry
+    columns; the operator tests above run on that form).  Each of the three
+    column forms, forced on the cfg0 matrix, gives the oracle's skew operator,
+    inner mrs and solution.  A random pattern with n = 120,000 keeps global
+    32-bit columns (its slots span more than 2^16 columns, and offset slots
+    would store far more entries): its skew operator is checked against the
+    exported CSR of J_tilde, componentwise and for exact skewness, and the
+    two forms that do not fit it are refused."""
     asss = _lib()
-    assert cfg0.h.info()["narrow_b_columns"] == 1
+    assert cfg0.h.info()["skew_form"] == 3 and cfg0.h.info()["narrow_b_columns"] == 0
+    w, st = cfg0.w, cfg0.st
+    v = np.random.default_rng(17).standard_normal(w.A.shape[0])
+    ref_skew = st.prec.jtilde(v)
+    bound = _skew_bound(st, v)
+    ref_mrs = O.mrs(1.0, st.prec.jbar, v, 25, 0.0, 25)[0]
+    xo, _ = O.solve(st, w.b, O.SolveOptions(tol=1e-12))
+    for form, code in (("wide", 1), ("narrow", 2), ("slots", 3)):
+        print(f"[forms] cfg0 forced {form}", flush=True)
+        h = asss.setup(w.A, k=8, s_pattern="tridiag", skew_form=form, row_block=128)
+        assert h.info()["skew_form"] == code
+        out, _ = h.apply("skew", _cuda(v))
+        _within_rounding(_np(out), ref_skew, bound)
+        out, _ = h.apply("skew", _cuda(v), inner_fp32=True)
+        assert _rel(_np(out), ref_skew) <= 2e-6, form
+        out, _ = h.apply("mrs", _cuda(v), fixed_inner_steps=25)
+        assert _rel(_np(out), ref_mrs) <= 1e-11, form
+        x, info = h.solve(_cuda(w.b), tol=1e-12)
+        assert info["status"] == "OK" and _rel(_np(x), xo) <= 1e-10, form
+        h.close()
     w = W.paper_like(120000, 600000, seed=3)
     print(f"[wide] n={w.A.shape[0]} nnz={w.A.nnz}", flush=True)
     h = asss.setup(w.A, k=4, s_pattern="tridiag")
-    assert h.info()["narrow_b_columns"] == 0
+    assert h.info()["skew_form"] == 1 and h.info()["narrow_b_columns"] == 0
     U = sp.csr_matrix((h.array("J_val"), h.array("J_colind"), h.array("J_rowptr")), shape=w.A.shape)
     J = (U - U.T).tocsr()
     v = np.random.default_rng(9).uniform(-1, 1, w.A.shape[0])
@@ -454,6 +476,10 @@ def test_column_storage_forms(cfg0):
         assert np.all(np.abs(y - J @ v) <= c * bound + 1e-300)
         assert abs(v @ y) <= (1e-5 if fp32 else 1e-12) * (np.abs(v) @ bound)
     h.close()
+    for form in ("narrow", "slots"):
+        with pytest.raises(asss.AsssError) as e:
+            asss.setup(w.A, k=4, s_pattern="tridiag", skew_form=form)
+        assert e.value.name == "INVALID_ARG"
 
 
 def test_torch_allocator():

@@ -1,8 +1,11 @@
 """Host logic of the sliced skew storage (no GPU): the packer's output, read
-back on the CPU, applies exactly the skew matrix of its CSR input (in-block
-and off-block parts, ragged last block, several row-block sizes), and grid
-patterns get the 16-bit off-block column form (the 32-bit form is exercised
-on the GPU with a random pattern)."""
+back on the CPU the way the kernels read it, applies exactly the skew matrix
+of its CSR input (in-block and off-block parts, ragged last block, several
+row-block sizes) in each column form: grid patterns get the offset-slot form
+by default, and the 32-bit, 16-bit and slot forms can be forced; a random
+pattern keeps per-entry columns and refuses the slot form.  In the slot form
+every real entry's column must be reachable without the clamp that the
+kernels apply to padding lanes."""
 import os
 import shutil
 import subprocess
@@ -26,9 +29,30 @@ def checker(tmp_path_factory):
     return exe
 
 
+def _run(checker, *args):
+    r = subprocess.run([checker, *map(str, args)], capture_output=True, text=True, timeout=300)
+    print(r.stdout)
+    return r
+
+
 @pytest.mark.parametrize("m,R", [(12, 64), (20, 128), (33, 512), (48, 2048)])
 def test_packed_skew_storage_is_exact(checker, m, R):
-    r = subprocess.run([checker, str(m), str(R)], capture_output=True, text=True, timeout=300)
-    print(r.stdout)
+    r = _run(checker, m, R)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert "narrow=1" in r.stdout
+    assert "form=3" in r.stdout  # offset slots for a grid pattern
+
+
+@pytest.mark.parametrize("form,tag", [(1, "form=1 narrow=0"), (2, "form=2 narrow=1"), (3, "form=3")])
+@pytest.mark.parametrize("m,R", [(12, 64), (33, 512)])
+def test_forced_column_forms_are_exact(checker, m, R, form, tag):
+    r = _run(checker, m, R, form)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert tag in r.stdout
+
+
+def test_random_pattern_keeps_entry_columns(checker):
+    r = _run(checker, 20, 128, 0, "random")
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "form=3" not in r.stdout
+    r = _run(checker, 20, 128, 3, "random")
+    assert r.returncode == 3 and "rejected" in r.stdout
