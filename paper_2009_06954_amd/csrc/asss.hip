@@ -1682,7 +1682,13 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
         }
       return worst;
     }
-    // worker streams (default priority) start after the caller's stream
+    // worker streams (default priority) start after the caller's stream; the
+    // caller's current device is restored on the way out
+    struct DeviceRestore {
+      int prev = -1;
+      ~DeviceRestore() { if (prev >= 0) (void)hipSetDevice(prev); }
+    } restore;
+    HIPCHK(hipGetDevice(&restore.prev));
     HIPCHK(hipSetDevice(hs[0]->device));
     hipEvent_t ready = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
@@ -1696,6 +1702,12 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
         HIPCHK(hipStreamWaitEvent(streams[w], ready, 0));
       }
       std::vector<std::thread> threads;
+      // a thread that cannot be started must not leave the started ones
+      // unjoined: they are joined before the error goes on
+      struct JoinAll {
+        std::vector<std::thread>& t;
+        ~JoinAll() { for (auto& x : t) if (x.joinable()) x.join(); }
+      } join_all{threads};
       for (int w = 0; w < nworkers; ++w)
         threads.emplace_back([&, w]() {
           try {
@@ -1714,6 +1726,9 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
           } catch (const std::exception& e) {
             out[w].code = ASSS_ERR_INTERNAL;
             out[w].msg = e.what();
+          } catch (...) {
+            out[w].code = ASSS_ERR_INTERNAL;
+            out[w].msg = "unknown error in a batched-solve worker";
           }
         });
       for (auto& t : threads) t.join();
