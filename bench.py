@@ -117,6 +117,13 @@ def batched(args, asss, torch, np, W):
     kw = dict(tol=args.tol, inner_fp32=not args.no_mixed, restart_m=64, inner_tol=1e-2)
     asss.solve_batched(hs[:2], Bs[:2], **kw)  # warm-up
     torch.cuda.synchronize()
+    per_streams = {}
+    for ns in args.batch_streams_sweep:
+        t0 = time.perf_counter()
+        asss.solve_batched(hs, Bs, batch_streams=ns, **kw)
+        torch.cuda.synchronize()
+        per_streams[ns] = round(time.perf_counter() - t0, 4)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     Xs, infos = asss.solve_batched(hs, Bs, **kw)
     torch.cuda.synchronize()
@@ -146,6 +153,8 @@ def batched(args, asss, torch, np, W):
            "speedup_block_vs_columns": round(t_cols / t_block, 3),
            "worst_relres_block": worst, "worst_relres_columns": worst1, "setup_s": round(setup_s, 1),
            "autotune": bool(args.autotune), "row_blocks": row_blocks}
+    if per_streams:
+        res["block_s_by_streams"] = per_streams
     print(json.dumps(res), flush=True)
 
 
@@ -217,6 +226,8 @@ def main():
                          "reports right-hand sides per second for the lockstep block solve and for "
                          "column-by-column solves")
     ap.add_argument("--nsys", type=int, default=64)
+    ap.add_argument("--batch-streams-sweep", type=int, nargs="*", default=[],
+                    help="with --batched: also time the block solve with these numbers of worker streams")
     ap.add_argument("--grad", action="store_true",
                     help="differentiation workload instead: 1000 x 1000 implicit-Euler grid (n = 1e6), "
                          "loss ||x - x_t||^2, forward solve + backward (adjoint solve and dL/dA, dL/db) "

@@ -171,6 +171,8 @@ typedef struct {
   int32_t inner_fp32;      /* -1 = handle default, 0 = FP64, 1 = FP32 inner */
   int32_t outer;           /* ASSS_OUTER_FGMRES (default) or ASSS_OUTER_TFQMR, the
                               transpose-free QMR of the paper's experiments (Sec. 4.1) */
+  int32_t batch_streams;   /* asss_solve_batched only: concurrent worker streams (one host
+                              thread each), 1..16; 0 = 16 (default) */
 } asss_solve_opts_t;
 
 enum { ASSS_OUTER_FGMRES = 0, ASSS_OUTER_TFQMR = 1 };
@@ -252,9 +254,10 @@ asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* r
  * each inner step reads J_tilde and Q_k once for all its columns; the inner
  * stop rule is the maximum over the group.  Each column restarts and stops on
  * its own true residual.  With TFQMR, or with more than 16 deflation vectors,
- * the columns are solved one at a time.  Systems run concurrently on up to 4
- * internal streams (one host thread each; all work on one handle stays on one
- * of them), ordered after hip_stream; the call returns when all are done.
+ * the columns are solved one at a time.  Systems run concurrently on up to
+ * batch_streams (default 16) internal streams (one host thread each; all work on
+ * one handle stays on one of them), ordered after hip_stream; the call returns
+ * when all are done.
  * All right-hand sides are checked for NaN/Inf first (NONFINITE, nothing
  * solved).  infos: nsys * max(nrhs) entries, row s * max(nrhs) + j (may be
  * NULL); inner_kernel_s / inner_launches are those of the column's group.

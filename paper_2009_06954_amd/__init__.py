@@ -88,7 +88,8 @@ def torch_allocator():
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart_m", C.c_int32), ("max_outer", C.c_int32),
                 ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
-                ("fixed_inner_steps", C.c_int32), ("inner_fp32", C.c_int32), ("outer", C.c_int32)]
+                ("fixed_inner_steps", C.c_int32), ("inner_fp32", C.c_int32), ("outer", C.c_int32),
+                ("batch_streams", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -201,13 +202,14 @@ OUTER = {"fgmres": 0, "tfqmr": 1}
 
 
 def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_maxit=1000,
-                  fixed_inner_steps=0, inner_fp32=None, outer="fgmres") -> SolveOpts:
+                  fixed_inner_steps=0, inner_fp32=None, outer="fgmres", batch_streams=0) -> SolveOpts:
     o = SolveOpts()
     load().asss_default_solve_opts(C.byref(o))
     o.tol, o.restart_m, o.max_outer = tol, restart_m, max_outer
     o.inner_tol, o.inner_maxit, o.fixed_inner_steps = inner_tol, inner_maxit, fixed_inner_steps
     o.inner_fp32 = -1 if inner_fp32 is None else int(bool(inner_fp32))
     o.outer = OUTER[outer]
+    o.batch_streams = batch_streams
     return o
 
 

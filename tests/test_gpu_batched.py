@@ -157,3 +157,21 @@ def test_batched_with_torch_allocator_and_autotune():
         h.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
+
+
+def test_batch_streams_option(batch):
+    """Any number of worker streams gives the same columns up to the solve's
+    tolerance (the in-block LDS scatter adds in a run-dependent order);
+    values outside [0, 16] are refused."""
+    asss, ws, nr, hs = batch
+    Bs = [_colmajor(w.b[:, :r]) for w, r in zip(ws, nr)]
+    ref, _ = asss.solve_batched(hs, Bs, tol=1e-11, batch_streams=1)
+    for ns in (2, 3, 16):
+        Xs, infos = asss.solve_batched(hs, Bs, tol=1e-11, batch_streams=ns)
+        for s in range(len(ws)):
+            assert all(i["converged"] == 1 for i in infos[s])
+            assert _rel(Xs[s].cpu().numpy(), ref[s].cpu().numpy()) <= 1e-8
+    for bad in (-1, 17):
+        with pytest.raises(asss.AsssError) as e:
+            asss.solve_batched(hs, Bs, tol=1e-8, batch_streams=bad)
+        assert e.value.name == "INVALID_ARG"

@@ -300,6 +300,43 @@ def test_edge_cases(cfg0):
     assert e.value.name == "INVALID_CSR"
 
 
+def _tiny_cases():
+    rng = np.random.default_rng(0)
+    cases = {"n=1": sp.csr_matrix(np.array([[3.0]])),
+             "diagonal n=100 (J_tilde = 0 up to rounding)": sp.diags(rng.uniform(0.5, 2, 100)).tocsr()}
+    for n in (65, 193):  # one row past a slice; a ragged third slice
+        cases[f"tridiagonal n={n}"] = sp.diags([rng.uniform(2, 3, n), rng.uniform(-1, 1, n - 1),
+                                                 rng.uniform(-1, 1, n - 1)], [0, 1, -1]).tocsr()
+    M = sp.random(50, 50, 0.1, random_state=1)
+    cases["identity + skew n=50"] = (sp.eye(50) + M - M.T).tocsr()
+    return cases
+
+
+@pytest.mark.parametrize("name", list(_tiny_cases()))
+@pytest.mark.parametrize("k", [0, 4])
+def test_tiny_and_degenerate_systems(name, k):
+    """Single-row and sub-slice systems, a skew part that vanishes (Lanczos
+    breaks down at once), and A = I + skew: solutions match the oracle and a
+    dense solve in FP64, the dense solve in the mixed path."""
+    asss = _lib()
+    A = _tiny_cases()[name]
+    n = A.shape[0]
+    b = A @ np.linspace(1.0, 2.0, n)
+    print(f"[tiny] {name} k={k}", flush=True)
+    st = O.setup(A, O.SetupOptions(k=k))
+    xo, _ = O.solve(st, b, O.SolveOptions(tol=1e-12))
+    xd = np.linalg.solve(A.toarray(), b)
+    h = asss.setup(A, k=k)
+    x, info = h.solve(_cuda(b), tol=1e-12)
+    assert info["status"] == "OK"
+    assert _rel(_np(x), xo) <= 1e-10 and _rel(_np(x), xd) <= 1e-10
+    x, info = h.solve(_cuda(b), tol=1e-8, inner_fp32=True)
+    assert info["status"] == "OK" and _rel(_np(x), xd) <= 1e-7
+    lam, info = h.solve_adjoint(_cuda(b), tol=1e-12)
+    assert info["status"] == "OK" and _rel(_np(lam), np.linalg.solve(A.toarray().T, b)) <= 1e-10
+    h.close()
+
+
 @pytest.mark.parametrize("k", [0, 1, 4, 9, 20, 32])
 def test_small_k(k):
     """k = 0 (no deflation), widths 8 / 16 / 32 of the deflation kernels, and
