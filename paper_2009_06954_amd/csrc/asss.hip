@@ -519,7 +519,12 @@ void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& ca
   h->tuned.assign(1, {h->J64.R, 1e6 * t_best});
   for (int R : cands) {
     if (R == best.J64.R) continue;
-    SkewSell sell = pack_skew_sell(Jup, R, h->opts.skew_form);
+    SkewSell sell;
+    try {
+      sell = pack_skew_sell(Jup, R, h->opts.skew_form);
+    } catch (const HostError&) {
+      continue;  // a forced column form that does not fit this row-block size
+    }
     SkewLayout cand = upload_layout(h->ar, sell, s);
     HIPCHK(hipStreamSynchronize(s));
     const double t = time_layout(h, cand, fp32, s);

@@ -109,5 +109,13 @@ def test_line_tiles_on_a_3d_grid():
         a = _np(xt)
         assert np.linalg.norm(w.b - w.A @ a) <= 1.01e-10 * np.linalg.norm(w.b)
         assert _rel(a, _np(xn)) <= 1e-6
+    # the caller's order with the row-block autotuner: candidates packed in that order
+    ha = asss.setup(w.A, k=8, s_pattern="tridiag", reorder=perm, autotune=True)
+    ia = ha.info()
+    assert ia["reordered"] == 1 and ia["tune_n"] >= 2 and ia["row_block"] in ia["tune_rows"]
+    xa, infoa = ha.solve(b, tol=1e-10, restart_m=100, inner_tol=0.2)
+    assert infoa["status"] == "OK"
+    assert np.linalg.norm(w.b - w.A @ _np(xa)) <= 1.01e-10 * np.linalg.norm(w.b)
+    ha.close()
     ht.close()
     hn.close()
