@@ -173,6 +173,10 @@ typedef struct {
                               transpose-free QMR of the paper's experiments (Sec. 4.1) */
   int32_t batch_streams;   /* asss_solve_batched only: concurrent worker streams (one host
                               thread each), 1..16; 0 = 16 (default) */
+  int32_t use_x0;          /* 0 (default): start from x = 0.  1: the output vector holds
+                              the initial guess x0 on entry (NONFINITE if it has NaN/Inf);
+                              the outer method corrects r0 = b - A x0 to tol ||b|| and
+                              returns x0 + d.  Batched solves then run column by column */
 } asss_solve_opts_t;
 
 enum { ASSS_OUTER_FGMRES = 0, ASSS_OUTER_TFQMR = 1 };

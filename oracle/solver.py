@@ -34,6 +34,7 @@ Readings:
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -337,12 +338,40 @@ def _outer(o: SolveOptions):
     raise ValueError(f"unknown outer method {o.outer!r}")
 
 
-def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None):
-    """x with A x = b (Sec. 3).  Returns (x, info)."""
+def _from_x0(solve_fn, M, st, b, o, x0):
+    """Start from an initial guess x0 (not in the paper; the solver's option).
+    The outer method corrects r0 = b - M x0 to the relative tolerance
+    tol ||b|| / ||r0||, and x = x0 + d: the right-preconditioned residual of
+    the transformed x0 is the transformed r0, so this is the iteration started
+    at x0 without applying S^-1.  The true residual reported is that of x
+    against b."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    if not np.all(np.isfinite(x0)):
+        raise ValueError("x0 has non-finite entries")
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return solve_fn(st, b, o)
+    r0 = b - M @ x0
+    rn = np.linalg.norm(r0)
+    if rn <= o.tol * bn:
+        return x0.copy(), dict(converged=True, outer_its=0, inner_its_total=0, inner_its_max=0,
+                               relres_true=rn / bn, relres_implicit=0.0, cycles=0,
+                               k_eff=st.Q.shape[1], rank_r=st.N.size)
+    d, info = solve_fn(st, r0, dataclasses.replace(o, tol=o.tol * bn / rn))
+    x = x0 + d
+    rel = np.linalg.norm(b - M @ x) / bn
+    info.update(relres_true=rel, converged=bool(rel <= o.tol))
+    return x, info
+
+
+def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None, x0=None):
+    """x with A x = b (Sec. 3), from x0 if given.  Returns (x, info)."""
     o = o or SolveOptions()
     b = np.asarray(b, dtype=np.float64)
     if not np.all(np.isfinite(b)):
         raise ValueError("b has non-finite entries")
+    if x0 is not None:
+        return _from_x0(solve, st.A, st, b, o, x0)
     bn = np.linalg.norm(b)
     if bn == 0.0:
         return np.zeros(st.n), dict(converged=True, outer_its=0, inner_its_total=0,
@@ -358,13 +387,15 @@ def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None):
     return st.back(x_chk), info
 
 
-def solve_adjoint(st: OracleSetup, g: np.ndarray, o: SolveOptions | None = None):
-    """lambda with A^T lambda = g: FGMRES on A_chk^T right-preconditioned with P^T.
-    Returns (lambda, info)."""
+def solve_adjoint(st: OracleSetup, g: np.ndarray, o: SolveOptions | None = None, x0=None):
+    """lambda with A^T lambda = g: FGMRES on A_chk^T right-preconditioned with P^T,
+    from x0 if given.  Returns (lambda, info)."""
     o = o or SolveOptions()
     g = np.asarray(g, dtype=np.float64)
     if not np.all(np.isfinite(g)):
         raise ValueError("g has non-finite entries")
+    if x0 is not None:
+        return _from_x0(solve_adjoint, st.A.T.tocsr(), st, g, o, x0)
     gn = np.linalg.norm(g)
     if gn == 0.0:
         return np.zeros(st.n), dict(converged=True, outer_its=0, inner_its_total=0,

@@ -89,7 +89,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart_m", C.c_int32), ("max_outer", C.c_int32),
                 ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("fixed_inner_steps", C.c_int32), ("inner_fp32", C.c_int32), ("outer", C.c_int32),
-                ("batch_streams", C.c_int32)]
+                ("batch_streams", C.c_int32), ("use_x0", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -202,7 +202,8 @@ OUTER = {"fgmres": 0, "tfqmr": 1}
 
 
 def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_maxit=1000,
-                  fixed_inner_steps=0, inner_fp32=None, outer="fgmres", batch_streams=0) -> SolveOpts:
+                  fixed_inner_steps=0, inner_fp32=None, outer="fgmres", batch_streams=0,
+                  use_x0=False) -> SolveOpts:
     o = SolveOpts()
     load().asss_default_solve_opts(C.byref(o))
     o.tol, o.restart_m, o.max_outer = tol, restart_m, max_outer
@@ -210,6 +211,7 @@ def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_
     o.inner_fp32 = -1 if inner_fp32 is None else int(bool(inner_fp32))
     o.outer = OUTER[outer]
     o.batch_streams = batch_streams
+    o.use_x0 = int(bool(use_x0))
     return o
 
 
@@ -239,11 +241,19 @@ class Handle:
             raise ValueError(f"expected a contiguous CUDA float64 tensor of length {self.n}")
         return v
 
-    def solve(self, b, out=None, stream=None, **opts):
-        """x = A^-1 b.  Returns (x, info dict); info['status'] is OK or NOT_CONVERGED."""
+    def _start(self, out, like, x0):
         import torch
+        x = out if out is not None else torch.empty_like(like)
+        if x0 is not None:
+            x.copy_(self._vec(x0))
+        return x
+
+    def solve(self, b, out=None, stream=None, x0=None, **opts):
+        """x = A^-1 b, from x0 if given (else from 0).  Returns (x, info dict);
+        info['status'] is OK or NOT_CONVERGED."""
         b = self._vec(b)
-        x = out if out is not None else torch.empty_like(b)
+        x = self._start(out, b, x0)
+        opts["use_x0"] = x0 is not None
         info = Info()
         st = _check(load().asss_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                       C.byref(solve_options(**opts)), C.byref(info), _stream(stream)))
@@ -251,11 +261,11 @@ class Handle:
         d["status"] = _STATUS_NAMES[st]
         return x, d
 
-    def solve_adjoint(self, g, out=None, stream=None, **opts):
-        """lambda = A^-T g.  Returns (lambda, info dict)."""
-        import torch
+    def solve_adjoint(self, g, out=None, stream=None, x0=None, **opts):
+        """lambda = A^-T g, from x0 if given.  Returns (lambda, info dict)."""
         g = self._vec(g)
-        lam = out if out is not None else torch.empty_like(g)
+        lam = self._start(out, g, x0)
+        opts["use_x0"] = x0 is not None
         info = Info()
         st = _check(load().asss_solve_adjoint(self._h, C.c_void_p(g.data_ptr()), C.c_void_p(lam.data_ptr()),
                                               C.byref(solve_options(**opts)), C.byref(info), _stream(stream)))
@@ -371,10 +381,11 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     return Handle(out.value, n, keep=alloc)
 
 
-def solve_batched(handles, Bs, stream=None, **opts):
+def solve_batched(handles, Bs, stream=None, X0s=None, **opts):
     """Solve several systems, each with several right-hand sides (B: n_s x nrhs_s
     CUDA float64, column-major i.e. the transpose of a contiguous (nrhs, n)
-    tensor is expected as B.T).  Returns (list of X, list of info lists)."""
+    tensor is expected as B.T), from the initial guesses X0s (same shapes) if
+    given.  Returns (list of X, list of info lists)."""
     import torch
     lib = load()
     ns = len(handles)
@@ -386,6 +397,10 @@ def solve_batched(handles, Bs, stream=None, **opts):
             raise ValueError("each B must be a column-major (n, nrhs) CUDA float64 tensor")
         Xs.append(torch.empty_like(B))
         nr.append(B.shape[1])
+    if X0s is not None:
+        for X, X0 in zip(Xs, X0s):
+            X.copy_(X0.reshape(X.shape))
+        opts["use_x0"] = True
     maxr = max(nr) if nr else 0
     hs = (C.c_void_p * ns)(*[h._h.value for h in handles])
     nra = (C.c_int32 * ns)(*nr)

@@ -175,3 +175,22 @@ def test_batch_streams_option(batch):
         with pytest.raises(asss.AsssError) as e:
             asss.solve_batched(hs, Bs, tol=1e-8, batch_streams=bad)
         assert e.value.name == "INVALID_ARG"
+
+
+def test_batched_initial_guesses(batch):
+    """X0s: every column starts from its own guess (one at a time) and reaches
+    the dense solution; exact guesses come back after no outer step."""
+    asss, ws, nr, hs = batch
+    Bs = [_colmajor(w.b[:, :r]) for w, r in zip(ws, nr)]
+    Xd = [np.linalg.solve(w.A.toarray(), w.b[:, :r]) for w, r in zip(ws, nr)]
+    rng = np.random.default_rng(11)
+    X0 = [_colmajor(x + 1e-3 * rng.standard_normal(x.shape)) for x in Xd]
+    Xs, infos = asss.solve_batched(hs, Bs, X0s=X0, tol=1e-11)
+    for s, w in enumerate(ws):
+        X = Xs[s].detach().cpu().numpy()
+        kappa = np.linalg.cond(w.A.toarray())
+        for j in range(nr[s]):
+            assert infos[s][j]["converged"] == 1
+            assert _rel(X[:, j], Xd[s][:, j]) <= max(1e-8, 10 * kappa * 1e-11)
+    Xs, infos = asss.solve_batched(hs, Bs, X0s=[_colmajor(x) for x in Xd], tol=1e-8)
+    assert all(i["outer_its"] == 0 for row in infos for i in row)

@@ -300,6 +300,36 @@ def test_edge_cases(cfg0):
     assert e.value.name == "INVALID_CSR"
 
 
+def test_initial_guess(cfg0):
+    """use_x0: the exact solution comes back unchanged after no outer step; a
+    random x0 gives the oracle's result for the same x0 (solution and, with
+    fixed inner steps, the outer count); adjoint and TFQMR likewise; a
+    non-finite x0 is refused."""
+    asss = _lib()
+    p = cfg0
+    b = _cuda(p.w.b)
+    xd = np.linalg.solve(p.A.toarray(), p.w.b)
+    x, info = p.h.solve(b, x0=_cuda(xd), tol=1e-10)
+    assert info["status"] == "OK" and info["outer_its"] == 0 and np.array_equal(_np(x), xd)
+    x0 = np.random.default_rng(5).standard_normal(p.n)
+    xo, _ = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-12), x0=x0)
+    x, info = p.h.solve(b, x0=_cuda(x0), tol=1e-12)
+    assert info["status"] == "OK" and info["relres_true"] <= 1e-12 and _rel(_np(x), xo) <= 1e-10
+    xo, io = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-8, fixed_inner_steps=30), x0=x0)
+    x, info = p.h.solve(b, x0=_cuda(x0), tol=1e-8, fixed_inner_steps=30)
+    assert info["outer_its"] == io["outer_its"] and _rel(_np(x), xo) <= 1e-10
+    lo, _ = O.solve_adjoint(p.st, p.w.b, O.SolveOptions(tol=1e-12), x0=x0)
+    lam, info = p.h.solve_adjoint(b, x0=_cuda(x0), tol=1e-12)
+    assert info["status"] == "OK" and _rel(_np(lam), lo) <= 1e-10
+    x, info = p.h.solve(b, x0=_cuda(x0), tol=1e-12, outer="tfqmr")
+    assert info["status"] == "OK" and _rel(_np(x), xd) <= 1e-10
+    bad = x0.copy()
+    bad[3] = np.inf
+    with pytest.raises(asss.AsssError) as e:
+        p.h.solve(b, x0=_cuda(bad))
+    assert e.value.name == "NONFINITE"
+
+
 def _tiny_cases():
     rng = np.random.default_rng(0)
     cases = {"n=1": sp.csr_matrix(np.array([[3.0]])),

@@ -154,3 +154,32 @@ def test_fixed_inner_steps(cfg0_setup):
     x, info = O.solve(cfg0_setup, w.b, O.SolveOptions(tol=1e-8, fixed_inner_steps=30))
     assert info["converged"]
     assert info["inner_its_total"] == 30 * info["outer_its"]
+
+
+def test_initial_guess(cfg0_setup):
+    """Starting from x0: the exact solution returns at once, unchanged; a
+    random or a nearby x0 reaches the dense solution with the true residual
+    below tol * ||b|| (not ||b - A x0||); the nearby start takes fewer outer
+    steps; the adjoint likewise; a non-finite x0 is refused."""
+    st = cfg0_setup
+    w = W.config(0)
+    A, b = w.A, w.b
+    Ad = A.toarray()
+    xd = np.linalg.solve(Ad, b)
+    kappa = np.linalg.cond(Ad)
+    o = O.SolveOptions(tol=1e-10)
+    x, info = O.solve(st, b, o, x0=xd)
+    assert info["converged"] and info["outer_its"] == 0 and np.array_equal(x, xd)
+    _, info_zero = O.solve(st, b, o)
+    rng = np.random.default_rng(3)
+    for x0 in (rng.standard_normal(st.n), xd + 1e-4 * rng.standard_normal(st.n)):
+        x, info = O.solve(st, b, o, x0=x0)
+        assert info["converged"]
+        assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+        assert np.linalg.norm(x - xd) <= 2 * kappa * 1e-10 * np.linalg.norm(xd)
+    assert info["outer_its"] < info_zero["outer_its"]
+    lamd = np.linalg.solve(Ad.T, b)
+    lam, info = O.solve_adjoint(st, b, o, x0=lamd + 1e-4 * rng.standard_normal(st.n))
+    assert info["converged"] and np.linalg.norm(lam - lamd) <= 2 * kappa * 1e-10 * np.linalg.norm(lamd)
+    with pytest.raises(ValueError):
+        O.solve(st, b, o, x0=np.full(st.n, np.nan))
