@@ -349,9 +349,23 @@ def main():
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per full step (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_GBs": round(traffic * steps / kern_s / 1e9, 1) if traffic else None,
+                "copy_ceiling_GBs": copy_gbs,
                 "kernel": "k_mrs_iter (fused inner mrs step)",
                 "bytes_per_step": int(per_step), "bytes_per_row": round(bpr, 1),
                 "avg_launch_us": round(avg * 1e6, 2), "launches": launches, "full_steps": steps}
+
+    # practical roof: a 1 GiB device-to-device copy (read + write), best of 5,
+    # HIP events on torch's stream, outside the timed region
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    copy_ms = []
+    for _ in range(5):
+        ev[0].record(); dst.copy_(src); ev[1].record(); torch.cuda.synchronize()
+        copy_ms.append(ev[0].elapsed_time(ev[1]))
+    copy_gbs = round(2 * src.numel() * 4 / (min(copy_ms) * 1e-3) / 1e9, 1)
+    del src, dst
 
     total64, inf64, err64 = run(False, args.steps, args.warmup)
     t64 = total64 / args.steps
