@@ -56,3 +56,25 @@ def test_random_pattern_keeps_entry_columns(checker):
     assert "form=3" not in r.stdout
     r = _run(checker, 20, 128, 3, "random")
     assert r.returncode == 3 and "rejected" in r.stdout
+
+
+def test_host_code_under_sanitizers(tmp_path):
+    """The host packer built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (g++, host code only) runs clean on grid and random patterns and each
+    column form (the setup stages: tests/test_host_setup.py)."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    flags = ["-O1", "-g", "-std=c++17", "-pthread", "-fsanitize=address,undefined",
+             "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", f"-I{CSRC}"]
+    pack = str(tmp_path / "pack")
+    r = subprocess.run([gxx, *flags, os.path.join(ROOT, "tests", "host_pack_check.cpp"),
+                        os.path.join(CSRC, "host_setup.cpp"), "-o", pack], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    for args, rc in (((12, 64, 0), 0), ((12, 64, 1), 0), ((12, 64, 2), 0), ((20, 128, 3), 0),
+                     ((12, 64, 0, "random"), 0), ((12, 64, 3, "random"), 3)):
+        r = subprocess.run([pack, *map(str, args)], capture_output=True, text=True, timeout=300, env=env)
+        assert r.returncode == rc, (args, r.stdout + r.stderr)
+        assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr

@@ -122,3 +122,27 @@ def test_host_setup_matches_oracle(harness, name, A, pattern, kind):
     Ju.sort_indices()
     assert np.array_equal(r["J_ptr"], Ju.indptr) and np.array_equal(r["J_col"], Ju.indices)
     assert _rel(r["J_val"], Ju.data) <= 1e-13
+
+
+def test_host_setup_under_sanitizers(tmp_path):
+    """The setup stages built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (g++, host code only) run clean on a stand-in with a non-identity
+    matching and still agree with the oracle."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    exe = str(tmp_path / "check_san")
+    r = subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-pthread", "-fsanitize=address,undefined",
+                        "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", f"-I{CSRC}",
+                        os.path.join(ROOT, "tests", "host_setup_check.cpp"),
+                        os.path.join(CSRC, "host_setup.cpp"), "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    os.environ.setdefault("ASAN_OPTIONS", "detect_leaks=1:abort_on_error=1")
+    A = W.paper_like(300, 1800, seed=1).A
+    st = O.setup(A, O.SetupOptions(k=0, s_pattern="tridiag"))
+    S = st.S.tocsr()
+    S.sort_indices()
+    res = _run((exe, tmp_path), A, 1, S.data)
+    assert np.array_equal(res["m"], st.m.astype(np.int32))
+    assert _rel(res["J_val"], st.Jup.tocsr().sorted_indices().data) <= 1e-13
