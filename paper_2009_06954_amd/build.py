@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasss.so")
 ARCH = os.environ.get("ASSS_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = "/opt/rocm/lib"  # roctx (ranges for rocprofv3 --marker-trace)
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -47,7 +48,8 @@ def build(verbose: bool = False) -> str:
             _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
             objs.append(o)
         out_tmp = LIB + ".tmp"
-        _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs, "-lpthread"])
+        _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs, "-lpthread",
+              f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"])
         os.replace(out_tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -3,6 +3,7 @@
 // the preconditioner P^-1 of eq. smw around the inner mrs, the adjoint solve,
 // and the C ABI declared in include/asss.h.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -11,6 +12,7 @@
 #include <cstddef>
 #include <cstring>
 #include <memory>
+#include <optional>
 #include <map>
 #include <string>
 #include <thread>
@@ -26,6 +28,15 @@ using namespace asss;
 namespace {
 
 thread_local std::string g_err = "";
+
+// roctx range around a phase (setup stages, a solve, an outer step, an inner
+// solve): visible in a rocprofv3 --marker-trace, a no-op call otherwise.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct Error {
   int code;
@@ -329,6 +340,7 @@ template <typename T, int NR = 1>
 int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s,
             int nc = 1) {
+  Range range(NR == 1 ? "asss:inner mrs" : "asss:inner mrs (4 columns)");
   MrsLaunch L = make_launch<T>(h, nc, sign, Q, f, NR == 1 && h->defl_rec != 0);
   if (J.nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
   mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
@@ -956,6 +968,7 @@ struct FgmresCol {
 
   // Arnoldi step j with z_j = Z[:, j] just written by the preconditioner.
   void after_prec(int its) {
+    Range range("asss:outer step");
     inf.inner_its_total += its;
     inf.inner_its_max = std::max(inf.inner_its_max, its);
     double* hbuf = h->d_small;
@@ -1413,6 +1426,7 @@ const char* asss_last_error(void) { return g_err.c_str(); }
 
 asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, void* hip_stream,
                          asss_handle_t* out) {
+  Range range("asss_setup");
   return guarded([&]() -> asss_status_t {
     if (!A || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
     *out = nullptr;
@@ -1440,6 +1454,8 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     }
     h->opts = o;
     h->opts.allocator = nullptr;
+    std::optional<Range> phase;
+    phase.emplace("asss_setup:host preprocessing");
     const double t0 = now_s();
     // ---- host preprocessing
     Csr Ah = validate_and_copy(A->n, A->nnz, A->rowptr, A->colind, A->val);
@@ -1455,6 +1471,8 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->lls_rows = L.B.nrows;
     h->lls_nnz = L.B.nnz();
     const double t1 = now_s();
+    phase.reset();
+    phase.emplace("asss_setup:LSQR for S");
     // ---- device: reducer and scalar buffers first (LSQR uses them)
     int R = o.row_block;
     if (R == 0) {
@@ -1480,6 +1498,8 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     HIPCHK(hipEventCreate(&h->ev1));
     std::vector<double> svals = lsqr_device(h.get(), L, o.lls_tol, o.lls_maxit, s);
     const double t2 = now_s();
+    phase.reset();
+    phase.emplace("asss_setup:split and pack");
     h->S = Spat;
     h->S.val = svals;
     Csr Ahat = spgemm_on_pattern(Abar, h->S, L.P);
@@ -1561,9 +1581,13 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->tmp = h->ar.alloc<double>(n);
     HIPCHK(hipStreamSynchronize(s));
     const double t3 = now_s();
+    phase.reset();
+    phase.emplace("asss_setup:Lanczos, X, C");
     device_setup(h.get(), s);
     const double t4 = now_s();
+    phase.reset();
     if (cands.size() > 1) {
+      Range tune("asss_setup:row-block autotune");
       tune_row_block(h.get(), Jup, cands, s);
       h->tune_s = now_s() - t4;
       if (o.verbose) {
@@ -1587,6 +1611,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
 
 asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, const asss_solve_opts_t* o,
                          asss_info_t* info, void* hip_stream) {
+  Range range("asss_solve");
   return guarded([&]() -> asss_status_t {
     check_handle(h);
     if (!b_dev || !x_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
@@ -1602,6 +1627,7 @@ asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, co
 
 asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* lambda_dev,
                                  const asss_solve_opts_t* o, asss_info_t* info, void* hip_stream) {
+  Range range("asss_solve_adjoint");
   return guarded([&]() -> asss_status_t {
     check_handle(h);
     if (!g_dev || !lambda_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
@@ -1657,6 +1683,7 @@ asss_status_t asss_value_gradient(asss_handle_t h, int64_t nnz, const int64_t* r
 asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const int32_t* nrhs,
                                  const double* const* B_dev, double* const* X_dev,
                                  const asss_solve_opts_t* o, asss_info_t* infos, void* hip_stream) {
+  Range range("asss_solve_batched");
   return guarded([&]() -> asss_status_t {
     if (nsys < 0 || (nsys > 0 && (!hs || !nrhs || !B_dev || !X_dev)))
       throw Error{ASSS_ERR_INVALID_ARG, "null argument"};

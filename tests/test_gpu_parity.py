@@ -330,6 +330,22 @@ def test_initial_guess(cfg0):
     assert e.value.name == "NONFINITE"
 
 
+def test_run_twice_determinism(cfg0):
+    """Everything but the in-block LDS scatter of the skew operator (atomic
+    adds in a run-dependent order) is bitwise reproducible: the CSR products
+    and the outer operator and its transpose.  The skew operator itself agrees
+    between runs to rounding."""
+    p = cfg0
+    v = _cuda(np.random.default_rng(21).standard_normal(p.n))
+    for op in ("A", "AT", "outer", "outer_t"):
+        a, _ = p.h.apply(op, v)
+        b, _ = p.h.apply(op, v)
+        assert torch.equal(a, b), op
+    a, _ = p.h.apply("skew", v)
+    b, _ = p.h.apply("skew", v)
+    assert _rel(_np(a), _np(b)) <= 1e-15
+
+
 def _tiny_cases():
     rng = np.random.default_rng(0)
     cases = {"n=1": sp.csr_matrix(np.array([[3.0]])),
