@@ -54,7 +54,12 @@ struct Error {
 // leading part of MrsState read back by the host: its, status, ..., relres_max
 constexpr size_t kStateHead = offsetof(MrsState, relres_max) + sizeof(double);
 // layout of the small device/pinned scalar buffers (doubles)
-constexpr int SM_H1 = 0, SM_H2 = 1024, SM_HN = 2047, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
+// d_small / h_small layout: [0, 2048) Arnoldi scratch, 512 doubles per lockstep
+// column (the Gram-Schmidt coefficients of the first pass and the new norm at
+// +0, those of a second pass at +256; restart_m <= 250), SM_T the SMW
+// coefficients, SM_Y the cycle's least-squares solution.
+constexpr int SM_COL = 512, SM_PASS2 = 256, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
+static_assert(4 * SM_COL <= SM_T, "Arnoldi scratch of four columns");
 // largest max|Q^T Q - I| for which the (opt-in) recurrence form of the
 // deflation is accepted
 constexpr double kRecurrenceOrthTol = 1e-10;
@@ -897,6 +902,8 @@ struct FgmresCol {
   double *V = nullptr, *Z = nullptr, *bchk = nullptr, *xchk = nullptr, *rv = nullptr;
   std::vector<double> H, cs, sn, g, y;
   double bn = 0.0, bcn = 0.0, thr = 0.0, t0 = 0.0;
+  int slot = 0;  // Arnoldi scratch: d_small / h_small + slot * SM_COL
+  int last_its = 0;
   int j = 0;
   bool first = true, done = false, implicit_ok = false;
   asss_info_t inf{};
@@ -967,30 +974,49 @@ struct FgmresCol {
   }
 
   // Arnoldi step j with z_j = Z[:, j] just written by the preconditioner.
-  void after_prec(int its) {
-    Range range("asss:outer step");
+  // Arnoldi step after the preconditioner application z_j, in two halves so
+  // that lockstep columns share one host round trip: arnoldi_enqueue puts
+  // w = A_chk z_j (straight into V[:, j+1]), the classical Gram-Schmidt
+  // coefficients V^T w and the updated norm on the stream and copies the j + 3
+  // values to this column's host scratch; arnoldi_finish (stream synchronized)
+  // takes them, runs a second pass when the norm dropped below 1/sqrt(10) of
+  // its value (DGKS), and updates the Givens QR and the residual estimate.
+  void arnoldi_enqueue(int its) {
+    last_its = its;
     inf.inner_its_total += its;
     inf.inner_its_max = std::max(inf.inner_its_max, its);
-    double* hbuf = h->d_small;
-    double* zj = Z + (int64_t)j * n;
-    // w = A_chk z_j written straight into V[:, j+1]; classical Gram-Schmidt with
-    // one more pass when the norm drops below 1/sqrt(10) of its value (DGKS)
+    double* hbuf = h->d_small + slot * SM_COL;
     double* vn = V + (int64_t)(j + 1) * n;
-    op(zj, vn);
-    gemm_tn<double, double>(n, j + 2, V, n, vn, 1, hbuf + SM_H1, nullptr, h->red, 4, s);
-    gemv_acc_norm(n, j + 1, V, n, hbuf + SM_H1, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
-    HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
+    op(Z + (int64_t)j * n, vn);
+    gemm_tn<double, double>(n, j + 2, V, n, vn, 1, hbuf, nullptr, h->red, 4, s);
+    gemv_acc_norm(n, j + 1, V, n, hbuf, -1.0, vn, hbuf + j + 2, h->red, 5, s);
+    HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL, hbuf, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+
+  void after_prec(int its) {
+    arnoldi_enqueue(its);
     HIPCHK(hipStreamSynchronize(s));
-    const double wn2 = h->h_small[SM_H1 + j + 1];
-    double hn2 = h->h_small[SM_HN];
-    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->h_small[SM_H1 + i];
+    arnoldi_finish();
+  }
+
+  void arnoldi_finish() {
+    Range range("asss:outer step");
+    double* hbuf = h->d_small + slot * SM_COL;
+    const double* hh = h->h_small + slot * SM_COL;
+    double* vn = V + (int64_t)(j + 1) * n;
+    const double wn2 = hh[j + 1];
+    double hn2 = hh[j + 2];
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
     if (hn2 < 0.1 * wn2) {
-      gemm_tn<double, double>(n, j + 1, V, n, vn, 1, hbuf + SM_H2, nullptr, h->red, 4, s);
-      gemv_acc_norm(n, j + 1, V, n, hbuf + SM_H2, -1.0, vn, hbuf + SM_HN, h->red, 5, s);
-      HIPCHK(hipMemcpyAsync(h->h_small, hbuf, SM_T * sizeof(double), hipMemcpyDeviceToHost, s));
+      double* h2 = hbuf + SM_PASS2;
+      gemm_tn<double, double>(n, j + 1, V, n, vn, 1, h2, nullptr, h->red, 4, s);
+      gemv_acc_norm(n, j + 1, V, n, h2, -1.0, vn, h2 + j + 1, h->red, 5, s);
+      HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL + SM_PASS2, h2, (j + 2) * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h->h_small[SM_H2 + i];
-      hn2 = h->h_small[SM_HN];
+      const double* hh2 = h->h_small + slot * SM_COL + SM_PASS2;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hh2[i];
+      hn2 = hh2[j + 1];
       inf.reorth++;
     }
     const double hn = std::sqrt(hn2);
@@ -1016,7 +1042,7 @@ struct FgmresCol {
     inf.outer_its++;
     implicit_ok = std::fabs(g[j + 1]) <= thr;
     if (h->opts.verbose)
-      std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, its,
+      std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, last_its,
                    std::fabs(g[j + 1]) / bcn);
     ++j;
     if (implicit_ok || hn == 0.0 || inf.outer_its >= o.max_outer || j == m) end_cycle();
@@ -1104,9 +1130,11 @@ asss_status_t fgmres_block(asss_handle_s* h, int nc, const double* const* B, dou
   h->prof_s = 0.0;
   h->prof_launches = 0;
   FgmresCol cols[NRMAX];
-  for (int c = 0; c < nc; ++c)
+  for (int c = 0; c < nc; ++c) {
+    cols[c].slot = c;
     cols[c].begin(h, false, B[c], X[c], o, h->mcol[c].V, h->mcol[c].Z, h->mcol[c].bchk, h->mcol[c].xchk,
                   h->mcol[c].rv, s);
+  }
   for (;;) {
     int act[NRMAX], na = 0;
     for (int c = 0; c < nc; ++c)
@@ -1122,13 +1150,17 @@ asss_status_t fgmres_block(asss_handle_s* h, int nc, const double* const* B, dou
     else
       its = run_mrs<double, NRMAX>(h, h->J64, h->d_Q64, h->d_f64, h->mb4_64, h->pin, h->pout, +1, o.inner_tol,
                                    o.inner_maxit, o.fixed_inner_steps, s, na);
+    // every active column's Arnoldi step goes on the stream, then one host
+    // round trip serves them all
     for (int i = 0; i < na; ++i) {
       FgmresCol& c = cols[act[i]];
       double* z = c.z_next();
       HIPCHK(hipMemcpyAsync(z, h->pout + (int64_t)i * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       smw_correct(h, z, s);
-      c.after_prec(its);
+      c.arnoldi_enqueue(its);
     }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < na; ++i) cols[act[i]].arnoldi_finish();
   }
   asss_status_t worst = ASSS_OK;
   for (int c = 0; c < nc; ++c) {
