@@ -273,6 +273,24 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
 
 asss_status_t asss_destroy(asss_handle_t h);
 
+/* Saved setups: the expensive results of asss_setup written to a file and read
+ * back without recomputing them (the setup handle is the checkpoint; the paper
+ * reuses one preprocessing for many right-hand sides, Sec. 4.1).
+ *
+ * asss_save writes A (its current values), the matching and scalings (Sec. 2),
+ * S (pattern and values, Sec. 2 / App. A), the inner order and the setup
+ * options (with the row-block size and column form in use) to `path`.
+ *
+ * asss_load reads such a file and builds a handle from it: the matching,
+ * scaling and least-squares solve for S are skipped; A_hat, D, J_tilde, its
+ * sliced storage, the skew-Lanczos vectors and the SMW data are rebuilt (so
+ * the handle equals the saved one up to rounding).  From `opts` (may be NULL)
+ * only `allocator` and `verbose` are used.  A missing, truncated or
+ * inconsistent file is INVALID_ARG, detected before any device call. */
+asss_status_t asss_save(asss_handle_t h, const char* path);
+asss_status_t asss_load(const char* path, const asss_setup_opts_t* opts, void* hip_stream,
+                        asss_handle_t* out);
+
 /* Thread-local description of the last error (never NULL). */
 const char* asss_last_error(void);
 

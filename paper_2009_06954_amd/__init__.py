@@ -39,7 +39,7 @@ ARRAYS = {"match": (0, np.int32), "Dr": (1, np.float64), "Dc": (2, np.float64),
 EXPORTED = ["asss_default_setup_opts", "asss_default_solve_opts", "asss_setup", "asss_solve",
             "asss_solve_adjoint", "asss_solve_batched", "asss_destroy", "asss_last_error",
             "asss_get_handle_info", "asss_get_array", "asss_apply", "asss_update_values",
-            "asss_value_gradient"]
+            "asss_value_gradient", "asss_save", "asss_load"]
 
 
 class CsrT(C.Structure):
@@ -160,6 +160,8 @@ def load(path: str = LIB_PATH):
     lib.asss_get_array.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]
     lib.asss_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
                                C.POINTER(C.c_int32), C.c_void_p]
+    lib.asss_save.argtypes = [C.c_void_p, C.c_char_p]
+    lib.asss_load.argtypes = [C.c_char_p, C.POINTER(SetupOpts), C.c_void_p, C.POINTER(C.c_void_p)]
     for f in EXPORTED:
         if f != "asss_last_error":
             getattr(lib, f).restype = None if f.startswith("asss_default") else C.c_int32
@@ -309,6 +311,10 @@ class Handle:
                                           _stream(stream)))
         return g
 
+    def save(self, path):
+        """Write the setup to `path` (asss_save); `load_handle` reads it back."""
+        _check(load().asss_save(self._h, os.fsencode(path)))
+
     def info(self) -> dict:
         hi = HandleInfo()
         _check(load().asss_get_handle_info(self._h, C.byref(hi)))
@@ -379,6 +385,26 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     out = C.c_void_p()
     _check(lib.asss_setup(C.byref(csr), C.byref(o), _stream(stream), C.byref(out)))
     return Handle(out.value, n, keep=alloc)
+
+
+def load_handle(path, stream=None, allocator=None, verbose=False) -> Handle:
+    """A handle from a file written by Handle.save (asss_load): the matching,
+    scalings and S are read, the rest of the setup is rebuilt."""
+    lib = load()
+    o = SetupOpts()
+    lib.asss_default_setup_opts(C.byref(o))
+    o.verbose = int(bool(verbose))
+    alloc = None
+    if allocator == "torch":
+        alloc = torch_allocator()
+        o.allocator = C.cast(C.pointer(alloc), C.c_void_p)
+    elif allocator is not None:
+        raise ValueError("allocator must be None or 'torch'")
+    out = C.c_void_p()
+    _check(lib.asss_load(os.fsencode(path), C.byref(o), _stream(stream), C.byref(out)))
+    hi = HandleInfo()
+    _check(lib.asss_get_handle_info(out, C.byref(hi)))
+    return Handle(out.value, int(hi.n), keep=alloc)
 
 
 def solve_batched(handles, Bs, stream=None, X0s=None, **opts):

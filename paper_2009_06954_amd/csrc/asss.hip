@@ -1417,47 +1417,17 @@ asss_status_t guarded(F&& f) {
 // C ABI
 // ===========================================================================
 
-extern "C" {
+// Matching, scalings and S of a saved setup (asss_load).
+struct Preset {
+  std::vector<int32_t> m;
+  std::vector<double> Dr, Dc;
+  Csr S;
+};
 
-void asss_default_setup_opts(asss_setup_opts_t* o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->gamma = 1.0;
-  o->s_pattern = ASSS_S_TRIDIAG;
-  o->k = 20;
-  o->lanczos_seed = 0x2009069540ull;
-  o->inner_fp32 = 0;
-  o->x_tol = 1e-10;
-  o->x_maxit = 2000;
-  o->lls_tol = 1e-15;
-  o->lls_maxit = 20000;
-  o->row_block = 0;
-  o->verbose = 0;
-  o->deflation = 0;
-  o->reorder = 0;
-  o->autotune = 0;
-  o->inner_perm = nullptr;
-  o->skew_form = 0;
-}
-
-void asss_default_solve_opts(asss_solve_opts_t* o) {
-  if (!o) return;
-  o->tol = 1e-8;
-  o->restart_m = 64;
-  o->max_outer = 2000;
-  o->inner_tol = 1e-5;
-  o->inner_maxit = 1000;
-  o->fixed_inner_steps = 0;
-  o->inner_fp32 = -1;
-  o->outer = ASSS_OUTER_FGMRES;
-  o->batch_streams = 0;
-  o->use_x0 = 0;
-}
-
-const char* asss_last_error(void) { return g_err.c_str(); }
-
-asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, void* hip_stream,
-                         asss_handle_t* out) {
+// Setup; `pre` (from asss_load) supplies the matching, the scalings and S
+// (pattern and values), which are then neither recomputed nor solved for.
+static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* opts, void* hip_stream,
+                                asss_handle_t* out, const Preset* pre) {
   Range range("asss_setup");
   return guarded([&]() -> asss_status_t {
     if (!A || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
@@ -1494,10 +1464,25 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->n = Ah.nrows;
     h->nnz_a = Ah.nnz();
     const int64_t n = h->n;
-    h->m = max_product_matching(Ah);
-    canonical_scaling(Ah, h->m, h->Dr, h->Dc);
+    if (pre) {
+      if ((int64_t)pre->m.size() != n || (int64_t)pre->Dr.size() != n || (int64_t)pre->Dc.size() != n ||
+          pre->S.nrows != n)
+        throw Error{ASSS_ERR_INVALID_ARG, "saved setup does not match the matrix size"};
+      h->m = pre->m;
+      h->Dr = pre->Dr;
+      h->Dc = pre->Dc;
+    } else {
+      h->m = max_product_matching(Ah);
+      canonical_scaling(Ah, h->m, h->Dr, h->Dc);
+    }
     Csr Abar = permute_scale(Ah, h->m, h->Dr, h->Dc);
-    Csr Spat = s_pattern(Abar, o.s_pattern, o.s_rowptr, o.s_colind);
+    Csr Spat;
+    if (pre) {
+      Spat = pre->S;
+      Spat.val.clear();
+    } else {
+      Spat = s_pattern(Abar, o.s_pattern, o.s_rowptr, o.s_colind);
+    }
     LlsSystem L;
     build_lls(Abar, Spat, o.gamma, L);
     h->lls_rows = L.B.nrows;
@@ -1528,7 +1513,7 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     h->d_state = h->ar.alloc<MrsState>(1);
     HIPCHK(hipEventCreate(&h->ev0));
     HIPCHK(hipEventCreate(&h->ev1));
-    std::vector<double> svals = lsqr_device(h.get(), L, o.lls_tol, o.lls_maxit, s);
+    std::vector<double> svals = pre ? pre->S.val : lsqr_device(h.get(), L, o.lls_tol, o.lls_maxit, s);
     const double t2 = now_s();
     phase.reset();
     phase.emplace("asss_setup:split and pack");
@@ -1639,6 +1624,50 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, voi
     *out = h.release();
     return ASSS_OK;
   });
+}
+
+extern "C" {
+
+void asss_default_setup_opts(asss_setup_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->gamma = 1.0;
+  o->s_pattern = ASSS_S_TRIDIAG;
+  o->k = 20;
+  o->lanczos_seed = 0x2009069540ull;
+  o->inner_fp32 = 0;
+  o->x_tol = 1e-10;
+  o->x_maxit = 2000;
+  o->lls_tol = 1e-15;
+  o->lls_maxit = 20000;
+  o->row_block = 0;
+  o->verbose = 0;
+  o->deflation = 0;
+  o->reorder = 0;
+  o->autotune = 0;
+  o->inner_perm = nullptr;
+  o->skew_form = 0;
+}
+
+void asss_default_solve_opts(asss_solve_opts_t* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->restart_m = 64;
+  o->max_outer = 2000;
+  o->inner_tol = 1e-5;
+  o->inner_maxit = 1000;
+  o->fixed_inner_steps = 0;
+  o->inner_fp32 = -1;
+  o->outer = ASSS_OUTER_FGMRES;
+  o->batch_streams = 0;
+  o->use_x0 = 0;
+}
+
+const char* asss_last_error(void) { return g_err.c_str(); }
+
+asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts, void* hip_stream,
+                         asss_handle_t* out) {
+  return setup_impl(A, opts, hip_stream, out, nullptr);
 }
 
 asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, const asss_solve_opts_t* o,
@@ -1873,6 +1902,121 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
     }
     return worst;
   });
+}
+
+// ---- saved setups ---------------------------------------------------------
+// File: "ASSSSAV1", then every array as an int64 count and its elements:
+// A (rowptr, colind, values), the matching, D_r, D_c, S (rowptr, colind,
+// values), the inner order (empty = natural) and the setup options
+// (8-byte numbers: gamma, k, seed, inner_fp32, x_tol, x_maxit, lls_tol,
+// lls_maxit, row_block, deflation, column form, S pattern kind).
+static const char kSaveMagic[8] = {'A', 'S', 'S', 'S', 'S', 'A', 'V', '1'};
+
+asss_status_t asss_save(asss_handle_t h, const char* path) {
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (!path) throw Error{ASSS_ERR_INVALID_ARG, "null path"};
+    std::vector<double> aval(h->dA.nnz);
+    if (h->dA.nnz)
+      HIPCHK(hipMemcpy(aval.data(), h->dA.val, h->dA.nnz * sizeof(double), hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw Error{ASSS_ERR_INVALID_ARG, std::string("cannot write ") + path};
+    bool ok = std::fwrite(kSaveMagic, 1, 8, f) == 8;
+    auto put = [&](const void* p, int64_t cnt, size_t esz) {
+      ok = ok && std::fwrite(&cnt, 8, 1, f) == 1;
+      if (cnt > 0) ok = ok && std::fwrite(p, esz, (size_t)cnt, f) == (size_t)cnt;
+    };
+    put(h->Apat.ptr.data(), (int64_t)h->Apat.ptr.size(), 8);
+    put(h->Apat.col.data(), (int64_t)h->Apat.col.size(), 4);
+    put(aval.data(), (int64_t)aval.size(), 8);
+    put(h->m.data(), (int64_t)h->m.size(), 4);
+    put(h->Dr.data(), (int64_t)h->Dr.size(), 8);
+    put(h->Dc.data(), (int64_t)h->Dc.size(), 8);
+    put(h->S.ptr.data(), (int64_t)h->S.ptr.size(), 8);
+    put(h->S.col.data(), (int64_t)h->S.col.size(), 4);
+    put(h->S.val.data(), (int64_t)h->S.val.size(), 8);
+    put(h->perm.data(), (int64_t)h->perm.size(), 4);
+    const asss_setup_opts_t& o = h->opts;
+    const double opt[12] = {o.gamma, (double)o.k, 0.0, (double)o.inner_fp32, o.x_tol, (double)o.x_maxit,
+                            o.lls_tol, (double)o.lls_maxit, (double)h->J64.R, (double)o.deflation,
+                            (double)h->skew_form, (double)o.s_pattern};
+    put(opt, 12, 8);
+    const uint64_t seed = o.lanczos_seed;  // exact, not through a double
+    put(&seed, 1, 8);
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) throw Error{ASSS_ERR_INVALID_ARG, std::string("write failed: ") + path};
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_load(const char* path, const asss_setup_opts_t* opts, void* hip_stream, asss_handle_t* out) {
+  // the file is read and checked before any HIP call
+  std::vector<int64_t> arp, srp;
+  std::vector<int32_t> aci, sci, perm;
+  std::vector<double> ava, sva, opt;
+  std::vector<uint64_t> seed;
+  Preset pre;
+  asss_status_t st = guarded([&]() -> asss_status_t {
+    if (!path || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw Error{ASSS_ERR_INVALID_ARG, std::string("cannot open ") + path};
+    char magic[8] = {};
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kSaveMagic, 8) == 0;
+    auto get = [&](auto& v) {
+      int64_t cnt = -1;
+      ok = ok && std::fread(&cnt, 8, 1, f) == 1 && cnt >= 0 && cnt < ((int64_t)1 << 40);
+      if (!ok) return;
+      v.resize((size_t)cnt);
+      if (cnt > 0) ok = std::fread(v.data(), sizeof(v[0]), (size_t)cnt, f) == (size_t)cnt;
+    };
+    get(arp); get(aci); get(ava); get(pre.m); get(pre.Dr); get(pre.Dc);
+    get(srp); get(sci); get(sva); get(perm); get(opt); get(seed);
+    std::fclose(f);
+    if (!ok) throw Error{ASSS_ERR_INVALID_ARG, std::string("not a saved setup (or truncated): ") + path};
+    const int64_t n = (int64_t)arp.size() - 1;
+    bool sane = n >= 1 && opt.size() == 12 && seed.size() == 1 && aci.size() == ava.size() &&
+                arp.back() == (int64_t)aci.size() && (int64_t)pre.m.size() == n && (int64_t)pre.Dr.size() == n &&
+                (int64_t)pre.Dc.size() == n && (int64_t)srp.size() == n + 1 && srp[0] == 0 &&
+                srp[n] == (int64_t)sci.size() && sci.size() == sva.size() && (perm.empty() || (int64_t)perm.size() == n);
+    for (int64_t i = 0; sane && i < n; ++i) {  // S pattern: sorted, in range
+      if (srp[i + 1] < srp[i]) { sane = false; break; }
+      for (int64_t p = srp[i]; p < srp[i + 1]; ++p)
+        if (sci[p] < 0 || sci[p] >= n || (p > srp[i] && sci[p] <= sci[p - 1])) { sane = false; break; }
+    }
+    for (int64_t j = 0; sane && j < n; ++j) sane = pre.m[j] >= 0 && pre.m[j] < n;
+    if (!sane) throw Error{ASSS_ERR_INVALID_ARG, std::string("inconsistent saved setup: ") + path};
+    pre.S.nrows = pre.S.ncols = n;
+    pre.S.ptr = srp;
+    pre.S.col = sci;
+    pre.S.val = sva;
+    return ASSS_OK;
+  });
+  if (st != ASSS_OK) return st;
+  asss_setup_opts_t o;
+  asss_default_setup_opts(&o);
+  o.gamma = opt[0];
+  o.k = (int32_t)opt[1];
+  o.lanczos_seed = seed[0];
+  o.inner_fp32 = (int32_t)opt[3];
+  o.x_tol = opt[4];
+  o.x_maxit = (int32_t)opt[5];
+  o.lls_tol = opt[6];
+  o.lls_maxit = (int32_t)opt[7];
+  o.row_block = (int32_t)opt[8];
+  o.deflation = (int32_t)opt[9];
+  o.skew_form = (int32_t)opt[10];
+  o.s_pattern = (int32_t)opt[11];
+  if (!perm.empty()) {
+    o.reorder = 3;
+    o.inner_perm = perm.data();
+  }
+  if (opts) {  // from the caller: where the memory comes from and the log level
+    o.allocator = opts->allocator;
+    o.verbose = opts->verbose;
+  }
+  const asss_csr_t A{(int64_t)arp.size() - 1, (int64_t)aci.size(), arp.data(), aci.data(), ava.data()};
+  return setup_impl(&A, &o, hip_stream, out, &pre);
 }
 
 asss_status_t asss_destroy(asss_handle_t h) {

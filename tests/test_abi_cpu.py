@@ -88,3 +88,19 @@ def test_missing_library_fails_loudly(tmp_path):
             asss.load(str(tmp_path / "nope.so"))
         finally:
             asss._lib = asss._lib_saved
+
+
+def test_load_rejects_bad_files_without_gpu(tmp_path):
+    """asss_load checks the file before any device call: a missing file, a
+    foreign file and a truncated saved setup are INVALID_ARG."""
+    asss, lib = _lib()
+    out = ctypes.c_void_p()
+    assert lib.asss_load(str(tmp_path / "missing.bin").encode(), None, None, ctypes.byref(out)) == -1
+    assert b"cannot open" in lib.asss_last_error()
+    bad = tmp_path / "foreign.bin"
+    bad.write_bytes(b"not a saved setup at all")
+    assert lib.asss_load(str(bad).encode(), None, None, ctypes.byref(out)) == -1
+    trunc = tmp_path / "trunc.bin"
+    trunc.write_bytes(b"ASSSSAV1" + (5).to_bytes(8, "little") + b"\x00" * 12)
+    assert lib.asss_load(str(trunc).encode(), None, None, ctypes.byref(out)) == -1
+    assert b"truncated" in lib.asss_last_error() and not out.value
