@@ -877,6 +877,13 @@ void ensure_outer(asss_handle_s* h, int m) {
   h->m_alloc = m;
 }
 
+// [a, a + la) and [b, b + lb) share an element
+bool overlaps(const double* a, int64_t la, const double* b, int64_t lb) {
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)la * sizeof(double);
+  const uintptr_t b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)lb * sizeof(double);
+  return a0 < b1 && b0 < a1;
+}
+
 bool b_is_finite(asss_handle_s* h, const double* b, hipStream_t s) {
   HIPCHK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
   check_finite(h->n, b, h->d_flag, s);
@@ -1676,6 +1683,7 @@ asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, co
   return guarded([&]() -> asss_status_t {
     check_handle(h);
     if (!b_dev || !x_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
+    if (overlaps(b_dev, h->n, x_dev, h->n)) throw Error{ASSS_ERR_INVALID_ARG, "b and x overlap"};
     hipStream_t s = (hipStream_t)hip_stream;
     asss_solve_opts_t oo = opts_or_default(o);
     if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
@@ -1692,6 +1700,7 @@ asss_status_t asss_solve_adjoint(asss_handle_t h, const double* g_dev, double* l
   return guarded([&]() -> asss_status_t {
     check_handle(h);
     if (!g_dev || !lambda_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
+    if (overlaps(g_dev, h->n, lambda_dev, h->n)) throw Error{ASSS_ERR_INVALID_ARG, "g and lambda overlap"};
     hipStream_t s = (hipStream_t)hip_stream;
     asss_solve_opts_t oo = opts_or_default(o);
     if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
@@ -1758,6 +1767,9 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
       if (!hs[sidx]) throw Error{ASSS_ERR_INVALID_ARG, "null handle"};
       if (nrhs[sidx] < 0 || (nrhs[sidx] > 0 && (!B_dev[sidx] || !X_dev[sidx])))
         throw Error{ASSS_ERR_INVALID_ARG, "bad nrhs or null block"};
+      if (nrhs[sidx] > 0 && overlaps(B_dev[sidx], hs[sidx]->n * (int64_t)nrhs[sidx], X_dev[sidx],
+                                     hs[sidx]->n * (int64_t)nrhs[sidx]))
+        throw Error{ASSS_ERR_INVALID_ARG, "a right-hand side block and its solution block overlap"};
       maxr = std::max(maxr, (int)nrhs[sidx]);
     }
     // every right-hand side is checked before any is solved

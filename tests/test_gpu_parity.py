@@ -289,6 +289,18 @@ def test_edge_cases(cfg0):
     assert info["status"] == "NOT_CONVERGED" and info["outer_its"] == 1
     x, info = p.h.solve(_cuda(p.w.b), tol=1e-10, restart_m=2)
     assert info["status"] == "OK" and info["cycles"] > 1
+    bb = _cuda(p.w.b)
+    for out in (bb, None):  # the output may not overlap the right-hand side
+        if out is None:
+            big = torch.zeros(2 * p.n, dtype=torch.float64, device="cuda")
+            big[:p.n] = bb
+            bb, out = big[:p.n], big[p.n // 2:p.n // 2 + p.n]
+        with pytest.raises(asss.AsssError) as e:
+            p.h.solve(bb, out=out)
+        assert e.value.name == "INVALID_ARG"
+        with pytest.raises(asss.AsssError) as e:
+            p.h.solve_adjoint(bb, out=out)
+        assert e.value.name == "INVALID_ARG"
     A = sp.csr_matrix(np.array([[1.0, 2.0, 0], [3.0, 4.0, 0], [5.0, 6.0, 0]]))
     with pytest.raises(asss.AsssError) as e:
         asss.setup(A, k=1)
