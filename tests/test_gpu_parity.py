@@ -342,6 +342,29 @@ def test_initial_guess(cfg0):
     assert e.value.name == "NONFINITE"
 
 
+@pytest.mark.parametrize("pattern", ["diag", "abar", "band5"])
+def test_s_patterns(pattern):
+    """The other patterns of S (Sec. 2: diagonal, the sparsity of Abar, and a
+    user-given one, here the band of half-width 2): S, J_tilde and the solution
+    against the oracle on cfg0."""
+    asss = _lib()
+    w = W.config(0, m=30)
+    n = w.A.shape[0]
+    pat = pattern
+    if pattern == "band5":
+        pat = sp.diags([np.ones(n - abs(d)) for d in range(-2, 3)], list(range(-2, 3)), format="csr")
+    p = Pair(w.A, k=6, pattern=pat)
+    S = p.st.S.tocsr()
+    S.sort_indices()
+    assert np.array_equal(p.h.array("S_rowptr"), S.indptr) and np.array_equal(p.h.array("S_colind"), S.indices)
+    assert _rel(p.h.array("S_val"), S.data) <= 1e-12
+    assert np.array_equal(p.h.array("J_colind"), p.st.Jup.indices)
+    assert _rel(p.h.array("J_val"), p.st.Jup.data) <= 1e-12
+    xo, _ = O.solve(p.st, w.b, O.SolveOptions(tol=1e-12))
+    x, info = p.h.solve(_cuda(w.b), tol=1e-12)
+    assert info["status"] == "OK" and _rel(_np(x), xo) <= 1e-10
+
+
 def test_run_twice_determinism(cfg0):
     """Everything but the in-block LDS scatter of the skew operator (atomic
     adds in a run-dependent order) is bitwise reproducible: the CSR products
