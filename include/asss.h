@@ -87,8 +87,10 @@ enum {
  * usable on the handle's device, or NULL (the entry point then fails with
  * ASSS_ERR_OOM); free gives it back.  Both are called from the calling thread
  * of asss_setup, of the solve entry points (workspaces are grown on first use)
- * and of asss_destroy, with ctx passed through.  The functions and ctx must
- * stay valid until the handle is destroyed (the structure itself is copied). */
+ * and of asss_destroy, with ctx passed through, and from the worker threads of
+ * asss_solve_batched, several at once for different handles: they must be
+ * thread-safe.  The functions and ctx must stay valid until the handle is
+ * destroyed (the structure itself is copied). */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
