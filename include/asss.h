@@ -15,10 +15,13 @@
  *   - k skew-Lanczos vectors Q_k, S_k (Fig. 2), the deflated J_bar =
  *     J_tilde - Q_k S_k Q_k^T, and the one-time Sherman-Morrison-Woodbury data
  *     for the rank-(k+r) term (Sec. 3.2, eqs. preconditioner and smw; Sec. 4.1).
- * Each solve (asss_solve) runs flexible GMRES on the scaled system
- * Omega Abar S Omega, right-preconditioned with P = sign(D) + J_tilde, where
- * P^-1 is applied through the SMW form around an inner minimal residual
- * solve (mrs, Sec. 3.1 and App. B) on I + J_bar.
+ * Each solve (asss_solve) runs flexible GMRES (or TFQMR, Sec. 4.1) on the
+ * scaled system Omega Abar S Omega, right-preconditioned with
+ * P = sign(D) + J_tilde, where P^-1 is applied through the SMW form around an
+ * inner minimal residual solve (mrs, Sec. 3.1 and App. B) on I + J_bar.  The
+ * adjoint solve (A^T lambda = g), batched solves of several systems with
+ * several right-hand sides, value gradients of a solve, and saved setups use
+ * the same preconditioner.
  *
  * Conventions
  *   - Every function returns asss_status_t: 0 = ASSS_OK, > 0 = soft status
@@ -30,8 +33,10 @@
  *     on the given HIP stream; they must stay valid until that stream has
  *     finished the call's work (the call itself synchronises the stream
  *     before it returns).
- *   - A handle owns all its device memory (allocated with hipMalloc on the
- *     device current at asss_setup) and is not thread-safe.
+ *   - A handle owns all its device memory (allocated with hipMalloc, or the
+ *     caller's allocator, on the device current at asss_setup) and is not
+ *     thread-safe: one call at a time per handle.  An output vector must not
+ *     overlap its right-hand side (INVALID_ARG).
  *   - hip_stream is a hipStream_t (NULL = the default stream).
  */
 #ifndef ASSS_H
