@@ -294,10 +294,12 @@ def main():
     ap.add_argument("--table5", action="store_true",
                     help="the paper's experimental settings (k = 20, S tridiagonal, tol 1e-5, b = A ones) on "
                          "the stand-in family: TFQMR and FGMRES iteration counts next to Table 5")
-    ap.add_argument("--inner-order", choices=["natural", "tiles"], default="tiles",
+    ap.add_argument("--inner-order", choices=["natural", "tiles", "grid"], default="tiles",
                     help="order of the inner system (a symmetric permutation of J_tilde that the "
-                         "solution does not depend on): tiles of whole x-lines (--tile TYxTZ lines per "
-                         "tile, one tile per row block; default) or the grid's natural order")
+                         "solution does not depend on): tiles of whole x-lines passed by the caller "
+                         "(--tile TYxTZ lines per tile, one tile per row block; default), the library's "
+                         "own line tiles for a detected 3D grid (reorder='grid'; the same 4 x 4 tiles at "
+                         "128^3), or the grid's natural order")
     ap.add_argument("--tile", default="4x4")
     ap.add_argument("--no-natural", action="store_true",
                     help="with tiles: skip the comparison solves in the natural order")
@@ -336,7 +338,10 @@ def main():
     log(f"n={n} nnz={nnz}; setup (host preprocessing + device data)")
     t0 = time.perf_counter()
     order_kw = {}
-    order_name = "natural" if args.inner_order == "natural" else f"x-line tiles {args.tile}"
+    order_name = {"natural": "natural", "tiles": f"x-line tiles {args.tile}",
+                  "grid": "library grid order"}[args.inner_order]
+    if args.inner_order == "grid":
+        order_kw["reorder"] = "grid"
     if args.inner_order == "tiles":
         ty, tz = (int(v) for v in args.tile.split("x"))
         order_kw["reorder"] = W.grid_line_tiles(args.m, ty, tz)
@@ -461,7 +466,7 @@ def main():
                         "relres_true": inf32[-1]["relres_true"], "rel_err_vs_xstar": err32,
                         "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
                         "solve_s_per_step": [round(i["solve_s"], 4) for i in inf32]}
-    if args.inner_order == "tiles" and not args.no_natural:
+    if args.inner_order != "natural" and not args.no_natural:
         # the same solves with the inner system in the grid's natural order
         log("natural order of the inner system: setup and one solve per precision")
         hn = asss.setup(w.A, k=args.k, s_pattern="abar")

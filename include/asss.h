@@ -139,7 +139,15 @@ typedef struct {
                                   order in which each block of row_block rows is a
                                   compact tile of whole grid lines keeps more pairs
                                   inside a block than the natural order and keeps
-                                  the neighbours of a wavefront at common offsets */
+                                  the neighbours of a wavefront at common offsets;
+                              4 = that order found by the library: when the pattern
+                                  of Abar is a lexicographic 3D grid (positive column
+                                  offsets exactly 1, m1 and m1 m2, with m1 m2 | n),
+                                  tiles of ty x tz whole x-lines, ty tz the largest
+                                  power of two with m1 ty tz <= the automatic row
+                                  block (or row_block if given) and a multiple of
+                                  64, ty | m2, tz | m3, as square as possible, one
+                                  tile per row block; otherwise the natural order */
   const asss_allocator_t* allocator; /* device memory of the handle; NULL = hipMalloc / hipFree */
   int32_t autotune;        /* row-block autotuner (only with row_block = 0; reorder = 2 is
                               rejected):

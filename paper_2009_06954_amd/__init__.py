@@ -345,8 +345,9 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     autotune: time the inner step for several row-block sizes at setup and keep
     the fastest (row_block must be 0; see info()["tune_rows"], ["tune_us"]).
     reorder: "auto"/"none" (natural order of the inner system), "blocks" (BFS
-    bisection into row blocks) or an integer array perm of length n (inner row
-    i is row perm[i]).
+    bisection into row blocks), "grid" (tiles of whole lines when A's pattern
+    is a lexicographic 3D grid, else natural) or an integer array perm of
+    length n (inner row i is row perm[i]).
     skew_form: storage of J_tilde's columns: "auto", "wide" (32-bit), "narrow"
     (16-bit deltas) or "slots" (one offset per slot, no per-entry columns)."""
     lib = load()
@@ -369,7 +370,7 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.skew_form = SKEW_FORMS[skew_form]
     o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2}[deflation]
     if isinstance(reorder, str):
-        o.reorder = {"auto": 0, "none": 1, "blocks": 2}[reorder]
+        o.reorder = {"auto": 0, "none": 1, "blocks": 2, "grid": 4}[reorder]
     else:  # the caller's order of the inner system: inner row i is row reorder[i]
         perm = np.ascontiguousarray(reorder, dtype=np.int32)
         if perm.shape != (n,):

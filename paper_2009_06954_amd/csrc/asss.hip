@@ -1445,7 +1445,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
     if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
     if (o.deflation < 0 || o.deflation > 2) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1 or 2"};
-    if (o.reorder < 0 || o.reorder > 3) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1, 2 or 3"};
+    if (o.reorder < 0 || o.reorder > 4) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1, 2, 3 or 4"};
     if (o.reorder == 3 && !o.inner_perm) throw Error{ASSS_ERR_INVALID_ARG, "reorder 3 needs inner_perm"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
@@ -1499,10 +1499,13 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     phase.emplace("asss_setup:LSQR for S");
     // ---- device: reducer and scalar buffers first (LSQR uses them)
     int R = o.row_block;
-    if (R == 0) {
-      R = 64;
-      while (R < 2048 && (int64_t)R * 2 * 1024 <= n) R *= 2;
-    }
+    int auto_R = 64;
+    while (auto_R < 2048 && (int64_t)auto_R * 2 * 1024 <= n) auto_R *= 2;
+    // reorder 4: tiles of whole grid lines when Abar is a lexicographic 3D grid
+    std::vector<int32_t> grid_perm;
+    int32_t grid_R = 0;
+    if (o.reorder == 4) grid_perm = grid_line_order(Abar, R ? R : auto_R, grid_R);
+    if (R == 0) R = grid_perm.empty() ? auto_R : grid_R;
     // autotuner candidates: the automatic size and up to two doublings and
     // halvings of it within [64, 2048]
     std::vector<int> cands;
@@ -1549,6 +1552,11 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
         h->cross_used = cross;
         reordered = true;
       }
+    } else if (o.reorder == 4 && !grid_perm.empty()) {  // line tiles of a detected grid
+      Jup = permute_skew_upper(Jup, grid_perm);
+      h->cross_used = count_cross_pairs(Jup, R);
+      h->perm = std::move(grid_perm);
+      reordered = true;
     } else if (o.reorder == 3) {  // the caller's order, validated as a permutation
       std::vector<int32_t> perm(o.inner_perm, o.inner_perm + n);
       std::vector<char> seen(n, 0);

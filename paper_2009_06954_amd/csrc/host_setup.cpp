@@ -859,6 +859,54 @@ int32_t bfs_part(const Csr& G, const std::vector<int32_t>& part, int32_t pid, in
 
 }  // namespace
 
+std::vector<int32_t> grid_line_order(const Csr& Abar, int32_t target_R, int32_t& R_out) {
+  const int64_t n = Abar.nrows;
+  R_out = 0;
+  // distinct positive column offsets (a grid stencil has a handful)
+  std::vector<int64_t> offs;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = Abar.ptr[i]; p < Abar.ptr[i + 1]; ++p) {
+      const int64_t d = (int64_t)Abar.col[p] - i;
+      if (d <= 0 || std::find(offs.begin(), offs.end(), d) != offs.end()) continue;
+      offs.push_back(d);
+      if (offs.size() > 3) return {};
+    }
+  std::sort(offs.begin(), offs.end());
+  if (offs.size() != 3 || offs[0] != 1) return {};
+  const int64_t m1 = offs[1], plane = offs[2];
+  if (m1 < 2 || plane % m1 != 0 || n % plane != 0) return {};
+  const int64_t m2 = plane / m1, m3 = n / plane;
+  if (m2 < 2 || m3 < 2) return {};
+  // lines per tile: the largest power of two <= target_R / m1 with a split
+  // ty x tz (powers of two, ty | m2, tz | m3, as square as possible) and
+  // m1 ty tz a multiple of 64 within 4096
+  int64_t best_ty = 0, best_tz = 0;
+  int64_t T0 = 1;
+  while (T0 * 2 <= target_R / m1) T0 *= 2;
+  for (int64_t T = T0; T >= 1 && !best_ty; T /= 2) {
+    if ((m1 * T) % 64 != 0 || m1 * T > 4096) continue;
+    int64_t gap = -1;
+    for (int64_t ty = 1; ty <= T; ty *= 2) {
+      const int64_t tz = T / ty;
+      if (ty * tz != T || m2 % ty != 0 || m3 % tz != 0) continue;
+      const int64_t g = std::max(ty, tz) / std::min(ty, tz);
+      if (gap < 0 || g < gap) { gap = g; best_ty = ty; best_tz = tz; }
+    }
+  }
+  if (!best_ty) return {};
+  const int64_t ty = best_ty, tz = best_tz;
+  std::vector<int32_t> perm((size_t)n);
+  int64_t k = 0;
+  for (int64_t TZ = 0; TZ < m3 / tz; ++TZ)
+    for (int64_t TY = 0; TY < m2 / ty; ++TY)
+      for (int64_t z = 0; z < tz; ++z)
+        for (int64_t y = 0; y < ty; ++y)
+          for (int64_t x = 0; x < m1; ++x)
+            perm[(size_t)k++] = (int32_t)(x + m1 * ((TY * ty + y) + m2 * (TZ * tz + z)));
+  R_out = (int32_t)(m1 * ty * tz);
+  return perm;
+}
+
 std::vector<int32_t> block_partition(const Csr& U, int32_t R) {
   const int64_t n = U.nrows;
   // full symmetric pattern G = U + U^T

@@ -134,6 +134,17 @@ SkewSell pack_skew_sell(const Csr& Jup, int32_t R, int32_t form = SKEW_AUTO);
 // in increasing original index.  Returns perm (new -> old).
 std::vector<int32_t> block_partition(const Csr& U, int32_t R);
 
+// Order of the inner system for a lexicographic 3D grid (node x + m1 y +
+// m1 m2 z): detected from the pattern of Abar, whose positive column offsets
+// must be exactly {1, m1, m1 m2} with m1 m2 dividing n.  Rows are then grouped
+// into tiles of ty x tz whole x-lines (tiles in lexicographic (y, z) order,
+// lines y-fastest inside a tile), ty tz a power of two as close to
+// target_R / m1 as fits, ty | m2, tz | m3, ty and tz as equal as possible, and
+// m1 ty tz a multiple of 64 (at most 4096): one tile per row block of that
+// size, returned in R_out.  Returns perm (new -> old), or an empty vector
+// when the pattern is not such a grid or no tile fits.
+std::vector<int32_t> grid_line_order(const Csr& Abar, int32_t target_R, int32_t& R_out);
+
 // Strict upper triangle of P J P^T for the permutation perm (new -> old) of
 // the skew matrix whose strict upper triangle is U (values u_ij, lower -u_ij).
 Csr permute_skew_upper(const Csr& U, const std::vector<int32_t>& perm);

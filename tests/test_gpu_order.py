@@ -119,3 +119,30 @@ def test_line_tiles_on_a_3d_grid():
     ha.close()
     ht.close()
     hn.close()
+
+
+def test_library_grid_order():
+    """reorder="grid": the library finds the lexicographic 3D grid in the
+    pattern of Abar and lays the inner system out in tiles of whole x-lines;
+    on 64^3 (automatic row block 256) that is the 2 x 2 line tiling the
+    caller could pass, and the solution does not change.  A 2D grid and a
+    random pattern keep the natural order."""
+    asss = _lib()
+    m = 64
+    w = W.convdiff3d(m=m, peclet=100.0, cfg=1)
+    hg = asss.setup(w.A, k=8, s_pattern="tridiag", reorder="grid")
+    hc = asss.setup(w.A, k=8, s_pattern="tridiag", reorder=W.grid_line_tiles(m, 2, 2), row_block=256)
+    ig, ic = hg.info(), hc.info()
+    assert ig["reordered"] == 1 and ig["row_block"] == 256
+    for key in ("cross_pairs_used", "sell_entries_a", "sell_entries_b", "skew_form"):
+        assert ig[key] == ic[key], key
+    b = _cuda(w.b)
+    xg, info = hg.solve(b, tol=1e-10, restart_m=100, inner_tol=0.2)
+    assert info["status"] == "OK"
+    assert np.linalg.norm(w.b - w.A @ _np(xg)) <= 1.01e-10 * np.linalg.norm(w.b)
+    hg.close()
+    hc.close()
+    for A in (W.config(0).A, W.paper_like(2000, 12000, seed=1).A):
+        h = asss.setup(A, k=4, reorder="grid")
+        assert h.info()["reordered"] == 0
+        h.close()
