@@ -1,8 +1,8 @@
 """The benchmark workload at full size (3D convection-diffusion, 128^3,
 n = 2,097,152, Peclet 100, S on the pattern of Abar, k = 16), in the launch
 configuration the benchmark times (the inner system in tiles of 4 x 4 whole
-x-lines, one tile per row block of 2048, one workgroup each, J_tilde in
-offset slots).
+x-lines that the library finds in the grid structure, one tile per row block
+of 2048, one workgroup each, J_tilde in offset slots).
 
 The oracle cannot build S at this size in seconds (its LLS is a 27M x 15M
 least-squares problem), so these tests check what holds at any size:
@@ -41,7 +41,7 @@ def full():
     asss.load()
     print(f"[full] building convdiff3d {M}^3", flush=True)
     w = W.convdiff3d(m=M, peclet=100.0, cfg=1)
-    h = asss.setup(w.A, k=16, s_pattern="abar", reorder=W.grid_line_tiles(M, 4, 4), row_block=2048)
+    h = asss.setup(w.A, k=16, s_pattern="abar", reorder="grid")
     info = h.info()
     print(f"[full] setup done: {info}", flush=True)
     U = sp.csr_matrix((h.array("J_val"), h.array("J_colind"), h.array("J_rowptr")), shape=w.A.shape)
@@ -56,6 +56,12 @@ def test_fullsize_launch_configuration(full):
     assert i["n"] == M ** 3 and i["row_block"] == 2048 and i["nblocks"] == M ** 3 // 2048
     assert i["k_eff"] == 16 and i["nh"] == full["J"].nnz // 2
     assert i["reordered"] == 1 and i["skew_form"] == 3  # x-line tiles, offset slots
+    # the blocks are those of the 4 x 4 line tiling: same pairs straddling two blocks
+    inv = np.empty(M ** 3, dtype=np.int64)
+    inv[W.grid_line_tiles(M, 4, 4)] = np.arange(M ** 3)
+    U = sp.triu(full["J"], k=1).tocoo()
+    blk = inv // 2048
+    assert i["cross_pairs_used"] == int(np.count_nonzero(blk[U.row] != blk[U.col]))
     assert i["cross_pairs_used"] < 0.6 * i["cross_pairs_natural"]
 
 
