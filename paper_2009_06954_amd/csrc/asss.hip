@@ -264,7 +264,7 @@ struct asss_handle_s {
   MrsBufs<float> mb32{};
   MrsState* d_state = nullptr;
   Reducer red;
-  double* d_small = nullptr;  // 1024 doubles of scalars
+  double* d_small = nullptr;  // SM_SIZE doubles of scalars (layout above)
   int* d_flag = nullptr;
   double* h_small = nullptr;  // pinned
   // outer workspace
