@@ -114,7 +114,13 @@ struct DevArena {
   }
 };
 
+// SpMV kernel shape: one row per thread when no row has more than 32 entries
+// (grid stencils, the least-squares matrices of App. A), else the smallest
+// power of two of lanes per row that covers the average row.
 int lanes_for(const Csr& M) {
+  int64_t longest = 0;
+  for (int64_t i = 0; i < M.nrows; ++i) longest = std::max(longest, M.ptr[i + 1] - M.ptr[i]);
+  if (longest <= 32) return 0;
   double avg = M.nrows ? (double)M.nnz() / (double)M.nrows : 1.0;
   int l = 1;
   while (l < avg && l < 64) l <<= 1;

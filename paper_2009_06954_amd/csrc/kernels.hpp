@@ -18,7 +18,7 @@ struct DCsr {
   int64_t* ptr = nullptr;
   int32_t* col = nullptr;
   double* val = nullptr;
-  int lanes = 1;  // lanes per row of the vector SpMV kernel
+  int lanes = 1;  // lanes per row of the vector SpMV kernel; 0: one row per thread
 };
 
 // Sliced skew operator (see host_setup.hpp: SkewSell).
