@@ -582,7 +582,21 @@ __global__ __launch_bounds__(WG) void k_gemv_acc(int64_t n, int kt, const double
   __shared__ double ts[1024];
   for (int l = threadIdx.x; l < kt && l < 1024; l += WG) ts[l] = t[l];
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+  // two rows per thread and round (i and i + stride), as in k_gemm_tn
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  for (; i + stride < n; i += 2 * stride) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int l = 0; l < kt; ++l) {
+      const double a0 = __builtin_nontemporal_load(&A[(int64_t)l * lda + i]);
+      const double a1 = __builtin_nontemporal_load(&A[(int64_t)l * lda + i + stride]);
+      s0 += a0 * ts[l];
+      s1 += a1 * ts[l];
+    }
+    y[i] += sign * s0;
+    y[i + stride] += sign * s1;
+  }
+  for (; i < n; i += stride) {
     double sacc = 0.0;
     for (int l = 0; l < kt; ++l) sacc += __builtin_nontemporal_load(&A[(int64_t)l * lda + i]) * ts[l];
     y[i] += sign * sacc;
@@ -592,7 +606,9 @@ void gemv_acc(int64_t n, int kt, const double* A, int64_t lda, const double* t, 
               double* y, hipStream_t s) {
   if (kt <= 0 || n <= 0) return;
   if (kt > 1024) kt = 1024;  // callers pass at most 512 (k + r and restart bounds)
-  hipLaunchKernelGGL(k_gemv_acc, grid_for(n), dim3(WG), 0, s, n, kt, A, lda, t, sign, y);
+  // at most 1024 workgroups, so that every thread has two rows in flight
+  const dim3 grid((unsigned)std::min<int64_t>((n + WG - 1) / WG, 1024));
+  hipLaunchKernelGGL(k_gemv_acc, grid, dim3(WG), 0, s, n, kt, A, lda, t, sign, y);
 }
 
 // y += sign * A t, then ||y||^2 reduced into *nrm2 (last workgroup, fixed order).
@@ -606,7 +622,22 @@ __global__ __launch_bounds__(WG) void k_gemv_acc_norm(int64_t n, int kt, const d
   for (int l = threadIdx.x; l < kt && l < 1024; l += WG) ts[l] = t[l];
   __syncthreads();
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  for (; i + stride < n; i += 2 * stride) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int l = 0; l < kt; ++l) {
+      const double a0 = __builtin_nontemporal_load(&A[(int64_t)l * lda + i]);
+      const double a1 = __builtin_nontemporal_load(&A[(int64_t)l * lda + i + stride]);
+      s0 += a0 * ts[l];
+      s1 += a1 * ts[l];
+    }
+    const double v0 = y[i] + sign * s0, v1 = y[i + stride] + sign * s1;
+    y[i] = v0;
+    y[i + stride] = v1;
+    acc[0] += v0 * v0 + v1 * v1;
+  }
+  for (; i < n; i += stride) {
     double sacc = 0.0;
     for (int l = 0; l < kt; ++l) sacc += __builtin_nontemporal_load(&A[(int64_t)l * lda + i]) * ts[l];
     const double v = y[i] + sign * sacc;
@@ -870,7 +901,37 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   const int64_t n = L.n;
   const int k = L.k;
-  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  int64_t i0 = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if constexpr (NR == 1 && sizeof(T) == 8) {
+    // one FP64 column: two rows per thread and round (i and i + stride), their
+    // loads issued before the sums (128^3, k = 16: 115 -> 86 us; the FP32 start
+    // does not gain, 62 -> 67 us, and keeps one row per round)
+    for (; i0 + stride < n; i0 += 2 * stride) {
+      const int64_t i1 = i0 + stride;
+      const int64_t src0 = perm ? (int64_t)perm[i0] : i0, src1 = perm ? (int64_t)perm[i1] : i1;
+      const double b0 = L.nr > 0 ? rhs[src0] : 0.0, b1 = L.nr > 0 ? rhs[src1] : 0.0;
+      double q0[KF > 0 ? KF : 1], q1[KF > 0 ? KF : 1];
+#pragma unroll
+      for (int l = 0; l < KF; ++l)
+        if (l < k) {
+          q0[l] = (double)Q[(int64_t)l * n + i0];
+          q1[l] = (double)Q[(int64_t)l * n + i1];
+        }
+      buf.w[1][i0] = (T)b0;
+      buf.w[1][i1] = (T)b1;
+      buf.w[0][i0] = T(0); buf.w[0][i1] = T(0);
+      buf.w[2][i0] = T(0); buf.w[2][i1] = T(0);
+      buf.p[0][i0] = T(0); buf.p[0][i1] = T(0);
+      buf.p[1][i0] = T(0); buf.p[1][i1] = T(0);
+      buf.x[i0] = T(0); buf.x[i1] = T(0);
+      acc[0] += b0 * b0 + b1 * b1;
+#pragma unroll
+      for (int l = 0; l < KF; ++l)
+        if (l < k) acc[1 + l] += q0[l] * (double)(T)b0 + q1[l] * (double)(T)b1;
+    }
+  }
+  for (int64_t i = i0; i < n; i += stride) {
     double b[NR];
     const int64_t src = perm ? (int64_t)perm[i] : i;
 #pragma unroll
