@@ -627,3 +627,55 @@ def test_torch_allocator():
     h.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
+
+
+def _long_row_matrix(n=300, seed=5):
+    """Rows of 5 entries, ten rows of about 20 and one of 60 (plus the diagonal):
+    A itself is longer than 32 entries in one row, A^T is not."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        cnt = 60 if i == 7 else (20 if 20 <= i < 30 else 5)
+        c = rng.choice(n, size=cnt, replace=False)
+        c = c[c != i]
+        rows += [i] * len(c)
+        cols += list(c)
+        vals += list(rng.standard_normal(len(c)) * (0.05 if cnt > 5 else 0.3))
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    A = (A + sp.diags(rng.uniform(2, 4, n) * rng.choice([-1.0, 1.0], n))).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+@pytest.fixture(scope="module")
+def longrow():
+    return Pair(_long_row_matrix(), k=4)
+
+
+def test_spmv_kernel_shapes(longrow):
+    """The CSR SpMV takes one row per thread (up to 8 entries per round) when
+    no row has more than 32 entries and lanes per row otherwise.  A has a row
+    of 60 entries (lane kernel), A^T and the rows of 20 take the row kernel
+    over several rounds; all agree with SciPy within rounding, and the outer
+    operators and the solve with the oracle."""
+    p = longrow
+    L, LT = np.diff(p.A.indptr), np.diff(p.A.T.tocsr().indptr)
+    assert L.max() > 32 and LT.max() <= 32 and np.count_nonzero(L > 8) >= 10
+    v = np.random.default_rng(6).standard_normal(p.n)
+    aA = abs(p.A)
+    out, _ = p.h.apply("A", _cuda(v))
+    _within_rounding(_np(out), p.A @ v, aA @ np.abs(v), c=64)
+    out, _ = p.h.apply("AT", _cuda(v))
+    _within_rounding(_np(out), p.A.T @ v, aA.T @ np.abs(v), c=64)
+    st = p.st
+    aS, aAb, om = abs(st.S), abs(st.Abar), st.Omega
+    out, _ = p.h.apply("outer", _cuda(v))
+    _within_rounding(_np(out), st.op(v), om * (aAb @ (aS @ (om * np.abs(v)))))
+    out, _ = p.h.apply("outer_t", _cuda(v))
+    _within_rounding(_np(out), st.op_T(v), om * (aS.T @ (aAb.T @ (om * np.abs(v)))))
+    b = p.A @ np.ones(p.n)
+    xo, io = O.solve(st, b, O.SolveOptions(tol=1e-12))
+    x, info = p.h.solve(_cuda(b), tol=1e-12)
+    assert io["converged"] and info["status"] == "OK" and info["relres_true"] <= 1e-12
+    assert _rel(_np(x), xo) <= 1e-9
