@@ -125,7 +125,16 @@ typedef struct {
                                   Numerically unstable: rounding components along the
                                   deflated directions are never re-projected and grow by
                                   ~3x per step on the 3D convection-diffusion workload;
-                                  only accepted when max|Q_k^T Q_k - I| <= 1e-10, else 1 */
+                                  only accepted when max|Q_k^T Q_k - I| <= 1e-10, else 1;
+                              3 = explicitly, with the Lanczos vectors rounded to FP32
+                                  values at setup and that basis used everywhere (the
+                                  deflated inner operator, U_bar, X, G): the SMW form of
+                                  eq. smw then gives back the same P = sign(D) + J_tilde
+                                  (the low-rank term adds back what the deflation takes
+                                  out, for any basis), arithmetic stays FP64, and the
+                                  FP64 inner step reads the basis as 4-byte values.  The
+                                  deflated operator and single mrs solves then differ
+                                  from those of the unrounded basis by its rounding */
   int32_t reorder;         /* order of the inner system (a symmetric permutation of
                               J_tilde, invisible to the caller):
                               0 or 1 = natural order (default);
@@ -318,7 +327,7 @@ typedef struct {
   int64_t sell_entries_a, sell_entries_b; /* stored skew entries: in-block upper, off-block both */
   double lls_relres, lls_kkt;             /* LSQR stopping quantities */
   double lanczos_orth_err;                /* max |Q_k^T Q_k - I| */
-  int32_t deflation_mode;                 /* 0 none, 1 explicit, 2 recurrence */
+  int32_t deflation_mode;                 /* 0 none, 1 explicit, 2 recurrence, 3 explicit with the FP32-valued basis */
   int32_t reordered;                      /* 1 if the inner system uses block order */
   int64_t cross_pairs_natural;            /* strictly upper pairs straddling two row blocks */
   int64_t cross_pairs_used;               /* the same in the order used */

@@ -349,7 +349,11 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     is a lexicographic 3D grid, else natural) or an integer array perm of
     length n (inner row i is row perm[i]).
     skew_form: storage of J_tilde's columns: "auto", "wide" (32-bit), "narrow"
-    (16-bit deltas) or "slots" (one offset per slot, no per-entry columns)."""
+    (16-bit deltas) or "slots" (one offset per slot, no per-entry columns).
+    deflation: "auto"/"explicit", "recurrence", or "explicit_fp32_basis" (the
+    Lanczos vectors rounded to FP32 values and used so everywhere: same
+    preconditioner P, FP64 arithmetic, half the basis bytes in the FP64 inner
+    step; see asss_setup_opts_t.deflation)."""
     lib = load()
     n, rp, ci, va = _csr_arrays(A, canonicalize)
     csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
@@ -368,7 +372,7 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.autotune = int(bool(autotune))
     o.skew_form = SKEW_FORMS[skew_form]
-    o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2}[deflation]
+    o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2, "explicit_fp32_basis": 3}[deflation]
     if isinstance(reorder, str):
         o.reorder = {"auto": 0, "none": 1, "blocks": 2, "grid": 4}[reorder]
     else:  # the caller's order of the inner system: inner row i is row reorder[i]

@@ -339,7 +339,9 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f
   L.f = f;
   L.qk1 = (h->k_eff >= 2) ? (const void*)(Q + (int64_t)(h->k_eff - 2) * h->n) : nullptr;
   L.alpha_last = (h->k_eff >= 2) ? h->alpha[h->k_eff - 2] : 0.0;
-  L.Qs = std::is_same<T, float>::value ? (const void*)h->d_Qs32 : (const void*)h->d_Qs64;
+  // deflation = 3: the basis holds FP32 values, and the FP64 step reads the FP32 copy
+  L.q32 = (!std::is_same<T, float>::value && h->opts.deflation == 3 && h->k_eff > 0) ? 1 : 0;
+  L.Qs = (std::is_same<T, float>::value || L.q32) ? (const void*)h->d_Qs32 : (const void*)h->d_Qs64;
   L.gram = std::is_same<T, float>::value ? h->d_G32 : h->d_G64;
   return L;
 }
@@ -724,6 +726,14 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   }
   h->k_eff = keff;
   h->alpha = alpha;
+  if (keff > 0) {
+    h->d_Q32 = h->ar.alloc<float>(n * (int64_t)keff);
+    cast_d2f(n * (int64_t)keff, h->d_Q64, h->d_Q32, s);
+    // deflation = 3: Q_k rounded to FP32 values and used so everywhere (the
+    // deflated operator, U_bar, X, G): eq. smw gives back the same P for any
+    // basis used consistently, and the FP64 inner step reads half the bytes
+    if (h->opts.deflation == 3) cast_f2d(n * (int64_t)keff, h->d_Q32, h->d_Q64, s);
+  }
   if (keff > 0 && h->d_perm) {
     h->d_Qorig = h->ar.alloc<double>(n * (int64_t)keff);
     for (int c = 0; c < keff; ++c)
@@ -733,8 +743,6 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   }
   h->d_alpha = h->ar.upload(alpha.empty() ? std::vector<double>{0.0} : alpha, s);
   if (keff > 0) {
-    h->d_Q32 = h->ar.alloc<float>(n * (int64_t)keff);
-    cast_d2f(n * (int64_t)keff, h->d_Q64, h->d_Q32, s);
     const int64_t npad = ((n + 63) / 64) * 64;
     h->d_Qs64 = h->ar.alloc<double>(npad * keff);
     h->d_Qs32 = h->ar.alloc<float>(npad * keff);
@@ -1450,7 +1458,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     if (opts) o = *opts;
     if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
     if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
-    if (o.deflation < 0 || o.deflation > 2) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1 or 2"};
+    if (o.deflation < 0 || o.deflation > 3) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1, 2 or 3"};
     if (o.reorder < 0 || o.reorder > 4) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1, 2, 3 or 4"};
     if (o.reorder == 3 && !o.inner_perm) throw Error{ASSS_ERR_INVALID_ARG, "reorder 3 needs inner_perm"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
@@ -1641,7 +1649,8 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
                    "[asss] setup n=%lld host %.3fs (pre %.3f, split/pack %.3f) lsqr %.3fs (%d its, kkt %.2e) "
                    "device %.3fs (k_eff %d, r %d, X its %d, orth %.1e, deflation %s)\n",
                    (long long)n, h->setup_host_s, t1 - t0, t3 - t2, t2 - t1, h->lls_its, h->lls_kkt,
-                   t4 - t3, h->k_eff, h->r, h->x_its, h->orth_err, h->defl_rec ? "recurrence" : "explicit");
+                   t4 - t3, h->k_eff, h->r, h->x_its, h->orth_err,
+                   h->defl_rec ? "recurrence" : (h->opts.deflation == 3 ? "explicit, FP32 basis" : "explicit"));
     *out = h.release();
     return ASSS_OK;
   });
@@ -2079,7 +2088,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.lanczos_orth_err = h->orth_err;
     i.narrow_b_columns = h->narrow_b;
     i.skew_form = h->skew_form;
-    i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : 1);
+    i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : (h->opts.deflation == 3 ? 3 : 1));
     i.reordered = h->d_perm ? 1 : 0;
     i.cross_pairs_natural = h->cross_natural;
     i.cross_pairs_used = h->cross_used;

@@ -1010,7 +1010,7 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
 
 // Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
 // 256 threads are resident per CU (1024 on the chip).
-template <typename T, int NR, int KF, bool STAGE, bool REC>
+template <typename T, int NR, int KF, bool STAGE, bool REC, typename TQ = T>
 __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
@@ -1124,12 +1124,14 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     }
     if (!REC) {
       // Q row i streams once: deflation term and Q^T a together (non-temporal
-      // in FP64, where it helps: 161 -> 150 us; in FP32 it costs 124 -> 132 us)
-      const T* __restrict__ qs = reinterpret_cast<const T*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
+      // for an FP64 basis, where it helps: 161 -> 150 us; for an FP32 basis it
+      // costs 124 -> 132 us).  TQ = float in an FP64 kernel: the basis is
+      // stored as FP32 values.
+      const TQ* __restrict__ qs = reinterpret_cast<const TQ*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
 #pragma unroll
       for (int l = 0; l < KF; ++l) {
         T q = T(0);
-        if (l < k) q = (sizeof(T) == 8) ? __builtin_nontemporal_load(&qs[l * 64]) : qs[l * 64];
+        if (l < k) q = (sizeof(TQ) == 8) ? (T)__builtin_nontemporal_load(&qs[l * 64]) : (T)qs[l * 64];
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
           defl[c] += q * cv[c][l];
@@ -1197,9 +1199,18 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
   constexpr bool STAGE = (NR == 1);
   size_t lds = (size_t)J.R * NR * (sizeof(double) + (STAGE ? sizeof(T) : 0));
   const int kf = pick_kf(L.k, NR);
-#define ASSS_ITER(KF)                                                                              \
-  hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false>), dim3(J.nblocks), dim3(WG), lds, s, L, J, \
-                     Q, buf, st, red.partials, red.tickets + 1)
+#define ASSS_ITER(KF)                                                                                  \
+  do {                                                                                                 \
+    if constexpr (sizeof(T) == 8) {                                                                    \
+      if (L.q32) {                                                                                     \
+        hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false, float>), dim3(J.nblocks), dim3(WG), lds, \
+                           s, L, J, Q, buf, st, red.partials, red.tickets + 1);                        \
+        break;                                                                                         \
+      }                                                                                                \
+    }                                                                                                  \
+    hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false>), dim3(J.nblocks), dim3(WG), lds, s, L, J, \
+                       Q, buf, st, red.partials, red.tickets + 1);                                     \
+  } while (0)
   if (L.rec && L.k > 0) {
     hipLaunchKernelGGL((k_mrs_iter<T, NR, 0, STAGE, true>), dim3(J.nblocks), dim3(WG), lds, s, L, J, Q,
                        buf, st, red.partials, red.tickets + 1);

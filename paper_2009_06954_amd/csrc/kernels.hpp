@@ -146,6 +146,9 @@ struct MrsLaunch {
   // G = Q_k^T Q_k (k x k, FP64) of Q_k as stored in the inner precision: the
   // iteration kernel forms Q_k^T q_new as Q_k^T a - sign G c (see k_mrs_iter)
   const double* gram;
+  // 1: Qs holds FP32 values for an FP64 kernel (a deflation basis rounded to
+  // FP32 values at setup, so that the FP32 copy is exact)
+  int q32;
 };
 
 // Initialise: w1 = rhs (col c at rhs + c * ldr), zero the other buffers,

@@ -679,3 +679,44 @@ def test_spmv_kernel_shapes(longrow):
     x, info = p.h.solve(_cuda(b), tol=1e-12)
     assert io["converged"] and info["status"] == "OK" and info["relres_true"] <= 1e-12
     assert _rel(_np(x), xo) <= 1e-9
+
+
+def test_deflation_fp32_basis():
+    """deflation = "explicit_fp32_basis": the Lanczos vectors are rounded to FP32
+    values at setup and that basis is used everywhere.  The exported basis is
+    FP32-valued and within FP32 rounding of the oracle's; the deflated inner
+    operator is J_tilde - Q S_k Q^T with that basis; P^-1 (inner solve run to
+    1e-13) equals the oracle's dense P solved directly, because the SMW term
+    of eq. smw adds back what the deflation takes out, for any basis (Sec. 3.2);
+    FP64, mixed and adjoint solves agree with the oracle's."""
+    asss = _lib()
+    w = W.config(0)
+    n = w.A.shape[0]
+    st = O.setup(w.A, O.SetupOptions(k=8))
+    h = asss.setup(w.A, k=8, deflation="explicit_fp32_basis")
+    info = h.info()
+    assert info["deflation_mode"] == 3 and info["k_eff"] == 8
+    Q = h.array("Q").reshape(8, n).T
+    assert np.array_equal(Q, Q.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(Q - st.Q)) <= 2 ** -24 * np.max(np.abs(st.Q)) * 1.1
+    alpha = h.array("alpha")
+    Sk = np.diag(alpha, 1) - np.diag(alpha, -1)
+    U = sp.csr_matrix((h.array("J_val"), h.array("J_colind"), h.array("J_rowptr")), shape=(n, n))
+    J = (U - U.T).tocsr()
+    rng = np.random.default_rng(31)
+    v = rng.standard_normal(n)
+    out, _ = h.apply("deflated", _cuda(v))
+    ref = J @ v - Q @ (Sk @ (Q.T @ v))
+    assert _rel(_np(out), ref) <= 1e-13
+    z, its = h.apply("prec", _cuda(v), inner_tol=1e-13, inner_maxit=4000)
+    zo = np.linalg.solve(st.prec.dense_P(), v)
+    assert its > 0 and _rel(_np(z), zo) <= 1e-10
+    for fp32 in (False, True):
+        xo, io = O.solve(st, w.b, O.SolveOptions(tol=1e-12))
+        x, inf = h.solve(_cuda(w.b), tol=1e-12 if not fp32 else 1e-8, inner_fp32=fp32)
+        assert inf["status"] == "OK"
+        assert _rel(_np(x), xo) <= (1e-10 if not fp32 else 1e-7)
+    g = rng.standard_normal(n)
+    lo, _ = O.solve_adjoint(st, g, O.SolveOptions(tol=1e-12))
+    lam, inf = h.solve_adjoint(_cuda(g), tol=1e-12)
+    assert inf["status"] == "OK" and _rel(_np(lam), lo) <= 1e-9
