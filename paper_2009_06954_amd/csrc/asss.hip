@@ -328,7 +328,7 @@ void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f, bool rec) {
+MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f, bool rec, bool one_col) {
   MrsLaunch L{};
   L.n = h->n;
   L.nr = nr;
@@ -339,8 +339,10 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f
   L.f = f;
   L.qk1 = (h->k_eff >= 2) ? (const void*)(Q + (int64_t)(h->k_eff - 2) * h->n) : nullptr;
   L.alpha_last = (h->k_eff >= 2) ? h->alpha[h->k_eff - 2] : 0.0;
-  // deflation = 3: the basis holds FP32 values, and the FP64 step reads the FP32 copy
-  L.q32 = (!std::is_same<T, float>::value && h->opts.deflation == 3 && h->k_eff > 0) ? 1 : 0;
+  // deflation = 3: the basis holds FP32 values, and the one-column FP64 step
+  // reads the FP32 copy (the 4-column step reads the FP64 copy of the same values,
+  // which it streams faster)
+  L.q32 = (!std::is_same<T, float>::value && one_col && h->opts.deflation == 3 && h->k_eff > 0) ? 1 : 0;
   L.Qs = (std::is_same<T, float>::value || L.q32) ? (const void*)h->d_Qs32 : (const void*)h->d_Qs64;
   L.gram = std::is_same<T, float>::value ? h->d_G32 : h->d_G64;
   return L;
@@ -354,7 +356,7 @@ int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs
             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s,
             int nc = 1) {
   Range range(NR == 1 ? "asss:inner mrs" : "asss:inner mrs (4 columns)");
-  MrsLaunch L = make_launch<T>(h, nc, sign, Q, f, NR == 1 && h->defl_rec != 0);
+  MrsLaunch L = make_launch<T>(h, nc, sign, Q, f, NR == 1 && h->defl_rec != 0, NR == 1);
   if (J.nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
   mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
   if constexpr (NR == 1) {
@@ -804,7 +806,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     for (int c0 = 0; c0 < kr; c0 += (use4 ? NRMAX : 1)) {
       const int nc = use4 ? std::min(NRMAX, kr - c0) : 1;
       if (use4) {
-        MrsLaunch L = make_launch<double>(h, nc, +1, h->d_Q64, h->d_f64, false);
+        MrsLaunch L = make_launch<double>(h, nc, +1, h->d_Q64, h->d_f64, false, false);
         mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_perm, h->d_Q64, mb4, h->d_state,
                                 h->opts.x_tol, h->opts.x_maxit, 0, h->red, s);
         int group_its = -1;
