@@ -317,7 +317,7 @@ def main():
     args = ap.parse_args()
     args.autotune = (args.autotune == "on") if args.autotune else bool(args.batched)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
