@@ -1017,13 +1017,13 @@ struct FgmresCol {
   }
 
   void after_prec(int its) {
+    Range range("asss:outer step");  // the whole Arnoldi step, GPU work and host round trip
     arnoldi_enqueue(its);
     HIPCHK(hipStreamSynchronize(s));
     arnoldi_finish();
   }
 
   void arnoldi_finish() {
-    Range range("asss:outer step");
     double* hbuf = h->d_small + slot * SM_COL;
     const double* hh = h->h_small + slot * SM_COL;
     double* vn = V + (int64_t)(j + 1) * n;
@@ -1175,6 +1175,7 @@ asss_status_t fgmres_block(asss_handle_s* h, int nc, const double* const* B, dou
                                    o.inner_maxit, o.fixed_inner_steps, s, na);
     // every active column's Arnoldi step goes on the stream, then one host
     // round trip serves them all
+    Range range("asss:outer steps (lockstep columns, with their SMW terms)");
     for (int i = 0; i < na; ++i) {
       FgmresCol& c = cols[act[i]];
       double* z = c.z_next();
