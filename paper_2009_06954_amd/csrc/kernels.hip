@@ -784,19 +784,49 @@ struct MrsTail {
   double gram[KF1 * KF1];
 };
 
+// The tail's values in registers: every thread loads at most one column-state
+// word, one c, one alpha and NG Gram entries.  Loaded at the start of a launch
+// and written to LDS after the block's w is staged, so that these loads
+// overlap the staging loads instead of adding round trips of their own.
+template <int NR, int KF>
+struct MrsTailRegs {
+  static constexpr int NC = NR * (int)sizeof(MrsCol) / 8;
+  static constexpr int KF1 = KF > 0 ? KF : 1;
+  static constexpr int NG = (KF1 * KF1 + WG - 1) / WG;
+  static_assert(NC <= WG && NR * KF1 <= WG && KF1 <= WG, "one tail word per thread");
+  double col, cvt, alpha, gram[NG];
+};
+
 template <typename T, int NR, int KF>
-__device__ __forceinline__ void mrs_tail_prefetch(MrsTail<NR, KF>& tl, const MrsState* st, const MrsLaunch& L,
-                                                  bool rec) {
-  const int k = L.k;
-  for (int e = threadIdx.x; e < NR * (int)sizeof(MrsCol) / 8; e += WG)
-    reinterpret_cast<double*>(tl.col)[e] = reinterpret_cast<const double*>(st->col)[e];
-  if (KF > 0 && !rec) {
-    for (int e = threadIdx.x; e < NR * k; e += WG) {
-      const int cc = e / k, l = e % k;
-      tl.cvt[cc][l] = (double)(T)st->cvec[cc * KMAX + l];
-    }
-    for (int e = threadIdx.x; e < k - 1; e += WG) tl.alpha[e] = L.alpha_dev[e];
-    for (int e = threadIdx.x; e < k * k; e += WG) tl.gram[e] = L.gram[e];
+__device__ __forceinline__ void mrs_tail_load(MrsTailRegs<NR, KF>& r, const MrsState* st, const MrsLaunch& L,
+                                              bool rec) {
+  using R = MrsTailRegs<NR, KF>;
+  const int e = threadIdx.x, k = L.k;
+  r.col = e < R::NC ? reinterpret_cast<const double*>(st->col)[e] : 0.0;
+  r.cvt = r.alpha = 0.0;
+#pragma unroll
+  for (int u = 0; u < R::NG; ++u) r.gram[u] = 0.0;
+  if (KF > 0 && !rec && k > 0) {
+    if (e < NR * k) r.cvt = st->cvec[(e / k) * KMAX + e % k];  // rounded to T at the store
+    if (e < k - 1) r.alpha = L.alpha_dev[e];
+#pragma unroll
+    for (int u = 0; u < R::NG; ++u)
+      if (e + u * WG < k * k) r.gram[u] = L.gram[e + u * WG];
+  }
+}
+
+template <typename T, int NR, int KF>
+__device__ __forceinline__ void mrs_tail_store(MrsTail<NR, KF>& tl, const MrsTailRegs<NR, KF>& r, int k,
+                                               bool rec) {
+  using R = MrsTailRegs<NR, KF>;
+  const int e = threadIdx.x;
+  if (e < R::NC) reinterpret_cast<double*>(tl.col)[e] = r.col;
+  if (KF > 0 && !rec && k > 0) {
+    if (e < NR * k) tl.cvt[e / k][e % k] = (double)(T)r.cvt;
+    if (e < k - 1) tl.alpha[e] = r.alpha;
+#pragma unroll
+    for (int u = 0; u < R::NG; ++u)
+      if (e + u * WG < k * k) tl.gram[e + u * WG] = r.gram[u];
   }
 }
 
@@ -1024,9 +1054,11 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   // the end of this one: every thread reads it with uniform (scalar) loads, so
   // the per-column coefficients and the deflation coefficients c live in
   // scalar registers rather than in LDS or vector registers.
+  // Everything below is loaded before the status test, so that the loads go
+  // out together instead of after a round trip for the status (the values
+  // are in bounds and unused when the solve is done).
   const int k = L.k;
   const int status = st->status;
-  if (status == MRS_DONE) return;
   const int t = st->its + 1;
   const bool pend = st->col[0].has_pending != 0;
   constexpr int KF1 = KF > 0 ? KF : 1;
@@ -1045,12 +1077,20 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     cy[c] = (T)col.ra;
     cq[c] = (T)(col.rb * L.alpha_last);
 #pragma unroll
-    for (int l = 0; l < KF1; ++l) cv[c][l] = (KF > 0 && l < k) ? (T)st->cvec[c * KMAX + l] : T(0);
+    for (int l = 0; l < KF1; ++l) {
+      // loaded for every l < KF1 <= KMAX (in bounds) and selected after: a load
+      // under the condition l < k became one scalar load and wait per l, a
+      // chain of 16 round trips at the start of every launch
+      const T v = (T)st->cvec[c * KMAX + l];
+      cv[c][l] = (KF > 0 && l < k) ? v : T(0);
+    }
   }
   const int st_fixed = st->fixed, st_maxit = st->maxit;
   const double st_tol = st->tol;
+  if (status == MRS_DONE) return;
   __shared__ MrsTail<NR, KF> tail;
-  if (status == MRS_RUNNING) mrs_tail_prefetch<T, NR, KF>(tail, st, L, REC);
+  MrsTailRegs<NR, KF> tail_r;
+  if (status == MRS_RUNNING) mrs_tail_load<T, NR, KF>(tail_r, st, L, REC);
   const int64_t n = L.n;
   const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, n - row0);
@@ -1084,6 +1124,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     acc_lds[r] = 0.0;
     if (STAGE) w_lds[r] = wcur[row0 * NR + r];
   }
+  mrs_tail_store<T, NR, KF>(tail, tail_r, k, REC);  // status is MRS_RUNNING here
   __syncthreads();
   skew_block_pass<T, NR, STAGE>(J, row0, nrow, wcur, w_lds, acc_lds);
   __syncthreads();
