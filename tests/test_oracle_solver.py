@@ -183,3 +183,28 @@ def test_initial_guess(cfg0_setup):
     assert info["converged"] and np.linalg.norm(lam - lamd) <= 2 * kappa * 1e-10 * np.linalg.norm(lamd)
     with pytest.raises(ValueError):
         O.solve(st, b, o, x0=np.full(st.n, np.nan))
+
+
+@pytest.mark.parametrize("case", ["cfg0", "neg"])
+def test_smw_preconditioner_does_not_depend_on_the_deflation_basis(case, cfg0_setup, neg_setup):
+    """Eq. smw adds back, through the low-rank term, exactly what the deflation
+    of J_tilde takes out, so P^-1 applied as mrs on I + J_tilde - Q S_k Q^T plus
+    the SMW correction is the inverse of the same P for any basis Q used
+    consistently (Sec. 3.2).  Checked on the Lanczos basis rounded to FP32
+    values and on a basis perturbed by 1e-3 (no longer a Lanczos basis), with
+    and without negative diagonal entries (r = 0 and r > 0): P^-1 v agrees with
+    a dense solve with the unperturbed P.  This is what lets the library store
+    its deflation basis as FP32 values in the FP64 path."""
+    from oracle.precond import Preconditioner
+    st = cfg0_setup if case == "cfg0" else neg_setup
+    assert (st.N.size > 0) == (case == "neg")
+    P = st.prec.dense_P()
+    v = np.random.default_rng(41).standard_normal(P.shape[0])
+    zd = np.linalg.solve(P, v)
+    rng = np.random.default_rng(42)
+    for Q in (st.Q.astype(np.float32).astype(np.float64),
+              st.Q + 1e-3 * rng.standard_normal(st.Q.shape)):
+        pr = Preconditioner(st.prec.Jup, st.N, Q, st.alpha)
+        z, its = pr.apply(v, 1e-14, 5000)
+        assert its > 0
+        assert np.linalg.norm(z - zd) <= 1e-9 * np.linalg.norm(zd)
