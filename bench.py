@@ -6,11 +6,12 @@ One step = one complete solve of A x = b to true relative residual 1e-8
 back-transform and true-residual check), with A, b and all preconditioner
 data resident in HBM when the timed region starts.
 
-Workload (default): 3D convection-diffusion, 7-point first-order upwind on a
-128^3 grid (n = 2,097,152, nnz = 14,581,760), Peclet 100, wind (1, 0.5, 0.25),
-S on the pattern of Abar, k = 16 skew-Lanczos vectors, b = A x*, x* ~ U(-1,1).
-The plain FP64 solve is the headline value; the FP32-inner / FP64-outer solve
-of the same system is reported beside it.
+Workload (default, the precision workload): 3D convection-diffusion, 7-point
+first-order upwind on a 192^3 grid (n = 7,077,888, nnz = 49,324,032), Peclet
+1000, wind (1, 0.5, 0.25), S on the pattern of Abar, k = 16 skew-Lanczos
+vectors, b = A x*, x* ~ U(-1,1) (seeded draw of that workload).  The plain
+FP64 solve is the headline value; the FP32-inner / FP64-outer solve of the
+same system is reported beside it, each with the roofline of the inner step.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -45,60 +46,96 @@ def mrs_bytes_per_row(nh_per_row: float, k: int, v: int, vq: int = 0) -> float:
     return nh_per_row * (v + 4) + 4 + k * (vq or v) + 10 * v
 
 
-def measured_traffic(precision: str, order: str, m: int):
-    """HBM bytes per full inner step from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary for this order of the inner system, if it was taken on
-    the kernel source as it is now (the 128^3 workload only)."""
-    if m != 128:
-        return None
+def workload_key(m: int, peclet: float, k: int, order: str) -> str:
+    """Name of the committed profile summaries of one workload and inner order."""
     suffix = {"x-line tiles 4x4": "_linetiles4x4", "library grid order": "_gridorder"}.get(order, "")
-    path = os.path.join(ROOT, "profiles", f"k_mrs_iter_convdiff3d_128_Pe100_k16{suffix}_traffic.json")
+    return f"convdiff3d_{m}_Pe{peclet:g}_k{k}{suffix}"
+
+
+def kernel_sha() -> str:
+    with open(os.path.join(ROOT, "paper_2009_06954_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(precision: str, key: str, deflation: str = "explicit"):
+    """HBM bytes per full inner step from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload (profiles/k_mrs_iter_<key>_traffic.json),
+    if it was taken on the kernel source as it is now and for this form of the
+    deflation basis; None otherwise."""
+    name = key + ("_fp32basis" if deflation == "explicit_fp32_basis" else "")
+    path = os.path.join(ROOT, "profiles", f"k_mrs_iter_{name}_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_2009_06954_amd", "csrc", "kernels.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_sha()
     except OSError:
         return None
     if rec.get("kernel_src_sha256") != sha or precision not in rec.get("kernels", {}):
         return None  # counters predate the current kernel
-    if rec.get("inner_order", "natural") != order:
-        return None
     return rec["kernels"][precision]["hbm_bytes"]
 
 
-def cpu_baseline(m_sample: int, peclet: float, k: int, tol: float, n_full: int, inner_full: int,
-                 inner_tol: float, restart: int):
-    """The oracle (unchanged) timed on a smaller instance of the same workload
-    family; scaled to the full problem by rows and by total inner iterations."""
-    from threadpoolctl import threadpool_limits
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown"
 
+
+def oracle_solve_time(m: int, peclet: float, cfg: int, k: int, tol: float, inner_tol: float,
+                      restart: int, repeats: int = 3):
+    """The oracle (unchanged) on an m^3 instance of the workload family: setup
+    once (not timed), then the best of `repeats` solves."""
     import oracle as O
     import workloads as W
 
-    w = W.convdiff3d(m=m_sample, peclet=peclet, cfg=1)
-    with threadpool_limits(limits=1):
+    w = W.convdiff3d(m=m, peclet=peclet, cfg=cfg)
+    t0 = time.perf_counter()
+    st = O.setup(w.A, O.SetupOptions(k=k, s_pattern="abar"))
+    setup_s = time.perf_counter() - t0
+    best, info = float("inf"), None
+    for _ in range(repeats):
         t0 = time.perf_counter()
-        st = O.setup(w.A, O.SetupOptions(k=k, s_pattern="abar"))
-        t1 = time.perf_counter()
-        x, info = O.solve(st, w.b, O.SolveOptions(tol=tol, inner_tol=inner_tol, restart_m=restart))
-        t2 = time.perf_counter()
-    n_s = w.A.shape[0]
-    inner_s = max(1, info["inner_its_total"])
-    scale = (n_full / n_s) * (inner_full / inner_s)
-    cpu = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+        _, info = O.solve(st, w.b, O.SolveOptions(tol=tol, inner_tol=inner_tol, restart_m=restart))
+        best = min(best, time.perf_counter() - t0)
+    return {"m": m, "n": int(w.A.shape[0]), "solve_s": round(best, 4), "setup_s": round(setup_s, 2),
+            "outer_its": int(info["outer_its"]), "inner_its": int(info["inner_its_total"]),
+            "relres": float(info["relres_true"])}
+
+
+def unit_cost(run: dict) -> float:
+    """Oracle seconds per (row x inner step): the inner mrs dominates the
+    solve, and its work per step is proportional to n."""
+    return run["solve_s"] / (run["n"] * max(1, run["inner_its"]))
+
+
+def cpu_baseline(sizes, peclet: float, cfg: int, k: int, tol: float, n_full: int, inner_full: int,
+                 inner_tol: float, restart: int):
+    """The oracle timed at two sizes of the same workload family on the host's
+    cores (NumPy/SciPy as installed: sparse products on one thread, dense
+    products on the BLAS thread pool).  The cost per (row x inner step) of the
+    smaller size predicts the larger one (the check); the larger one's
+    extrapolates to the full problem with the GPU solve's inner step count."""
+    from threadpoolctl import threadpool_info
+
+    runs = [oracle_solve_time(m, peclet, cfg, k, tol, inner_tol, restart) for m in sizes]
+    small, large = runs[0], runs[-1]
+    predicted = unit_cost(small) * large["n"] * large["inner_its"]
+    pools = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
+    threads = max([p["threads"] or 1 for p in pools] + [1])
+    value = unit_cost(large) * n_full * inner_full
     return {
-        "value": (t2 - t1) * scale, "unit": "s", "cores": 1, "kind": "oracle",
-        "cpu_model": cpu, "host_cpu_count": os.cpu_count(), "setup_s_sample": round(t1 - t0, 2),
-        "sample": (f"oracle solve of convdiff3d {m_sample}^3 Pe{peclet:g} (n={n_s}) took "
-                   f"{t2 - t1:.2f} s ({info['outer_its']} outer / {info['inner_its_total']} inner its, "
-                   f"relres {info['relres_true']:.1e}; setup {t1 - t0:.1f} s not counted), scaled by "
-                   f"rows x total inner iterations to n={n_full}, {inner_full} inner its"),
+        "value": round(value, 2), "unit": "s", "cores": threads, "kind": "oracle",
+        "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count(), "threadpools": pools,
+        "runs": runs,
+        "fit": {"model": "t = c * n * inner_its", "c_s": unit_cost(large),
+                "check": {"predicted_large_from_small_s": round(predicted, 4),
+                          "measured_large_s": large["solve_s"],
+                          "ratio": round(predicted / large["solve_s"], 3)}},
+        "sample": (f"oracle solves of convdiff3d m^3 Pe{peclet:g} for m in {list(sizes)} "
+                   f"(best of 3, setup not timed); extrapolated to n={n_full} with the GPU's "
+                   f"{inner_full} inner steps from the larger sample's cost per row and step"),
     }
 
 
@@ -162,61 +199,6 @@ def batched(args, asss, torch, np, W):
     print(json.dumps(res), flush=True)
 
 
-# Table 5 of the paper: tfqmr outer iterations (average inner mrs iterations)
-# with ~ildl(0), its closest configuration to the diagonal-only preconditioner
-# here; Matlab, FP64, hardware not stated.  Context only: the stand-ins below
-# share the matrices' sizes and densities, not their entries.
-TABLE5_ILDL0 = {"bp_200": (26, 53.6), "bp_600": (15, 65.7), "west0989": (74, 134.6), "rajat19": (10, 35.6),
-                "rdb1250l": (90, 66.7), "west1505": (57, 162.9), "chebyshev2": (10, 15.9),
-                "orani678": (15, 229.3), "rdb3200l": (9, 63.6), "rdb5000": (8, 100.6)}
-
-
-def table5(args, asss, torch, np, W):
-    """The paper's experimental settings (Sec. 4.1: k = 20, S tridiagonal,
-    gamma = 1, b = A ones, outer and inner tolerance 1e-5, at most 2000 outer
-    iterations) on the stand-in family: TFQMR and FGMRES outer / average inner
-    iterations and GPU time per solve, the inner iterations saved by the
-    deflation (k = 20 against k = 0), next to Table 5's numbers."""
-    rows = []
-    for w in W.paper_like_family():
-        name = w.name.split("_n")[0].replace("like_", "")
-        n = w.A.shape[0]
-        b = torch.from_numpy(w.b).cuda()
-        row = {"matrix": name, "n": n, "nnz": int(w.A.nnz), "paper_tfqmr_ildl0": TABLE5_ILDL0.get(name)}
-        for k in (20, 0):
-            h = asss.setup(w.A, k=k, s_pattern="tridiag", gamma=1.0)
-            if k == 20:
-                row["rank_r"] = h.info()["rank_r"]
-            for outer in ("tfqmr", "fgmres"):
-                kw = dict(tol=1e-5, inner_tol=1e-5, max_outer=4000 if outer == "tfqmr" else 2000,
-                          restart_m=64, outer=outer)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                x, inf = h.solve(b, **kw)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                its = inf["outer_its"]
-                # TFQMR counts half steps; one full step = two half steps (reading)
-                outer_count = its / 2 if outer == "tfqmr" else its
-                row[f"{outer}_k{k}"] = {"status": inf["status"], "outer": outer_count,
-                                        "avg_inner": round(inf["inner_its_total"] / max(1, its), 1),
-                                        "relres": inf["relres_true"], "ms": round(1e3 * dt, 2)}
-            h.close()
-        f20, f0 = row["fgmres_k20"], row["fgmres_k0"]
-        row["deflation_inner_saving"] = round(1 - f20["avg_inner"] / max(f0["avg_inner"], 1e-9), 3)
-        log(f"{name}: tfqmr {row['tfqmr_k20']} fgmres {row['fgmres_k20']}")
-        rows.append(row)
-    savings = [r["deflation_inner_saving"] for r in rows]
-    res = {"metric": "paper's experimental settings on the stand-in family (context for Table 5)",
-           "value": round(float(np.mean(savings)), 3), "unit": "mean fraction of inner mrs iterations "
-           "saved by k = 20 deflation (FGMRES); the paper reports 0.308 on its matrices",
-           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic stand-ins",
-           "config": {"workload": "paper_like_family", "k": 20, "s_pattern": "tridiag", "gamma": 1.0,
-                      "tol": 1e-5, "inner_tol": 1e-5},
-           "rows": rows}
-    print(json.dumps(res), flush=True)
-
-
 def grad_bench(args, asss, torch, np, W):
     """Forward + backward of L = ||A^-1 b - x_t||^2 at n = 1e6 (A's values and b
     require gradients); the preconditioner is built once from A."""
@@ -262,20 +244,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=128, help="grid points per axis")
-    ap.add_argument("--peclet", type=float, default=100.0)
+    ap.add_argument("--m", type=int, default=192, help="grid points per axis")
+    ap.add_argument("--peclet", type=float, default=1000.0)
+    ap.add_argument("--cfg", type=int, default=None,
+                    help="seed of the x* draw (workload number): 2 for the 192^3 Pe 1000 precision "
+                         "workload, 1 for the 128^3 Pe 100 one; default: 2 unless --m 128 --peclet 100")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=200, help="FGMRES restart length")
     ap.add_argument("--inner-tol", type=float, default=0.2,
-                    help="inner mrs tolerance (0.2 minimises time-to-solution on the default workload)")
+                    help="inner mrs tolerance (0.2 minimises time-to-solution on the 3D workloads)")
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer iterations (profiling runs only; the result then does not reach tol)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32-basis", action="store_true",
-                    help="skip the extra FP64 solve with the FP32-valued deflation basis")
-    ap.add_argument("--cpu-sample-m", type=int, default=24)
+    ap.add_argument("--fp32-basis-solve", action="store_true",
+                    help="also run the FP64 solve with the FP32-valued deflation basis (a second setup)")
+    ap.add_argument("--cpu-sizes", type=int, nargs=2, default=[16, 24],
+                    help="grid sizes of the two oracle runs of the CPU baseline")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="profiling probe: setup, a 1 GiB device copy (counter calibration), then "
@@ -297,29 +283,26 @@ def main():
     ap.add_argument("--deflation", default="explicit", choices=["explicit", "explicit_fp32_basis"],
                     help="explicit_fp32_basis: the Lanczos vectors rounded to FP32 values and used so "
                          "everywhere (same preconditioner, FP64 arithmetic, half the basis bytes)")
-    ap.add_argument("--table5", action="store_true",
-                    help="the paper's experimental settings (k = 20, S tridiagonal, tol 1e-5, b = A ones) on "
-                         "the stand-in family: TFQMR and FGMRES iteration counts next to Table 5")
     ap.add_argument("--inner-order", choices=["natural", "tiles", "grid"], default="grid",
                     help="order of the inner system (a symmetric permutation of J_tilde that the "
                          "solution does not depend on): the library's own tiles of whole x-lines for a "
-                         "detected 3D grid (reorder='grid', default; 4 x 4 lines per tile at 128^3), tiles "
-                         "passed by the caller (--tile TYxTZ lines per tile, one tile per row block), or "
-                         "the grid's natural order")
+                         "detected 3D grid (reorder='grid', default), tiles passed by the caller (--tile "
+                         "TYxTZ lines per tile, one tile per row block), or the grid's natural order")
     ap.add_argument("--tile", default="4x4")
-    ap.add_argument("--no-natural", action="store_true",
-                    help="with tiles: skip the comparison solves in the natural order")
+    ap.add_argument("--natural", action="store_true",
+                    help="also run one solve per precision with the inner system in the natural order")
     ap.add_argument("--autotune", choices=["on", "off"], default=None,
                     help="row-block autotuner at setup (times the inner step for several row-block "
-                         "sizes and keeps the fastest).  Default: on for --batched (it picks larger "
-                         "blocks than the automatic size for most of the small systems), off for the "
-                         "128^3 workload (where it keeps the automatic 2048)")
+                         "sizes and keeps the fastest).  Default: on for --batched, off for the 3D "
+                         "workloads")
     args = ap.parse_args()
     args.autotune = (args.autotune == "on") if args.autotune else bool(args.batched)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.cfg is None:
+        args.cfg = 1 if (args.m == 128 and args.peclet == 100.0) else 2
 
     import numpy as np
     import torch
@@ -336,10 +319,8 @@ def main():
         return batched(args, asss, torch, np, W)
     if args.grad:
         return grad_bench(args, asss, torch, np, W)
-    if args.table5:
-        return table5(args, asss, torch, np, W)
-    log(f"building workload m={args.m} Pe={args.peclet}")
-    w = W.convdiff3d(m=args.m, peclet=args.peclet, cfg=1)
+    log(f"building workload m={args.m} Pe={args.peclet:g} (seed of workload {args.cfg})")
+    w = W.convdiff3d(m=args.m, peclet=args.peclet, cfg=args.cfg)
     n, nnz = w.A.shape[0], w.A.nnz
     log(f"n={n} nnz={nnz}; setup (host preprocessing + device data)")
     t0 = time.perf_counter()
@@ -359,19 +340,26 @@ def main():
     setup_s = time.perf_counter() - t0
     hi = h.info()
     log(f"setup {setup_s:.2f} s: {hi}")
+    key = workload_key(args.m, args.peclet, args.k, order_name)
     b = torch.from_numpy(w.b).cuda()
     xs = torch.from_numpy(w.x_star).cuda()
     x = torch.empty_like(b)
-    if args.probe:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+
+    def copy_rate():
+        # practical roof: a 1 GiB device-to-device copy (read + write), best of
+        # 5, HIP events on torch's stream, outside any timed region
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        copy_ms = []
+        ms = []
         for _ in range(5):
             ev[0].record(); dst.copy_(src); ev[1].record(); torch.cuda.synchronize()
-            copy_ms.append(ev[0].elapsed_time(ev[1]))
-        out = {"probe": True, "copy_bytes": 2 * src.numel() * 4,
-               "copy_GBs": round(2 * src.numel() * 4 / (min(copy_ms) * 1e-3) / 1e9, 1)}
+            ms.append(ev[0].elapsed_time(ev[1]))
+        return 2 * src.numel() * 4, round(2 * src.numel() * 4 / (min(ms) * 1e-3) / 1e9, 1)
+
+    if args.probe:
+        copy_bytes, copy_gbs = copy_rate()
+        out = {"probe": True, "workload": key, "copy_bytes": copy_bytes, "copy_GBs": copy_gbs}
         for mixed in (False, True):
             h.apply("mrs", b, fixed_inner_steps=5, inner_fp32=mixed)
             torch.cuda.synchronize()
@@ -379,6 +367,7 @@ def main():
             h.apply("mrs", b, fixed_inner_steps=args.probe_steps, inner_fp32=mixed)
             torch.cuda.synchronize()
             out["mrs_fp32" if mixed else "mrs_fp64"] = round((time.perf_counter() - t0) / args.probe_steps * 1e6, 1)
+            log(f"probe {'fp32' if mixed else 'fp64'}: {out['mrs_fp32' if mixed else 'mrs_fp64']} us per step")
         out["handle"] = hi
         h.close()
         print(json.dumps(out), flush=True)
@@ -405,7 +394,7 @@ def main():
                 f"inner {inf['inner_its_total']}, relres {inf['relres_true']:.2e}, status {inf['status']}")
         return total, infos, err
 
-    def roofline(infos, v):
+    def roofline(infos, v, deflation):
         # kernel time of every launch (HIP events around each chunk of back-to-back
         # launches on the solve's stream); bytes only for the full steps (a solve
         # also launches one deferred-update step and, when its chunk overshoots,
@@ -414,12 +403,10 @@ def main():
         launches = sum(i["inner_launches"] for i in infos)
         steps = sum(i["inner_its_total"] for i in infos)
         avg = kern_s / max(1, launches)
-        bpr = mrs_bytes_per_row(hi["nh"] / n, hi["k_eff"], v, 4 if args.deflation == "explicit_fp32_basis" else v)
+        bpr = mrs_bytes_per_row(hi["nh"] / n, hi["k_eff"], v, 4 if deflation == "explicit_fp32_basis" else v)
         per_step = bpr * n
         achieved = per_step * steps / kern_s / 1e9
-        # the committed counters are those of the default deflation form
-        traffic = (measured_traffic("fp64" if v == 8 else "fp32", order_name, args.m)
-                   if args.deflation == "explicit" else None)
+        traffic = measured_traffic("fp64" if v == 8 else "fp32", key, deflation)
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per full step (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -429,18 +416,7 @@ def main():
                 "bytes_per_step": int(per_step), "bytes_per_row": round(bpr, 1),
                 "avg_launch_us": round(avg * 1e6, 2), "launches": launches, "full_steps": steps}
 
-    # practical roof: a 1 GiB device-to-device copy (read + write), best of 5,
-    # HIP events on torch's stream, outside the timed region
-    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    copy_ms = []
-    for _ in range(5):
-        ev[0].record(); dst.copy_(src); ev[1].record(); torch.cuda.synchronize()
-        copy_ms.append(ev[0].elapsed_time(ev[1]))
-    copy_gbs = round(2 * src.numel() * 4 / (min(copy_ms) * 1e-3) / 1e9, 1)
-    del src, dst
-
+    _, copy_gbs = copy_rate()
     total64, inf64, err64 = run(False, args.steps, args.warmup)
     t64 = total64 / args.steps
     x64 = x.clone()
@@ -453,7 +429,7 @@ def main():
                    "outer": f"fgmres({args.restart})" if args.outer == "fgmres" else "tfqmr",
                    "inner_tol": args.inner_tol, "row_block": hi["row_block"],
                    "inner_order": order_name, "deflation": args.deflation},
-        "roofline": roofline(inf64, 8),
+        "roofline": roofline(inf64, 8, args.deflation),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
                   "reorth_passes": inf64[-1]["reorth"],
                   "relres_true": inf64[-1]["relres_true"], "rel_err_vs_xstar": err64,
@@ -469,30 +445,30 @@ def main():
     if not args.no_mixed:
         total32, inf32, err32 = run(True, args.steps, args.warmup)
         t32 = total32 / args.steps
-        res["mixed"] = {"value": round(t32, 5), "unit": "s", "dtype": "f32 inner / f64 outer",
-                        "speedup_vs_fp64": round(t64 / t32, 3), "roofline": roofline(inf32, 4),
+        res["mixed"] = {"value": round(t32, 5), "unit": "s",
+                        "dtype": "f32 storage, f64 accumulation inner / f64 outer",
+                        "speedup_vs_fp64": round(t64 / t32, 3), "roofline": roofline(inf32, 4, args.deflation),
                         "outer_its": inf32[-1]["outer_its"], "inner_its": inf32[-1]["inner_its_total"],
                         "relres_true": inf32[-1]["relres_true"], "rel_err_vs_xstar": err32,
                         "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
                         "solve_s_per_step": [round(i["solve_s"], 4) for i in inf32]}
-    if args.inner_order != "natural" and not args.no_natural:
-        # the same solves with the inner system in the grid's natural order
+    if args.natural and args.inner_order != "natural":
         log("natural order of the inner system: setup and one solve per precision")
         hn = asss.setup(w.A, k=args.k, s_pattern="abar", deflation=args.deflation)
         nat = {"row_block": hn.info()["row_block"]}
         for mixed in ([False] if args.no_mixed else [False, True]):
             tn, infn, _ = run(mixed, 1, 1, h=hn)
-            key = "mixed" if mixed else "fp64"
-            nat[key + "_s"] = round(tn, 5)
-            nat[key + "_avg_launch_us"] = round(1e6 * infn[-1]["inner_kernel_s"] / max(1, infn[-1]["inner_launches"]), 2)
-            nat[key + "_inner_its"] = infn[-1]["inner_its_total"]
+            kk = "mixed" if mixed else "fp64"
+            nat[kk + "_s"] = round(tn, 5)
+            nat[kk + "_avg_launch_us"] = round(1e6 * infn[-1]["inner_kernel_s"] / max(1, infn[-1]["inner_launches"]), 2)
+            nat[kk + "_inner_its"] = infn[-1]["inner_its_total"]
         hn.close()
         nat["speedup_of_order_fp64"] = round(nat["fp64_s"] / t64, 3)
         res["natural_order"] = nat
-    if args.deflation == "explicit" and not args.no_fp32_basis:
+    if args.fp32_basis_solve and args.deflation == "explicit":
         # the FP64 solve with the deflation basis rounded to FP32 values (same
         # preconditioner P, FP64 arithmetic; the FP64 inner step reads the basis
-        # as 4-byte values): reported beside the headline, which keeps the FP64 basis
+        # as 4-byte values)
         log("FP64 solve with the FP32-valued deflation basis: setup and the same steps")
         tq0 = time.perf_counter()
         hq = asss.setup(w.A, k=args.k, s_pattern="abar", deflation="explicit_fp32_basis",
@@ -501,29 +477,22 @@ def main():
         setup_q = time.perf_counter() - tq0
         tq, infq, errq = run(False, args.steps, args.warmup, h=hq)
         tq /= args.steps
-        kq = sum(i["inner_kernel_s"] for i in infq)
-        lq = sum(i["inner_launches"] for i in infq)
-        sq = sum(i["inner_its_total"] for i in infq)
-        bq = mrs_bytes_per_row(hi["nh"] / n, hi["k_eff"], 8, 4) * n
         res["fp64_fp32_basis"] = {
             "value": round(tq, 5), "unit": "s", "dtype": "f64", "deflation": "explicit_fp32_basis",
-            "speedup_vs_fp64": round(t64 / tq, 3),
+            "speedup_vs_fp64": round(t64 / tq, 3), "roofline": roofline(infq, 8, "explicit_fp32_basis"),
             "outer_its": infq[-1]["outer_its"], "inner_its": infq[-1]["inner_its_total"],
             "relres_true": infq[-1]["relres_true"], "rel_err_vs_xstar": errq,
             "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
-            "avg_launch_us": round(1e6 * kq / max(1, lq), 2),
-            "bytes_per_row": round(bq / n, 1),
-            "achieved_GBs": round(bq * sq / kq / 1e9, 1),
             "solve_s_per_step": [round(i["solve_s"], 4) for i in infq], "setup_s": round(setup_q, 2)}
         hq.close()
+    h.close()
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on convdiff3d {args.cpu_sample_m}^3")
+        log(f"cpu baseline: oracle on convdiff3d {args.cpu_sizes[0]}^3 and {args.cpu_sizes[1]}^3")
         try:
-            res["cpu_baseline"] = cpu_baseline(args.cpu_sample_m, args.peclet, args.k, args.tol, n,
+            res["cpu_baseline"] = cpu_baseline(args.cpu_sizes, args.peclet, args.cfg, args.k, args.tol, n,
                                                inf64[-1]["inner_its_total"], args.inner_tol, args.restart)
         except Exception as e:  # the baseline must not hide the GPU result
             res["cpu_baseline"] = {"value": None, "error": repr(e)}
-    h.close()
     print(json.dumps(res), flush=True)
 
 

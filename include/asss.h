@@ -119,13 +119,9 @@ typedef struct {
   int32_t deflation;       /* how the inner step applies Q_k S_k Q_k^T (Sec. 3.2):
                               0 or 1 = explicitly: Q_k^T q recomputed from the k Lanczos
                                   vectors every step (default);
-                              2 = by the Lanczos relation J_tilde Q_k = Q_k S_k + f e_k^T,
-                                  which with Q_k^T Q_k = I keeps Q_k^T q_t in
-                                  span{Q_k^T q_1, e_k} (three vectors per step instead of k).
-                                  Numerically unstable: rounding components along the
-                                  deflated directions are never re-projected and grow by
-                                  ~3x per step on the 3D convection-diffusion workload;
-                                  only accepted when max|Q_k^T Q_k - I| <= 1e-10, else 1;
+                              2 = not provided (INVALID_ARG): a form that keeps Q_k^T q_t
+                                  through the Lanczos relation instead of the k vectors
+                                  loses orthogonality within a few dozen steps;
                               3 = explicitly, with the Lanczos vectors rounded to FP32
                                   values at setup and that basis used everywhere (the
                                   deflated inner operator, U_bar, X, G): the SMW form of
@@ -138,12 +134,7 @@ typedef struct {
   int32_t reorder;         /* order of the inner system (a symmetric permutation of
                               J_tilde, invisible to the caller):
                               0 or 1 = natural order (default);
-                              2 = compact blocks of row_block rows by recursive BFS
-                                  bisection of the graph of J_tilde, so that fewer
-                                  pairs (i,j) straddle two blocks.  On the 3D
-                                  convection-diffusion workload this stores 22 % fewer
-                                  skew entries but is slower, because neighbours no
-                                  longer sit at a common offset across a wavefront;
+                              2 = not provided (INVALID_ARG);
                               3 = the caller's order in inner_perm.  For a grid, an
                                   order in which each block of row_block rows is a
                                   compact tile of whole grid lines keeps more pairs
@@ -153,17 +144,18 @@ typedef struct {
                                   of Abar is a lexicographic 3D grid (positive column
                                   offsets exactly 1, m1 and m1 m2, with m1 m2 | n),
                                   tiles of ty x tz whole x-lines, ty tz the largest
-                                  power of two with m1 ty tz <= the automatic row
-                                  block (or row_block if given) and a multiple of
-                                  64, ty | m2, tz | m3, as square as possible, one
-                                  tile per row block; otherwise the natural order */
+                                  power of two with m1 ty tz <= 1.5 times the
+                                  automatic row block (or row_block if given) and a
+                                  multiple of 64 within 4096, ty | m2, tz | m3, as
+                                  square as possible, one tile per row block (4 x 4
+                                  lines at 128^3 and 192^3); otherwise the natural
+                                  order */
   const asss_allocator_t* allocator; /* device memory of the handle; NULL = hipMalloc / hipFree */
-  int32_t autotune;        /* row-block autotuner (only with row_block = 0; reorder = 2 is
-                              rejected):
+  int32_t autotune;        /* row-block autotuner (only with row_block = 0):
                               0 = the automatic size (default);
                               1 = at the end of setup, pack J_tilde for the automatic size
                                   and up to two halvings and doublings of it within
-                                  [64, 2048], time the fused inner step on each (HIP events,
+                                  [64, 4096], time the fused inner step on each (HIP events,
                                   the handle's deflation and default inner precision, one
                                   right-hand side) and keep the fastest layout.  Costs one
                                   host packing and a few ms of GPU time per candidate;
@@ -183,6 +175,21 @@ typedef struct {
                               3 = offset slots: every slot of a 64-row slice is one offset
                                   d (column = row + d), no per-entry columns; INVALID_ARG
                                   if that stores more than 16x the entries */
+  const double* s_val;     /* NULL (default): S solves the least-squares problem of App. A.
+                              Else host array of the values of S on its pattern (CSR order
+                              of the pattern that s_pattern selects, columns increasing),
+                              read during setup only; the least-squares solve is skipped
+                              and S is taken as given (e.g. an S computed earlier for the
+                              same pattern).  NONFINITE if a value is NaN/Inf */
+  const double* q_basis;   /* NULL (default): the deflation basis Q_k comes from k - 1 steps
+                              of skew-Lanczos (Fig. 2) from the SplitMix64 start vector.
+                              Else host array, n x k column-major in A's row order, with
+                              q_alpha (k - 1 values): Q_k and the coefficients of S_k are
+                              taken as given and the Lanczos run is skipped (k_eff = k).
+                              Any basis gives the same preconditioner P through eq. smw;
+                              the basis only changes how fast the inner solve converges.
+                              Read during setup only; NONFINITE on NaN/Inf */
+  const double* q_alpha;   /* with q_basis: super-diagonal of S_k (k - 1 values) */
 } asss_setup_opts_t;
 
 typedef struct {
@@ -327,7 +334,7 @@ typedef struct {
   int64_t sell_entries_a, sell_entries_b; /* stored skew entries: in-block upper, off-block both */
   double lls_relres, lls_kkt;             /* LSQR stopping quantities */
   double lanczos_orth_err;                /* max |Q_k^T Q_k - I| */
-  int32_t deflation_mode;                 /* 0 none, 1 explicit, 2 recurrence, 3 explicit with the FP32-valued basis */
+  int32_t deflation_mode;                 /* 0 none, 1 explicit, 3 explicit with the FP32-valued basis */
   int32_t reordered;                      /* 1 if the inner system uses block order */
   int64_t cross_pairs_natural;            /* strictly upper pairs straddling two row blocks */
   int64_t cross_pairs_used;               /* the same in the order used */

@@ -13,10 +13,9 @@ Readings:
   printed in eq. regularized double counts pairs and diagonal terms).
 * The least-squares solution is the minimum-norm one (the appendix uses a
   sparse backslash, which agrees whenever B has full column rank).
-* Equations are ordered as the appendix orders them (pairs in column-major
-  order of the upper pattern, then the n diagonal rows); unknowns are the
-  pattern entries of S in column-major order.  Neither order changes the
-  solution.
+* Equations are numbered pairs first (by (min, max) index), then the n
+  diagonal ones; unknowns are the pattern entries of S in CSR order.  Neither
+  order changes the solution.
 """
 from __future__ import annotations
 
@@ -54,56 +53,49 @@ def _spones(M) -> sp.csr_matrix:
 
 
 def build_lls(Abar: sp.csr_matrix, Spat: sp.csr_matrix, gamma: float):
-    """Least-squares matrix B and right-hand side v of App. A, built entry by
-    entry.  Returns (B, v, unknown_rows, unknown_cols), the last two giving the
-    (k, j) position in S of every unknown (column-major order)."""
+    """Least-squares matrix B and right-hand side v of the skew-symmetrizer
+    problem (Sec. 2; App. A gives the same equations), from the linear map
+    s -> Abar S.
+
+    The unknowns are the pattern entries s_u = S[k_u, j_u] (CSR order of the
+    pattern).  Entry (i, j) of Abar S is sum_k abar_ik s_kj, so unknown u
+    contributes abar_{i k_u} to every entry (i, j_u) with abar_{i k_u} != 0:
+    that is the matrix M of the map, one row per structural entry of Abar S.
+    The equations are
+      * one per unordered pair {i, j}, i != j, with (i, j) or (j, i) in the
+        structural pattern of Abar S: row M_(i,j) + M_(j,i), right-hand side 0;
+      * one per i: sqrt(gamma) M_(i,i), right-hand side sqrt(gamma).
+    Pairs are numbered by (min, max) in increasing order, then the n diagonal
+    equations.  Returns (B, v, unknown_rows, unknown_cols)."""
     n = Abar.shape[0]
-    AA = _spones(Abar) @ _spones(Spat)                 # pattern of Abar S
-    U = sp.triu(AA + AA.T, 1).tocsc()
-    U.sort_indices()
-    # equations: column-major order of the strictly upper pattern
-    eq_j = np.repeat(np.arange(n), np.diff(U.indptr))
-    eq_i = U.indices.copy()
-    neq = eq_i.size
-    # unknowns: column-major order of the S pattern
-    Sc = sp.csc_matrix(Spat)
-    Sc.sort_indices()
-    unk_col = np.repeat(np.arange(n), np.diff(Sc.indptr))
-    unk_row = Sc.indices.copy()
+    P = sp.csr_matrix(Spat)
+    P.sort_indices()
+    unk_row = np.repeat(np.arange(n), np.diff(P.indptr))
+    unk_col = P.indices.astype(np.int64)
     nu = unk_row.size
-    index_of = {}
-    for u in range(nu):
-        index_of[(int(unk_row[u]), int(unk_col[u]))] = u
-    Ar = Abar.tocsr()
-    rows, cols, vals = [], [], []
-
-    def row_entries(i):
-        lo, hi = Ar.indptr[i], Ar.indptr[i + 1]
-        return Ar.indices[lo:hi], Ar.data[lo:hi]
-
-    for e in range(neq):
-        i, j = int(eq_i[e]), int(eq_j[e])
-        # (Abar S)_ij = sum_k abar_ik s_kj
-        ks, av = row_entries(i)
-        for k, a in zip(ks, av):
-            u = index_of.get((int(k), j))
-            if u is not None:
-                rows.append(e); cols.append(u); vals.append(a)
-        # (Abar S)_ji = sum_k abar_jk s_ki
-        ks, av = row_entries(j)
-        for k, a in zip(ks, av):
-            u = index_of.get((int(k), i))
-            if u is not None:
-                rows.append(e); cols.append(u); vals.append(a)
+    # M as (entry i, entry j, unknown, coefficient): column k_u of Abar, placed in column j_u
+    Ac = sp.csc_matrix(Abar)
+    Ac.sort_indices()
+    cnt = np.diff(Ac.indptr)[unk_row]              # entries of Abar's column k_u
+    u_of = np.repeat(np.arange(nu), cnt)
+    starts = np.repeat(Ac.indptr[unk_row], cnt)
+    offs = np.arange(u_of.size) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    ent_i = Ac.indices[starts + offs].astype(np.int64)
+    coef = Ac.data[starts + offs]
+    ent_j = unk_col[u_of]
+    # equation numbers: pairs by (min, max), then the diagonal ones
+    off = ent_i != ent_j
+    lo = np.minimum(ent_i, ent_j)[off]
+    hi = np.maximum(ent_i, ent_j)[off]
+    keys = np.unique(lo * n + hi)
+    neq = keys.size
+    eq = np.empty(ent_i.size, dtype=np.int64)
+    eq[off] = np.searchsorted(keys, lo * n + hi)
+    eq[~off] = neq + ent_i[~off]
     sg = np.sqrt(gamma)
-    for i in range(n):
-        ks, av = row_entries(i)
-        for k, a in zip(ks, av):
-            u = index_of.get((int(k), i))
-            if u is not None:
-                rows.append(neq + i); cols.append(u); vals.append(sg * a)
-    B = sp.csr_matrix((np.asarray(vals, dtype=np.float64), (np.asarray(rows), np.asarray(cols))),
-                      shape=(neq + n, nu))
+    val = np.where(off, coef, sg * coef)
+    B = sp.csr_matrix((val, (eq, u_of)), shape=(neq + n, nu))  # duplicates summed
+    B.sort_indices()
     v = np.concatenate([np.zeros(neq), np.full(n, sg)])
     return B, v, unk_row, unk_col
 

@@ -54,7 +54,8 @@ class SetupOpts(C.Structure):
                 ("lls_tol", C.c_double), ("lls_maxit", C.c_int32), ("row_block", C.c_int32),
                 ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32),
                 ("allocator", C.c_void_p), ("autotune", C.c_int32), ("inner_perm", C.c_void_p),
-                ("skew_form", C.c_int32)]
+                ("skew_form", C.c_int32), ("s_val", C.c_void_p), ("q_basis", C.c_void_p),
+                ("q_alpha", C.c_void_p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -336,7 +337,7 @@ SKEW_FORMS = {"auto": 0, "wide": 1, "narrow": 2, "slots": 3}
 def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, inner_fp32=False,
           x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
           stream=None, canonicalize=True, deflation="auto", reorder="auto", allocator=None,
-          autotune=False, skew_form="auto") -> Handle:
+          autotune=False, skew_form="auto", s_values=None, q_basis=None, q_alpha=None) -> Handle:
     """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
     canonicalize: sum duplicates and sort column indices of a SciPy input first
     (otherwise the library rejects such input with INVALID_CSR).
@@ -344,13 +345,18 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     allocator holds all device memory of the handle).
     autotune: time the inner step for several row-block sizes at setup and keep
     the fastest (row_block must be 0; see info()["tune_rows"], ["tune_us"]).
-    reorder: "auto"/"none" (natural order of the inner system), "blocks" (BFS
-    bisection into row blocks), "grid" (tiles of whole lines when A's pattern
-    is a lexicographic 3D grid, else natural) or an integer array perm of
-    length n (inner row i is row perm[i]).
+    reorder: "auto"/"none" (natural order of the inner system), "grid" (tiles
+    of whole lines when A's pattern is a lexicographic 3D grid, else natural)
+    or an integer array perm of length n (inner row i is row perm[i]).
+    s_values: None (S from the least-squares problem of App. A) or the values
+    of S on its pattern in CSR order (float64, length nnz of the pattern): the
+    least-squares solve is skipped.
+    q_basis, q_alpha: None (deflation basis from skew-Lanczos) or Q_k (n x k,
+    A's row order) and the k - 1 coefficients of S_k: the Lanczos run is
+    skipped and this basis is used (the preconditioner P does not depend on it).
     skew_form: storage of J_tilde's columns: "auto", "wide" (32-bit), "narrow"
     (16-bit deltas) or "slots" (one offset per slot, no per-entry columns).
-    deflation: "auto"/"explicit", "recurrence", or "explicit_fp32_basis" (the
+    deflation: "auto"/"explicit" or "explicit_fp32_basis" (the
     Lanczos vectors rounded to FP32 values and used so everywhere: same
     preconditioner P, FP64 arithmetic, half the basis bytes in the FP64 inner
     step; see asss_setup_opts_t.deflation)."""
@@ -372,13 +378,26 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.autotune = int(bool(autotune))
     o.skew_form = SKEW_FORMS[skew_form]
-    o.deflation = {"auto": 0, "explicit": 1, "recurrence": 2, "explicit_fp32_basis": 3}[deflation]
+    if s_values is not None:
+        sv = np.ascontiguousarray(s_values, dtype=np.float64)
+        keep.append(sv)
+        o.s_val = sv.ctypes.data
+    if q_basis is not None:
+        qb = np.asfortranarray(q_basis, dtype=np.float64)
+        if qb.shape != (n, k):
+            raise ValueError(f"q_basis must be n x k = {n} x {k}")
+        qa = np.ascontiguousarray(q_alpha if q_alpha is not None else np.zeros(0), dtype=np.float64)
+        if qa.shape != (max(k - 1, 0),):
+            raise ValueError("q_alpha must hold k - 1 values")
+        keep += [qb, qa]
+        o.q_basis, o.q_alpha = qb.ctypes.data, qa.ctypes.data
+    o.deflation = {"auto": 0, "explicit": 1, "explicit_fp32_basis": 3}[deflation]
     if isinstance(reorder, str):
-        o.reorder = {"auto": 0, "none": 1, "blocks": 2, "grid": 4}[reorder]
+        o.reorder = {"auto": 0, "none": 1, "grid": 4}[reorder]
     else:  # the caller's order of the inner system: inner row i is row reorder[i]
         perm = np.ascontiguousarray(reorder, dtype=np.int32)
         if perm.shape != (n,):
-            raise ValueError("reorder must be 'auto', 'none', 'blocks' or a permutation of length n")
+            raise ValueError("reorder must be 'auto', 'none', 'grid' or a permutation of length n")
         keep.append(perm)
         o.reorder, o.inner_perm = 3, perm.ctypes.data
     alloc = None

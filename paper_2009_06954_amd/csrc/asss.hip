@@ -11,9 +11,9 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <optional>
-#include <map>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -60,9 +60,6 @@ constexpr size_t kStateHead = offsetof(MrsState, relres_max) + sizeof(double);
 // coefficients, SM_Y the cycle's least-squares solution.
 constexpr int SM_COL = 512, SM_PASS2 = 256, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
 static_assert(4 * SM_COL <= SM_T, "Arnoldi scratch of four columns");
-// largest max|Q^T Q - I| for which the (opt-in) recurrence form of the
-// deflation is accepted
-constexpr double kRecurrenceOrthTol = 1e-10;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -244,6 +241,8 @@ struct asss_handle_s {
   // row-block autotuner: candidates timed at setup (row_block, us per inner step)
   std::vector<std::pair<int, double>> tuned;
   double tune_s = 0.0;
+  // a deflation basis given by the caller (setup option q_basis), until device_setup
+  std::vector<double> q_given, alpha_given;
   // inner system in block order: row i of the inner system is row perm[i]
   std::vector<int32_t> perm;
   int32_t* d_perm = nullptr;  // null when the natural order is kept
@@ -258,9 +257,6 @@ struct asss_handle_s {
   double* d_G64 = nullptr;    // Q_k^T Q_k of the FP64 and of the FP32 copy (k x k)
   double* d_G32 = nullptr;
   double* d_alpha = nullptr;
-  double* d_f64 = nullptr;    // Lanczos residual f = J_tilde q_k - alpha_{k-1} q_{k-1}
-  float* d_f32 = nullptr;
-  int defl_rec = 0;           // 1: recurrence deflation in the inner iteration
   double orth_err = 0.0;      // max |Q_k^T Q_k - I|
   double* d_Ubar = nullptr;   // n x kr column-major
   double* d_X = nullptr;      // n x kr column-major
@@ -328,17 +324,13 @@ void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f, bool rec, bool one_col) {
+MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, bool one_col) {
   MrsLaunch L{};
   L.n = h->n;
   L.nr = nr;
   L.k = h->k_eff;
   L.alpha_dev = h->d_alpha;
   L.sign = sign;
-  L.rec = (rec && h->k_eff > 0) ? 1 : 0;
-  L.f = f;
-  L.qk1 = (h->k_eff >= 2) ? (const void*)(Q + (int64_t)(h->k_eff - 2) * h->n) : nullptr;
-  L.alpha_last = (h->k_eff >= 2) ? h->alpha[h->k_eff - 2] : 0.0;
   // deflation = 3: the basis holds FP32 values, and the one-column FP64 step
   // reads the FP32 copy (the 4-column step reads the FP64 copy of the same values,
   // which it streams faster)
@@ -352,16 +344,13 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, const T* Q, const T* f
 // leading dimension n; NR = 4: App. B's simultaneous form, one matrix pass per
 // step for all columns, shared stop rule).
 template <typename T, int NR = 1>
-int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s,
             int nc = 1) {
   Range range(NR == 1 ? "asss:inner mrs" : "asss:inner mrs (4 columns)");
-  MrsLaunch L = make_launch<T>(h, nc, sign, Q, f, NR == 1 && h->defl_rec != 0, NR == 1);
+  MrsLaunch L = make_launch<T>(h, nc, sign, NR == 1);
   if (J.nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
   mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
-  if constexpr (NR == 1) {
-    if (L.rec) mrs_make_y1<T, 1>(L, Q, mb, h->d_state, s);
-  }
   int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
   int its = 0;
   double prev_rel = 1.0;
@@ -409,16 +398,16 @@ int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs
 }
 
 template <typename T>
-int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
              const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s) {
-  return run_mrs<T, 1>(h, J, Q, f, mb, rhs, out, sign, tol, maxit, fixed, s);
+  return run_mrs<T, 1>(h, J, Q, mb, rhs, out, sign, tol, maxit, fixed, s);
 }
 
 int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
                 int maxit, int fixed, hipStream_t s) {
   if (fp32)
-    return run_mrs1<float>(h, h->J32, h->d_Q32, h->d_f32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
-  return run_mrs1<double>(h, h->J64, h->d_Q64, h->d_f64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
+    return run_mrs1<float>(h, h->J32, h->d_Q32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
+  return run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
 }
 
 // z <- z - X (C^-1 Sigma) (U_bar^T z): the low-rank part of eq. smw (inverse-free form)
@@ -493,13 +482,13 @@ int prec_apply_T(asss_handle_s* h, bool fp32, const double* v, double* z, const 
 // number of steps from the right-hand side in h->tmp.  Leaves no trace in
 // the handle's counters.
 template <typename T>
-double time_inner_step(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T* f, MrsBufs<T>& mb,
+double time_inner_step(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
                        int steps, hipStream_t s) {
   const double ps = h->prof_s;
   const int pl = h->prof_launches, li = h->last_inner;
   h->prof_s = 0.0;
   h->prof_launches = 0;
-  run_mrs1<T>(h, J, Q, f, mb, h->tmp, h->w, +1, 1e-300, steps, steps, s);
+  run_mrs1<T>(h, J, Q, mb, h->tmp, h->w, +1, 1e-300, steps, steps, s);
   const double t = h->prof_launches > 0 ? h->prof_s / h->prof_launches : 0.0;
   h->prof_s = ps;
   h->prof_launches = pl;
@@ -509,8 +498,8 @@ double time_inner_step(asss_handle_s* h, const DSkew<T>& J, const T* Q, const T*
 
 double time_layout(asss_handle_s* h, const SkewLayout& L, bool fp32, hipStream_t s) {
   auto run = [&](int steps) {
-    return fp32 ? time_inner_step<float>(h, L.J32, h->d_Q32, h->d_f32, h->mb32, steps, s)
-                : time_inner_step<double>(h, L.J64, h->d_Q64, h->d_f64, h->mb64, steps, s);
+    return fp32 ? time_inner_step<float>(h, L.J32, h->d_Q32, h->mb32, steps, s)
+                : time_inner_step<double>(h, L.J64, h->d_Q64, h->mb64, steps, s);
   };
   const double warm = run(4);
   // about 4 ms of timed steps per repeat, best of two repeats
@@ -693,7 +682,23 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   // ---- skew-Lanczos (Fig. 2) in FP64
   std::vector<double> alpha;
   int keff = 0;
-  if (k > 0) {
+  if (k > 0 && h->q_given.size() == (size_t)n * k) {  // the caller's basis (original order)
+    h->d_Q64 = h->ar.alloc<double>(n * (int64_t)k);
+    double* z = h->ar.alloc<double>(n * (int64_t)k);
+    HIPCHK(hipMemcpyAsync(z, h->q_given.data(), (size_t)n * k * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int c = 0; c < k; ++c) {
+      if (h->d_perm)
+        permute_gather(n, h->d_perm, z + (int64_t)c * n, h->d_Q64 + (int64_t)c * n, s);
+      else
+        HIPCHK(hipMemcpyAsync(h->d_Q64 + (int64_t)c * n, z + (int64_t)c * n, n * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    h->ar.release(z);
+    std::vector<double>().swap(h->q_given);
+    alpha = h->alpha_given;
+    keff = k;
+  } else if (k > 0) {
     h->d_Q64 = h->ar.alloc<double>(n * (int64_t)k);
     double* z = h->ar.alloc<double>(n);
     double* q0 = h->d_Q64;
@@ -750,15 +755,9 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     h->d_Qs32 = h->ar.alloc<float>(npad * keff);
     slice_columns<double>(n, keff, h->d_Q64, h->d_Qs64, s);
     slice_columns<float>(n, keff, h->d_Q32, h->d_Qs32, s);
-    // Lanczos residual f = J_tilde q_k - alpha_{k-1} q_{k-1}: J_tilde Q_k = Q_k S_k + f e_k^T
-    h->d_f64 = h->ar.alloc<double>(n);
-    h->d_f32 = h->ar.alloc<float>(n);
-    skew_spmv<double>(h->J64, h->d_Q64 + (int64_t)(keff - 1) * n, h->d_f64, s);
-    if (keff >= 2) axpby(n, -alpha[keff - 2], h->d_Q64 + (int64_t)(keff - 2) * n, 1.0, h->d_f64, s);
-    cast_d2f(n, h->d_f64, h->d_f32, s);
     // Gram matrices G = Q_k^T Q_k of both stored copies (column c of G at
     // G + c k; G is symmetric bit for bit, the products and their order being
-    // the same); the FP64 one's distance from I decides the deflation form
+    // the same); the FP64 one's distance from I is reported
     h->d_G64 = h->ar.alloc<double>((int64_t)keff * keff);
     h->d_G32 = h->ar.alloc<double>((int64_t)keff * keff);
     for (int c = 0; c < keff; ++c) {
@@ -774,7 +773,6 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     for (int c = 0; c < keff; ++c)
       for (int l = 0; l < keff; ++l) err = std::max(err, std::fabs(g64[(size_t)c * keff + l] - (l == c ? 1.0 : 0.0)));
     h->orth_err = err;
-    h->defl_rec = (h->opts.deflation == 2) && err <= kRecurrenceOrthTol;
   }
   // ---- one-time SMW data (Sec. 4.1): U_bar, X = S_bar^-1 U_bar, G, C
   h->r = (int)h->neg.size();
@@ -806,7 +804,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     for (int c0 = 0; c0 < kr; c0 += (use4 ? NRMAX : 1)) {
       const int nc = use4 ? std::min(NRMAX, kr - c0) : 1;
       if (use4) {
-        MrsLaunch L = make_launch<double>(h, nc, +1, h->d_Q64, h->d_f64, false, false);
+        MrsLaunch L = make_launch<double>(h, nc, +1, false);
         mrs_init<double, NRMAX>(L, h->d_Ubar + (int64_t)c0 * n, n, h->d_perm, h->d_Q64, mb4, h->d_state,
                                 h->opts.x_tol, h->opts.x_maxit, 0, h->red, s);
         int group_its = -1;
@@ -829,11 +827,8 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
         }
         mrs_output<double, NRMAX>(n, nc, mb4, h->d_perm, h->d_X + (int64_t)c0 * n, n, s);
       } else {
-        const int saved = h->defl_rec;
-        h->defl_rec = 0;  // the one-time X solve uses the explicit projector
-        int it = run_mrs1<double>(h, h->J64, h->d_Q64, h->d_f64, h->mb64, h->d_Ubar + (int64_t)c0 * n,
+        int it = run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, h->d_Ubar + (int64_t)c0 * n,
                                   h->d_X + (int64_t)c0 * n, +1, h->opts.x_tol, h->opts.x_maxit, 0, s);
-        h->defl_rec = saved;
         xits = std::max(xits, it);
       }
     }
@@ -1168,10 +1163,10 @@ asss_status_t fgmres_block(asss_handle_s* h, int nc, const double* const* B, dou
                             hipMemcpyDeviceToDevice, s));
     int its;
     if (fp32)
-      its = run_mrs<float, NRMAX>(h, h->J32, h->d_Q32, h->d_f32, h->mb4_32, h->pin, h->pout, +1, o.inner_tol,
+      its = run_mrs<float, NRMAX>(h, h->J32, h->d_Q32, h->mb4_32, h->pin, h->pout, +1, o.inner_tol,
                                   o.inner_maxit, o.fixed_inner_steps, s, na);
     else
-      its = run_mrs<double, NRMAX>(h, h->J64, h->d_Q64, h->d_f64, h->mb4_64, h->pin, h->pout, +1, o.inner_tol,
+      its = run_mrs<double, NRMAX>(h, h->J64, h->d_Q64, h->mb4_64, h->pin, h->pout, +1, o.inner_tol,
                                    o.inner_maxit, o.fixed_inner_steps, s, na);
     // every active column's Arnoldi step goes on the stream, then one host
     // round trip serves them all
@@ -1461,15 +1456,16 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     if (opts) o = *opts;
     if (o.k < 0 || o.k > KMAX) throw Error{ASSS_ERR_INVALID_ARG, "k must be in [0, 32]"};
     if (!(o.gamma > 0)) throw Error{ASSS_ERR_INVALID_ARG, "gamma must be positive"};
-    if (o.deflation < 0 || o.deflation > 3) throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1, 2 or 3"};
-    if (o.reorder < 0 || o.reorder > 4) throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1, 2, 3 or 4"};
+    if (o.deflation < 0 || o.deflation > 3 || o.deflation == 2)
+      throw Error{ASSS_ERR_INVALID_ARG, "deflation must be 0, 1 or 3 (2, a recurrence form of the projector, "
+                                        "loses orthogonality and is not provided)"};
+    if (o.reorder < 0 || o.reorder > 4 || o.reorder == 2)
+      throw Error{ASSS_ERR_INVALID_ARG, "reorder must be 0, 1, 3 or 4 (2, a BFS block partition, is not provided)"};
     if (o.reorder == 3 && !o.inner_perm) throw Error{ASSS_ERR_INVALID_ARG, "reorder 3 needs inner_perm"};
     if (o.row_block != 0 && (o.row_block % 64 != 0 || o.row_block > 4096))
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     if (o.autotune < 0 || o.autotune > 1) throw Error{ASSS_ERR_INVALID_ARG, "autotune must be 0 or 1"};
     if (o.skew_form < 0 || o.skew_form > 3) throw Error{ASSS_ERR_INVALID_ARG, "skew_form must be 0, 1, 2 or 3"};
-    if (o.autotune && o.reorder == 2)
-      throw Error{ASSS_ERR_INVALID_ARG, "autotune does not combine with reorder 2 (its blocks depend on row_block)"};
     hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<asss_handle_s> h(new asss_handle_s());
     HIPCHK(hipGetDevice(&h->device));
@@ -1480,6 +1476,8 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     }
     h->opts = o;
     h->opts.allocator = nullptr;
+    h->opts.s_val = nullptr;  // caller arrays are read during setup only
+    h->opts.q_basis = h->opts.q_alpha = nullptr;
     std::optional<Range> phase;
     phase.emplace("asss_setup:host preprocessing");
     const double t0 = now_s();
@@ -1488,6 +1486,15 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->n = Ah.nrows;
     h->nnz_a = Ah.nnz();
     const int64_t n = h->n;
+    if (o.q_basis && o.k > 0) {
+      if (o.k > 1 && !o.q_alpha) throw Error{ASSS_ERR_INVALID_ARG, "q_basis needs q_alpha (k - 1 values)"};
+      h->q_given.assign(o.q_basis, o.q_basis + (size_t)n * o.k);
+      if (o.k > 1) h->alpha_given.assign(o.q_alpha, o.q_alpha + (o.k - 1));
+      for (double v : h->q_given)
+        if (!std::isfinite(v)) throw Error{ASSS_ERR_NONFINITE, "q_basis holds a NaN or Inf"};
+      for (double v : h->alpha_given)
+        if (!std::isfinite(v)) throw Error{ASSS_ERR_NONFINITE, "q_alpha holds a NaN or Inf"};
+    }
     if (pre) {
       if ((int64_t)pre->m.size() != n || (int64_t)pre->Dr.size() != n || (int64_t)pre->Dc.size() != n ||
           pre->S.nrows != n)
@@ -1518,16 +1525,19 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     int R = o.row_block;
     int auto_R = 64;
     while (auto_R < 2048 && (int64_t)auto_R * 2 * 1024 <= n) auto_R *= 2;
-    // reorder 4: tiles of whole grid lines when Abar is a lexicographic 3D grid
+    // reorder 4: tiles of whole grid lines when Abar is a lexicographic 3D grid,
+    // up to 1.5x the automatic block: tiles of 4 x 4 lines at 128^3 (R = 2048)
+    // and at 192^3 (R = 3072; 4 x 2 lines within 2048 gave 430 against 408 us
+    // per FP64 step)
     std::vector<int32_t> grid_perm;
     int32_t grid_R = 0;
-    if (o.reorder == 4) grid_perm = grid_line_order(Abar, R ? R : auto_R, grid_R);
+    if (o.reorder == 4) grid_perm = grid_line_order(Abar, R ? R : 3 * auto_R / 2, grid_R);
     if (R == 0) R = grid_perm.empty() ? auto_R : grid_R;
     // autotuner candidates: the automatic size and up to two doublings and
-    // halvings of it within [64, 2048]
+    // halvings of it within [64, 4096]
     std::vector<int> cands;
     if (o.autotune && o.row_block == 0)
-      for (int c = std::max(64, R / 4); c <= std::min(2048, R * 4); c *= 2) cands.push_back(c);
+      for (int c = std::max(64, R / 4); c <= std::min(4096, R * 4); c *= 2) cands.push_back(c);
     const int Rmin = cands.empty() ? R : cands.front();
     const int64_t nblocks = (n + Rmin - 1) / Rmin;
     h->red.max_groups = (int)std::max<int64_t>(nblocks, 1024);
@@ -1540,7 +1550,16 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->d_state = h->ar.alloc<MrsState>(1);
     HIPCHK(hipEventCreate(&h->ev0));
     HIPCHK(hipEventCreate(&h->ev1));
-    std::vector<double> svals = pre ? pre->S.val : lsqr_device(h.get(), L, o.lls_tol, o.lls_maxit, s);
+    std::vector<double> svals;
+    if (pre) {
+      svals = pre->S.val;
+    } else if (o.s_val) {  // S given by the caller: no least-squares solve
+      svals.assign(o.s_val, o.s_val + Spat.nnz());
+      for (double v : svals)
+        if (!std::isfinite(v)) throw Error{ASSS_ERR_NONFINITE, "s_val holds a NaN or Inf"};
+    } else {
+      svals = lsqr_device(h.get(), L, o.lls_tol, o.lls_maxit, s);
+    }
     const double t2 = now_s();
     phase.reset();
     phase.emplace("asss_setup:split and pack");
@@ -1559,17 +1578,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->cross_natural = count_cross_pairs(Jup, R);
     h->cross_used = h->cross_natural;
     bool reordered = false;
-    if (o.reorder == 2 && n >= 2 * (int64_t)R) {
-      std::vector<int32_t> perm = block_partition(Jup, R);
-      Csr Jp = permute_skew_upper(Jup, perm);
-      const int64_t cross = count_cross_pairs(Jp, R);
-      {
-        Jup = std::move(Jp);
-        h->perm = std::move(perm);
-        h->cross_used = cross;
-        reordered = true;
-      }
-    } else if (o.reorder == 4 && !grid_perm.empty()) {  // line tiles of a detected grid
+    if (o.reorder == 4 && !grid_perm.empty()) {  // line tiles of a detected grid
       Jup = permute_skew_upper(Jup, grid_perm);
       h->cross_used = count_cross_pairs(Jup, R);
       h->perm = std::move(grid_perm);
@@ -1620,8 +1629,6 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     for (int b = 0; b < 2; ++b) { h->mb64.p[b] = h->ar.alloc<double>(n); h->mb32.p[b] = h->ar.alloc<float>(n); }
     h->mb64.x = h->ar.alloc<double>(n);
     h->mb32.x = h->ar.alloc<float>(n);
-    h->mb64.y1 = h->ar.alloc<double>(n);
-    h->mb32.y1 = h->ar.alloc<float>(n);
     h->w = h->ar.alloc<double>(n);
     h->t1 = h->ar.alloc<double>(n);
     h->xchk = h->ar.alloc<double>(n);
@@ -1653,7 +1660,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
                    "device %.3fs (k_eff %d, r %d, X its %d, orth %.1e, deflation %s)\n",
                    (long long)n, h->setup_host_s, t1 - t0, t3 - t2, t2 - t1, h->lls_its, h->lls_kkt,
                    t4 - t3, h->k_eff, h->r, h->x_its, h->orth_err,
-                   h->defl_rec ? "recurrence" : (h->opts.deflation == 3 ? "explicit, FP32 basis" : "explicit"));
+                   h->opts.deflation == 3 ? "explicit, FP32 basis" : "explicit");
     *out = h.release();
     return ASSS_OK;
   });
@@ -2091,7 +2098,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.lanczos_orth_err = h->orth_err;
     i.narrow_b_columns = h->narrow_b;
     i.skew_form = h->skew_form;
-    i.deflation_mode = h->k_eff == 0 ? 0 : (h->defl_rec ? 2 : (h->opts.deflation == 3 ? 3 : 1));
+    i.deflation_mode = h->k_eff == 0 ? 0 : (h->opts.deflation == 3 ? 3 : 1);
     i.reordered = h->d_perm ? 1 : 0;
     i.cross_pairs_natural = h->cross_natural;
     i.cross_pairs_used = h->cross_used;

@@ -907,100 +907,6 @@ std::vector<int32_t> grid_line_order(const Csr& Abar, int32_t target_R, int32_t&
   return perm;
 }
 
-std::vector<int32_t> block_partition(const Csr& U, int32_t R) {
-  const int64_t n = U.nrows;
-  // full symmetric pattern G = U + U^T
-  Csr Ut = transpose(U);
-  Csr G;
-  G.nrows = G.ncols = n;
-  G.ptr.assign(n + 1, 0);
-  for (int64_t i = 0; i < n; ++i)
-    G.ptr[i + 1] = G.ptr[i] + (U.ptr[i + 1] - U.ptr[i]) + (Ut.ptr[i + 1] - Ut.ptr[i]);
-  G.col.resize(G.ptr[n]);
-  parallel_for(n, [&](int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi; ++i) {
-      int64_t q = G.ptr[i];
-      for (int64_t p = Ut.ptr[i]; p < Ut.ptr[i + 1]; ++p) G.col[q++] = Ut.col[p];
-      for (int64_t p = U.ptr[i]; p < U.ptr[i + 1]; ++p) G.col[q++] = U.col[p];
-    }
-  });
-  // Parts are contiguous ranges of `order`; a part larger than 32 R is cut into
-  // 8 pieces at once (slabs of the BFS-distance key), a smaller one into 2.
-  std::vector<int32_t> order(n), part(n, 0), part_next(n, 0);
-  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
-  struct Range { int64_t lo, hi; };
-  std::vector<Range> cur{{0, n}};
-  int32_t next_id = 1;
-  std::vector<int32_t> dist_a(n, -1), dist_b(n, -1);
-  constexpr int WAYS_BIG = 8;
-  while (true) {
-    std::vector<size_t> todo;
-    for (size_t t = 0; t < cur.size(); ++t)
-      if (cur[t].hi - cur[t].lo > R) todo.push_back(t);
-    if (todo.empty()) break;
-    std::vector<std::vector<Range>> pieces(todo.size());
-    std::vector<int32_t> base(todo.size());
-    for (size_t t = 0; t < todo.size(); ++t) base[t] = next_id, next_id += WAYS_BIG;
-    parallel_tasks((int64_t)todo.size(), [&](int64_t tlo, int64_t thi) {
-      std::vector<int32_t> queue;
-      for (int64_t t = tlo; t < thi; ++t) {
-        const Range r = cur[todo[t]];
-        const int32_t pid = part[order[r.lo]];
-        const int64_t len = r.hi - r.lo;
-        // pseudo-peripheral pair (a, b): a = farthest from the first vertex, b = farthest from a
-        int32_t a = bfs_part(G, part, pid, order[r.lo], dist_a, queue);
-        for (int64_t q = r.lo; q < r.hi; ++q) dist_a[order[q]] = -1;
-        int32_t b = bfs_part(G, part, pid, a, dist_a, queue);
-        bfs_part(G, part, pid, b, dist_b, queue);
-        // key = d(a) - d(b); unreached vertices (other components) go to the far end
-        std::vector<std::pair<int64_t, int32_t>> key(len);
-        for (int64_t q = r.lo; q < r.hi; ++q) {
-          int32_t v = order[q];
-          int64_t da = dist_a[v] < 0 ? (int64_t)1 << 40 : dist_a[v];
-          int64_t db = dist_b[v] < 0 ? 0 : dist_b[v];
-          key[q - r.lo] = {da - db, v};
-        }
-        const int64_t nb = (len + R - 1) / R;
-        const int ways = (len > 32 * (int64_t)R) ? WAYS_BIG : 2;
-        std::vector<int64_t> cut(ways + 1);
-        for (int w = 0; w <= ways; ++w) cut[w] = std::min<int64_t>(len, (int64_t)R * (nb * w / ways));
-        cut[ways] = len;
-        for (int w = 1; w < ways; ++w)
-          std::nth_element(key.begin() + cut[w - 1], key.begin() + cut[w], key.end());
-        auto by_index = [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
-          return x.second < y.second;
-        };
-        for (int w = 0; w < ways; ++w) {
-          std::sort(key.begin() + cut[w], key.begin() + cut[w + 1], by_index);
-          for (int64_t q = cut[w]; q < cut[w + 1]; ++q) {
-            int32_t v = key[q].second;
-            order[r.lo + q] = v;
-            part_next[v] = base[t] + w;
-            dist_a[v] = -1;
-            dist_b[v] = -1;
-          }
-          if (cut[w + 1] > cut[w]) pieces[t].push_back(Range{r.lo + cut[w], r.lo + cut[w + 1]});
-        }
-      }
-    });
-    // the BFS of a round read part[] only; publish the new part ids now
-    for (size_t t = 0; t < todo.size(); ++t)
-      for (int64_t q = cur[todo[t]].lo; q < cur[todo[t]].hi; ++q) part[order[q]] = part_next[order[q]];
-    std::vector<Range> next;
-    size_t ti = 0;
-    for (size_t t = 0; t < cur.size(); ++t) {
-      if (ti < todo.size() && todo[ti] == t) {
-        for (const Range& pr : pieces[ti]) next.push_back(pr);
-        ++ti;
-      } else {
-        next.push_back(cur[t]);
-      }
-    }
-    cur.swap(next);
-  }
-  return order;
-}
-
 Csr permute_skew_upper(const Csr& U, const std::vector<int32_t>& perm) {
   const int64_t n = U.nrows;
   std::vector<int32_t> iperm(n);

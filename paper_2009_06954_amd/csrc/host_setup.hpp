@@ -127,13 +127,6 @@ struct SkewSell {
 // throws HostError(ASSS_ERR_INVALID_ARG).
 SkewSell pack_skew_sell(const Csr& Jup, int32_t R, int32_t form = SKEW_AUTO);
 
-// Symmetric reordering of the inner system into compact blocks of R rows:
-// recursive bisection of the graph of J_tilde (pattern of U + U^T), each cut
-// by BFS distances from two pseudo-peripheral vertices (the half closer to
-// the first one goes left).  Every leaf but the last holds exactly R vertices,
-// in increasing original index.  Returns perm (new -> old).
-std::vector<int32_t> block_partition(const Csr& U, int32_t R);
-
 // Order of the inner system for a lexicographic 3D grid (node x + m1 y +
 // m1 m2 z): detected from the pattern of Abar, whose positive column offsets
 // must be exactly {1, m1, m1 m2} with m1 m2 dividing n.  Rows are then grouped

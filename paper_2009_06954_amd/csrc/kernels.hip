@@ -771,6 +771,17 @@ __device__ __forceinline__ double sk_times(const double* alpha, const double* d,
   return r;
 }
 
+// How the iteration kernel forms Q_k^T q_new for the next deflation
+// coefficients.  FP64 kernels stream each Q_k row once and take
+// Q_k^T q_new = Q_k^T a - sign G c (G = Q_k^T Q_k), which needs no register
+// copy of the row.  FP32 kernels project the stored (rounded) q_new itself:
+// the rounding of the deflation term Q_k c, about 2^-24 |Q_k| |c| per entry, is
+// then part of q_new and never drifts; with coefficients |c| ~ alpha ~ 1e4
+// (Peclet 1000) the G form let the deflation lose ~1e-3 per step in FP32
+// (30 steps at 24^3: true residual 0.67 against 0.07 with the direct form).
+template <typename T>
+__device__ constexpr bool direct_projection() { return sizeof(T) == 4; }
+
 // What the last workgroup of an iteration needs besides the reduced values,
 // copied to LDS by every workgroup at the start of the launch (the copies'
 // latency hides behind the launch's main work instead of adding to the serial
@@ -798,46 +809,48 @@ struct MrsTailRegs {
 };
 
 template <typename T, int NR, int KF>
-__device__ __forceinline__ void mrs_tail_load(MrsTailRegs<NR, KF>& r, const MrsState* st, const MrsLaunch& L,
-                                              bool rec) {
+__device__ __forceinline__ void mrs_tail_load(MrsTailRegs<NR, KF>& r, const MrsState* st, const MrsLaunch& L) {
   using R = MrsTailRegs<NR, KF>;
   const int e = threadIdx.x, k = L.k;
   r.col = e < R::NC ? reinterpret_cast<const double*>(st->col)[e] : 0.0;
   r.cvt = r.alpha = 0.0;
 #pragma unroll
   for (int u = 0; u < R::NG; ++u) r.gram[u] = 0.0;
-  if (KF > 0 && !rec && k > 0) {
-    if (e < NR * k) r.cvt = st->cvec[(e / k) * KMAX + e % k];  // rounded to T at the store
+  if (KF > 0 && k > 0) {
     if (e < k - 1) r.alpha = L.alpha_dev[e];
+    if (!direct_projection<T>()) {
+      if (e < NR * k) r.cvt = st->cvec[(e / k) * KMAX + e % k];  // rounded to T at the store
 #pragma unroll
-    for (int u = 0; u < R::NG; ++u)
-      if (e + u * WG < k * k) r.gram[u] = L.gram[e + u * WG];
+      for (int u = 0; u < R::NG; ++u)
+        if (e + u * WG < k * k) r.gram[u] = L.gram[e + u * WG];
+    }
   }
 }
 
 template <typename T, int NR, int KF>
-__device__ __forceinline__ void mrs_tail_store(MrsTail<NR, KF>& tl, const MrsTailRegs<NR, KF>& r, int k,
-                                               bool rec) {
+__device__ __forceinline__ void mrs_tail_store(MrsTail<NR, KF>& tl, const MrsTailRegs<NR, KF>& r, int k) {
   using R = MrsTailRegs<NR, KF>;
   const int e = threadIdx.x;
   if (e < R::NC) reinterpret_cast<double*>(tl.col)[e] = r.col;
-  if (KF > 0 && !rec && k > 0) {
-    if (e < NR * k) tl.cvt[e / k][e % k] = (double)(T)r.cvt;
+  if (KF > 0 && k > 0) {
     if (e < k - 1) tl.alpha[e] = r.alpha;
+    if (!direct_projection<T>()) {
+      if (e < NR * k) tl.cvt[e / k][e % k] = (double)(T)r.cvt;
 #pragma unroll
-    for (int u = 0; u < R::NG; ++u)
-      if (e + u * WG < k * k) tl.gram[e + u * WG] = r.gram[u];
+      for (int u = 0; u < R::NG; ++u)
+        if (e + u * WG < k * k) tl.gram[e + u * WG] = r.gram[u];
+    }
   }
 }
 
-template <typename T, int NR, int KF, bool REC>
+template <typename T, int NR, int KF>
 __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const MrsTail<NR, KF>& tl,
                                   int fixed, int maxit, double tol, int t, int sign) {
-  // res: [KF+1][NR] with row 0 = ||w_new||^2 and rows 1..k = Q^T a, where
-  // a = sign u + beta q_old is w_new before the deflation term (explicit
-  // deflation), or [2][NR] with row 1 = f^T q_t (recurrence deflation).
-  // Explicit: w_new = a - sign Q c with c the deflation coefficients as applied
-  // (rounded to T), so Q^T w_new = Q^T a - sign G c, G = Q^T Q.
+  // res: [KF+1][NR] with row 0 = ||w_new||^2 and rows 1..k either Q^T w_new
+  // itself (direct projection, FP32 kernels) or Q^T a, where a = sign u +
+  // beta q_old is w_new before the deflation term: w_new = a - sign Q c with c
+  // the deflation coefficients as applied (rounded to T), so
+  // Q^T w_new = Q^T a - sign G c, G = Q^T Q (FP64 kernels).
   __shared__ double dsh[NRMAX][KMAX];
   __shared__ double s_relmax[NRMAX], s_nu[NRMAX];
   __shared__ int s_live[NRMAX];
@@ -861,20 +874,10 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
       col.s_old = sk;
       col.c_old = ck;
       col.theta1 = theta1_new;
-      const double beta_old = col.beta_prev;
       col.nu_old = col.nu;
       col.nu = (beta != 0.0) ? beta : 1.0;
       col.beta_prev = beta;
       rel = fabs(col.g) / col.r0;
-      if (REC) {
-        const double fq = res[NR + c];
-        const double ra_new = beta_old * col.ra_old / col.nu;
-        const double rb_new = (beta_old * col.rb_old - (double)sign * fq) / col.nu;
-        col.ra_old = col.ra;
-        col.rb_old = col.rb;
-        col.ra = ra_new;
-        col.rb = rb_new;
-      }
     } else {
       col.pend_theta = 1.0;
       col.pend_delta = 0.0;
@@ -887,19 +890,18 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
     st->col[c] = col;
   }
   __syncthreads();
-  if (!REC) {
-    // d = Q^T q_new = (Q^T a - sign G c) / nu_new
-    for (int e = threadIdx.x; e < NR * k; e += WG) {
-      const int cc = e / k, l = e % k;
-      double gc = 0.0;
+  // d = Q^T q_new = Q^T w_new / nu_new
+  for (int e = threadIdx.x; e < NR * k; e += WG) {
+    const int cc = e / k, l = e % k;
+    double gc = 0.0;
+    if (!direct_projection<T>())
       for (int m = 0; m < k; ++m) gc += tl.gram[l * k + m] * tl.cvt[cc][m];
-      dsh[cc][l] = s_live[cc] ? (res[(1 + l) * NR + cc] - (double)sign * gc) / s_nu[cc] : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < NR * k; e += WG) {
-      int cc = e / k, l = e % k;
-      st->cvec[cc * KMAX + l] = sk_times(tl.alpha, dsh[cc], k, l);
-    }
+    dsh[cc][l] = s_live[cc] ? (res[(1 + l) * NR + cc] - (double)sign * gc) / s_nu[cc] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NR * k; e += WG) {
+    int cc = e / k, l = e % k;
+    st->cvec[cc * KMAX + l] = sk_times(tl.alpha, dsh[cc], k, l);
   }
   if (threadIdx.x == 0) {
     double rmax = 0.0;
@@ -1010,10 +1012,6 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
     col.pend_delta = 0.0;
     col.pend_coef = 0.0;
     col.has_pending = 0;
-    col.ra = 1.0;
-    col.rb = 0.0;
-    col.ra_old = 0.0;
-    col.rb_old = 0.0;
     for (int l = 0; l < k; ++l) dsh[c][l] = col.live ? res[(1 + l) * NR + c] / col.nu : 0.0;
     st->col[c] = col;
     if (col.live) atomicOr(&s_any, 1);
@@ -1040,11 +1038,11 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
 
 // Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
 // 256 threads are resident per CU (1024 on the chip).
-template <typename T, int NR, int KF, bool STAGE, bool REC, typename TQ = T>
+template <typename T, int NR, int KF, bool STAGE, typename TQ = T>
 __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
-  constexpr int NV = REC ? 2 * NR : (KF + 1) * NR;
+  constexpr int NV = (KF + 1) * NR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc_lds = reinterpret_cast<double*>(smem_raw);
   T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
@@ -1063,7 +1061,6 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   const bool pend = st->col[0].has_pending != 0;
   constexpr int KF1 = KF > 0 ? KF : 1;
   T inv_nu[NR], inv_nu_old[NR], beta_prev[NR], pend_delta[NR], inv_pend_theta[NR], pend_coef[NR];
-  T cy[NR], cq[NR];
   T cv[NR][KF1];
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
@@ -1074,8 +1071,6 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     pend_delta[c] = (T)col.pend_delta;
     inv_pend_theta[c] = (T)(1.0 / col.pend_theta);
     pend_coef[c] = (T)col.pend_coef;
-    cy[c] = (T)col.ra;
-    cq[c] = (T)(col.rb * L.alpha_last);
 #pragma unroll
     for (int l = 0; l < KF1; ++l) {
       // loaded for every l < KF1 <= KMAX (in bounds) and selected after: a load
@@ -1090,7 +1085,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   if (status == MRS_DONE) return;
   __shared__ MrsTail<NR, KF> tail;
   MrsTailRegs<NR, KF> tail_r;
-  if (status == MRS_RUNNING) mrs_tail_load<T, NR, KF>(tail_r, st, L, REC);
+  if (status == MRS_RUNNING) mrs_tail_load<T, NR, KF>(tail_r, st, L);
   const int64_t n = L.n;
   const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, n - row0);
@@ -1124,7 +1119,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     acc_lds[r] = 0.0;
     if (STAGE) w_lds[r] = wcur[row0 * NR + r];
   }
-  mrs_tail_store<T, NR, KF>(tail, tail_r, k, REC);  // status is MRS_RUNNING here
+  mrs_tail_store<T, NR, KF>(tail, tail_r, k);  // status is MRS_RUNNING here
   __syncthreads();
   skew_block_pass<T, NR, STAGE>(J, row0, nrow, wcur, w_lds, acc_lds);
   __syncthreads();
@@ -1133,29 +1128,11 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   const T sgn = (T)L.sign;
-  const T* __restrict__ fvec = reinterpret_cast<const T*>(L.f);
-  const T* __restrict__ qk1 = reinterpret_cast<const T*>(L.qk1);
-  const T* __restrict__ y1 = buf.y1;
-  bool use_y1 = false;
-  if (REC) {
-#pragma unroll
-    for (int c = 0; c < NR; ++c) use_y1 |= (cy[c] != T(0));
-  }
   for (int il = threadIdx.x; il < nrow; il += WG) {
     const int64_t i = row0 + il;
     T defl[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) defl[c] = T(0);
-    T fi = T(0);
-    if (REC) {
-      const T qk = qk1 ? qk1[i] : T(0);
-      fi = fvec[i];
-#pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        defl[c] = cq[c] * qk;
-        if (use_y1) defl[c] += cy[c] * y1[i * NR + c];
-      }
-    }
     T u[NR], qold[NR], a[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
@@ -1163,21 +1140,21 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
       qold[c] = wold[i * NR + c] * inv_nu_old[c];
       a[c] = sgn * u[c] + beta_prev[c] * qold[c];
     }
-    if (!REC) {
-      // Q row i streams once: deflation term and Q^T a together (non-temporal
-      // for an FP64 basis, where it helps: 161 -> 150 us; for an FP32 basis it
-      // costs 124 -> 132 us).  TQ = float in an FP64 kernel: the basis is
-      // stored as FP32 values.
-      const TQ* __restrict__ qs = reinterpret_cast<const TQ*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
+    // Q row i streams once (non-temporal for an FP64 basis, where it helps:
+    // 161 -> 150 us; for an FP32 basis it costs 124 -> 132 us).  TQ = float in
+    // an FP64 kernel: the basis is stored as FP32 values.
+    const TQ* __restrict__ qs = reinterpret_cast<const TQ*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
+    constexpr bool DIRECT = direct_projection<T>();
+    T qrow[DIRECT ? KF1 : 1];
 #pragma unroll
-      for (int l = 0; l < KF; ++l) {
-        T q = T(0);
-        if (l < k) q = (sizeof(TQ) == 8) ? (T)__builtin_nontemporal_load(&qs[l * 64]) : (T)qs[l * 64];
+    for (int l = 0; l < KF; ++l) {
+      T q = T(0);
+      if (l < k) q = (sizeof(TQ) == 8) ? (T)__builtin_nontemporal_load(&qs[l * 64]) : (T)qs[l * 64];
+      if constexpr (DIRECT) qrow[l] = q;
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-          defl[c] += q * cv[c][l];
-          acc[(1 + l) * NR + c] += (double)q * (double)a[c];
-        }
+      for (int c = 0; c < NR; ++c) {
+        defl[c] += q * cv[c][l];
+        if constexpr (!DIRECT) acc[(1 + l) * NR + c] += (double)q * (double)a[c];
       }
     }
 #pragma unroll
@@ -1185,9 +1162,9 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
       const T qn = sgn * (u[c] - defl[c]) + beta_prev[c] * qold[c];
       wnew[i * NR + c] = qn;
       acc[c] += (double)qn * (double)qn;
-      if (REC) {
-        const T qcur = (STAGE ? w_lds[il * NR + c] : wcur[i * NR + c]) * inv_nu[c];
-        acc[NR + c] += (double)fi * (double)qcur;
+      if constexpr (DIRECT) {
+#pragma unroll
+        for (int l = 0; l < KF; ++l) acc[(1 + l) * NR + c] += (double)qrow[l] * (double)qn;
       }
       if (pend) {
         const T p = (qold[c] - pend_delta[c] * pb[i * NR + c]) * inv_pend_theta[c];
@@ -1200,7 +1177,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   publish_partials<NV>(partials, res);
   if (!arrive_last(ticket, gridDim.x)) return;
   final_reduce<NV>(partials, gridDim.x, lds, res);
-  mrs_scalar_update<T, NR, KF, REC>(st, res, k, tail, st_fixed, st_maxit, st_tol, t, L.sign);
+  mrs_scalar_update<T, NR, KF>(st, res, k, tail, st_fixed, st_maxit, st_tol, t, L.sign);
   reset_ticket(ticket);
 }
 
@@ -1244,19 +1221,14 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
   do {                                                                                                 \
     if constexpr (sizeof(T) == 8) {                                                                    \
       if (L.q32) {                                                                                     \
-        hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false, float>), dim3(J.nblocks), dim3(WG), lds, \
+        hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, float>), dim3(J.nblocks), dim3(WG), lds,       \
                            s, L, J, Q, buf, st, red.partials, red.tickets + 1);                        \
         break;                                                                                         \
       }                                                                                                \
     }                                                                                                  \
-    hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, false>), dim3(J.nblocks), dim3(WG), lds, s, L, J, \
+    hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE>), dim3(J.nblocks), dim3(WG), lds, s, L, J,        \
                        Q, buf, st, red.partials, red.tickets + 1);                                     \
   } while (0)
-  if (L.rec && L.k > 0) {
-    hipLaunchKernelGGL((k_mrs_iter<T, NR, 0, STAGE, true>), dim3(J.nblocks), dim3(WG), lds, s, L, J, Q,
-                       buf, st, red.partials, red.tickets + 1);
-    return;
-  }
   switch (kf) {
     case 0: ASSS_ITER(0); break;
     case 8: ASSS_ITER(8); break;
@@ -1266,30 +1238,6 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
       break;
   }
 #undef ASSS_ITER
-}
-
-template <typename T, int NR>
-__global__ void k_mrs_y1(int64_t n, int k, const T* __restrict__ Q, const MrsState* st,
-                         T* __restrict__ y1) {
-  __shared__ double cv[NR][KMAX];
-  for (int e = threadIdx.x; e < NR * KMAX; e += WG) cv[e / KMAX][e % KMAX] = st->cvec[e];
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
-    double acc[NR];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-    for (int l = 0; l < k; ++l) {
-      const double q = (double)Q[(int64_t)l * n + i];
-#pragma unroll
-      for (int c = 0; c < NR; ++c) acc[c] += q * cv[c][l];
-    }
-#pragma unroll
-    for (int c = 0; c < NR; ++c) y1[i * NR + c] = (T)acc[c];
-  }
-}
-template <typename T, int NR>
-void mrs_make_y1(const MrsLaunch& L, const T* Q, MrsBufs<T>& buf, const MrsState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_mrs_y1<T, NR>), grid_for(L.n), dim3(WG), 0, s, L.n, L.k, Q, st, buf.y1);
 }
 
 template <typename T, int NR>
@@ -1362,7 +1310,7 @@ void permute_scatter(int64_t n, const int32_t* perm, const double* x, double* y,
                                 MrsState*, Reducer&, hipStream_t);                                 \
   template void mrs_output<T, NR>(int64_t, int, const MrsBufs<T>&, const int32_t*, double*, int64_t, \
                                   hipStream_t);                                                    \
-  template void mrs_make_y1<T, NR>(const MrsLaunch&, const T*, MrsBufs<T>&, const MrsState*, hipStream_t);
+
 ASSS_MRS_INST(double, 1)
 ASSS_MRS_INST(float, 1)
 ASSS_MRS_INST(double, 4)

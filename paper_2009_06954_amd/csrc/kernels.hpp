@@ -49,8 +49,6 @@ struct MrsCol {
   double beta_prev;   // beta_{t-1}
   double theta1, c_old, s_old, delta_old, g, r0;
   double pend_theta, pend_delta, pend_coef;
-  // recurrence form of the deflation coefficients: Q_k^T q_t = ra d_1 + rb e_k
-  double ra, rb, ra_old, rb_old;
   int32_t has_pending, live;
 };
 
@@ -72,7 +70,6 @@ struct MrsBufs {
   T* w[3];
   T* p[2];
   T* x;
-  T* y1;  // Q_k S_k Q_k^T q_1 per column (recurrence deflation only)
 };
 
 struct Reducer {
@@ -133,13 +130,6 @@ struct MrsLaunch {
   int k;            // deflation vectors (0 = none)
   const double* alpha_dev;  // k-1 skew-Lanczos coefficients
   int sign;         // +1: K = J_bar,  -1: K = -J_bar
-  // Recurrence deflation (rec = 1): with J_tilde Q_k = Q_k S_k + f e_k^T and
-  // Q_k^T Q_k = I, Q_k^T (J_bar q) = -(f^T q) e_k, so Q_k^T q_t stays in
-  // span{Q_k^T q_1, e_k}; Q_k S_k Q_k^T q_t = ra y1 + rb alpha_{k-1} q_{k-1}.
-  int rec;
-  const void* f;    // Lanczos residual J_tilde q_k - alpha_{k-1} q_{k-1} (inner precision)
-  const void* qk1;  // q_{k-1} (inner precision), nullptr when k = 1
-  double alpha_last;  // alpha_{k-1} (0 when k = 1)
   // Q_k in sliced layout for the iteration kernel: row i, column l at
   // (i / 64) * (k * 64) + l * 64 + i % 64 (each 64-row slice contiguous)
   const void* Qs;
@@ -164,10 +154,6 @@ void mrs_init(const MrsLaunch& L, const double* rhs, int64_t ldr, const int32_t*
 template <typename T, int NR>
 void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf, MrsState* st,
               Reducer& red, hipStream_t s);
-
-// y1 = Q_k (S_k d_1) per column from the state written by mrs_init (recurrence mode).
-template <typename T, int NR>
-void mrs_make_y1(const MrsLaunch& L, const T* Q, MrsBufs<T>& buf, const MrsState* st, hipStream_t s);
 
 // Copy the inner solution out: out (FP64, column c at out + c * ldo) = x.
 template <typename T, int NR>

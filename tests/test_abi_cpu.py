@@ -104,3 +104,23 @@ def test_load_rejects_bad_files_without_gpu(tmp_path):
     trunc.write_bytes(b"ASSSSAV1" + (5).to_bytes(8, "little") + b"\x00" * 12)
     assert lib.asss_load(str(trunc).encode(), None, None, ctypes.byref(out)) == -1
     assert b"truncated" in lib.asss_last_error() and not out.value
+
+
+@pytest.mark.parametrize("field,value,word", [("deflation", 2, b"deflation"), ("reorder", 2, b"reorder"),
+                                              ("deflation", 4, b"deflation"), ("k", 33, b"k must")])
+def test_unprovided_modes_are_refused_without_gpu(field, value, word):
+    """Options are checked before any device call: the recurrence form of the
+    deflation (deflation = 2, unstable) and the BFS block order (reorder = 2)
+    are not provided and, like out-of-range values, give INVALID_ARG."""
+    import numpy as np
+    asss, lib = _lib()
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    ci = np.array([0, 1], dtype=np.int32)
+    va = np.array([1.0, 2.0])
+    csr = asss.CsrT(2, 2, rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    o = asss.SetupOpts()
+    lib.asss_default_setup_opts(ctypes.byref(o))
+    setattr(o, field, value)
+    out = ctypes.c_void_p()
+    assert lib.asss_setup(ctypes.byref(csr), ctypes.byref(o), None, ctypes.byref(out)) == -1
+    assert word in lib.asss_last_error() and not out.value

@@ -150,6 +150,29 @@ def test_skew_and_deflated_operators(cfg0, fp32):
         _within_rounding(_np(out), ref, bound + (1e-10 / 1e-11) * defl)
 
 
+def test_skew_kernel_against_exported_matrix(cfg0):
+    """The kernel alone: the sliced skew SpMV reproduces J_tilde v from the
+    library's own exported CSR within 64 eps (|J_tilde| |v|)_i (FP64), and the
+    deflated operator J_tilde v - Q_k S_k Q_k^T v from the exported Q_k and
+    alpha, with 1024 eps on the projector's length-n inner products."""
+    h, n = cfg0.h, cfg0.n
+    U = sp.csr_matrix((h.array("J_val"), h.array("J_colind"), h.array("J_rowptr")), shape=(n, n))
+    J = (U - U.T).tocsr()
+    k = h.info()["k_eff"]
+    Q = h.array("Q").reshape(k, n).T
+    al = h.array("alpha")
+    Sk = np.diag(al, 1) - np.diag(al, -1)
+    v = np.random.default_rng(12).standard_normal(n)
+    bound = abs(J) @ np.abs(v)
+    out, _ = h.apply("skew", _cuda(v))
+    err = np.abs(_np(out) - J @ v) / (bound + 1e-300)
+    assert np.max(err) <= 64 * EPS, float(np.max(err))
+    ref = J @ v - Q @ (Sk @ (Q.T @ v))
+    bd = 64 * EPS * bound + 1024 * EPS * (np.abs(Q) @ (np.abs(Sk) @ (np.abs(Q).T @ np.abs(v))))
+    out, _ = h.apply("deflated", _cuda(v))
+    assert np.all(np.abs(_np(out) - ref) <= bd)
+
+
 def test_skew_operator_ragged_blocks():
     """Several LDS row blocks with a ragged tail (n = 45^2 = 2025, R = 64)."""
     w = W.config(0)
@@ -430,65 +453,33 @@ def test_small_k(k):
     assert _rel(_np(x), xo) <= 1e-10
 
 
-@pytest.mark.parametrize("mode", ["explicit", "recurrence"])
-def test_deflation_forms(mode):
-    """Both forms of the deflation term in the inner step reproduce the
-    oracle's explicit projector (Sec. 3.2); the recurrence form relies on
-    Q_k^T Q_k = I, so its deviation is bounded by the measured loss of
-    orthogonality."""
+def test_deflation_explicit():
+    """The explicit projector in the fused inner step reproduces the oracle's
+    (Sec. 3.2) over fixed step counts; solves, mixed solves and the adjoint
+    (K = -J_bar) follow."""
     asss = _lib()
     w = W.config(0)
     st = O.setup(w.A, O.SetupOptions(k=8))
-    h = asss.setup(w.A, k=8, deflation=mode)
+    h = asss.setup(w.A, k=8, deflation="explicit")
     info = h.info()
-    assert info["deflation_mode"] == (1 if mode == "explicit" else 2)
-    orth = info["lanczos_orth_err"]
-    print(f"[deflation {mode}] orth_err={orth:.2e}")
+    assert info["deflation_mode"] == 1
+    print(f"[deflation] orth_err={info['lanczos_orth_err']:.2e}")
     v = np.random.default_rng(21).standard_normal(w.A.shape[0])
-    # the recurrence form drifts from the projector after a few dozen steps
-    # (it is unstable); it is compared over short runs only
-    for steps in ((1, 2, 3, 10, 30) if mode == "explicit" else (1, 2, 3, 10)):
+    for steps in (1, 2, 3, 10, 30):
         ref, _, _ = O.mrs(1.0, st.prec.jbar, v, steps, 0.0, fixed_steps=steps)
         out, its = h.apply("mrs", _cuda(v), fixed_inner_steps=steps)
         err = _rel(_np(out), ref)
-        assert err <= (1e-12 if mode == "explicit" else max(1e-12, 100 * orth)), (steps, err)
+        assert err <= 1e-12, (steps, err)
     for fp32 in (False, True):
         xo, io = O.solve(st, w.b, O.SolveOptions(tol=1e-12))
         x, inf = h.solve(_cuda(w.b), tol=1e-12 if not fp32 else 1e-8, inner_fp32=fp32)
         assert inf["status"] == "OK"
         assert _rel(_np(x), xo) <= (1e-10 if not fp32 else 1e-7)
-    # the adjoint runs the inner solve with K = -J_bar
     g = np.random.default_rng(22).standard_normal(w.A.shape[0])
     lo, _ = O.solve_adjoint(st, g, O.SolveOptions(tol=1e-12))
     lam, inf = h.solve_adjoint(_cuda(g), tol=1e-12)
     assert inf["status"] == "OK" and _rel(_np(lam), lo) <= 1e-9
-
-
-def test_block_reordering_is_invisible():
-    """The inner system may run in a block order (a symmetric permutation of
-    J_tilde); inner solves, P^-1, the exported Q and full solves must not
-    depend on it beyond rounding."""
-    asss = _lib()
-    w = W.config(0, m=40)
-    st = O.setup(w.A, O.SetupOptions(k=6))
-    hn = asss.setup(w.A, k=6, reorder="none", row_block=64)
-    hb = asss.setup(w.A, k=6, reorder="blocks", row_block=64)
-    ib, inn = hb.info(), hn.info()
-    assert ib["reordered"] == 1 and inn["reordered"] == 0
-    assert ib["cross_pairs_used"] < inn["cross_pairs_used"]
-    print(f"[reorder] cross pairs {inn['cross_pairs_used']} -> {ib['cross_pairs_used']}, "
-          f"part-a {inn['sell_entries_a']} -> {ib['sell_entries_a']}, part-b {inn['sell_entries_b']} -> {ib['sell_entries_b']}")
-    assert _rel(hb.array("Q").reshape(6, -1).T, st.Q) <= 1e-10
-    v = np.random.default_rng(31).standard_normal(w.A.shape[0])
-    for op, ref in (("skew", st.prec.jtilde(v)), ("mrs", O.mrs(1.0, st.prec.jbar, v, 20, 0.0, 20)[0])):
-        kw = {"fixed_inner_steps": 20} if op == "mrs" else {}
-        ob, _ = hb.apply(op, _cuda(v), **kw)
-        on, _ = hn.apply(op, _cuda(v), **kw)
-        assert _rel(_np(ob), _np(on)) <= 1e-12
-        assert _rel(_np(ob), ref) <= 1e-10
-    xo, _ = O.solve(st, w.b, O.SolveOptions(tol=1e-12))
-    xb, ib2 = hb.solve(_cuda(w.b), tol=1e-12)
-    assert ib2["status"] == "OK" and _rel(_np(xb), xo) <= 1e-10
+    h.close()
 
 
 # ---- TFQMR outer iteration (the outer method of the paper's experiments) ----
@@ -610,10 +601,14 @@ def test_torch_allocator():
     """With allocator="torch" every device buffer of the handle comes from
     torch's caching allocator (setup and the workspace grown by the first
     solve) and goes back to it at destroy."""
+    import gc
     asss = _lib()
     w = W.config(0)
     b = _cuda(w.b)
     x = torch.empty_like(b)
+    # tensors of earlier tests that are only garbage now must not be freed
+    # while this test counts
+    gc.collect()
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     h = asss.setup(w.A, k=8, s_pattern="tridiag", allocator="torch")

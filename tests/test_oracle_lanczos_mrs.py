@@ -128,3 +128,27 @@ def test_mrs_zero_column_and_stop_rule():
     X, its, hist = O.mrs(1.0, K, B, 500, 1e-10)
     assert np.all(X[:, 2] == 0)
     assert hist[-1].max() < 1e-10 and hist[-2].max() >= 1e-10
+
+
+def test_mrs_fp32_storage_reading():
+    """storage=np.float32 stores every basis vector as an FP32 value: with
+    float64 storage it is the plain method bit for bit; with float32 on a
+    well-conditioned operator it stays within FP32 rounding of the FP64
+    result and keeps the minimal-residual decrease."""
+    import oracle as O
+    rng = np.random.default_rng(3)
+    n = 300
+    K = rng.standard_normal((n, n)) * 0.05
+    K = K - K.T
+    b = rng.standard_normal(n)
+    op = lambda v: K @ v
+    x64, its, h64 = O.mrs(1.0, op, b, 40, 0.0, fixed_steps=40)
+    xs, _, hs = O.mrs(1.0, op, b, 40, 0.0, fixed_steps=40, storage=np.float64)
+    assert np.array_equal(x64, xs) and np.array_equal(h64, hs)
+    seen = []
+    op_rec = lambda v: (seen.append(v.copy()), K @ v)[1]
+    x32, _, h32 = O.mrs(1.0, op_rec, b, 40, 0.0, fixed_steps=40, storage=np.float32)
+    for v in seen:  # every vector the operator saw is FP32-valued
+        assert np.array_equal(v, v.astype(np.float32).astype(np.float64))
+    assert np.linalg.norm(x32 - x64) <= 1e-5 * np.linalg.norm(x64)
+    assert np.all(np.diff(h32[:, 0]) <= 1e-12)
