@@ -247,6 +247,24 @@ asss_status_t asss_setup(const asss_csr_t* A, const asss_setup_opts_t* opts,
 asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev,
                          const asss_solve_opts_t* o, asss_info_t* info, void* hip_stream);
 
+/* For callers that cannot allocate device memory during a solve (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * asss_solve with the Krylov workspace (FGMRES: 2 restart_m + 1 vectors;
+ * TFQMR: 13) and the two vectors of a solve from x0 placed in a fixed device
+ * array of 128 MiB that the library holds per GPU until the process ends,
+ * instead of memory the handle allocates (asss_solve grows the handle's
+ * workspace on first use).  It calls no hipMalloc, hipFree or allocating
+ * routine; the handle itself comes from asss_setup as usual, and b, x are the
+ * caller's.  Limit: n (2 m + 3) 8 bytes <= 128 MiB with m = restart_m (FGMRES)
+ * or 6 (TFQMR), e.g. n <= 127,000 at m = 64; larger problems are refused with
+ * ASSS_ERR_INVALID_ARG and a message giving both sizes.  Results equal those of
+ * asss_solve with the same options.  Every call on a GPU shares that GPU's
+ * array and leaves its contents behind (nothing in it must start at zero):
+ * calls that overlap in time on one GPU, from any thread or stream, race and
+ * must not be made. */
+asss_status_t asss_solve_noalloc(asss_handle_t h, const double* b_dev, double* x_dev,
+                                 const asss_solve_opts_t* o, asss_info_t* info, void* hip_stream);
+
 /* lambda = A^-T g: the same scheme on the transposed system, with P^-T
  * applied as S_bar^-T (v - U_bar Sigma_bar^T C^-T X^T v) (derived from eq.
  * smw by transposition). */

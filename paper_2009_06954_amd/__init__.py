@@ -37,7 +37,7 @@ ARRAYS = {"match": (0, np.int32), "Dr": (1, np.float64), "Dc": (2, np.float64),
           "X": (12, np.float64), "neg": (13, np.int32)}
 
 EXPORTED = ["asss_default_setup_opts", "asss_default_solve_opts", "asss_setup", "asss_solve",
-            "asss_solve_adjoint", "asss_solve_batched", "asss_destroy", "asss_last_error",
+            "asss_solve_noalloc", "asss_solve_adjoint", "asss_solve_batched", "asss_destroy", "asss_last_error",
             "asss_get_handle_info", "asss_get_array", "asss_apply", "asss_update_values",
             "asss_value_gradient", "asss_save", "asss_load"]
 
@@ -150,6 +150,7 @@ def load(path: str = LIB_PATH):
     lib.asss_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
                                C.POINTER(Info), C.c_void_p]
     lib.asss_solve_adjoint.argtypes = lib.asss_solve.argtypes
+    lib.asss_solve_noalloc.argtypes = lib.asss_solve.argtypes
     lib.asss_solve_batched.argtypes = [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                        C.POINTER(SolveOpts), C.POINTER(Info), C.c_void_p]
@@ -260,6 +261,22 @@ class Handle:
         info = Info()
         st = _check(load().asss_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                       C.byref(solve_options(**opts)), C.byref(info), _stream(stream)))
+        d = info.to_dict()
+        d["status"] = _STATUS_NAMES[st]
+        return x, d
+
+    def solve_noalloc(self, b, out, stream=None, x0=None, **opts):
+        """x = A^-1 b through asss_solve_noalloc (no device allocation inside
+        the call; the workspace is the library's fixed array).  `out` is the
+        caller's x (contiguous CUDA float64, length n).  Returns (out, info)."""
+        b = self._vec(b)
+        x = self._vec(out)
+        if x0 is not None:
+            x.copy_(self._vec(x0))
+        opts["use_x0"] = x0 is not None
+        info = Info()
+        st = _check(load().asss_solve_noalloc(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                              C.byref(solve_options(**opts)), C.byref(info), _stream(stream)))
         d = info.to_dict()
         d["status"] = _STATUS_NAMES[st]
         return x, d

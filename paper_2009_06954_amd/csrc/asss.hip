@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <optional>
 #include <string>
 #include <thread>
@@ -24,6 +25,13 @@
 #include "kernels.hpp"
 
 using namespace asss;
+
+// Workspace of asss_solve_noalloc: one fixed device array per GPU, held until
+// the process ends, instead of Krylov workspace the handle would allocate.
+// Host code never uses the array's name as a device address: the address of
+// each device's copy comes from hipGetSymbolAddress (noalloc_scratch).
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;  // 128 MiB
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
 
 namespace {
 
@@ -282,6 +290,7 @@ struct asss_handle_s {
   MrsBufs<float> mb4_32{};
   double *w = nullptr, *t1 = nullptr, *xchk = nullptr, *bchk = nullptr, *rv = nullptr, *tmp = nullptr;
   double *x0r = nullptr, *x0d = nullptr;  // residual and correction of a solve from x0
+  bool no_alloc = false;  // a call of asss_solve_noalloc is running: never allocate
   int last_inner = 0;
   // HIP events bracketing each chunk of back-to-back mrs iteration kernels
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -882,6 +891,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
 
 void ensure_outer(asss_handle_s* h, int m) {
   if (h->m_alloc >= m) return;
+  if (h->no_alloc) throw Error{ASSS_ERR_INTERNAL, "the fixed workspace is smaller than the solve needs"};
   if (h->V) { h->ar.release(h->V); h->ar.release(h->Z); }
   h->V = h->ar.alloc<double>(h->n * (int64_t)(m + 1));
   h->Z = h->ar.alloc<double>(h->n * (int64_t)m);
@@ -1359,6 +1369,7 @@ asss_status_t outer_solve(asss_handle_s* h, bool adjoint, const double* b, doubl
   const int64_t n = h->n;
   if (!b_is_finite(h, x, s)) throw Error{ASSS_ERR_NONFINITE, "x0 has a non-finite entry"};
   if (!h->x0r) {
+    if (h->no_alloc) throw Error{ASSS_ERR_INTERNAL, "no workspace for a solve from x0"};
     h->x0r = h->ar.alloc<double>(n);
     h->x0d = h->ar.alloc<double>(n);
   }
@@ -1399,6 +1410,50 @@ asss_status_t outer_solve(asss_handle_s* h, bool adjoint, const double* b, doubl
   if (info) *info = inf;
   return inf.converged ? ASSS_OK : ASSS_NOT_CONVERGED;
 }
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device with that device current and kept.
+double* noalloc_scratch(int device) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != device) HIPCHK(hipSetDevice(device));
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) HIPCHK(hipSetDevice(cur));
+  HIPCHK(e);
+  if (!p) throw Error{ASSS_ERR_HIP, "hipGetSymbolAddress gave no address for the fixed workspace"};
+  addr[device] = (double*)p;
+  return (double*)p;
+}
+
+// Points the handle's Krylov workspace (m columns) and the buffers of a
+// solve from x0 into the fixed scratch for one call, forbids allocation, and
+// puts the handle's own workspace back afterwards (also when the call throws).
+struct ScratchWorkspace {
+  asss_handle_s* h;
+  double *V, *Z, *x0r, *x0d;
+  int m_alloc;
+  ScratchWorkspace(asss_handle_s* h_, double* base, int m)
+      : h(h_), V(h_->V), Z(h_->Z), x0r(h_->x0r), x0d(h_->x0d), m_alloc(h_->m_alloc) {
+    const int64_t n = h->n;
+    h->V = base;
+    h->Z = base + n * (int64_t)(m + 1);
+    h->x0r = h->Z + n * (int64_t)m;
+    h->x0d = h->x0r + n;
+    h->m_alloc = m;
+    h->no_alloc = true;
+  }
+  ~ScratchWorkspace() {
+    h->V = V; h->Z = Z; h->x0r = x0r; h->x0d = x0d;
+    h->m_alloc = m_alloc;
+    h->no_alloc = false;
+  }
+};
 
 void check_handle(asss_handle_s* h) {
   if (!h) throw Error{ASSS_ERR_INVALID_ARG, "null handle"};
@@ -1723,6 +1778,36 @@ asss_status_t asss_solve(asss_handle_t h, const double* b_dev, double* x_dev, co
     if (oo.outer != ASSS_OUTER_FGMRES && oo.outer != ASSS_OUTER_TFQMR)
       throw Error{ASSS_ERR_INVALID_ARG, "outer must be ASSS_OUTER_FGMRES or ASSS_OUTER_TFQMR"};
     if (!b_is_finite(h, b_dev, s)) throw Error{ASSS_ERR_NONFINITE, "b has a non-finite entry"};
+    return outer_solve(h, false, b_dev, x_dev, oo, info, s);
+  });
+}
+
+asss_status_t asss_solve_noalloc(asss_handle_t h, const double* b_dev, double* x_dev, const asss_solve_opts_t* o,
+                                 asss_info_t* info, void* hip_stream) {
+  Range range("asss_solve_noalloc");
+  return guarded([&]() -> asss_status_t {
+    check_handle(h);
+    if (!b_dev || !x_dev) throw Error{ASSS_ERR_INVALID_ARG, "null vector"};
+    if (overlaps(b_dev, h->n, x_dev, h->n)) throw Error{ASSS_ERR_INVALID_ARG, "b and x overlap"};
+    hipStream_t s = (hipStream_t)hip_stream;
+    asss_solve_opts_t oo = opts_or_default(o);
+    if (oo.restart_m < 1 || oo.restart_m > 250) throw Error{ASSS_ERR_INVALID_ARG, "restart_m must be in [1, 250]"};
+    if (oo.outer != ASSS_OUTER_FGMRES && oo.outer != ASSS_OUTER_TFQMR)
+      throw Error{ASSS_ERR_INVALID_ARG, "outer must be ASSS_OUTER_FGMRES or ASSS_OUTER_TFQMR"};
+    // FGMRES(m): V (m + 1 vectors) and Z (m); TFQMR: 7 + 6 vectors; x0: 2 more
+    const int m = oo.outer == ASSS_OUTER_TFQMR ? 6 : oo.restart_m;
+    const uint64_t need = (uint64_t)h->n * (uint64_t)(2 * m + 3) * sizeof(double);
+    if (need > kNoAllocBytes) {
+      char msg[200];
+      std::snprintf(msg, sizeof msg,
+                    "asss_solve_noalloc needs n (2 m + 3) 8 = %llu bytes of workspace (n = %lld, m = %d); "
+                    "its fixed workspace holds %llu",
+                    (unsigned long long)need, (long long)h->n, m, (unsigned long long)kNoAllocBytes);
+      throw Error{ASSS_ERR_INVALID_ARG, msg};
+    }
+    double* base = noalloc_scratch(h->device);
+    if (!b_is_finite(h, b_dev, s)) throw Error{ASSS_ERR_NONFINITE, "b has a non-finite entry"};
+    ScratchWorkspace ws(h, base, m);
     return outer_solve(h, false, b_dev, x_dev, oo, info, s);
   });
 }
