@@ -208,6 +208,15 @@ typedef struct {
                               the initial guess x0 on entry (NONFINITE if it has NaN/Inf);
                               the outer method corrects r0 = b - A x0 to tol ||b|| and
                               returns x0 + d.  Batched solves then run column by column */
+  int32_t batch_engine;    /* asss_solve_batched only: 0 (default) = all systems in one lockstep
+                              (rows of all systems concatenated; one persistent work-queue
+                              launch per inner step for every system, captured in HIP graph
+                              chunks; segmented outer kernels; one host round trip per outer
+                              step for all columns) when every system qualifies (FGMRES from
+                              zero, no fixed inner steps, <= 4 right-hand sides, k <= 16,
+                              k + r <= 256, natural inner order, one device, one inner
+                              precision), else per-system workers; 1 = the lockstep engine or
+                              INVALID_ARG; 2 = per-system workers */
 } asss_solve_opts_t;
 
 enum { ASSS_OUTER_FGMRES = 0, ASSS_OUTER_TFQMR = 1 };

@@ -90,7 +90,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart_m", C.c_int32), ("max_outer", C.c_int32),
                 ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("fixed_inner_steps", C.c_int32), ("inner_fp32", C.c_int32), ("outer", C.c_int32),
-                ("batch_streams", C.c_int32), ("use_x0", C.c_int32)]
+                ("batch_streams", C.c_int32), ("use_x0", C.c_int32), ("batch_engine", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -207,7 +207,7 @@ OUTER = {"fgmres": 0, "tfqmr": 1}
 
 def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_maxit=1000,
                   fixed_inner_steps=0, inner_fp32=None, outer="fgmres", batch_streams=0,
-                  use_x0=False) -> SolveOpts:
+                  use_x0=False, batch_engine="auto") -> SolveOpts:
     o = SolveOpts()
     load().asss_default_solve_opts(C.byref(o))
     o.tol, o.restart_m, o.max_outer = tol, restart_m, max_outer
@@ -216,6 +216,7 @@ def solve_options(tol=1e-8, restart_m=64, max_outer=2000, inner_tol=1e-5, inner_
     o.outer = OUTER[outer]
     o.batch_streams = batch_streams
     o.use_x0 = int(bool(use_x0))
+    o.batch_engine = {"auto": 0, "lockstep": 1, "workers": 2}[batch_engine]
     return o
 
 

@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(tmp, "host_setup.o")
         _run([gxx, *HOST_FLAGS, "-c", os.path.join(CSRC, "host_setup.cpp"), "-o", o])
         objs.append(o)
-        for src in ("kernels.hip", "asss.hip"):
+        for src in ("kernels.hip", "asss.hip", "batch.hip"):
             o = os.path.join(tmp, src.replace(".hip", ".o"))
             _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
             objs.append(o)

@@ -6,6 +6,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,10 +22,13 @@
 #include <vector>
 
 #include "../../include/asss.h"
+#include "batch.hpp"
+#include "handle.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
 
 using namespace asss;
+using namespace asss::host;
 
 // Workspace of asss_solve_noalloc: one fixed device array per GPU, held until
 // the process ends, instead of Krylov workspace the handle would allocate.
@@ -37,30 +41,6 @@ namespace {
 
 thread_local std::string g_err = "";
 
-// roctx range around a phase (setup stages, a solve, an outer step, an inner
-// solve): visible in a rocprofv3 --marker-trace, a no-op call otherwise.
-struct Range {
-  explicit Range(const char* name) { roctxRangePushA(name); }
-  ~Range() { roctxRangePop(); }
-  Range(const Range&) = delete;
-  Range& operator=(const Range&) = delete;
-};
-
-struct Error {
-  int code;
-  std::string msg;
-};
-
-#define HIPCHK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      throw Error{e_ == hipErrorOutOfMemory ? ASSS_ERR_OOM : ASSS_ERR_HIP,                  \
-                  std::string(#expr) + ": " + hipGetErrorString(e_)};                       \
-  } while (0)
-
-// leading part of MrsState read back by the host: its, status, ..., relres_max
-constexpr size_t kStateHead = offsetof(MrsState, relres_max) + sizeof(double);
 // layout of the small device/pinned scalar buffers (doubles)
 // d_small / h_small layout: [0, 2048) Arnoldi scratch, 512 doubles per lockstep
 // column (the Gram-Schmidt coefficients of the first pass and the new norm at
@@ -69,55 +49,10 @@ constexpr size_t kStateHead = offsetof(MrsState, relres_max) + sizeof(double);
 constexpr int SM_COL = 512, SM_PASS2 = 256, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
 static_assert(4 * SM_COL <= SM_T, "Arnoldi scratch of four columns");
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
+}  // namespace
 
-// Device allocations owned by a handle.
-struct DevArena {
-  std::vector<void*> ptrs;
-  asss_allocator_t al{};  // al.alloc == nullptr: hipMalloc / hipFree
-  DevArena() = default;
-  explicit DevArena(const asss_allocator_t& a) : al(a) {}
-  DevArena(const DevArena&) = delete;
-  DevArena& operator=(const DevArena&) = delete;
-  template <typename T>
-  T* alloc(int64_t count) {
-    if (count <= 0) count = 1;
-    const size_t bytes = (size_t)count * sizeof(T);
-    void* p = nullptr;
-    if (al.alloc) {
-      p = al.alloc(bytes, al.ctx);
-      if (!p) throw Error{ASSS_ERR_OOM, "the caller's allocator returned no memory"};
-    } else {
-      const hipError_t e = hipMalloc(&p, bytes);
-      if (e == hipErrorOutOfMemory) throw Error{ASSS_ERR_OOM, "hipMalloc: out of device memory"};
-      HIPCHK(e);
-    }
-    ptrs.push_back(p);
-    return (T*)p;
-  }
-  template <typename T>
-  T* upload(const std::vector<T>& v, hipStream_t s) {
-    T* p = alloc<T>((int64_t)v.size());
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return p;
-  }
-  void give_back(void* p) {
-    if (al.alloc) al.free(p, al.ctx);
-    else (void)hipFree(p);
-  }
-  void release(void* p) {
-    auto it = std::find(ptrs.begin(), ptrs.end(), p);
-    if (it != ptrs.end()) {
-      give_back(*it);
-      ptrs.erase(it);
-    }
-  }
-  ~DevArena() {
-    for (void* p : ptrs) give_back(p);
-  }
-};
+namespace asss {
+namespace host {
 
 // SpMV kernel shape: one row per thread when no row has more than 32 entries
 // (grid stencils, the least-squares matrices of App. A), else the smallest
@@ -172,14 +107,6 @@ DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32
 
 // One sliced layout of J_tilde on the device, in both precisions (the index
 // arrays are shared), with the list of its buffers so that it can be replaced.
-struct SkewLayout {
-  DSkew<double> J64;
-  DSkew<float> J32;
-  std::vector<const void*> bufs;
-  int64_t a_entries = 0, b_entries = 0;
-  int narrow = 0;
-  int form = SKEW_WIDE;
-};
 
 SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s) {
   SkewLayout L;
@@ -219,90 +146,8 @@ void release_layout(DevArena& ar, SkewLayout& L, hipStream_t s) {
   L = SkewLayout{};
 }
 
-}  // namespace
-
-struct asss_handle_s {
-  int device = 0;
-  int64_t n = 0;
-  asss_setup_opts_t opts{};
-  DevArena ar;  // every device buffer of the handle (caller's allocator if given)
-  // host data kept for inspection
-  std::vector<int32_t> m;
-  std::vector<double> Dr, Dc, D, Omega, alpha;
-  Csr S, U;
-  std::vector<double> jval;
-  std::vector<int32_t> neg;
-  int64_t nnz_a = 0, nnz_ahat = 0, lls_rows = 0, lls_nnz = 0;
-  int lls_its = 0, x_its = 0;
-  double lls_relres = 0, lls_kkt = 0;
-  int64_t sell_a = 0, sell_b = 0;
-  int k_eff = 0, r = 0, kr = 0;
-  double setup_host_s = 0, setup_device_s = 0;
-  // device data
-  DCsr dA, dAt, dAbar, dAbarT, dS, dSt;
-  Csr Apat;  // pattern of A as stored (explicit zeros dropped), for value updates
-  int32_t* d_m = nullptr;
-  double *d_drp = nullptr, *d_om = nullptr, *d_dc = nullptr;
-  DSkew<double> J64;
-  DSkew<float> J32;
-  std::vector<const void*> lay_bufs;  // buffers of the J64 / J32 layout
-  // row-block autotuner: candidates timed at setup (row_block, us per inner step)
-  std::vector<std::pair<int, double>> tuned;
-  double tune_s = 0.0;
-  // a deflation basis given by the caller (setup option q_basis), until device_setup
-  std::vector<double> q_given, alpha_given;
-  // inner system in block order: row i of the inner system is row perm[i]
-  std::vector<int32_t> perm;
-  int32_t* d_perm = nullptr;  // null when the natural order is kept
-  int64_t cross_natural = 0, cross_used = 0;
-  int narrow_b = 0;  // part-b columns stored as 16-bit deltas
-  int skew_form = 0; // column form of the sliced J_tilde (SKEW_*)
-  double* d_Qorig = nullptr;  // Q_k in the original order (U_bar, export)
-  double* d_Q64 = nullptr;    // Q_k in the inner (block) order
-  float* d_Q32 = nullptr;
-  double* d_Qs64 = nullptr;   // sliced copies for the inner iteration kernel
-  float* d_Qs32 = nullptr;
-  double* d_G64 = nullptr;    // Q_k^T Q_k of the FP64 and of the FP32 copy (k x k)
-  double* d_G32 = nullptr;
-  double* d_alpha = nullptr;
-  double orth_err = 0.0;      // max |Q_k^T Q_k - I|
-  double* d_Ubar = nullptr;   // n x kr column-major
-  double* d_X = nullptr;      // n x kr column-major
-  double* d_Mf = nullptr;     // C^-1 Sigma (kr x kr row-major)
-  double* d_Ma = nullptr;     // Sigma^T C^-T (kr x kr row-major)
-  MrsBufs<double> mb64{};
-  MrsBufs<float> mb32{};
-  MrsState* d_state = nullptr;
-  Reducer red;
-  double* d_small = nullptr;  // SM_SIZE doubles of scalars (layout above)
-  int* d_flag = nullptr;
-  double* h_small = nullptr;  // pinned
-  // outer workspace
-  int m_alloc = 0;
-  double *V = nullptr, *Z = nullptr;
-  // lockstep columns of a batched solve (up to NRMAX) and the 4-column inner buffers
-  struct MultiCol {
-    double *V = nullptr, *Z = nullptr, *bchk = nullptr, *xchk = nullptr, *rv = nullptr;
-  } mcol[NRMAX];
-  int m_alloc_multi = 0;
-  double *pin = nullptr, *pout = nullptr;
-  MrsBufs<double> mb4_64{};
-  MrsBufs<float> mb4_32{};
-  double *w = nullptr, *t1 = nullptr, *xchk = nullptr, *bchk = nullptr, *rv = nullptr, *tmp = nullptr;
-  double *x0r = nullptr, *x0d = nullptr;  // residual and correction of a solve from x0
-  bool no_alloc = false;  // a call of asss_solve_noalloc is running: never allocate
-  int last_inner = 0;
-  // HIP events bracketing each chunk of back-to-back mrs iteration kernels
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double prof_s = 0.0;
-  int prof_launches = 0;
-
-  ~asss_handle_s() {
-    if (h_small) (void)hipHostFree(h_small);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-  }
-};
+}  // namespace host
+}  // namespace asss
 
 namespace {
 
@@ -345,6 +190,7 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, bool one_col) {
   // which it streams faster)
   L.q32 = (!std::is_same<T, float>::value && one_col && h->opts.deflation == 3 && h->k_eff > 0) ? 1 : 0;
   L.Qs = (std::is_same<T, float>::value || L.q32) ? (const void*)h->d_Qs32 : (const void*)h->d_Qs64;
+  L.kq = h->k_eff;
   L.gram = std::is_same<T, float>::value ? h->d_G32 : h->d_G64;
   return L;
 }
@@ -1523,6 +1369,8 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     if (o.skew_form < 0 || o.skew_form > 3) throw Error{ASSS_ERR_INVALID_ARG, "skew_form must be 0, 1, 2 or 3"};
     hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<asss_handle_s> h(new asss_handle_s());
+    static std::atomic<uint64_t> next_uid{1};
+    h->uid = next_uid++;
     HIPCHK(hipGetDevice(&h->device));
     if (o.allocator) {
       if (!o.allocator->alloc || !o.allocator->free)
@@ -1756,6 +1604,7 @@ void asss_default_solve_opts(asss_solve_opts_t* o) {
   o->outer = ASSS_OUTER_FGMRES;
   o->batch_streams = 0;
   o->use_x0 = 0;
+  o->batch_engine = 0;
 }
 
 const char* asss_last_error(void) { return g_err.c_str(); }
@@ -1897,6 +1746,17 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
         if (!b_is_finite(hs[sidx], B_dev[sidx] + (int64_t)j * hs[sidx]->n, s))
           throw Error{ASSS_ERR_NONFINITE, "a right-hand side has a non-finite entry"};
     }
+    if (oo.batch_streams < 0 || oo.batch_streams > 16)
+      throw Error{ASSS_ERR_INVALID_ARG, "batch_streams must be in [0, 16]"};
+    if (oo.batch_engine < 0 || oo.batch_engine > 2)
+      throw Error{ASSS_ERR_INVALID_ARG, "batch_engine must be 0, 1 or 2"};
+    if (oo.batch_engine != 2 && batch::applies(nsys, hs, nrhs, oo))
+      return batch::run(nsys, hs, nrhs, B_dev, X_dev, oo, infos, maxr, s);
+    if (oo.batch_engine == 1)
+      throw Error{ASSS_ERR_INVALID_ARG, "the batch engine does not take these systems (it needs FGMRES from zero, no "
+                                        "fixed inner steps, at most 4 right-hand sides, 16 deflation vectors and "
+                                        "256 low-rank columns per system, the natural inner order, one device and "
+                                        "one inner precision)"};
     // Work list: systems (all right-hand sides of one handle stay together, a
     // handle is not used from two threads), largest first, dealt to up to
     // batch_streams workers -- one host thread and one stream each -- so that
@@ -1913,8 +1773,6 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
     std::sort(groups.begin(), groups.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     bool one_device = true;
     for (int sidx = 0; sidx < nsys; ++sidx) one_device &= hs[sidx]->device == hs[0]->device;
-    if (oo.batch_streams < 0 || oo.batch_streams > 16)
-      throw Error{ASSS_ERR_INVALID_ARG, "batch_streams must be in [0, 16]"};
     // 16 by default: the systems' host round trips (Givens, stop checks) leave
     // gaps on each stream that the other streams fill (64 uneven systems:
     // 1 / 4 / 8 / 16 streams 0.62 / 0.32 / 0.26 / 0.22 s)
@@ -2154,6 +2012,7 @@ asss_status_t asss_destroy(asss_handle_t h) {
     if (!h) return ASSS_OK;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
+    batch::forget(h);
     delete h;
     return ASSS_OK;
   });

@@ -102,6 +102,12 @@ __device__ __forceinline__ void publish_partials(double* partials, const double*
     store_partial(partials + (int64_t)j * gridDim.x + blockIdx.x, res[j]);
 }
 
+// The same for block g of ng blocks (a system's blocks in a batched launch).
+template <int NV>
+__device__ __forceinline__ void publish_partials_at(double* partials, const double* res, int g, int ng) {
+  for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)j * ng + g, res[j]);
+}
+
 // In the last workgroup: res[j] = sum over groups g of partials[j * ngroups + g].
 // Thread t adds groups t, t + WG, t + 2 WG, ... in that order, then the
 // workgroup reduction runs in its fixed order, so the result does not depend
@@ -918,6 +924,10 @@ __device__ void mrs_scalar_update(MrsState* st, const double* res, int k, const 
   }
 }
 
+template <int NR>
+__device__ void mrs_init_finish(const MrsLaunch& L, MrsState* st, const double* res, double tol, int maxit,
+                                int fixed);
+
 template <typename T, int NR, int KF>
 __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __restrict__ rhs,
                                                  int64_t ldr, const int32_t* __restrict__ perm,
@@ -990,6 +1000,16 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
   publish_partials<NV>(partials, res);
   if (!arrive_last(ticket, gridDim.x)) return;
   final_reduce<NV>(partials, gridDim.x, lds, res);
+  mrs_init_finish<NR>(L, st, res, tol, maxit, fixed);
+  reset_ticket(ticket);
+}
+
+// The last block of a start: the column states (r0 = ||b||, App. B's
+// initial Givens values), d = Q_k^T q_1 and c = S_k d, and the solve state.
+template <int NR>
+__device__ void mrs_init_finish(const MrsLaunch& L, MrsState* st, const double* res, double tol, int maxit,
+                                int fixed) {
+  const int k = L.k;
   __shared__ double dsh[NRMAX][KMAX];
   __shared__ int s_any;
   if (threadIdx.x == 0) s_any = 0;
@@ -1033,19 +1053,88 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
     st->alpha = 1.0;
     st->relres_max = s_any ? 1.0 : 0.0;
   }
-  reset_ticket(ticket);
 }
 
-// Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
-// 256 threads are resident per CU (1024 on the chip).
-template <typename T, int NR, int KF, bool STAGE, typename TQ = T>
-__global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
-                                                 MrsBufs<T> buf, MrsState* st, double* partials,
-                                                 unsigned* ticket) {
+// Batched start: every block of the batch (taken from the work queue) loads
+// its rows' right-hand sides, zeroes the other buffers and sums ||b||^2 and
+// Q_k^T b for its system; the last block of a system runs mrs_init_finish.
+template <typename T, int NR, int KF>
+__global__ __launch_bounds__(WG) void k_mrs_init_batched(MrsBatch B, int R, const double* __restrict__ rhs,
+                                                         int64_t ldr, MrsBufs<T> buf, double tol, int maxit,
+                                                         int fixed) {
   constexpr int NV = (KF + 1) * NR;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* acc_lds = reinterpret_cast<double*>(smem_raw);
-  T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
+  __shared__ double lds[(WG / 64) * NV];
+  __shared__ double res[NV];
+  __shared__ int s_item;
+  const T* __restrict__ Qs = reinterpret_cast<const T*>(B.Qs);
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)__hip_atomic_fetch_add(B.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int b = s_item;
+    __syncthreads();
+    if (b >= B.nblocks) {
+      if (threadIdx.x == 0 && b == B.nblocks + (int)gridDim.x - 1)
+        __hip_atomic_store(B.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    const MrsBatchSys& sys = B.sys[B.block_sys[b]];
+    const int k = sys.k;
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    const int64_t row0 = (int64_t)b * R;
+    const int64_t row1 = min(row0 + R, B.n);
+    for (int64_t i = row0 + threadIdx.x; i < row1; i += WG) {
+      double bv[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        bv[c] = rhs[(int64_t)c * ldr + i];
+        buf.w[1][i * NR + c] = (T)bv[c];
+        buf.w[0][i * NR + c] = T(0);
+        buf.w[2][i * NR + c] = T(0);
+        buf.p[0][i * NR + c] = T(0);
+        buf.p[1][i * NR + c] = T(0);
+        buf.x[i * NR + c] = T(0);
+        acc[c] += bv[c] * bv[c];
+      }
+      const T* qs = Qs + (i >> 6) * (int64_t)(B.kq * 64) + (i & 63);
+#pragma unroll
+      for (int l = 0; l < KF; ++l)
+        if (l < k) {
+          const double q = (double)qs[l * 64];
+#pragma unroll
+          for (int c = 0; c < NR; ++c) acc[(1 + l) * NR + c] += q * (double)(T)bv[c];
+        }
+    }
+    wg_reduce<NV>(acc, lds, res);
+    const int g = b - sys.first_block;
+    publish_partials_at<NV>(sys.partials, res, g, sys.nblocks);
+    if (arrive_last(sys.ticket, sys.nblocks)) {
+      final_reduce<NV>(sys.partials, sys.nblocks, lds, res);
+      MrsLaunch L{};
+      L.nr = NR;
+      L.k = k;
+      L.alpha_dev = sys.alpha;
+      L.sign = B.sign;
+      mrs_init_finish<NR>(L, sys.st, res, tol, maxit, fixed);
+      reset_ticket(sys.ticket);
+    }
+    __syncthreads();
+  }
+}
+
+// One inner step (App. B), or the final deferred update once converged, or
+// nothing once done, on rows [row0, row0 + nrow) of one system: block g of
+// that system's ng blocks, whose partial sums go to `partials` (value j of
+// block g at j * ng + g) and whose last block, found with `ticket`, runs the
+// scalar recurrence.  Shared by the one-system kernel (one block per
+// workgroup) and the batched work-queue kernel (blocks of many systems).
+template <typename T, int NR, int KF, bool STAGE, typename TQ>
+__device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T>& J, const MrsBufs<T>& buf,
+                                               MrsState* st, double* partials, unsigned* ticket,
+                                               int64_t row0, int nrow, int g, int ng, double* acc_lds,
+                                               T* w_lds) {
+  constexpr int NV = (KF + 1) * NR;
   __shared__ double lds[(WG / 64) * NV];
   __shared__ double res[NV];
   // The state was written by the previous launch and is not written before
@@ -1086,9 +1175,6 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   __shared__ MrsTail<NR, KF> tail;
   MrsTailRegs<NR, KF> tail_r;
   if (status == MRS_RUNNING) mrs_tail_load<T, NR, KF>(tail_r, st, L);
-  const int64_t n = L.n;
-  const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
-  const int nrow = (int)min((int64_t)J.R, n - row0);
   const T* __restrict__ wcur = buf.w[t % 3];
   const T* __restrict__ wold = buf.w[(t + 2) % 3];
   T* __restrict__ wnew = buf.w[(t + 1) % 3];
@@ -1108,7 +1194,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
         }
       }
     }
-    if (!arrive_last(ticket, gridDim.x)) return;
+    if (!arrive_last(ticket, ng)) return;
     if (threadIdx.x == 0) st->status = MRS_DONE;
     reset_ticket(ticket);
     return;
@@ -1143,7 +1229,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     // Q row i streams once (non-temporal for an FP64 basis, where it helps:
     // 161 -> 150 us; for an FP32 basis it costs 124 -> 132 us).  TQ = float in
     // an FP64 kernel: the basis is stored as FP32 values.
-    const TQ* __restrict__ qs = reinterpret_cast<const TQ*>(L.Qs) + (i >> 6) * (int64_t)(k * 64) + (i & 63);
+    const TQ* __restrict__ qs = reinterpret_cast<const TQ*>(L.Qs) + (i >> 6) * (int64_t)(L.kq * 64) + (i & 63);
     constexpr bool DIRECT = direct_projection<T>();
     T qrow[DIRECT ? KF1 : 1];
 #pragma unroll
@@ -1174,11 +1260,71 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
     }
   }
   wg_reduce<NV>(acc, lds, res);
-  publish_partials<NV>(partials, res);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  final_reduce<NV>(partials, gridDim.x, lds, res);
+  publish_partials_at<NV>(partials, res, g, ng);
+  if (!arrive_last(ticket, ng)) return;
+  final_reduce<NV>(partials, ng, lds, res);
   mrs_scalar_update<T, NR, KF>(st, res, k, tail, st_fixed, st_maxit, st_tol, t, L.sign);
   reset_ticket(ticket);
+}
+
+// Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
+// 256 threads are resident per CU (1024 on the chip).
+template <typename T, int NR, int KF, bool STAGE, typename TQ = T>
+__global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
+                                                 MrsBufs<T> buf, MrsState* st, double* partials,
+                                                 unsigned* ticket) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc_lds = reinterpret_cast<double*>(smem_raw);
+  T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
+  const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
+  const int nrow = (int)min((int64_t)J.R, L.n - row0);
+  mrs_iter_block<T, NR, KF, STAGE, TQ>(L, J, buf, st, partials, ticket, row0, nrow, blockIdx.x, gridDim.x,
+                                       acc_lds, w_lds);
+}
+
+// The batched inner step: one launch advances the inner solves of every
+// system of a batch by one step.  The systems' rows are concatenated (each
+// padded to whole row blocks of the common size J.R, so no block straddles
+// two systems) and the launch is persistent: a fixed number of workgroups
+// take row blocks from a device work queue (an atomic counter) until none is
+// left, so that uneven systems share the chip without one launch per system.
+// Each system keeps its own state, partial sums and ticket; the last block of
+// a system runs that system's scalar recurrence.  The workgroup that takes
+// the last ticket of the queue (nblocks + workgroups - 1: every workgroup
+// takes exactly one value past the blocks) puts the counter back to zero.
+template <typename T, int NR, int KF, bool STAGE>
+__global__ __launch_bounds__(WG, sizeof(T) == 4 ? 2 : 1) void k_mrs_iter_batched(MrsBatch B, DSkew<T> J, MrsBufs<T> buf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc_lds = reinterpret_cast<double*>(smem_raw);
+  T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)__hip_atomic_fetch_add(B.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int b = s_item;
+    __syncthreads();
+    if (b >= B.nblocks) {
+      if (threadIdx.x == 0 && b == B.nblocks + (int)gridDim.x - 1)
+        __hip_atomic_store(B.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    const MrsBatchSys& sys = B.sys[B.block_sys[b]];
+    MrsLaunch L{};
+    L.n = B.n;
+    L.nr = NR;
+    L.k = sys.k;
+    L.kq = B.kq;
+    L.alpha_dev = sys.alpha;
+    L.sign = B.sign;
+    L.Qs = B.Qs;
+    L.gram = sys.gram;
+    L.q32 = 0;
+    const int64_t row0 = (int64_t)b * J.R;
+    const int nrow = (int)min((int64_t)J.R, B.n - row0);
+    mrs_iter_block<T, NR, KF, STAGE, T>(L, J, buf, sys.st, sys.partials, sys.ticket, row0, nrow,
+                                        b - sys.first_block, sys.nblocks, acc_lds, w_lds);
+    __syncthreads();
+  }
 }
 
 // The deflation width KF is a compile-time bound (registers): the smallest of
@@ -1238,6 +1384,36 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
       break;
   }
 #undef ASSS_ITER
+}
+
+template <typename T, int NR>
+void mrs_init_batched(const MrsBatch& B, const DSkew<T>& J, const double* rhs, int64_t ldr, MrsBufs<T>& buf,
+                      double tol, int maxit, int fixed, int kf, int groups, hipStream_t s) {
+  groups = std::max(1, std::min(groups, B.nblocks));
+#define ASSS_BINIT(KF)                                                                                    \
+  hipLaunchKernelGGL((k_mrs_init_batched<T, NR, KF>), dim3(groups), dim3(WG), 0, s, B, J.R, rhs, ldr, buf, \
+                     tol, maxit, fixed)
+  switch (kf) {
+    case 0: ASSS_BINIT(0); break;
+    case 8: ASSS_BINIT(8); break;
+    default: ASSS_BINIT(16); break;
+  }
+#undef ASSS_BINIT
+}
+
+template <typename T, int NR>
+void mrs_iter_batched(const MrsBatch& B, const DSkew<T>& J, MrsBufs<T>& buf, int kf, int groups, hipStream_t s) {
+  constexpr bool STAGE = (NR == 1);
+  const size_t lds = (size_t)J.R * NR * (sizeof(double) + (STAGE ? sizeof(T) : 0));
+  groups = std::max(1, std::min(groups, B.nblocks));
+#define ASSS_BITER(KF)                                                                                    \
+  hipLaunchKernelGGL((k_mrs_iter_batched<T, NR, KF, STAGE>), dim3(groups), dim3(WG), lds, s, B, J, buf)
+  switch (kf) {
+    case 0: ASSS_BITER(0); break;
+    case 8: ASSS_BITER(8); break;
+    default: ASSS_BITER(16); break;
+  }
+#undef ASSS_BITER
 }
 
 template <typename T, int NR>
@@ -1315,5 +1491,12 @@ ASSS_MRS_INST(double, 1)
 ASSS_MRS_INST(float, 1)
 ASSS_MRS_INST(double, 4)
 ASSS_MRS_INST(float, 4)
+
+#define ASSS_BATCH_INST(T, NR)                                                                             \
+  template void mrs_init_batched<T, NR>(const MrsBatch&, const DSkew<T>&, const double*, int64_t,           \
+                                        MrsBufs<T>&, double, int, int, int, int, hipStream_t);              \
+  template void mrs_iter_batched<T, NR>(const MrsBatch&, const DSkew<T>&, MrsBufs<T>&, int, int, hipStream_t);
+ASSS_BATCH_INST(double, 4)
+ASSS_BATCH_INST(float, 4)
 
 }  // namespace asss

@@ -131,8 +131,10 @@ struct MrsLaunch {
   const double* alpha_dev;  // k-1 skew-Lanczos coefficients
   int sign;         // +1: K = J_bar,  -1: K = -J_bar
   // Q_k in sliced layout for the iteration kernel: row i, column l at
-  // (i / 64) * (k * 64) + l * 64 + i % 64 (each 64-row slice contiguous)
+  // (i / 64) * (kq * 64) + l * 64 + i % 64 (each 64-row slice contiguous;
+  // kq = k for one system, the batch's largest k in a batched launch)
   const void* Qs;
+  int kq;
   // G = Q_k^T Q_k (k x k, FP64) of Q_k as stored in the inner precision: the
   // iteration kernel forms Q_k^T q_new as Q_k^T a - sign G c (see k_mrs_iter)
   const double* gram;
@@ -140,6 +142,42 @@ struct MrsLaunch {
   // FP32 values at setup, so that the FP32 copy is exact)
   int q32;
 };
+
+// A batch of systems for the batched inner kernels: rows of all systems
+// concatenated, each system padded to whole blocks of the common row block;
+// per system its state, partial sums, ticket, Lanczos coefficients, Gram
+// matrix (FP64 kernels) and number of deflation vectors.
+struct MrsBatchSys {
+  MrsState* st;
+  double* partials;      // nblocks * RED_SLOTS values
+  unsigned* ticket;
+  const double* alpha;   // k - 1 skew-Lanczos coefficients
+  const double* gram;    // k x k, Q_k^T Q_k of the stored inner-precision basis
+  int k;                 // deflation vectors of this system (<= kq)
+  int nblocks;           // row blocks of this system
+  int first_block;       // its first block in the batch
+  int pad;
+};
+
+struct MrsBatch {
+  int64_t n;             // rows of the batch (padded)
+  int nblocks;           // row blocks of the batch
+  int kq;                // stride of the sliced basis (largest k)
+  int sign;              // +1: K = J_bar
+  const MrsBatchSys* sys;
+  const int32_t* block_sys;  // system of every block
+  unsigned* queue;           // work-queue counter (0 between launches)
+  const void* Qs;            // sliced basis of the batch (inner precision)
+};
+
+// Batched start and step (all systems of B; rhs column c of the batch at
+// rhs + c * ldr, no inner permutation).  `groups` workgroups take the row
+// blocks from B.queue.
+template <typename T, int NR>
+void mrs_init_batched(const MrsBatch& B, const DSkew<T>& J, const double* rhs, int64_t ldr, MrsBufs<T>& buf,
+                      double tol, int maxit, int fixed, int kf, int groups, hipStream_t s);
+template <typename T, int NR>
+void mrs_iter_batched(const MrsBatch& B, const DSkew<T>& J, MrsBufs<T>& buf, int kf, int groups, hipStream_t s);
 
 // Initialise: w1 = rhs (col c at rhs + c * ldr), zero the other buffers,
 // r0 = ||rhs_c||, d = Q^T q_1, c = S_k d.

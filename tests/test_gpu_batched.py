@@ -160,14 +160,14 @@ def test_batched_with_torch_allocator_and_autotune():
 
 
 def test_batch_streams_option(batch):
-    """Any number of worker streams gives the same columns up to the solve's
+    """The per-system workers: any number of worker streams gives the same columns up to the solve's
     tolerance (the in-block LDS scatter adds in a run-dependent order);
     values outside [0, 16] are refused."""
     asss, ws, nr, hs = batch
     Bs = [_colmajor(w.b[:, :r]) for w, r in zip(ws, nr)]
-    ref, _ = asss.solve_batched(hs, Bs, tol=1e-11, batch_streams=1)
+    ref, _ = asss.solve_batched(hs, Bs, tol=1e-11, batch_streams=1, batch_engine="workers")
     for ns in (2, 3, 16):
-        Xs, infos = asss.solve_batched(hs, Bs, tol=1e-11, batch_streams=ns)
+        Xs, infos = asss.solve_batched(hs, Bs, tol=1e-11, batch_streams=ns, batch_engine="workers")
         for s in range(len(ws)):
             assert all(i["converged"] == 1 for i in infos[s])
             assert _rel(Xs[s].cpu().numpy(), ref[s].cpu().numpy()) <= 1e-8
