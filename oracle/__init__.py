@@ -18,6 +18,7 @@ split       A_hat = Abar S, D, Omega, J_tilde, negative-diagonal set (Sec. 3)
 lanczos     counter-based start vector and the skew-Lanczos process (Fig. 2)
 mrs         simultaneous minimal residual iterations for (alpha I + K) x = b (App. B)
 precond     deflated operator, combined low-rank term and its SMW application (Sec. 3.2)
+ildl        Bunch-Kaufman incomplete LDL^T of M_hat, |D| factor, low-rank term (Sec. 3, Fig. 1)
 solver      outer iterations (flexible GMRES; TFQMR as in the experiments),
             back-transform, adjoint, value gradient of a solve (Sec. 3, Sec. 4.1)
 """
@@ -29,7 +30,8 @@ from .lanczos import splitmix64_uniform, start_vector, skew_lanczos
 from .mrs import mrs
 from .precond import Preconditioner
 from .solver import (SolveOptions, SetupOptions, OracleSetup, setup, solve, solve_adjoint,
-                     value_gradient)
+                     value_gradient, IldlOracleSetup, setup_ildl)
+from .ildl import IldlOptions, IldlFactor, ildl, scaled_factor, low_rank
 
 __all__ = [
     "StructurallySingular", "ZeroDiagonal", "validate_csr", "max_product_matching",
@@ -37,4 +39,6 @@ __all__ = [
     "skew_symmetrizer", "lls_gradient", "split_ahat", "splitmix64_uniform",
     "start_vector", "skew_lanczos", "mrs", "Preconditioner", "SolveOptions",
     "SetupOptions", "OracleSetup", "setup", "solve", "solve_adjoint", "value_gradient",
+    "IldlOracleSetup", "setup_ildl", "IldlOptions", "IldlFactor", "ildl", "scaled_factor",
+    "low_rank",
 ]

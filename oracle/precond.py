@@ -9,7 +9,10 @@ With Q_k, S_k from the skew-Lanczos process:
     P      = U_bar Sigma_bar U_bar^T + S_bar
 
 where U_r = [e_i : D_i < 0] (the 1x1 blocks of the low-rank decomposition of
-Fig. 1 -- with a diagonal D_tilde no 2x2 blocks arise).
+Fig. 1 -- with a diagonal D_tilde no 2x2 blocks arise).  For the general
+incomplete LDL^T (oracle.ildl) J_tilde is an operator (two triangular solves
+around J_hat) and U_r, Sigma_r come from Fig. 1 with 2x2 blocks; the
+formulas below are the same.
 
 Reading of eq. smw (the printed inner matrix (Sigma + U^T S^-1 U)^-1 needs
 Sigma^-1, and S_k is singular for odd k): the inverse-free form
@@ -35,22 +38,34 @@ from .split import jtilde_apply
 
 
 class Preconditioner:
-    def __init__(self, Jup, N, Q, alpha, x_tol=1e-10, x_maxit=2000):
+    """Jup, N: the diagonal reading (J_tilde from its strict upper triangle,
+    U_r = unit vectors at N, Sigma_r = -2 I).  jtilde, Ur, sigma_r: the
+    general one (J_tilde as an operator on vectors or column blocks, U_r and
+    the diagonal of Sigma_r given)."""
+
+    def __init__(self, Jup, N, Q, alpha, x_tol=1e-10, x_maxit=2000, jtilde=None, Ur=None,
+                 sigma_r=None):
         self.Jup = Jup
-        self.n = Jup.shape[0]
+        self._jt = jtilde
+        self.n = Q.shape[0]
         self.Q = Q
         self.k = Q.shape[1]
         self.Sk = skew_tridiagonal(alpha) if self.k > 0 else np.zeros((0, 0))
-        self.N = np.asarray(N, dtype=np.int64)
-        r = self.N.size
+        if Ur is None:
+            self.N = np.asarray(N, dtype=np.int64)
+            r = self.N.size
+            Ur = np.zeros((self.n, r))
+            Ur[self.N, np.arange(r)] = 1.0
+            sigma_r = -2.0 * np.ones(r)
+        else:
+            r = Ur.shape[1]
+            self.N = np.zeros(0, dtype=np.int64)
         self.r = r
-        Ur = np.zeros((self.n, r))
-        Ur[self.N, np.arange(r)] = 1.0
         self.U = np.concatenate([Q, Ur], axis=1)
         m = self.k + r
         self.Sigma = np.zeros((m, m))
         self.Sigma[:self.k, :self.k] = self.Sk
-        self.Sigma[self.k:, self.k:] = -2.0 * np.eye(r)
+        self.Sigma[self.k:, self.k:] = np.diag(np.asarray(sigma_r, dtype=np.float64))
         self.x_its = 0
         if m > 0:
             self.X, self.x_its, _ = mrs(1.0, self.jbar, self.U, x_maxit, x_tol)
@@ -63,6 +78,8 @@ class Preconditioner:
             self.lu = None
 
     def jtilde(self, v):
+        if self._jt is not None:
+            return self._jt(v)
         return jtilde_apply(self.Jup, v)
 
     def jbar(self, v):

@@ -38,6 +38,7 @@ import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .lanczos import DEFAULT_SEED, skew_lanczos, start_vector
@@ -93,6 +94,10 @@ class OracleSetup:
     def n(self):
         return self.A.shape[0]
 
+    @property
+    def rank_r(self):
+        return self.N.size
+
     # outer operator and its transpose (Sec. 3, eq. modified with the scaling)
     def op(self, z):
         return self.Omega * (self.Abar @ (self.S @ (self.Omega * z)))
@@ -135,6 +140,119 @@ def setup(A, opts: SetupOptions | None = None) -> OracleSetup:
     return OracleSetup(A=A, m=m, Dr=Dr, Dc=Dc, Abar=Abar, S=S, Ahat=parts["Ahat"],
                        D=parts["D"], Omega=parts["Omega"], Jup=Jup, N=parts["N"],
                        Q=Q, alpha=alpha, prec=prec, extra={"B_shape": B.shape, "B_nnz": B.nnz})
+
+
+@dataclass
+class IldlOracleSetup:
+    """The two-level scheme with the general incomplete LDL^T of M_hat
+    (Sec. 3, eqs. absfac and preconditioner; oracle.ildl).  The outer method
+    runs in the positions of the factorization:
+
+        A_chk = Lcal^-1 A_hat[perm][:, perm] Lcal^-T,
+        b_chk = Lcal^-1 (P Dr b)[perm],
+        x_hat[perm] = Lcal^-T x_chk,  x = Dc S x_hat,
+
+    right-preconditioned with P = M_r + I + J_tilde (deflated, in the SMW form
+    of oracle.precond).  The Lanczos start vector is indexed by positions."""
+    A: sp.csr_matrix
+    m: np.ndarray
+    Dr: np.ndarray
+    Dc: np.ndarray
+    Abar: sp.csr_matrix
+    S: sp.csr_matrix
+    Ahat: sp.csr_matrix
+    factor: object          # oracle.ildl.IldlFactor
+    Lcal: sp.csr_matrix
+    Mr: sp.csr_matrix
+    Ur: np.ndarray
+    sigma_r: np.ndarray
+    Ap: sp.csr_matrix       # A_hat[perm][:, perm]
+    Jp: sp.csr_matrix       # J_hat[perm][:, perm]
+    Q: np.ndarray
+    alpha: np.ndarray
+    prec: Preconditioner
+    Ld: np.ndarray = None   # Lcal as a dense array (triangular solves)
+
+    @property
+    def n(self):
+        return self.A.shape[0]
+
+    @property
+    def rank_r(self):
+        return self.Ur.shape[1]
+
+    @property
+    def perm(self):
+        return self.factor.perm
+
+    def lsolve(self, v):
+        return sla.solve_triangular(self.Ld, v, lower=True)
+
+    def lsolve_T(self, v):
+        return sla.solve_triangular(self.Ld, v, lower=True, trans="T")
+
+    def jtilde(self, v):
+        """J_tilde v = Lcal^-1 J_hat_p Lcal^-T v."""
+        return self.lsolve(self.Jp @ self.lsolve_T(v))
+
+    def op(self, z):
+        return self.lsolve(self.Ap @ self.lsolve_T(z))
+
+    def op_T(self, z):
+        return self.lsolve(self.Ap.T @ self.lsolve_T(z))
+
+    def rhs(self, b):
+        bh = self.Dr[self.m] * b[self.m]
+        return self.lsolve(bh[self.perm])
+
+    def back(self, x_chk):
+        xh = np.empty(self.n)
+        xh[self.perm] = self.lsolve_T(x_chk)
+        return self.Dc * (self.S @ xh)
+
+    def rhs_T(self, g):
+        gh = self.S.T @ (self.Dc * g)
+        return self.lsolve(gh[self.perm])
+
+    def back_T(self, l_chk):
+        y = np.empty(self.n)
+        y[self.perm] = self.lsolve_T(l_chk)
+        lam = np.empty(self.n)
+        lam[self.m] = self.Dr[self.m] * y
+        return lam
+
+
+def setup_ildl(A, opts: SetupOptions | None = None, iopts=None) -> IldlOracleSetup:
+    """Setup with the incomplete LDL^T of M_hat (Sec. 3): matching, scaling
+    and S as in setup(); then M_hat, J_hat, the factorization, the scaled
+    factor, the low-rank term (Fig. 1), the skew-Lanczos basis of J_tilde
+    (Fig. 2) and the SMW data."""
+    from .ildl import IldlOptions, ildl, low_rank, scaled_factor
+    from .split import ahat_on_pattern, symmetric_skew_parts
+    opts = opts or SetupOptions()
+    iopts = iopts or IldlOptions()
+    A = validate_csr(A)
+    m = max_product_matching(A)
+    Dr, Dc = canonical_scaling(A, m)
+    Abar = permute_scale(A, m, Dr, Dc)
+    S, _, _ = skew_symmetrizer(Abar, opts.s_pattern, opts.gamma, dense_limit=opts.lls_dense_limit)
+    Ahat, _ = ahat_on_pattern(Abar, S)
+    Mh, Jh = symmetric_skew_parts(Ahat)
+    F = ildl(Mh, iopts)
+    Lcal, _, Mr = scaled_factor(F)
+    Ur, sig = low_rank(F, Mr)
+    p = F.perm
+    Ap = sp.csr_matrix(Ahat[p][:, p])
+    Jp = sp.csr_matrix(Jh[p][:, p])
+    st = IldlOracleSetup(A=A, m=m, Dr=Dr, Dc=Dc, Abar=Abar, S=S, Ahat=Ahat, factor=F, Lcal=Lcal,
+                         Mr=Mr, Ur=Ur, sigma_r=sig, Ap=Ap, Jp=Jp, Q=None, alpha=None, prec=None,
+                         Ld=Lcal.toarray())
+    n = A.shape[0]
+    Q, alpha = skew_lanczos(st.jtilde, start_vector(opts.lanczos_seed, n), opts.k)
+    st.Q, st.alpha = Q, alpha
+    st.prec = Preconditioner(None, None, Q, alpha, opts.x_tol, opts.x_maxit, jtilde=st.jtilde,
+                             Ur=Ur, sigma_r=sig)
+    return st
 
 
 def _fgmres(op, prec_apply, rhs, back, true_relres, o: SolveOptions):
@@ -356,7 +474,7 @@ def _from_x0(solve_fn, M, st, b, o, x0):
     if rn <= o.tol * bn:
         return x0.copy(), dict(converged=True, outer_its=0, inner_its_total=0, inner_its_max=0,
                                relres_true=rn / bn, relres_implicit=0.0, cycles=0,
-                               k_eff=st.Q.shape[1], rank_r=st.N.size)
+                               k_eff=st.Q.shape[1], rank_r=st.rank_r)
     d, info = solve_fn(st, r0, dataclasses.replace(o, tol=o.tol * bn / rn))
     x = x0 + d
     rel = np.linalg.norm(b - M @ x) / bn
@@ -376,14 +494,14 @@ def solve(st: OracleSetup, b: np.ndarray, o: SolveOptions | None = None, x0=None
     if bn == 0.0:
         return np.zeros(st.n), dict(converged=True, outer_its=0, inner_its_total=0,
                                     inner_its_max=0, relres_true=0.0, relres_implicit=0.0,
-                                    cycles=0, k_eff=st.Q.shape[1], rank_r=st.N.size)
+                                    cycles=0, k_eff=st.Q.shape[1], rank_r=st.rank_r)
 
     def true_relres(x):
         return np.linalg.norm(b - st.A @ x) / bn
 
     prec = lambda v: st.prec.apply(v, o.inner_tol, o.inner_maxit, o.fixed_inner_steps)
     x_chk, info = _outer(o)(st.op, prec, st.rhs(b), st.back, true_relres, o)
-    info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
+    info.update(k_eff=st.Q.shape[1], rank_r=st.rank_r)
     return st.back(x_chk), info
 
 
@@ -400,14 +518,14 @@ def solve_adjoint(st: OracleSetup, g: np.ndarray, o: SolveOptions | None = None,
     if gn == 0.0:
         return np.zeros(st.n), dict(converged=True, outer_its=0, inner_its_total=0,
                                     inner_its_max=0, relres_true=0.0, relres_implicit=0.0,
-                                    cycles=0, k_eff=st.Q.shape[1], rank_r=st.N.size)
+                                    cycles=0, k_eff=st.Q.shape[1], rank_r=st.rank_r)
 
     def true_relres(lam):
         return np.linalg.norm(g - st.A.T @ lam) / gn
 
     prec = lambda v: st.prec.apply_T(v, o.inner_tol, o.inner_maxit, o.fixed_inner_steps)
     l_chk, info = _outer(o)(st.op_T, prec, st.rhs_T(g), st.back_T, true_relres, o)
-    info.update(k_eff=st.Q.shape[1], rank_r=st.N.size)
+    info.update(k_eff=st.Q.shape[1], rank_r=st.rank_r)
     return st.back_T(l_chk), info
 
 

@@ -24,13 +24,30 @@ from .preprocess import ZeroDiagonal
 from .skewsym import _on_pattern, _spones
 
 
+def ahat_on_pattern(Abar: sp.csr_matrix, S: sp.csr_matrix):
+    """(A_hat, P): A_hat = Abar S stored on its structural pattern P (the
+    pattern of |Abar||S|, explicit zeros of the product kept)."""
+    P = sp.csr_matrix(_spones(Abar) @ _spones(S))
+    P.sort_indices()
+    return _on_pattern(sp.csr_matrix(Abar @ S), P), P
+
+
+def symmetric_skew_parts(Ahat: sp.csr_matrix):
+    """M_hat = (A_hat + A_hat^T)/2 and J_hat = (A_hat - A_hat^T)/2 (Sec. 3),
+    both on the pattern of A_hat + A_hat^T."""
+    At = sp.csr_matrix(Ahat.T)
+    Mh = sp.csr_matrix((Ahat + At) / 2.0)
+    Jh = sp.csr_matrix((Ahat - At) / 2.0)
+    Mh.sort_indices()
+    Jh.sort_indices()
+    return Mh, Jh
+
+
 def split_ahat(Abar: sp.csr_matrix, S: sp.csr_matrix):
     """Returns dict with Ahat (on its structural pattern), D, Omega, Jup
     (strict upper CSR of J_tilde), N (indices with D_i < 0, increasing)."""
     n = Abar.shape[0]
-    P = sp.csr_matrix(_spones(Abar) @ _spones(S))
-    P.sort_indices()
-    Ahat = _on_pattern(sp.csr_matrix(Abar @ S), P)
+    Ahat, P = ahat_on_pattern(Abar, S)
     D = Ahat.diagonal()
     if np.any(D == 0):
         raise ZeroDiagonal("diag(Abar S) has a zero entry")
