@@ -18,7 +18,12 @@
  * Each solve (asss_solve) runs flexible GMRES (or TFQMR, Sec. 4.1) on the
  * scaled system Omega Abar S Omega, right-preconditioned with
  * P = sign(D) + J_tilde, where P^-1 is applied through the SMW form around an
- * inner minimal residual solve (mrs, Sec. 3.1 and App. B) on I + J_bar.  The
+ * inner minimal residual solve (mrs, Sec. 3.1 and App. B) on I + J_bar.
+ * With the setup option precond = ASSS_PRECOND_ILDL the symmetric part
+ * M_hat = (A_hat + A_hat^T) / 2 is instead factorized incompletely, M_hat ~
+ * L D L^T with Bunch-Kaufman pivoting (Sec. 3), Lcal = L |D|^(1/2) as in eq.
+ * absfac, J_tilde = Lcal^-1 J_hat Lcal^-T, and the low-rank term of Fig. 1
+ * carries the negative eigenvalues of D (1x1 and 2x2 blocks).  The
  * adjoint solve (A^T lambda = g), batched solves of several systems with
  * several right-hand sides, value gradients of a solve, and saved setups use
  * the same preconditioner.
@@ -85,6 +90,12 @@ enum {
   ASSS_S_TRIDIAG = 1,
   ASSS_S_PATTERN_OF_ABAR = 2,
   ASSS_S_USER = 3          /* s_rowptr / s_colind, a CSR pattern in Abar's index space */
+};
+
+/* Preconditioner of the inner level (Sec. 3, eqs. preconditioner and absfac). */
+enum {
+  ASSS_PRECOND_DIAG = 0,   /* L = I, D = diag(A_hat): P = sign(D) + Omega J_hat Omega */
+  ASSS_PRECOND_ILDL = 1    /* incomplete LDL^T of M_hat with Bunch-Kaufman pivoting */
 };
 
 /* Device memory provider for a handle, e.g. a framework's caching allocator.
@@ -190,6 +201,27 @@ typedef struct {
                               the basis only changes how fast the inner solve converges.
                               Read during setup only; NONFINITE on NaN/Inf */
   const double* q_alpha;   /* with q_basis: super-diagonal of S_k (k - 1 values) */
+  int32_t precond;         /* ASSS_PRECOND_DIAG (default) or ASSS_PRECOND_ILDL: the incomplete
+                              factorization M_hat[p][:, p] = L D L^T + E, D with 1x1 and 2x2
+                              blocks (Sec. 3).  The scaled system then runs in the
+                              factorization's positions p: A_chk = Lcal^-1 A_hat_p Lcal^-T,
+                              Lcal = L C with C the block Cholesky factor of |D| (eq. absfac),
+                              P = C^-1 D C^-T + J_tilde with J_tilde = Lcal^-1 J_hat_p Lcal^-T,
+                              deflated and corrected in the SMW form as above; every product
+                              with J_tilde is two sparse triangular solves around J_hat_p,
+                              run level by level in one workgroup (sizes of the paper's
+                              problems: n up to some 10^4).  Needs reorder = 0, deflation 0/1,
+                              autotune = 0 (INVALID_ARG else); ZERO_DIAGONAL if a zero pivot
+                              cannot be avoided (pivoting off, or a zero pivot with a nonzero
+                              column).  Q and X of asss_get_array are then in positions */
+  double ildl_droptol;     /* drop l_ij when |l_ij| < ildl_droptol ||l_j||_2, the norm of column j
+                              of L as computed (entries below its pivot block), default 0 */
+  double ildl_fill;        /* keep at most ceil(ildl_fill c_j) entries of column j of L, the
+                              largest in magnitude, c_j = nonzeros of M_hat's column j among the
+                              rows still to be eliminated; default +inf (no cap).  Dropping is
+                              applied to each column before it updates the rest of the matrix */
+  int32_t ildl_pivoting;   /* 1 (default): Bunch-Kaufman partial pivoting, alpha = (1 + sqrt 17)/8;
+                              0: 1x1 pivots in the natural order */
 } asss_setup_opts_t;
 
 typedef struct {
@@ -373,6 +405,12 @@ typedef struct {
   int32_t tune_rows[8];                   /* their row_block values, ascending */
   double tune_us[8];                      /* their inner-step times (microseconds) */
   double tune_s;                          /* wall time of the autotuner */
+  int32_t precond;                        /* ASSS_PRECOND_* of the handle */
+  int32_t ildl_n2x2;                      /* 2x2 pivot blocks of the incomplete LDL^T */
+  int32_t ildl_levels_lower;              /* levels of the forward solve with Lcal */
+  int32_t ildl_levels_upper;              /* levels of the backward solve with Lcal^T */
+  int64_t ildl_nnz_l;                     /* strictly lower entries of L */
+  int64_t ildl_dropped;                   /* entries of L dropped by droptol and fill */
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);
@@ -387,7 +425,22 @@ enum {
   ASSS_ARR_S_ROWPTR = 3, ASSS_ARR_S_COLIND = 4, ASSS_ARR_S_VAL = 5,
   ASSS_ARR_D = 6,       /* diag(A_hat) */
   ASSS_ARR_J_ROWPTR = 7, ASSS_ARR_J_COLIND = 8, ASSS_ARR_J_VAL = 9, /* strict upper J_tilde */
-  ASSS_ARR_Q = 10, ASSS_ARR_ALPHA = 11, ASSS_ARR_X = 12, ASSS_ARR_NEG = 13
+  ASSS_ARR_Q = 10, ASSS_ARR_ALPHA = 11, ASSS_ARR_X = 12, ASSS_ARR_NEG = 13,
+  /* the incomplete LDL^T of a handle with precond = ASSS_PRECOND_ILDL (count 0 otherwise),
+     and of an asss_ildl_t: */
+  ASSS_ARR_ILDL_PERM = 14,     /* int32 n: position p holds index perm[p] of Abar */
+  ASSS_ARR_ILDL_L_ROWPTR = 15, /* int64 n+1: strictly lower part of the unit factor L, positions */
+  ASSS_ARR_ILDL_L_COLIND = 16, /* int32 */
+  ASSS_ARR_ILDL_L_VAL = 17,    /* FP64 */
+  ASSS_ARR_ILDL_BSIZE = 18,    /* int32 per position: 1, or 2 at the first position of a 2x2 block and
+                                  0 at its second */
+  ASSS_ARR_ILDL_D = 19,        /* FP64 3 per position p: (d_pp, d_{p+1,p}, d_{p+1,p+1}) at the first
+                                  position of a block (zeros at the others; d of a 1x1 block in the first) */
+  ASSS_ARR_LCAL_ROWPTR = 20,   /* int64 n+1: Lcal = L C, lower triangular with its diagonal, positions */
+  ASSS_ARR_LCAL_COLIND = 21,   /* int32 */
+  ASSS_ARR_LCAL_VAL = 22,      /* FP64 */
+  ASSS_ARR_UR = 23,            /* FP64 n x r column-major: U_r of the low-rank term, positions */
+  ASSS_ARR_SIGMA_R = 24        /* FP64 r: the diagonal of Sigma_r */
 };
 asss_status_t asss_get_array(asss_handle_t h, int32_t which, void* dst, int64_t* count);
 
@@ -407,6 +460,19 @@ enum {
 };
 asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in_dev, double* out_dev,
                          const asss_solve_opts_t* o, int32_t* inner_its, void* hip_stream);
+
+/* ---- The incomplete LDL^T alone, on the host (no device is used) --------
+ * For inspection and tests: the Bunch-Kaufman incomplete factorization of a
+ * symmetric matrix M (host CSR, exactly symmetric in pattern and values, else
+ * INVALID_ARG) with the options of asss_setup_opts_t, its scaled factor and
+ * low-rank term, exactly as a handle with precond = ASSS_PRECOND_ILDL builds
+ * them from M_hat.  asss_ildl_get reads the ASSS_ARR_ILDL_* / LCAL / UR /
+ * SIGMA_R arrays as asss_get_array does.  ZERO_DIAGONAL as for asss_setup. */
+typedef struct asss_ildl_s* asss_ildl_t;
+asss_status_t asss_ildl_factor(const asss_csr_t* M, double droptol, double fill, int32_t pivoting,
+                               asss_ildl_t* out);
+asss_status_t asss_ildl_get(asss_ildl_t f, int32_t which, void* dst, int64_t* count);
+asss_status_t asss_ildl_destroy(asss_ildl_t f);
 
 #ifdef __cplusplus
 }

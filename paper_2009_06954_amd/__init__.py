@@ -34,12 +34,19 @@ ARRAYS = {"match": (0, np.int32), "Dr": (1, np.float64), "Dc": (2, np.float64),
           "S_rowptr": (3, np.int64), "S_colind": (4, np.int32), "S_val": (5, np.float64),
           "D": (6, np.float64), "J_rowptr": (7, np.int64), "J_colind": (8, np.int32),
           "J_val": (9, np.float64), "Q": (10, np.float64), "alpha": (11, np.float64),
-          "X": (12, np.float64), "neg": (13, np.int32)}
+          "X": (12, np.float64), "neg": (13, np.int32),
+          # the incomplete LDL^T (precond="ildl"), in the factorization's positions
+          "ildl_perm": (14, np.int32), "ildl_L_rowptr": (15, np.int64), "ildl_L_colind": (16, np.int32),
+          "ildl_L_val": (17, np.float64), "ildl_bsize": (18, np.int32), "ildl_D": (19, np.float64),
+          "Lcal_rowptr": (20, np.int64), "Lcal_colind": (21, np.int32), "Lcal_val": (22, np.float64),
+          "Ur": (23, np.float64), "sigma_r": (24, np.float64)}
+PRECONDS = {"diag": 0, "ildl": 1}
 
 EXPORTED = ["asss_default_setup_opts", "asss_default_solve_opts", "asss_setup", "asss_solve",
             "asss_solve_noalloc", "asss_solve_adjoint", "asss_solve_batched", "asss_destroy", "asss_last_error",
             "asss_get_handle_info", "asss_get_array", "asss_apply", "asss_update_values",
-            "asss_value_gradient", "asss_save", "asss_load"]
+            "asss_value_gradient", "asss_save", "asss_load", "asss_ildl_factor", "asss_ildl_get",
+            "asss_ildl_destroy"]
 
 
 class CsrT(C.Structure):
@@ -55,7 +62,8 @@ class SetupOpts(C.Structure):
                 ("verbose", C.c_int32), ("deflation", C.c_int32), ("reorder", C.c_int32),
                 ("allocator", C.c_void_p), ("autotune", C.c_int32), ("inner_perm", C.c_void_p),
                 ("skew_form", C.c_int32), ("s_val", C.c_void_p), ("q_basis", C.c_void_p),
-                ("q_alpha", C.c_void_p)]
+                ("q_alpha", C.c_void_p), ("precond", C.c_int32), ("ildl_droptol", C.c_double),
+                ("ildl_fill", C.c_double), ("ildl_pivoting", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -115,7 +123,9 @@ class HandleInfo(C.Structure):
                 ("lanczos_orth_err", C.c_double), ("deflation_mode", C.c_int32), ("reordered", C.c_int32),
                 ("cross_pairs_natural", C.c_int64), ("cross_pairs_used", C.c_int64),
                 ("narrow_b_columns", C.c_int32), ("skew_form", C.c_int32), ("tune_n", C.c_int32),
-                ("tune_rows", C.c_int32 * 8), ("tune_us", C.c_double * 8), ("tune_s", C.c_double)]
+                ("tune_rows", C.c_int32 * 8), ("tune_us", C.c_double * 8), ("tune_s", C.c_double),
+                ("precond", C.c_int32), ("ildl_n2x2", C.c_int32), ("ildl_levels_lower", C.c_int32),
+                ("ildl_levels_upper", C.c_int32), ("ildl_nnz_l", C.c_int64), ("ildl_dropped", C.c_int64)]
 
     def to_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -164,6 +174,9 @@ def load(path: str = LIB_PATH):
                                C.POINTER(C.c_int32), C.c_void_p]
     lib.asss_save.argtypes = [C.c_void_p, C.c_char_p]
     lib.asss_load.argtypes = [C.c_char_p, C.POINTER(SetupOpts), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.asss_ildl_factor.argtypes = [C.POINTER(CsrT), C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_void_p)]
+    lib.asss_ildl_get.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]
+    lib.asss_ildl_destroy.argtypes = [C.c_void_p]
     for f in EXPORTED:
         if f != "asss_last_error":
             getattr(lib, f).restype = None if f.startswith("asss_default") else C.c_int32
@@ -248,7 +261,7 @@ class Handle:
 
     def _start(self, out, like, x0):
         import torch
-        x = out if out is not None else torch.empty_like(like)
+        x = self._vec(out) if out is not None else torch.empty_like(like)
         if x0 is not None:
             x.copy_(self._vec(x0))
         return x
@@ -298,7 +311,7 @@ class Handle:
         """One operator of the method (see asss_apply).  Returns (out, inner_its)."""
         import torch
         v = self._vec(v)
-        o = out if out is not None else torch.empty_like(v)
+        o = self._vec(out) if out is not None else torch.empty_like(v)
         its = C.c_int32(0)
         _check(load().asss_apply(self._h, OPS[op], C.c_void_p(v.data_ptr()), C.c_void_p(o.data_ptr()),
                                  C.byref(solve_options(**opts)), C.byref(its), _stream(stream)))
@@ -323,6 +336,9 @@ class Handle:
                 and colind.is_contiguous()):
             raise ValueError("rowptr must be CUDA int64 (n + 1), colind CUDA int32")
         nnz = colind.numel()
+        if out is not None and not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+                                    and out.is_contiguous() and out.numel() == nnz):
+            raise ValueError(f"out must be a contiguous CUDA float64 tensor of length {nnz}")
         g = out if out is not None else torch.empty(nnz, dtype=torch.float64, device=x.device)
         _check(load().asss_value_gradient(self._h, nnz, C.c_void_p(rowptr.data_ptr()),
                                           C.c_void_p(colind.data_ptr()), C.c_void_p(lam.data_ptr()),
@@ -355,7 +371,8 @@ SKEW_FORMS = {"auto": 0, "wide": 1, "narrow": 2, "slots": 3}
 def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, inner_fp32=False,
           x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
           stream=None, canonicalize=True, deflation="auto", reorder="auto", allocator=None,
-          autotune=False, skew_form="auto", s_values=None, q_basis=None, q_alpha=None) -> Handle:
+          autotune=False, skew_form="auto", s_values=None, q_basis=None, q_alpha=None, precond="diag",
+          ildl_droptol=0.0, ildl_fill=float("inf"), ildl_pivoting=True) -> Handle:
     """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
     canonicalize: sum duplicates and sort column indices of a SciPy input first
     (otherwise the library rejects such input with INVALID_CSR).
@@ -377,7 +394,10 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     deflation: "auto"/"explicit" or "explicit_fp32_basis" (the
     Lanczos vectors rounded to FP32 values and used so everywhere: same
     preconditioner P, FP64 arithmetic, half the basis bytes in the FP64 inner
-    step; see asss_setup_opts_t.deflation)."""
+    step; see asss_setup_opts_t.deflation).
+    precond: "diag" (L = I, D = diag(A_hat)) or "ildl" (incomplete LDL^T of
+    M_hat with Bunch-Kaufman pivoting; ildl_droptol, ildl_fill and
+    ildl_pivoting as in asss_setup_opts_t; reorder must stay "auto")."""
     lib = load()
     n, rp, ci, va = _csr_arrays(A, canonicalize)
     csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
@@ -396,6 +416,8 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.row_block, o.verbose = row_block, int(bool(verbose))
     o.autotune = int(bool(autotune))
     o.skew_form = SKEW_FORMS[skew_form]
+    o.precond = PRECONDS[precond]
+    o.ildl_droptol, o.ildl_fill, o.ildl_pivoting = ildl_droptol, ildl_fill, int(bool(ildl_pivoting))
     if s_values is not None:
         sv = np.ascontiguousarray(s_values, dtype=np.float64)
         keep.append(sv)
@@ -478,3 +500,33 @@ def solve_batched(handles, Bs, stream=None, X0s=None, **opts):
     _check(lib.asss_solve_batched(ns, hs, nra, bp, xp, C.byref(solve_options(**opts)), infos, _stream(stream)))
     out_infos = [[infos[s * maxr + j].to_dict() for j in range(nr[s])] for s in range(ns)]
     return Xs, out_infos
+
+
+ILDL_ARRAYS = ("ildl_perm", "ildl_L_rowptr", "ildl_L_colind", "ildl_L_val", "ildl_bsize", "ildl_D",
+               "Lcal_rowptr", "Lcal_colind", "Lcal_val", "Ur", "sigma_r")
+
+
+def ildl_factor(M, droptol=0.0, fill=float("inf"), pivoting=True) -> dict:
+    """The library's incomplete LDL^T of a symmetric matrix M (host only, no
+    GPU): asss_ildl_factor, then every ASSS_ARR_ILDL_* / LCAL / UR / SIGMA_R
+    array.  Ur is returned as an n x r array."""
+    lib = load()
+    n, rp, ci, va = _csr_arrays(M)
+    csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    f = C.c_void_p()
+    _check(lib.asss_ildl_factor(C.byref(csr), droptol, fill, int(bool(pivoting)), C.byref(f)))
+    try:
+        out = {}
+        for name in ILDL_ARRAYS:
+            which, dt = ARRAYS[name]
+            cnt = C.c_int64(0)
+            _check(lib.asss_ildl_get(f, which, None, C.byref(cnt)))
+            a = np.empty(cnt.value, dtype=dt)
+            if cnt.value:
+                _check(lib.asss_ildl_get(f, which, C.c_void_p(a.ctypes.data), C.byref(cnt)))
+            out[name] = a
+        r = out["sigma_r"].size
+        out["Ur"] = out["Ur"].reshape(r, n).T if r else np.zeros((n, 0))
+        return out
+    finally:
+        lib.asss_ildl_destroy(f)

@@ -12,6 +12,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -39,14 +40,17 @@ def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     gxx = shutil.which("g++") or "g++"
     with tempfile.TemporaryDirectory() as tmp:
-        objs = []
-        o = os.path.join(tmp, "host_setup.o")
-        _run([gxx, *HOST_FLAGS, "-c", os.path.join(CSRC, "host_setup.cpp"), "-o", o])
-        objs.append(o)
-        for src in ("kernels.hip", "asss.hip", "batch.hip"):
+        jobs = []
+        for src in ("host_setup.cpp", "ildl_host.cpp"):
+            o = os.path.join(tmp, src.replace(".cpp", ".o"))
+            jobs.append(([gxx, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], o))
+        for src in ("kernels.hip", "ildl.hip", "ildl_setup.hip", "asss.hip", "batch.hip"):
             o = os.path.join(tmp, src.replace(".hip", ".o"))
-            _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
-            objs.append(o)
+            jobs.append(([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], o))
+        # the translation units compile independently: run them side by side
+        with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+            list(ex.map(lambda j: _run(j[0]), jobs))
+        objs = [o for _, o in jobs]
         out_tmp = LIB + ".tmp"
         _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs, "-lpthread",
               f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"])

@@ -25,6 +25,8 @@
 #include "batch.hpp"
 #include "handle.hpp"
 #include "host_setup.hpp"
+#include "ildl_kernels.hpp"
+#include "ildl_setup.hpp"
 #include "kernels.hpp"
 
 using namespace asss;
@@ -162,15 +164,73 @@ double dot_host(asss_handle_s* h, int64_t n, const double* a, const double* b, h
   return h->h_small[0];
 }
 
-// w = Omega Abar S Omega z   (t1 scratch)
+// w = Omega Abar S Omega z   (t1 scratch); with the incomplete LDL^T
+// preconditioner w = Lcal^-1 A_hat Lcal^-T z in the factorization's positions
 void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
+  if (h->il.on) {
+    auto& il = h->il;
+    ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], s);
+    return;
+  }
   spmv(h->dS, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
   spmv(h->dAbar, h->t1, w, h->d_om, nullptr, 0, nullptr, s);
 }
 // w = (Omega Abar S Omega)^T z = Omega S^T Abar^T Omega z
 void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
+  if (h->il.on) {
+    auto& il = h->il;
+    ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], s);
+    return;
+  }
   spmv(h->dAbarT, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
   spmv(h->dSt, h->t1, w, h->d_om, nullptr, 0, nullptr, s);
+}
+
+// Right-hand side of the scaled system: b_chk = Omega P Dr b, or for the
+// adjoint g_chk = Omega S^T Dc g; with the incomplete LDL^T, Lcal^-1 applied
+// to (P Dr b)[perm] and to (S^T Dc g)[perm] (t1, tmp scratch).
+void rhs_transform(asss_handle_s* h, bool adjoint, const double* b, double* bchk, hipStream_t s) {
+  const int64_t n = h->n;
+  if (h->il.on) {
+    auto& il = h->il;
+    if (!adjoint) {
+      gather_scale(n, il.d_mp, il.d_drp, il.d_ones, b, h->tmp, s);
+    } else {
+      spmv(h->dSt, b, h->t1, nullptr, h->d_dc, 0, nullptr, s);
+      permute_gather(n, il.d_perm, h->t1, h->tmp, s);
+    }
+    ildl_trsv(il.Lf64, h->tmp, bchk, s);
+    return;
+  }
+  if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, bchk, s);
+  else spmv(h->dSt, b, bchk, h->d_om, h->d_dc, 0, nullptr, s);  // g_chk = Omega S^T (Dc o g)
+}
+
+// Solution from the scaled one: x = Dc S Omega x_chk, or for the adjoint
+// lambda = Dr P^T Omega l_chk; with the incomplete LDL^T the positions are
+// mapped back after Lcal^-T (t1, tmp scratch).
+void back_transform(asss_handle_s* h, bool adjoint, const double* xchk, double* x, hipStream_t s) {
+  const int64_t n = h->n;
+  if (h->il.on) {
+    auto& il = h->il;
+    ildl_trsv(il.Lb64, xchk, h->t1, s);
+    permute_scatter(n, il.d_perm, h->t1, h->tmp, s);
+    if (!adjoint) spmv(h->dS, h->tmp, x, h->d_dc, nullptr, 0, nullptr, s);
+    else scatter_scale(n, h->d_m, h->d_drp, il.d_ones, h->tmp, x, s);
+    return;
+  }
+  if (!adjoint) spmv(h->dS, xchk, x, h->d_dc, h->d_om, 0, nullptr, s);
+  else scatter_scale(n, h->d_m, h->d_drp, h->d_om, xchk, x, s);
+}
+
+// J_tilde v in FP64 (skew-Lanczos, operator export)
+void jtilde_apply(asss_handle_s* h, const double* in, double* out, hipStream_t s) {
+  if (h->il.on) {
+    auto& il = h->il;
+    ildl_sandwich<double>(il.Lb64, il.J64, il.Lf64, in, out, il.t64[0], il.t64[1], il.t64[2], s);
+  } else {
+    skew_spmv<double>(h->J64, in, out, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -204,6 +264,7 @@ int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
             int nc = 1) {
   Range range(NR == 1 ? "asss:inner mrs" : "asss:inner mrs (4 columns)");
   MrsLaunch L = make_launch<T>(h, nc, sign, NR == 1);
+  if (J.nblocks <= 0) throw Error{ASSS_ERR_INTERNAL, "the sliced inner operator is not built for this handle"};
   if (J.nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
   mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
   int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
@@ -258,8 +319,55 @@ int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
   return run_mrs<T, 1>(h, J, Q, mb, rhs, out, sign, tol, maxit, fixed, s);
 }
 
+// The inner solve with the incomplete LDL^T preconditioner: one launch of the
+// persistent one-workgroup kernel (start, all steps, final update, output).
+template <typename T>
+int run_ildl_mrs(asss_handle_s* h, const double* rhs, double* out, int sign, double tol, int maxit, int fixed,
+                 hipStream_t s) {
+  Range range("asss:inner mrs (incomplete LDL^T)");
+  auto& il = h->il;
+  constexpr bool f32 = std::is_same<T, float>::value;
+  IldlMrsArgs<T> a;
+  a.n = (int32_t)h->n;
+  a.k = h->k_eff;
+  a.sign = sign;
+  a.alpha = h->d_alpha;
+  if constexpr (f32) {
+    a.Q = h->d_Q32; a.gram = h->d_G32; a.Lb = il.Lb32; a.Lf = il.Lf32; a.J = il.J32;
+    a.buf = h->mb32; a.y = il.y32; a.z = il.z32; a.u = il.u32;
+  } else {
+    a.Q = h->d_Q64; a.gram = h->d_G64; a.Lb = il.Lb64; a.Lf = il.Lf64; a.J = il.J64;
+    a.buf = h->mb64; a.y = il.y64; a.z = il.z64; a.u = il.u64;
+  }
+  a.rhs = rhs;
+  a.out = out;
+  a.st = h->d_state;
+  a.tol = tol;
+  a.maxit = maxit;
+  a.fixed = fixed;
+  HIPCHK(hipEventRecord(h->ev0, s));
+  ildl_mrs<T>(a, s);
+  HIPCHK(hipEventRecord(h->ev1, s));
+  HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->prof_s += 1e-3 * ms;
+  h->prof_launches += 1;
+  int32_t st_its, st_status;
+  std::memcpy(&st_its, (char*)h->h_small + offsetof(MrsState, its), 4);
+  std::memcpy(&st_status, (char*)h->h_small + offsetof(MrsState, status), 4);
+  if (st_status != MRS_DONE) throw Error{ASSS_ERR_INTERNAL, "inner mrs (incomplete LDL^T) did not finish"};
+  h->last_inner = st_its;
+  return st_its;
+}
+
 int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
                 int maxit, int fixed, hipStream_t s) {
+  if (h->il.on) {
+    if (fp32) return run_ildl_mrs<float>(h, rhs, out, sign, tol, maxit, fixed, s);
+    return run_ildl_mrs<double>(h, rhs, out, sign, tol, maxit, fixed, s);
+  }
   if (fp32)
     return run_mrs1<float>(h, h->J32, h->d_Q32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
   return run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
@@ -567,14 +675,14 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     scale(n, 1.0 / nq, q0, q0, s);
     keff = 1;
     if (k >= 2) {
-      skew_spmv<double>(h->J64, q0, z, s);
+      jtilde_apply(h, q0, z, s);
       double a1 = std::sqrt(dot_host(h, n, z, z, s));
       if (a1 != 0.0) {
         alpha.push_back(a1);
         scale(n, -1.0 / a1, z, h->d_Q64 + n, s);
         keff = 2;
         for (int i = 2; i < k; ++i) {
-          skew_spmv<double>(h->J64, h->d_Q64 + (int64_t)(i - 1) * n, z, s);
+          jtilde_apply(h, h->d_Q64 + (int64_t)(i - 1) * n, z, s);
           axpby(n, -alpha[i - 2], h->d_Q64 + (int64_t)(i - 2) * n, 1.0, z, s);
           double ai = std::sqrt(dot_host(h, n, z, z, s));
           if (ai <= 1e-14 * a1) break;
@@ -630,7 +738,9 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     h->orth_err = err;
   }
   // ---- one-time SMW data (Sec. 4.1): U_bar, X = S_bar^-1 U_bar, G, C
-  h->r = (int)h->neg.size();
+  // U_r: unit vectors at the negative entries of D (diagonal reading), or the
+  // columns of the low-rank term of the scaled incomplete factor (Fig. 1)
+  h->r = h->il.on ? (int)h->il.Sc.sigma.size() : (int)h->neg.size();
   const int kr = keff + h->r;
   if (kr > 512) throw Error{ASSS_ERR_INTERNAL, "rank of the low-rank term k + r exceeds 512"};
   h->kr = kr;
@@ -639,7 +749,15 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
   HIPCHK(hipMemsetAsync(h->d_Ubar, 0, n * (int64_t)kr * sizeof(double), s));
   if (keff > 0)
     HIPCHK(hipMemcpyAsync(h->d_Ubar, h->d_Qorig, n * (int64_t)keff * sizeof(double), hipMemcpyDeviceToDevice, s));
-  {
+  if (h->il.on) {
+    const auto& Sc = h->il.Sc;
+    for (int j = 0; j < h->r; ++j)
+      for (int t = 0; t < 2; ++t)
+        if (Sc.ur_pos[2 * j + t] >= 0)
+          HIPCHK(hipMemcpyAsync(h->d_Ubar + (int64_t)(keff + j) * n + Sc.ur_pos[2 * j + t], &Sc.ur_val[2 * j + t],
+                                sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
     std::vector<double> one(1, 1.0);
     for (int j = 0; j < h->r; ++j)
       HIPCHK(hipMemcpyAsync(h->d_Ubar + (int64_t)(keff + j) * n + h->neg[j], one.data(), sizeof(double),
@@ -647,8 +765,13 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
   }
   h->d_X = h->ar.alloc<double>(n * (int64_t)kr);
-  // simultaneous mrs (App. B) on groups of NRMAX columns in FP64
-  {
+  if (h->il.on) {  // X = S_bar^-1 U_bar column by column (one-workgroup inner solves)
+    int xits = 0;
+    for (int c = 0; c < kr; ++c)
+      xits = std::max(xits, run_ildl_mrs<double>(h, h->d_Ubar + (int64_t)c * n, h->d_X + (int64_t)c * n, +1,
+                                                 h->opts.x_tol, h->opts.x_maxit, 0, s));
+    h->x_its = xits;
+  } else {  // simultaneous mrs (App. B) on groups of NRMAX columns in FP64
     DevArena tmp(h->ar.al);
     MrsBufs<double> mb4;
     for (int b = 0; b < 3; ++b) mb4.w[b] = tmp.alloc<double>(n * NRMAX);
@@ -703,7 +826,8 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     Sig[(size_t)i * kr + i + 1] = alpha[i];
     Sig[(size_t)(i + 1) * kr + i] = -alpha[i];
   }
-  for (int j = 0; j < h->r; ++j) Sig[(size_t)(keff + j) * kr + keff + j] = -2.0;
+  for (int j = 0; j < h->r; ++j)
+    Sig[(size_t)(keff + j) * kr + keff + j] = h->il.on ? h->il.Sc.sigma[j] : -2.0;
   std::vector<double> C((size_t)kr * kr, 0.0);
   for (int i = 0; i < kr; ++i)
     for (int j = 0; j < kr; ++j) {
@@ -810,8 +934,7 @@ struct FgmresCol {
       done = true;
       return;
     }
-    if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, bchk, s);
-    else spmv(h->dSt, b, bchk, h->d_om, h->d_dc, 0, nullptr, s);  // g_chk = Omega S^T (Dc o g)
+    rhs_transform(h, adjoint, b, bchk, s);
     bcn = std::sqrt(dot_host(h, n, bchk, bchk, s));
     thr = o.tol * bcn;
     HIPCHK(hipMemsetAsync(xchk, 0, n * sizeof(double), s));
@@ -935,13 +1058,9 @@ struct FgmresCol {
       gemv_acc(n, j_used, Z, n, h->d_small + SM_Y, 1.0, xchk, s);
     }
     inf.relres_implicit = std::fabs(g[j_used]) / bcn;
-    if (!adjoint) {
-      spmv(h->dS, xchk, x, h->d_dc, h->d_om, 0, nullptr, s);       // x = Dc S Omega x_chk
-      spmv(h->dA, x, rv, nullptr, nullptr, 1, b, s);                 // r = b - A x
-    } else {
-      scatter_scale(n, h->d_m, h->d_drp, h->d_om, xchk, x, s);      // lambda = Dr P^T Omega l_chk
-      spmv(h->dAt, x, rv, nullptr, nullptr, 1, b, s);                // r = g - A^T lambda
-    }
+    back_transform(h, adjoint, xchk, x, s);
+    if (!adjoint) spmv(h->dA, x, rv, nullptr, nullptr, 1, b, s);   // r = b - A x
+    else spmv(h->dAt, x, rv, nullptr, nullptr, 1, b, s);           // r = g - A^T lambda
     const double relres = std::sqrt(dot_host(h, n, rv, rv, s)) / bn;
     inf.relres_true = relres;
     if (relres <= o.tol) {
@@ -1084,8 +1203,7 @@ asss_status_t tfqmr(asss_handle_s* h, bool adjoint, const double* b, double* x,
   double* z = h->Z;
   double* zm_buf = h->Z + n;
   double* dz = h->Z + 2 * n;
-  if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, h->bchk, s);
-  else spmv(h->dSt, b, h->bchk, h->d_om, h->d_dc, 0, nullptr, s);
+  rhs_transform(h, adjoint, b, h->bchk, s);
   const double bcn = std::sqrt(dot_host(h, n, h->bchk, h->bchk, s));
   double thr = o.tol * bcn;
   HIPCHK(hipMemsetAsync(h->xchk, 0, n * sizeof(double), s));
@@ -1171,13 +1289,9 @@ asss_status_t tfqmr(asss_handle_s* h, bool adjoint, const double* b, double* x,
     }
     inf.relres_implicit = bound / bcn;
     double relres;
-    if (!adjoint) {
-      spmv(h->dS, h->xchk, x, h->d_dc, h->d_om, 0, nullptr, s);
-      spmv(h->dA, x, h->rv, nullptr, nullptr, 1, b, s);
-    } else {
-      scatter_scale(n, h->d_m, h->d_drp, h->d_om, h->xchk, x, s);
-      spmv(h->dAt, x, h->rv, nullptr, nullptr, 1, b, s);
-    }
+    back_transform(h, adjoint, h->xchk, x, s);
+    if (!adjoint) spmv(h->dA, x, h->rv, nullptr, nullptr, 1, b, s);
+    else spmv(h->dAt, x, h->rv, nullptr, nullptr, 1, b, s);
     relres = std::sqrt(dot_host(h, n, h->rv, h->rv, s)) / bn;
     inf.relres_true = relres;
     if (relres <= o.tol) {
@@ -1367,6 +1481,18 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     if (o.autotune < 0 || o.autotune > 1) throw Error{ASSS_ERR_INVALID_ARG, "autotune must be 0 or 1"};
     if (o.skew_form < 0 || o.skew_form > 3) throw Error{ASSS_ERR_INVALID_ARG, "skew_form must be 0, 1, 2 or 3"};
+    if (o.precond != ASSS_PRECOND_DIAG && o.precond != ASSS_PRECOND_ILDL)
+      throw Error{ASSS_ERR_INVALID_ARG, "precond must be ASSS_PRECOND_DIAG or ASSS_PRECOND_ILDL"};
+    if (o.precond == ASSS_PRECOND_ILDL) {
+      if (o.reorder > 1)
+        throw Error{ASSS_ERR_INVALID_ARG, "the incomplete LDL^T preconditioner runs in its factorization's order "
+                                          "(reorder must be 0)"};
+      if (o.deflation == 3 || o.autotune)
+        throw Error{ASSS_ERR_INVALID_ARG, "the incomplete LDL^T preconditioner takes neither the FP32-valued "
+                                          "deflation basis nor the row-block autotuner"};
+      if (!(o.ildl_droptol >= 0.0) || !(o.ildl_fill > 0.0))
+        throw Error{ASSS_ERR_INVALID_ARG, "ildl_droptol must be >= 0 and ildl_fill > 0"};
+    }
     hipStream_t s = (hipStream_t)hip_stream;
     std::unique_ptr<asss_handle_s> h(new asss_handle_s());
     static std::atomic<uint64_t> next_uid{1};
@@ -1471,16 +1597,35 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     Csr Ahat = spgemm_on_pattern(Abar, h->S, L.P);
     h->nnz_ahat = Ahat.nnz();
     h->U = L.U;
-    split_ahat(Ahat, h->U, h->D, h->Omega, h->jval);
+    const bool ildl = o.precond == ASSS_PRECOND_ILDL;
     h->neg.clear();
+    Csr Jup;
+    bool reordered = false;
+    SkewSell sell;
+    if (ildl) {
+      // D = diag(A_hat) and J_hat = (A_hat - A_hat^T) / 2 on U, unscaled: the
+      // scaling is inside the factor Lcal (ildl_setup)
+      h->D.assign(n, 0.0);
+      h->Omega.assign(n, 1.0);
+      Csr Ms, Js;
+      symmetric_skew_split(Ahat, Ms, Js);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = Ahat.ptr[i]; e < Ahat.ptr[i + 1]; ++e)
+          if (Ahat.col[e] == i) h->D[i] = Ahat.val[e];
+      h->jval.clear();
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = Js.ptr[i]; e < Js.ptr[i + 1]; ++e)
+          if (Js.col[e] > i) h->jval.push_back(Js.val[e]);
+      if ((int64_t)h->jval.size() != h->U.nnz()) throw Error{ASSS_ERR_INTERNAL, "pattern of J_hat differs from U"};
+    } else {
+    split_ahat(Ahat, h->U, h->D, h->Omega, h->jval);
     for (int64_t i = 0; i < n; ++i)
       if (h->D[i] < 0) h->neg.push_back((int32_t)i);
-    Csr Jup = h->U;
+    Jup = h->U;
     Jup.val = h->jval;
     // block order of the inner system (fewer pairs stored twice in the sliced layout)
     h->cross_natural = count_cross_pairs(Jup, R);
     h->cross_used = h->cross_natural;
-    bool reordered = false;
     if (o.reorder == 4 && !grid_perm.empty()) {  // line tiles of a detected grid
       Jup = permute_skew_upper(Jup, grid_perm);
       h->cross_used = count_cross_pairs(Jup, R);
@@ -1499,9 +1644,10 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
       h->perm = std::move(perm);
       reordered = true;
     }
-    SkewSell sell = pack_skew_sell(Jup, R, o.skew_form);
+    sell = pack_skew_sell(Jup, R, o.skew_form);
     h->sell_a = sell.a_entries;
     h->sell_b = sell.b_entries;
+    }
     { LlsSystem dummy; std::swap(L, dummy); }
     // ---- device uploads
     h->Apat.nrows = h->Apat.ncols = n;
@@ -1520,7 +1666,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->d_drp = h->ar.upload(drp, s);
     h->d_om = h->ar.upload(h->Omega, s);
     h->d_dc = h->ar.upload(h->Dc, s);
-    {
+    if (!ildl) {
       SkewLayout lay = upload_layout(h->ar, sell, s);
       h->narrow_b = lay.narrow;
       h->skew_form = lay.form;
@@ -1539,6 +1685,13 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->rv = h->ar.alloc<double>(n);
     h->tmp = h->ar.alloc<double>(n);
     HIPCHK(hipStreamSynchronize(s));
+    if (ildl) {
+      Range r3("asss_setup:incomplete LDL^T");
+      h->il.opts.droptol = o.ildl_droptol;
+      h->il.opts.fill = o.ildl_fill;
+      h->il.opts.pivoting = o.ildl_pivoting != 0;
+      ildl_setup(h.get(), Ahat, s);
+    }
     const double t3 = now_s();
     phase.reset();
     phase.emplace("asss_setup:Lanczos, X, C");
@@ -1569,6 +1722,11 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
   });
 }
 
+struct asss_ildl_s {
+  IldlFactor F;
+  IldlScaled S;
+};
+
 extern "C" {
 
 void asss_default_setup_opts(asss_setup_opts_t* o) {
@@ -1590,6 +1748,10 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->autotune = 0;
   o->inner_perm = nullptr;
   o->skew_form = 0;
+  o->precond = ASSS_PRECOND_DIAG;
+  o->ildl_droptol = 0.0;
+  o->ildl_fill = HUGE_VAL;
+  o->ildl_pivoting = 1;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -1682,6 +1844,9 @@ asss_status_t asss_update_values(asss_handle_t h, const asss_csr_t* A, void* hip
   return guarded([&]() -> asss_status_t {
     check_handle(h);
     if (!A) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    if (h->il.on)
+      throw Error{ASSS_ERR_INVALID_ARG, "value updates are not provided for the incomplete LDL^T preconditioner "
+                                        "(its outer operator holds A_hat itself)"};
     hipStream_t s = (hipStream_t)hip_stream;
     Csr Ah = map_values_onto(h->Apat, A->n, A->nnz, A->rowptr, A->colind, A->val);
     Csr Abar = permute_scale(Ah, h->m, h->Dr, h->Dc);
@@ -1793,8 +1958,9 @@ asss_status_t asss_solve_batched(int32_t nsys, const asss_handle_t* hs, const in
         const int nc = std::min(NRMAX, (int)nrhs[sidx] - j0);
         asss_info_t inf[NRMAX] = {};
         asss_status_t stt;
-        // the 4-column inner kernels hold at most 16 deflation vectors
-        if (nc >= 2 && oo.outer == ASSS_OUTER_FGMRES && h->k_eff <= 16 && !oo.use_x0) {
+        // the 4-column inner kernels hold at most 16 deflation vectors and act
+        // on the sliced J_tilde (the incomplete LDL^T solves one column at a time)
+        if (nc >= 2 && oo.outer == ASSS_OUTER_FGMRES && h->k_eff <= 16 && !oo.use_x0 && !h->il.on) {
           const double* bs[NRMAX];
           double* xs[NRMAX];
           for (int c = 0; c < nc; ++c) {
@@ -1904,6 +2070,7 @@ asss_status_t asss_save(asss_handle_t h, const char* path) {
   return guarded([&]() -> asss_status_t {
     check_handle(h);
     if (!path) throw Error{ASSS_ERR_INVALID_ARG, "null path"};
+    if (h->il.on) throw Error{ASSS_ERR_INVALID_ARG, "saved setups are not provided for the incomplete LDL^T preconditioner"};
     std::vector<double> aval(h->dA.nnz);
     if (h->dA.nnz)
       HIPCHK(hipMemcpy(aval.data(), h->dA.val, h->dA.nnz * sizeof(double), hipMemcpyDeviceToHost));
@@ -2018,6 +2185,42 @@ asss_status_t asss_destroy(asss_handle_t h) {
   });
 }
 
+asss_status_t asss_ildl_factor(const asss_csr_t* M, double droptol, double fill, int32_t pivoting,
+                               asss_ildl_t* out) {
+  return guarded([&]() -> asss_status_t {
+    if (!M || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    *out = nullptr;
+    if (!(droptol >= 0.0) || !(fill > 0.0)) throw Error{ASSS_ERR_INVALID_ARG, "droptol must be >= 0 and fill > 0"};
+    Csr Mh = validate_and_copy(M->n, M->nnz, M->rowptr, M->colind, M->val);
+    std::unique_ptr<asss_ildl_s> f(new asss_ildl_s());
+    IldlOpts o;
+    o.droptol = droptol;
+    o.fill = fill;
+    o.pivoting = pivoting != 0;
+    f->F = ildl_bunch_kaufman(Mh, o);
+    f->S = ildl_scale(f->F);
+    *out = f.release();
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_ildl_get(asss_ildl_t f, int32_t which, void* dst, int64_t* count) {
+  return guarded([&]() -> asss_status_t {
+    if (!f || !count) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
+    std::vector<unsigned char> bytes;
+    int64_t cnt = 0;
+    if (!ildl_export(f->F, f->S, which, bytes, cnt)) throw Error{ASSS_ERR_INVALID_ARG, "unknown array id"};
+    *count = cnt;
+    if (dst && !bytes.empty()) std::memcpy(dst, bytes.data(), bytes.size());
+    return ASSS_OK;
+  });
+}
+
+asss_status_t asss_ildl_destroy(asss_ildl_t f) {
+  delete f;
+  return ASSS_OK;
+}
+
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
   return guarded([&]() -> asss_status_t {
     if (!h || !out) throw Error{ASSS_ERR_INVALID_ARG, "null argument"};
@@ -2052,6 +2255,14 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
       i.tune_us[c] = h->tuned[c].second;
     }
     i.tune_s = h->tune_s;
+    i.precond = h->il.on ? ASSS_PRECOND_ILDL : ASSS_PRECOND_DIAG;
+    if (h->il.on) {
+      i.ildl_n2x2 = h->il.F.n2x2;
+      i.ildl_levels_lower = h->il.nlev_f;
+      i.ildl_levels_upper = h->il.nlev_b;
+      i.ildl_nnz_l = h->il.F.L.nnz();
+      i.ildl_dropped = h->il.F.dropped;
+    }
     *out = i;
     return ASSS_OK;
   });
@@ -2087,7 +2298,20 @@ asss_status_t asss_get_array(asss_handle_t h, int32_t which, void* dst, int64_t*
       case ASSS_ARR_ALPHA: give(h->alpha.data(), (int64_t)h->alpha.size(), 8); break;
       case ASSS_ARR_X: give_dev(h->d_X, n * (int64_t)h->kr, 8); break;
       case ASSS_ARR_NEG: give(h->neg.data(), (int64_t)h->neg.size(), 4); break;
-      default: throw Error{ASSS_ERR_INVALID_ARG, "unknown array id"};
+      default: {
+        std::vector<unsigned char> bytes;
+        int64_t cnt = 0;
+        if (which < ASSS_ARR_ILDL_PERM || which > ASSS_ARR_SIGMA_R)
+          throw Error{ASSS_ERR_INVALID_ARG, "unknown array id"};
+        if (!h->il.on) {
+          *count = 0;
+          break;
+        }
+        ildl_export(h->il.F, h->il.Sc, which, bytes, cnt);
+        *count = cnt;
+        if (dst && !bytes.empty()) std::memcpy(dst, bytes.data(), bytes.size());
+        break;
+      }
     }
     return ASSS_OK;
   });
@@ -2114,7 +2338,11 @@ asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in, double* 
           vin = h->tmp;
           vout = h->w;
         }
-        if (fp32) {
+        if (h->il.on) {
+          auto& il = h->il;
+          if (fp32) ildl_sandwich<float>(il.Lb32, il.J32, il.Lf32, vin, vout, il.t32[0], il.t32[1], il.t32[2], s);
+          else ildl_sandwich<double>(il.Lb64, il.J64, il.Lf64, vin, vout, il.t64[0], il.t64[1], il.t64[2], s);
+        } else if (fp32) {
           cast_d2f(n, vin, h->mb32.w[0], s);
           skew_spmv<float>(h->J32, h->mb32.w[0], h->mb32.w[1], s);
           cast_f2d(n, h->mb32.w[1], vout, s);

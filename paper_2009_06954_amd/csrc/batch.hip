@@ -400,7 +400,7 @@ std::mutex g_mu;
 std::vector<std::unique_ptr<Plan>> g_plans;
 
 bool eligible(asss_handle_t h, int nrhs, const asss_solve_opts_t& o) {
-  return h->d_perm == nullptr && h->k_eff <= 16 && h->kr <= 256 && nrhs <= NC && o.outer == ASSS_OUTER_FGMRES &&
+  return !h->il.on && h->d_perm == nullptr && h->k_eff <= 16 && h->kr <= 256 && nrhs <= NC && o.outer == ASSS_OUTER_FGMRES &&
          !o.use_x0 && o.fixed_inner_steps == 0;
 }
 

@@ -15,6 +15,8 @@
 
 #include "../../include/asss.h"
 #include "host_setup.hpp"
+#include "ildl_host.hpp"
+#include "ildl_kernels.hpp"
 #include "kernels.hpp"
 
 namespace asss {
@@ -197,6 +199,28 @@ struct asss_handle_s {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double prof_s = 0.0;
   int prof_launches = 0;
+
+  // The general incomplete LDL^T preconditioner (setup option precond = 1,
+  // paper Sec. 3): the scaled system lives in the factorization's positions.
+  struct Ildl {
+    bool on = false;
+    asss::IldlOpts opts;
+    asss::IldlFactor F;     // perm, L, pivot blocks (host copy, for inspection)
+    asss::IldlScaled Sc;    // Lcal, U_r, Sigma_r
+    int32_t nlev_f = 0, nlev_b = 0;
+    asss::DTri<double> Lf64, Lb64;  // Lcal (forward solves) and Lcal^T (backward)
+    asss::DTri<float> Lf32, Lb32;
+    asss::DCsr32<double> J64, Ap, ApT;  // J_hat, A_hat and A_hat^T in positions
+    asss::DCsr32<float> J32;
+    int32_t* d_perm = nullptr;  // position p -> index perm[p] of Abar
+    int32_t* d_mp = nullptr;    // m[perm[p]]: row of A behind position p
+    double* d_drp = nullptr;    // Dr[m[perm[p]]]
+    double* d_ones = nullptr;
+    double* t64[3] = {nullptr, nullptr, nullptr};
+    float* t32[3] = {nullptr, nullptr, nullptr};
+    double *y64 = nullptr, *z64 = nullptr, *u64 = nullptr;
+    float *y32 = nullptr, *z32 = nullptr, *u32 = nullptr;
+  } il;
 
   ~asss_handle_s() {
     if (h_small) (void)hipHostFree(h_small);

@@ -1,0 +1,152 @@
+// Setup of the general incomplete LDL^T preconditioner (paper Sec. 3): the
+// symmetric and skew parts of A_hat, the Bunch-Kaufman factorization of
+// M_hat on the host, the scaled factor and low-rank term, and the device
+// copies that the triangular-solve kernels read.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "handle.hpp"
+#include "ildl_host.hpp"
+#include "ildl_kernels.hpp"
+#include "ildl_setup.hpp"
+
+namespace asss {
+namespace host {
+
+namespace {
+
+// Lanes per row for rows of at most `longest` entries, `rows` rows solved
+// side by side: about four entries per lane, fewer lanes when the rows would
+// not fit the workgroup in one pass.
+int lanes_per_row(int64_t longest, int64_t rows, int64_t width) {
+  int lpr = 1;
+  while (lpr < 64 && (int64_t)lpr * 4 < longest) lpr *= 2;
+  while (lpr > 1 && rows * lpr > width) lpr /= 2;
+  return lpr;
+}
+
+// A triangular CSR (rows over positions, diagonal stored in each row) in
+// schedule order: the rows level by level, each with its off-diagonal
+// entries and its diagonal; the lanes per row of every level.  Uploaded in
+// FP64 and FP32 (index arrays shared).
+void upload_tri(DevArena& ar, const Csr& T, bool lower, DTri<double>& d64, DTri<float>& d32, int32_t& nlev,
+                hipStream_t s) {
+  const int64_t n = T.nrows;
+  if (T.nnz() >= (int64_t)INT32_MAX) throw Error{ASSS_ERR_INVALID_ARG, "the incomplete factor has 2^31 entries or more"};
+  LevelSchedule L = level_schedule(T, lower);
+  nlev = L.nlevels();
+  std::vector<int32_t> eptr(n + 1, 0), col, lpr(nlev);
+  std::vector<double> val, diag(n, 0.0);
+  col.reserve(T.nnz());
+  val.reserve(T.nnz());
+  for (int64_t e = 0; e < n; ++e) {
+    const int32_t i = L.rows[e];
+    for (int64_t q = T.ptr[i]; q < T.ptr[i + 1]; ++q) {
+      if (T.col[q] == i) {
+        diag[e] = T.val[q];
+      } else {
+        col.push_back(T.col[q]);
+        val.push_back(T.val[q]);
+      }
+    }
+    eptr[e + 1] = (int32_t)col.size();
+    if (diag[e] == 0.0) throw Error{ASSS_ERR_INTERNAL, "the scaled incomplete factor has a zero diagonal entry"};
+  }
+  for (int32_t l = 0; l < nlev; ++l) {
+    int64_t longest = 0;
+    for (int32_t e = L.ptr[l]; e < L.ptr[l + 1]; ++e) longest = std::max<int64_t>(longest, eptr[e + 1] - eptr[e]);
+    lpr[l] = lanes_per_row(longest, L.ptr[l + 1] - L.ptr[l], TRI_WG);
+  }
+  const int32_t* dlp = ar.upload(L.ptr, s);
+  const int32_t* dlpr = ar.upload(lpr, s);
+  const int32_t* drow = ar.upload(L.rows, s);
+  const int32_t* dptr = ar.upload(eptr, s);
+  const int32_t* dcol = ar.upload(col, s);
+  std::vector<float> val32(val.begin(), val.end()), diag32(diag.begin(), diag.end());
+  d64.n = d32.n = (int32_t)n;
+  d64.nlev = d32.nlev = nlev;
+  d64.lev_ptr = d32.lev_ptr = dlp;
+  d64.lev_lpr = d32.lev_lpr = dlpr;
+  d64.row = d32.row = drow;
+  d64.eptr = d32.eptr = dptr;
+  d64.col = d32.col = dcol;
+  d64.val = ar.upload(val, s);
+  d64.diag = ar.upload(diag, s);
+  d32.val = ar.upload(val32, s);
+  d32.diag = ar.upload(diag32, s);
+}
+
+template <typename T>
+DCsr32<T> upload_csr32(DevArena& ar, const Csr& M, const int32_t** shared_ptr_col, hipStream_t s) {
+  if (M.nnz() >= (int64_t)INT32_MAX) throw Error{ASSS_ERR_INVALID_ARG, "an operator has 2^31 entries or more"};
+  DCsr32<T> d;
+  d.n = (int32_t)M.nrows;
+  int64_t longest = 0;
+  for (int64_t i = 0; i < M.nrows; ++i) longest = std::max<int64_t>(longest, M.ptr[i + 1] - M.ptr[i]);
+  // up to two passes of the workgroup over the rows
+  d.lpr = lanes_per_row(longest, M.nrows, 2 * TRI_WG);
+  if (shared_ptr_col && shared_ptr_col[0]) {
+    d.ptr = shared_ptr_col[0];
+    d.col = shared_ptr_col[1];
+  } else {
+    std::vector<int32_t> ptr(M.ptr.begin(), M.ptr.end());
+    d.ptr = ar.upload(ptr, s);
+    d.col = ar.upload(M.col, s);
+    if (shared_ptr_col) {
+      shared_ptr_col[0] = d.ptr;
+      shared_ptr_col[1] = d.col;
+    }
+  }
+  std::vector<T> v(M.val.begin(), M.val.end());
+  d.val = ar.upload(v, s);
+  return d;
+}
+
+}  // namespace
+
+void ildl_setup(asss_handle_s* h, const Csr& Ahat, hipStream_t s) {
+  auto& il = h->il;
+  const int64_t n = h->n;
+  Csr M, J;
+  symmetric_skew_split(Ahat, M, J);
+  il.F = ildl_bunch_kaufman(M, il.opts);
+  il.Sc = ildl_scale(il.F);
+  il.on = true;
+  // the positions of the factorization are the order of the scaled system
+  const std::vector<int32_t>& perm = il.F.perm;
+  Csr Ap = permute_symmetric(Ahat, perm);
+  Csr Jp = permute_symmetric(J, perm);
+  upload_tri(h->ar, il.Sc.Lc, true, il.Lf64, il.Lf32, il.nlev_f, s);
+  upload_tri(h->ar, il.Sc.LcT, false, il.Lb64, il.Lb32, il.nlev_b, s);
+  const int32_t* jpc[2] = {nullptr, nullptr};
+  il.J64 = upload_csr32<double>(h->ar, Jp, jpc, s);
+  il.J32 = upload_csr32<float>(h->ar, Jp, jpc, s);
+  il.Ap = upload_csr32<double>(h->ar, Ap, nullptr, s);
+  il.ApT = upload_csr32<double>(h->ar, transpose(Ap), nullptr, s);
+  std::vector<int32_t> mp(n);
+  std::vector<double> drp(n);
+  for (int64_t p = 0; p < n; ++p) {
+    mp[p] = h->m[perm[p]];
+    drp[p] = h->Dr[h->m[perm[p]]];
+  }
+  il.d_perm = h->ar.upload(perm, s);
+  il.d_mp = h->ar.upload(mp, s);
+  il.d_drp = h->ar.upload(drp, s);
+  il.d_ones = h->ar.upload(std::vector<double>(n, 1.0), s);
+  for (int b = 0; b < 3; ++b) {
+    il.t64[b] = h->ar.alloc<double>(n);
+    il.t32[b] = h->ar.alloc<float>(n);
+  }
+  il.y64 = h->ar.alloc<double>(n);
+  il.z64 = h->ar.alloc<double>(n);
+  il.u64 = h->ar.alloc<double>(n);
+  il.y32 = h->ar.alloc<float>(n);
+  il.z32 = h->ar.alloc<float>(n);
+  il.u32 = h->ar.alloc<float>(n);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+}  // namespace host
+}  // namespace asss
