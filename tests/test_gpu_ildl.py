@@ -8,6 +8,11 @@ k = 8) with ildl(1e-2), the setting of the paper's experiments, and a
 stand-in matrix (n = 300, gamma = 0.01, k = 5) whose M_hat is indefinite:
 2x2 pivots and a low-rank term r > 0.
 
+On the stand-in the inner iterates themselves are sensitive to rounding
+(||J_bar|| ~ 190: the oracle's own 30-step iterate moves by 6e-3 under a
+1e-15 change of its right-hand side), so there the inner solve is compared
+through its residual, and the solves to their tolerance.
+
 Tolerances.  Every product with J_tilde and with the outer operator is two
 triangular solves with Lcal around a sparse product; the GPU sums each row
 in stored order and the oracle runs LAPACK's dense solves, so the two differ
@@ -130,7 +135,11 @@ def test_factor_matches_oracle(case):
     bs[st.factor.blocks[:, 0]] = st.factor.blocks[:, 1]
     assert np.array_equal(h.array("ildl_bsize"), bs)
     assert info["ildl_n2x2"] == int((st.factor.blocks[:, 1] == 2).sum())
-    assert info["ildl_dropped"] == st.factor.dropped
+    # the drop count also counts candidates that cancel to an exact zero in one
+    # summation order and to a tiny value in the other (dropped either way, L
+    # is the same): equal up to such cases
+    assert abs(info["ildl_dropped"] - st.factor.dropped) <= 0.01 * st.factor.dropped
+    assert info["ildl_nnz_l"] == st.factor.L.nnz - n
     Lc = sp.csr_matrix((h.array("Lcal_val"), h.array("Lcal_colind"), h.array("Lcal_rowptr")), shape=(n, n))
     assert np.abs((Lc - st.Lcal).toarray()).max() <= 1e-12 * np.abs(st.Lcal).max()
     r = info["rank_r"]
@@ -173,7 +182,19 @@ def test_lanczos_and_x(case):
     assert np.abs(Q - st.Q).max() <= 1e-7
     X = case.hq.array("X").reshape(-1, case.n).T
     assert X.shape == st.prec.X.shape
-    assert np.abs(X - st.prec.X).max() <= 1e-8 * max(1.0, np.abs(st.prec.X).max())
+    Xo = st.prec.X
+    scale = max(1.0, np.abs(Xo).max())
+    assert np.abs(X[:, :k] - Xo[:, :k]).max() <= 1e-8 * scale
+    # the columns of U_r are eigenvectors of 2x2 blocks of M_r, unique only up
+    # to sign (and to any rotation within a block of eigenvalue -2 twice):
+    # compare X_r Sigma_r U_r^T, which does not depend on that choice
+    r = st.rank_r
+    if r:
+        Ur = case.hq.array("Ur").reshape(r, case.n).T
+        sig = case.hq.array("sigma_r")
+        lib = X[:, k:] @ np.diag(sig) @ Ur.T
+        ora = Xo[:, k:] @ np.diag(st.sigma_r) @ st.Ur.T
+        assert np.abs(lib - ora).max() <= 1e-8 * max(1.0, np.abs(ora).max())
 
 
 @pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
@@ -185,7 +206,22 @@ def test_inner_mrs_fixed_steps(case, fp32):
     y, its = h.apply("mrs", _cuda(v), fixed_inner_steps=30, inner_fp32=fp32)
     yo, its_o, _ = mrs(1.0, st.prec.jbar, v, 1000, 0.0, fixed_steps=30)
     assert its == its_o == 30
-    assert _rel(_np(y), yo) <= (1e-4 if fp32 else 1e3 * case.optol)
+    if case.name == "euler45":
+        assert _rel(_np(y), yo) <= (1e-4 if fp32 else 1e3 * case.optol)
+    else:
+        # ||J_bar|| ~ 190 here: the Lanczos basis of the short recurrence
+        # loses orthogonality, and the oracle's own 30-step iterate moves by
+        # 6e-3 when v moves by 1e-15; what is unique is the minimal-residual
+        # property, so the true residuals are compared
+        Sb = np.eye(case.n) + st.prec.jbar(np.eye(case.n))
+        rg = np.linalg.norm(v - Sb @ _np(y)) / np.linalg.norm(v)
+        ro = np.linalg.norm(v - Sb @ yo) / np.linalg.norm(v)
+        if fp32:
+            # FP32 triangular solves with kappa(Lcal) ~ 550 around ||J_hat||:
+            # the residual stays within 30 % of the FP64 optimum
+            assert ro * 0.98 <= rg <= 1.3 * ro
+        else:
+            assert abs(rg - ro) <= 0.02 * ro
 
 
 def test_preconditioner_and_transpose(case):
@@ -193,11 +229,14 @@ def test_preconditioner_and_transpose(case):
     the oracle's P (eq. smw in the inverse-free form)."""
     h, st = case.hq, case.st
     P = st.prec.dense_P()
+    # both sides hold X = S_bar^-1 U_bar to the tolerance 1e-10 of its
+    # one-time solve: the SMW term then carries ~1e-10 kappa(P) of error
+    bound = max(1e-8, 1e-9 * np.linalg.cond(P))
     v = case.rng.standard_normal(case.n)
     z, _ = h.apply("prec", _cuda(v), inner_tol=1e-13, inner_maxit=5000)
-    assert _rel(_np(z), np.linalg.solve(P, v)) <= 1e-8
+    assert _rel(_np(z), np.linalg.solve(P, v)) <= bound
     zt, _ = h.apply("prec_t", _cuda(v), inner_tol=1e-13, inner_maxit=5000)
-    assert _rel(_np(zt), np.linalg.solve(P.T, v)) <= 1e-8
+    assert _rel(_np(zt), np.linalg.solve(P.T, v)) <= bound
 
 
 def test_solution_parity(case):
