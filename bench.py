@@ -244,6 +244,69 @@ def grad_bench(args, asss, torch, np, W):
     print(json.dumps(res), flush=True)
 
 
+def ildl_bench(args, asss, torch, np, W):
+    """The general incomplete LDL^T preconditioner (precond = ILDL, Sec. 3;
+    ildl(1e-2) as in the paper's experiments) against the diagonal reading on
+    implicit-Euler grids (the 45 x 45 grid of the small parity workload and a
+    100 x 100 one), S tridiagonal, k = 8, tol 1e-8, FGMRES(64), inner
+    tolerance 1e-2; FP64.  Each inner step of the ILDL path is two
+    level-scheduled triangular solves in one workgroup, so its time is the
+    chain of levels: reported per level as well.  The oracle's ILDL solve of
+    the 45 x 45 grid is timed beside it."""
+    import oracle as O
+    from oracle.ildl import IldlOptions
+    out = {"metric": "time-to-1e-8 rel. residual with the incomplete LDL^T preconditioner", "unit": "s",
+           "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic", "cases": []}
+    kw = dict(tol=1e-8, restart_m=64, inner_tol=1e-2, max_outer=2000)
+    for m in (45, 100):
+        w = W.implicit_euler_grid(m=m, h=0.1, cfg=0)
+        b = torch.from_numpy(w.b).cuda()
+        rec = {"workload": f"implicit_euler_{m}x{m}_h0.1", "n": int(w.A.shape[0]), "k": 8, "s_pattern": "tridiag"}
+        for name, skw in (("ildl", dict(precond="ildl", ildl_droptol=1e-2)), ("diag", {})):
+            t0 = time.perf_counter()
+            h = asss.setup(w.A, k=8, s_pattern="tridiag", **skw)
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            h.solve(b, **kw)  # warm-up
+            best, inf = float("inf"), None
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, inf = h.solve(b, **kw)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            err = float(torch.linalg.norm(x.cpu() - torch.from_numpy(w.x_star)) / np.linalg.norm(w.x_star))
+            r = {"solve_s": round(best, 5), "setup_s": round(setup_s, 3), "outer_its": inf["outer_its"],
+                 "inner_its": inf["inner_its_total"], "relres_true": inf["relres_true"], "rel_err_vs_xstar": err,
+                 "inner_step_us": round(1e6 * inf["inner_kernel_s"] / max(1, inf["inner_its_total"]), 2)}
+            if name == "ildl":
+                hi = h.info()
+                lev = hi["ildl_levels_lower"] + hi["ildl_levels_upper"]
+                r.update(levels_lower=hi["ildl_levels_lower"], levels_upper=hi["ildl_levels_upper"],
+                         nnz_l=hi["ildl_nnz_l"], us_per_level=round(r["inner_step_us"] / max(1, lev), 3))
+            rec[name] = r
+            log(f"{rec['workload']} {name}: {r}")
+            h.close()
+        rec["speedup_ildl_vs_diag"] = round(rec["diag"]["solve_s"] / rec["ildl"]["solve_s"], 3)
+        out["cases"].append(rec)
+    out["value"] = out["cases"][0]["ildl"]["solve_s"]
+    out["config"] = {"workload": out["cases"][0]["workload"], "precond": "ildl(1e-2)", "outer": "fgmres(64)",
+                     "inner_tol": 1e-2, "tol": 1e-8}
+    if not args.no_cpu_baseline:
+        w = W.implicit_euler_grid(m=45, h=0.1, cfg=0)
+        st = O.setup_ildl(w.A, O.SetupOptions(k=8, s_pattern="tridiag"), IldlOptions(droptol=1e-2))
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, info = O.solve(st, w.b, O.SolveOptions(tol=1e-8, restart_m=64, inner_tol=1e-2))
+            best = min(best, time.perf_counter() - t0)
+        out["cpu_baseline"] = {"value": round(best, 4), "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"oracle ILDL solve of the 45 x 45 grid (best of 3, setup not timed; "
+                                         f"{info['outer_its']} outer / {info['inner_its_total']} inner steps, dense "
+                                         f"triangular solves)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +347,9 @@ def main():
                     help="differentiation workload instead: 1000 x 1000 implicit-Euler grid (n = 1e6), "
                          "loss ||x - x_t||^2, forward solve + backward (adjoint solve and dL/dA, dL/db) "
                          "through the autograd function, FP64, tol 1e-10")
+    ap.add_argument("--ildl", action="store_true",
+                    help="incomplete LDL^T workload instead: the ILDL preconditioner (ildl(1e-2)) against the "
+                         "diagonal reading on 45 x 45 and 100 x 100 implicit-Euler grids, FP64, tol 1e-8")
     ap.add_argument("--outer", default="fgmres", choices=["fgmres", "tfqmr"])
     ap.add_argument("--deflation", default="explicit", choices=["explicit", "explicit_fp32_basis"],
                     help="explicit_fp32_basis: the Lanczos vectors rounded to FP32 values and used so "
@@ -324,6 +390,8 @@ def main():
         return batched(args, asss, torch, np, W)
     if args.grad:
         return grad_bench(args, asss, torch, np, W)
+    if args.ildl:
+        return ildl_bench(args, asss, torch, np, W)
     log(f"building workload m={args.m} Pe={args.peclet:g} (seed of workload {args.cfg})")
     w = W.convdiff3d(m=args.m, peclet=args.peclet, cfg=args.cfg)
     n, nnz = w.A.shape[0], w.A.nnz
