@@ -52,9 +52,17 @@ def workload_key(m: int, peclet: float, k: int, order: str) -> str:
     return f"convdiff3d_{m}_Pe{peclet:g}_k{k}{suffix}"
 
 
+KERNEL_SOURCES = ("kernels.hip", "mrs_common.hpp", "kernels.hpp")
+
+
 def kernel_sha() -> str:
-    with open(os.path.join(ROOT, "paper_2009_06954_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 of the inner step's source: the kernel file, the recurrence it
+    shares with the other inner kernels, and their data structures."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2009_06954_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(precision: str, key: str, deflation: str = "explicit"):
