@@ -106,7 +106,13 @@ enum {
  * and of asss_destroy, with ctx passed through, and from the worker threads of
  * asss_solve_batched, several at once for different handles: they must be
  * thread-safe.  The functions and ctx must stay valid until the handle is
- * destroyed (the structure itself is copied). */
+ * destroyed (the structure itself is copied).
+ * The callbacks take no stream (a stream-ordered allocator would get one):
+ * a handle's buffers serve every stream its calls are given, they are taken
+ * at setup or on first use, and given back by asss_destroy (after a device
+ * synchronisation) or when a workspace grows (every entry point synchronises
+ * its stream before it returns), so no kernel can still be reading memory
+ * that is given back. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);

@@ -31,6 +31,11 @@ class LinearSolve:
         if not A.has_canonical_format:
             A.sum_duplicates()
             A.sort_indices()
+        if np.any(A.data == 0.0):
+            # the library drops stored zeros at setup (a stored zero is no
+            # nonzero of A), so such an entry could never take another value
+            # in a later call: refuse it here rather than after a step
+            raise ValueError("A has stored zeros: remove them (A.eliminate_zeros()) or give them nonzero values")
         self.n = A.shape[0]
         self.indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
         self.indices = np.ascontiguousarray(A.indices, dtype=np.int32)
