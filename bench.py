@@ -102,14 +102,14 @@ def oracle_solve_time(m: int, peclet: float, cfg: int, k: int, tol: float, inner
     t0 = time.perf_counter()
     st = O.setup(w.A, O.SetupOptions(k=k, s_pattern="abar"))
     setup_s = time.perf_counter() - t0
-    best, info = float("inf"), None
+    best, info, x = float("inf"), None, None
     for _ in range(repeats):
         t0 = time.perf_counter()
-        _, info = O.solve(st, w.b, O.SolveOptions(tol=tol, inner_tol=inner_tol, restart_m=restart))
+        x, info = O.solve(st, w.b, O.SolveOptions(tol=tol, inner_tol=inner_tol, restart_m=restart))
         best = min(best, time.perf_counter() - t0)
     return {"m": m, "n": int(w.A.shape[0]), "solve_s": round(best, 4), "setup_s": round(setup_s, 2),
             "outer_its": int(info["outer_its"]), "inner_its": int(info["inner_its_total"]),
-            "relres": float(info["relres_true"])}
+            "relres": float(info["relres_true"]), "_x": x}
 
 
 def unit_cost(run: dict) -> float:
@@ -128,6 +128,7 @@ def cpu_baseline(sizes, peclet: float, cfg: int, k: int, tol: float, n_full: int
     from threadpoolctl import threadpool_info
 
     runs = [oracle_solve_time(m, peclet, cfg, k, tol, inner_tol, restart) for m in sizes]
+    xs = {r["m"]: r.pop("_x") for r in runs}
     small, large = runs[0], runs[-1]
     predicted = unit_cost(small) * large["n"] * large["inner_its"]
     pools = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
@@ -144,7 +145,32 @@ def cpu_baseline(sizes, peclet: float, cfg: int, k: int, tol: float, n_full: int
         "sample": (f"oracle solves of convdiff3d m^3 Pe{peclet:g} for m in {list(sizes)} "
                    f"(best of 3, setup not timed); extrapolated to n={n_full} with the GPU's "
                    f"{inner_full} inner steps from the larger sample's cost per row and step"),
+        "_x": xs,
     }
+
+
+def oracle_parity(asss, torch, np, W, m, peclet, cfg, k, tol, inner_tol, restart, x_oracle):
+    """The library on the same smaller instance of the workload family, in the
+    benchmark's launch configuration (grid order, offset slots, FGMRES(restart),
+    the same inner tolerance), FP64 and FP32 inner: relative error of each
+    solution against the oracle's solution of the same system at the same
+    tolerance, and against the oracle's x solved further (both sides at 1e-8
+    differ from A^-1 b by up to kappa * tol)."""
+    w = W.convdiff3d(m=m, peclet=peclet, cfg=cfg)
+    h = asss.setup(w.A, k=k, s_pattern="abar", reorder="grid")
+    b = torch.from_numpy(w.b).cuda()
+    out = {"workload": f"convdiff3d_{m}^3_Pe{peclet:g}", "n": int(w.A.shape[0]), "tol": tol}
+    xn = float(np.linalg.norm(x_oracle))
+    for mixed in (False, True):
+        x, inf = h.solve(b, tol=tol, inner_fp32=mixed, restart_m=restart, inner_tol=inner_tol)
+        xg = x.cpu().numpy()
+        key = "mixed" if mixed else "fp64"
+        out[key + "_rel_err_vs_oracle"] = float(np.linalg.norm(xg - x_oracle) / xn)
+        out[key + "_rel_err_vs_xstar"] = float(np.linalg.norm(xg - w.x_star) / np.linalg.norm(w.x_star))
+        out[key + "_outer_its"] = inf["outer_its"]
+    out["oracle_rel_err_vs_xstar"] = float(np.linalg.norm(x_oracle - w.x_star) / np.linalg.norm(w.x_star))
+    h.close()
+    return out
 
 
 def batched(args, asss, torch, np, W):
@@ -574,6 +600,15 @@ def main():
                                                inf64[-1]["inner_its_total"], args.inner_tol, args.restart)
         except Exception as e:  # the baseline must not hide the GPU result
             res["cpu_baseline"] = {"value": None, "error": repr(e)}
+        xs = res["cpu_baseline"].pop("_x", None)
+        if xs:
+            mo = max(xs)
+            log(f"error against the oracle on convdiff3d {mo}^3")
+            try:
+                res["oracle_parity"] = oracle_parity(asss, torch, np, W, mo, args.peclet, args.cfg, args.k,
+                                                     args.tol, args.inner_tol, args.restart, xs[mo])
+            except Exception as e:
+                res["oracle_parity"] = {"error": repr(e)}
     print(json.dumps(res), flush=True)
 
 

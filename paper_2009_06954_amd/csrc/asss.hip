@@ -169,7 +169,7 @@ double dot_host(asss_handle_s* h, int64_t n, const double* a, const double* b, h
 void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
   if (h->il.on) {
     auto& il = h->il;
-    ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], s);
+    ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
   spmv(h->dS, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
@@ -179,7 +179,7 @@ void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
 void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
   if (h->il.on) {
     auto& il = h->il;
-    ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], s);
+    ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
   spmv(h->dAbarT, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
@@ -199,7 +199,7 @@ void rhs_transform(asss_handle_s* h, bool adjoint, const double* b, double* bchk
       spmv(h->dSt, b, h->t1, nullptr, h->d_dc, 0, nullptr, s);
       permute_gather(n, il.d_perm, h->t1, h->tmp, s);
     }
-    ildl_trsv(il.Lf64, h->tmp, bchk, s);
+    ildl_trsv(il.Lf64, h->tmp, bchk, il.t64[3], s);
     return;
   }
   if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, bchk, s);
@@ -213,7 +213,7 @@ void back_transform(asss_handle_s* h, bool adjoint, const double* xchk, double* 
   const int64_t n = h->n;
   if (h->il.on) {
     auto& il = h->il;
-    ildl_trsv(il.Lb64, xchk, h->t1, s);
+    ildl_trsv(il.Lb64, xchk, h->t1, il.t64[3], s);
     permute_scatter(n, il.d_perm, h->t1, h->tmp, s);
     if (!adjoint) spmv(h->dS, h->tmp, x, h->d_dc, nullptr, 0, nullptr, s);
     else scatter_scale(n, h->d_m, h->d_drp, il.d_ones, h->tmp, x, s);
@@ -227,7 +227,7 @@ void back_transform(asss_handle_s* h, bool adjoint, const double* xchk, double* 
 void jtilde_apply(asss_handle_s* h, const double* in, double* out, hipStream_t s) {
   if (h->il.on) {
     auto& il = h->il;
-    ildl_sandwich<double>(il.Lb64, il.J64, il.Lf64, in, out, il.t64[0], il.t64[1], il.t64[2], s);
+    ildl_sandwich<double>(il.Lb64, il.J64, il.Lf64, in, out, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
   } else {
     skew_spmv<double>(h->J64, in, out, s);
   }
@@ -334,10 +334,10 @@ int run_ildl_mrs(asss_handle_s* h, const double* rhs, double* out, int sign, dou
   a.alpha = h->d_alpha;
   if constexpr (f32) {
     a.Q = h->d_Q32; a.gram = h->d_G32; a.Lb = il.Lb32; a.Lf = il.Lf32; a.J = il.J32;
-    a.buf = h->mb32; a.y = il.y32; a.z = il.z32; a.u = il.u32;
+    a.buf = h->mb32; a.y = il.y32; a.z = il.z32; a.u = il.u32; a.bs = il.t32[3];
   } else {
     a.Q = h->d_Q64; a.gram = h->d_G64; a.Lb = il.Lb64; a.Lf = il.Lf64; a.J = il.J64;
-    a.buf = h->mb64; a.y = il.y64; a.z = il.z64; a.u = il.u64;
+    a.buf = h->mb64; a.y = il.y64; a.z = il.z64; a.u = il.u64; a.bs = il.t64[3];
   }
   a.rhs = rhs;
   a.out = out;
@@ -2340,8 +2340,8 @@ asss_status_t asss_apply(asss_handle_t h, int32_t op, const double* in, double* 
         }
         if (h->il.on) {
           auto& il = h->il;
-          if (fp32) ildl_sandwich<float>(il.Lb32, il.J32, il.Lf32, vin, vout, il.t32[0], il.t32[1], il.t32[2], s);
-          else ildl_sandwich<double>(il.Lb64, il.J64, il.Lf64, vin, vout, il.t64[0], il.t64[1], il.t64[2], s);
+          if (fp32) ildl_sandwich<float>(il.Lb32, il.J32, il.Lf32, vin, vout, il.t32[0], il.t32[1], il.t32[2], il.t32[3], s);
+          else ildl_sandwich<double>(il.Lb64, il.J64, il.Lf64, vin, vout, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
         } else if (fp32) {
           cast_d2f(n, vin, h->mb32.w[0], s);
           skew_spmv<float>(h->J32, h->mb32.w[0], h->mb32.w[1], s);

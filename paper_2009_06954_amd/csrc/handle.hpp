@@ -216,8 +216,8 @@ struct asss_handle_s {
     int32_t* d_mp = nullptr;    // m[perm[p]]: row of A behind position p
     double* d_drp = nullptr;    // Dr[m[perm[p]]]
     double* d_ones = nullptr;
-    double* t64[3] = {nullptr, nullptr, nullptr};
-    float* t32[3] = {nullptr, nullptr, nullptr};
+    double* t64[4] = {nullptr, nullptr, nullptr, nullptr};
+    float* t32[4] = {nullptr, nullptr, nullptr, nullptr};
     double *y64 = nullptr, *z64 = nullptr, *u64 = nullptr;
     float *y32 = nullptr, *z32 = nullptr, *u32 = nullptr;
   } il;

@@ -36,29 +36,145 @@ __device__ __forceinline__ T group_sum(T v, int lpr) {
   return v;
 }
 
+// What a lane needs of its slot in one level, loaded ahead: the first PF
+// entries of the slot, the row, its right-hand side (schedule order) and
+// inverse diagonal.  None of it depends on the solution and every address
+// comes from per-level scalars, so the loads of a level are issued two levels
+// before it is solved, with no branch and no wait between them, and stay in
+// flight across the separations of the levels (which wait for LDS only).
+template <typename T, int PF>
+struct LevelRow {
+  int e0, sc, row, lpr, w, base, nslots;
+  bool active;  // the thread's wave has a slot in this level (wave-uniform)
+  bool valid;   // the thread's slot exists in this level
+  int col[PF];
+  T val[PF];
+  T b, d;
+};
+
+template <typename T, int PF, int NT>
+__device__ __forceinline__ void load_level(const DTri<T>& F, const T* __restrict__ bs, int l, LevelRow<T, PF>& r) {
+  const int slot = threadIdx.x;  // < NT
+  r.lpr = F.lev_lpr[l];
+  r.e0 = F.lev_ptr[l];
+  r.nslots = (F.lev_ptr[l + 1] - r.e0) * r.lpr;
+  r.w = F.lev_w[l];
+  r.base = F.lev_base[l];
+  // a wave with no slot in this level loads nothing (in the workgroup form
+  // most waves of a narrow level are idle: their loads would only queue in
+  // the CU's memory pipeline ahead of the busy wave's)
+  r.active = (int)(threadIdx.x & ~63u) < r.nslots;
+  if (!r.active) return;
+  r.valid = slot < r.nslots;
+  r.sc = min(slot, r.nslots - 1);  // a slot that exists: its loads stay in bounds
+  const int e = r.e0 + r.sc / r.lpr;
+  r.row = F.row[e];
+  r.d = F.dinv[e];
+  r.b = bs[e];
+  const int wl = max(r.w - 1, 0);
+#pragma unroll
+  for (int t = 0; t < PF; ++t) {
+    const int idx = r.base + min(t, wl) * r.nslots + r.sc;  // within the level's block or the tail
+    r.col[t] = F.ecol[idx];
+    r.val[t] = F.eval[idx];
+  }
+}
+
+// Level l from the thread's loaded slot r (every thread calls it; groups of
+// lpr lanes share a row): the group's gathered products, summed with
+// shuffles, and y[row] = (b - sum) times the inverse diagonal by lane 0; the
+// slots of a level wider than NT threads in further passes with plain loads.
+template <typename T, int PF, int NT>
+__device__ __forceinline__ void solve_level(const DTri<T>& F, const T* __restrict__ bs, T* __restrict__ y,
+                                            const LevelRow<T, PF>& r) {
+  if (!r.active) return;
+  const int lpr = r.lpr;
+  const int j = threadIdx.x & (lpr - 1);
+  T acc = T(0);
+#pragma unroll
+  for (int t = 0; t < PF; ++t) {
+    // a loaded entry past the slot's count is not used: the product is
+    // discarded, never multiplied by 0 (its y may not be solved yet)
+    const T p = r.val[t] * y[r.col[t]];
+    acc += (t < r.w) ? p : T(0);
+  }
+  for (int t = PF; t < r.w; ++t) {
+    const int idx = r.base + t * r.nslots + r.sc;
+    acc += F.eval[idx] * y[F.ecol[idx]];
+  }
+  acc = group_sum(acc, lpr);
+  if (r.valid && j == 0) y[r.row] = (r.b - acc) * r.d;
+  for (int s2 = (int)threadIdx.x + NT; s2 < r.nslots; s2 += NT) {
+    T a2 = T(0);
+    for (int t = 0; t < r.w; ++t) {
+      const int idx = r.base + t * r.nslots + s2;
+      a2 += F.eval[idx] * y[F.ecol[idx]];
+    }
+    a2 = group_sum(a2, lpr);
+    if (j == 0) {
+      const int e = r.e0 + s2 / lpr;
+      y[F.row[e]] = (bs[e] - a2) * F.dinv[e];
+    }
+  }
+}
+
+// The levels of a solve taken by NT threads (the whole workgroup, or one
+// wave), the row data of level l + 2 loaded while level l is solved, into
+// one of three register sets (the loop is unrolled by three, so no copy
+// forces a wait); sync() separates the levels.
+template <typename T, int NT, class Sync>
+__device__ __forceinline__ void trsv_levels(const DTri<T>& F, const T* __restrict__ b, T* __restrict__ y,
+                                            const T* __restrict__ bs, Sync sync) {
+  constexpr int PF = 4;
+  LevelRow<T, PF> ra, rb, rc;
+  const int nl = F.nlev;
+  if (nl > 0) load_level<T, PF, NT>(F, bs, 0, ra);
+  if (nl > 1) load_level<T, PF, NT>(F, bs, 1, rb);
+  for (int l = 0; l < nl; l += 3) {
+    if (l + 2 < nl) load_level<T, PF, NT>(F, bs, l + 2, rc);
+    solve_level<T, PF, NT>(F, bs, y, ra);
+    sync();
+    if (l + 1 >= nl) break;
+    if (l + 3 < nl) load_level<T, PF, NT>(F, bs, l + 3, ra);
+    solve_level<T, PF, NT>(F, bs, y, rb);
+    sync();
+    if (l + 2 >= nl) break;
+    if (l + 4 < nl) load_level<T, PF, NT>(F, bs, l + 4, rb);
+    solve_level<T, PF, NT>(F, bs, y, rc);
+    sync();
+  }
+}
+
 // y = T^-1 b by levels (every thread of the workgroup calls it).  A group of
 // lpr lanes takes one row of the level: its lanes gather entries
 // j, j + lpr, ... of the row, the group sums them with shuffles, and lane 0
-// divides by the diagonal.  y may live in LDS (the gathers of a level then
-// cost an LDS round trip instead of a cache round trip).
-template <typename T>
-__device__ __forceinline__ void trsv_block(const DTri<T>& F, const T* __restrict__ b, T* __restrict__ y) {
-  const int tid = threadIdx.x;
-  for (int l = 0; l < F.nlev; ++l) {
-    const int e1 = F.lev_ptr[l + 1];
-    const int lpr = F.lev_lpr[l];
-    const int j = tid & (lpr - 1);
-    for (int e = F.lev_ptr[l] + tid / lpr; e < e1; e += TRI_WG / lpr) {
-      const int q1 = F.eptr[e + 1];
-      T acc = T(0);
-      for (int q = F.eptr[e] + j; q < q1; q += lpr) acc += F.val[q] * y[F.col[q]];
-      acc = group_sum(acc, lpr);
-      if (j == 0) {
-        const int i = F.row[e];
-        y[i] = (b[i] - acc) / F.diag[e];
-      }
-    }
+// scales by the inverse diagonal.  The right-hand side is first copied into
+// schedule order (bs, n values of scratch), so that all row data of a level
+// is at addresses known without a dependent load, and that data is loaded two
+// levels ahead; it stays in flight across the separations of the levels,
+// which wait for LDS operations only.
+// Narrow factors (F.wave: every level fits one wave in one pass)
+// with y in LDS are solved by wave 0 alone: consecutive levels of one wave
+// need no workgroup barrier (its LDS operations complete in program order;
+// a wavefront-scope fence keeps the compiler from reordering them), and the
+// other 15 waves do not spend issue slots on levels they have no rows in.
+// Wider factors, or y in global memory, use the whole workgroup with one
+// barrier per level.
+template <typename T, bool YLDS>
+__device__ __forceinline__ void trsv_block(const DTri<T>& F, const T* __restrict__ b, T* __restrict__ y,
+                                           T* __restrict__ bs) {
+  for (int e = threadIdx.x; e < F.n; e += TRI_WG) bs[e] = b[F.row[e]];
+  __syncthreads();
+  if (YLDS && F.wave) {
+    if (threadIdx.x < 64)
+      trsv_levels<T, 64>(F, b, y, bs, [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      });
     __syncthreads();
+  } else {
+    trsv_levels<T, TRI_WG>(F, b, y, bs, [] { __syncthreads(); });
   }
 }
 
@@ -109,45 +225,47 @@ __device__ __forceinline__ T* tri_lds() {
 template <typename T, bool YLDS>
 __global__ __launch_bounds__(TRI_WG) void k_ildl_sandwich(DTri<T> Lb, DCsr32<T> M, DTri<T> Lf,
                                                           const double* __restrict__ in, double* __restrict__ out,
-                                                          T* t0, T* t1, T* t2) {
+                                                          T* t0, T* t1, T* t2, T* t3) {
   const int n = Lb.n;
   T* y = YLDS ? tri_lds<T>() : t1;
   for (int i = threadIdx.x; i < n; i += TRI_WG) t0[i] = (T)in[i];
   __syncthreads();
-  trsv_block<T>(Lb, t0, y);
+  trsv_block<T, YLDS>(Lb, t0, y, t3);
   spmv_block<T>(M, y, t2);
-  trsv_block<T>(Lf, t2, y);
+  trsv_block<T, YLDS>(Lf, t2, y, t3);
   for (int i = threadIdx.x; i < n; i += TRI_WG) out[i] = (double)y[i];
 }
 
 template <bool YLDS>
 __global__ __launch_bounds__(TRI_WG) void k_ildl_trsv(DTri<double> F, const double* __restrict__ in,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, double* __restrict__ bs) {
   double* y = YLDS ? tri_lds<double>() : out;
-  trsv_block<double>(F, in, y);
+  trsv_block<double, YLDS>(F, in, y, bs);
   if (YLDS)
     for (int i = threadIdx.x; i < F.n; i += TRI_WG) out[i] = y[i];
 }
 
 template <typename T>
 void ildl_sandwich(const DTri<T>& Lb, const DCsr32<T>& M, const DTri<T>& Lf, const double* in, double* out,
-                   T* t0, T* t1, T* t2, hipStream_t s) {
+                   T* t0, T* t1, T* t2, T* t3, hipStream_t s) {
   if (Lb.n <= tri_lds_rows<T>())
     hipLaunchKernelGGL((k_ildl_sandwich<T, true>), dim3(1), dim3(TRI_WG), (size_t)Lb.n * sizeof(T), s, Lb, M, Lf,
-                       in, out, t0, t1, t2);
+                       in, out, t0, t1, t2, t3);
   else
-    hipLaunchKernelGGL((k_ildl_sandwich<T, false>), dim3(1), dim3(TRI_WG), 0, s, Lb, M, Lf, in, out, t0, t1, t2);
+    hipLaunchKernelGGL((k_ildl_sandwich<T, false>), dim3(1), dim3(TRI_WG), 0, s, Lb, M, Lf, in, out, t0, t1, t2,
+                       t3);
 }
 template void ildl_sandwich<double>(const DTri<double>&, const DCsr32<double>&, const DTri<double>&,
-                                    const double*, double*, double*, double*, double*, hipStream_t);
+                                    const double*, double*, double*, double*, double*, double*, hipStream_t);
 template void ildl_sandwich<float>(const DTri<float>&, const DCsr32<float>&, const DTri<float>&,
-                                   const double*, double*, float*, float*, float*, hipStream_t);
+                                   const double*, double*, float*, float*, float*, float*, hipStream_t);
 
-void ildl_trsv(const DTri<double>& F, const double* in, double* out, hipStream_t s) {
+void ildl_trsv(const DTri<double>& F, const double* in, double* out, double* bs, hipStream_t s) {
   if (F.n <= tri_lds_rows<double>())
-    hipLaunchKernelGGL((k_ildl_trsv<true>), dim3(1), dim3(TRI_WG), (size_t)F.n * sizeof(double), s, F, in, out);
+    hipLaunchKernelGGL((k_ildl_trsv<true>), dim3(1), dim3(TRI_WG), (size_t)F.n * sizeof(double), s, F, in, out,
+                       bs);
   else
-    hipLaunchKernelGGL((k_ildl_trsv<false>), dim3(1), dim3(TRI_WG), 0, s, F, in, out);
+    hipLaunchKernelGGL((k_ildl_trsv<false>), dim3(1), dim3(TRI_WG), 0, s, F, in, out, bs);
 }
 
 // The inner solve.  Each step is the step of the sliced kernel (k_mrs_iter)
@@ -211,21 +329,29 @@ __global__ __launch_bounds__(TRI_WG) void k_ildl_mrs(IldlMrsArgs<T> A) {
     const int status = sst.status;
     if (status == MRS_DONE) break;
     const int t = sst.its + 1;
-    const MrsCol col = sst.col[0];
-    const bool pend = col.has_pending != 0;
-    const T inv_nu = (T)(1.0 / col.nu), inv_nu_old = (T)(1.0 / col.nu_old), beta_prev = (T)col.beta_prev;
-    const T pend_delta = (T)col.pend_delta, inv_pend_theta = (T)(1.0 / col.pend_theta);
-    const T pend_coef = (T)col.pend_coef;
-    T cv[KF1];
-#pragma unroll
-    for (int l = 0; l < KF1; ++l) cv[l] = (KF > 0 && l < k) ? (T)sst.cvec[l] : T(0);
     const T* __restrict__ wcur = A.buf.w[t % 3];
     const T* __restrict__ wold = A.buf.w[(t + 2) % 3];
     T* __restrict__ wnew = A.buf.w[(t + 1) % 3];
     T* __restrict__ pb = A.buf.p[(t + 1) % 2];
     T* __restrict__ x = A.buf.x;
+    // the column's coefficients are read from the LDS copy of the state where
+    // they are used (after the operator), not held in registers across it
+    auto coefs = [&](T& inv_nu, T& inv_nu_old, T& beta_prev, T& pend_delta, T& inv_pend_theta, T& pend_coef,
+                     bool& pend) {
+      const MrsCol& col = sst.col[0];
+      pend = col.has_pending != 0;
+      inv_nu = (T)(1.0 / col.nu);
+      inv_nu_old = (T)(1.0 / col.nu_old);
+      beta_prev = (T)col.beta_prev;
+      pend_delta = (T)col.pend_delta;
+      inv_pend_theta = (T)(1.0 / col.pend_theta);
+      pend_coef = (T)col.pend_coef;
+    };
+    T inv_nu, inv_nu_old, beta_prev, pend_delta, inv_pend_theta, pend_coef;
+    bool pend;
 
     if (status == MRS_CONVERGED) {  // last deferred update, then done
+      coefs(inv_nu, inv_nu_old, beta_prev, pend_delta, inv_pend_theta, pend_coef, pend);
       if (pend)
         for (int i = tid; i < n; i += TRI_WG) {
           const T qold = wold[i] * inv_nu_old;
@@ -250,9 +376,13 @@ __global__ __launch_bounds__(TRI_WG) void k_ildl_mrs(IldlMrsArgs<T> A) {
     // the vector fits)
     T* const yv = YLDS ? tri_lds<T>() : A.y;
     T* const uv = YLDS ? tri_lds<T>() : A.u;
-    trsv_block<T>(A.Lb, wcur, yv);
+    trsv_block<T, YLDS>(A.Lb, wcur, yv, A.bs);
     spmv_block<T>(A.J, yv, A.z);
-    trsv_block<T>(A.Lf, A.z, uv);
+    trsv_block<T, YLDS>(A.Lf, A.z, uv, A.bs);
+    coefs(inv_nu, inv_nu_old, beta_prev, pend_delta, inv_pend_theta, pend_coef, pend);
+    T cv[KF1];
+#pragma unroll
+    for (int l = 0; l < KF1; ++l) cv[l] = (KF > 0 && l < k) ? (T)sst.cvec[l] : T(0);
 
     double acc[NV];
 #pragma unroll

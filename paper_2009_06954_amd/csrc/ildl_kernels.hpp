@@ -19,22 +19,30 @@ namespace asss {
 constexpr int TRI_WG = 1024;
 
 // A triangular factor for a level-scheduled solve T y = b, stored level by
-// level: the e-th row of the schedule is row[e]; its off-diagonal entries
-// (columns before the row for a lower factor, after it for an upper one) are
-// col / val[eptr[e] .. eptr[e+1]), its diagonal diag[e].  Level l holds rows
-// lev_ptr[l] .. lev_ptr[l+1] - 1 and is solved with lev_lpr[l] lanes per
-// row (a power of two up to 64: long rows of few-row levels spread their
-// entries over a group of lanes that sums with shuffles).
+// level.  The e-th row of the schedule is row[e], with inverse diagonal
+// dinv[e]; level l holds schedule rows lev_ptr[l] .. lev_ptr[l+1] - 1 and is
+// solved with lev_lpr[l] lanes per row (a power of two up to 64: long rows
+// spread their entries over a group of lanes that sums with shuffles).  The
+// off-diagonal entries of a level form one padded block (ELL) at
+// lev_base[l]: with N = rows * lpr slots (slot = local row * lpr + lane in
+// the group), the t-th entry of a slot (the row's entry lane + t * lpr) is at
+// lev_base[l] + t * N + slot, t < lev_w[l]; padding holds value 0 and the
+// column of a row of level 0 (solved before any level that reads it).  Every
+// address of a level's block is so known from per-level scalars: its loads
+// are issued ahead without waiting for anything.  The entry arrays carry a
+// tail of TRI_WG padding entries.
 template <typename T>
 struct DTri {
   int32_t n = 0, nlev = 0;
+  int32_t wave = 0;                  // 1: every level fits one wave in one pass, <= 4 entries per lane
   const int32_t* lev_ptr = nullptr;  // nlev + 1
   const int32_t* lev_lpr = nullptr;  // nlev
+  const int32_t* lev_w = nullptr;    // nlev: entries per slot
+  const int32_t* lev_base = nullptr; // nlev: offset of the level's block
   const int32_t* row = nullptr;      // n
-  const int32_t* eptr = nullptr;     // n + 1
-  const int32_t* col = nullptr;
-  const T* val = nullptr;
-  const T* diag = nullptr;           // n, in schedule order
+  const int32_t* ecol = nullptr;
+  const T* eval = nullptr;
+  const T* dinv = nullptr;           // n: 1 / diagonal, in schedule order
 };
 
 // Square CSR with 32-bit offsets (the operators between the two solves),
@@ -54,13 +62,13 @@ template <typename T>
 constexpr int tri_lds_rows() { return (40 * 1024) / (int)sizeof(T); }
 
 // out = Lf^-1 (M (Lb^-1 in)): Lb the upper factor Lcal^T, Lf the lower Lcal.
-// Arithmetic in T; in and out FP64.  t0, t1, t2: n values of scratch each.
+// Arithmetic in T; in and out FP64.  t0 .. t3: n values of scratch each.
 template <typename T>
 void ildl_sandwich(const DTri<T>& Lb, const DCsr32<T>& M, const DTri<T>& Lf, const double* in, double* out,
-                   T* t0, T* t1, T* t2, hipStream_t s);
+                   T* t0, T* t1, T* t2, T* t3, hipStream_t s);
 
-// out = F^-1 in (FP64); in and out may not alias.
-void ildl_trsv(const DTri<double>& F, const double* in, double* out, hipStream_t s);
+// out = F^-1 in (FP64); in and out may not alias; bs: n values of scratch.
+void ildl_trsv(const DTri<double>& F, const double* in, double* out, double* bs, hipStream_t s);
 
 // The arguments of one inner solve on I + J_bar (sign = -1: its transpose).
 template <typename T>
@@ -77,6 +85,7 @@ struct IldlMrsArgs {
   T* y = nullptr;                 // n: Lcal^-T q
   T* z = nullptr;                 // n: J_hat Lcal^-T q
   T* u = nullptr;                 // n: J_tilde q
+  T* bs = nullptr;                // n: a triangular solve's right-hand side in schedule order
   MrsState* st = nullptr;
   double tol = 0.0;
   int32_t maxit = 0, fixed = 0;

@@ -28,54 +28,90 @@ int lanes_per_row(int64_t longest, int64_t rows, int64_t width) {
 }
 
 // A triangular CSR (rows over positions, diagonal stored in each row) in
-// schedule order: the rows level by level, each with its off-diagonal
-// entries and its diagonal; the lanes per row of every level.  Uploaded in
+// schedule order: the rows level by level with their inverse diagonals, and
+// each level's off-diagonal entries as one padded block (slot-major within an
+// entry index, see DTri), the lanes per row chosen per level.  Uploaded in
 // FP64 and FP32 (index arrays shared).
 void upload_tri(DevArena& ar, const Csr& T, bool lower, DTri<double>& d64, DTri<float>& d32, int32_t& nlev,
                 hipStream_t s) {
   const int64_t n = T.nrows;
-  if (T.nnz() >= (int64_t)INT32_MAX) throw Error{ASSS_ERR_INVALID_ARG, "the incomplete factor has 2^31 entries or more"};
   LevelSchedule L = level_schedule(T, lower);
   nlev = L.nlevels();
-  std::vector<int32_t> eptr(n + 1, 0), col, lpr(nlev);
-  std::vector<double> val, diag(n, 0.0);
-  col.reserve(T.nnz());
-  val.reserve(T.nnz());
-  for (int64_t e = 0; e < n; ++e) {
-    const int32_t i = L.rows[e];
-    for (int64_t q = T.ptr[i]; q < T.ptr[i + 1]; ++q) {
-      if (T.col[q] == i) {
-        diag[e] = T.val[q];
-      } else {
-        col.push_back(T.col[q]);
-        val.push_back(T.val[q]);
-      }
-    }
-    eptr[e + 1] = (int32_t)col.size();
-    if (diag[e] == 0.0) throw Error{ASSS_ERR_INTERNAL, "the scaled incomplete factor has a zero diagonal entry"};
-  }
+  // one wave takes the whole solve when every level fits its 64 lanes in one
+  // pass with at most four entries per lane (a level then costs one round of
+  // LDS gathers); else the workgroup, with lanes per row chosen for it
+  std::vector<int32_t> lpr(nlev), lw(nlev), lbase(nlev);
+  std::vector<int64_t> longest(nlev, 0);
+  int wave = 1;
   for (int32_t l = 0; l < nlev; ++l) {
-    int64_t longest = 0;
-    for (int32_t e = L.ptr[l]; e < L.ptr[l + 1]; ++e) longest = std::max<int64_t>(longest, eptr[e + 1] - eptr[e]);
-    lpr[l] = lanes_per_row(longest, L.ptr[l + 1] - L.ptr[l], TRI_WG);
+    for (int32_t e = L.ptr[l]; e < L.ptr[l + 1]; ++e) {
+      const int32_t i = L.rows[e];
+      longest[l] = std::max<int64_t>(longest[l], T.ptr[i + 1] - T.ptr[i] - 1);  // off-diagonal entries
+    }
+    int lw1 = 1;
+    while (lw1 < 64 && (int64_t)lw1 * 4 < longest[l]) lw1 *= 2;
+    if ((int64_t)(L.ptr[l + 1] - L.ptr[l]) * lw1 > 64 || (int64_t)lw1 * 4 < longest[l]) wave = 0;
+  }
+  std::vector<double> dinv(n, 0.0);
+  int64_t total = 0;
+  for (int32_t l = 0; l < nlev; ++l) {
+    const int64_t rows = L.ptr[l + 1] - L.ptr[l];
+    lpr[l] = lanes_per_row(longest[l], rows, wave ? 64 : TRI_WG);
+    lw[l] = (int32_t)((longest[l] + lpr[l] - 1) / lpr[l]);
+    lbase[l] = (int32_t)total;
+    total += (int64_t)lw[l] * rows * lpr[l];
+    if (total >= (int64_t)INT32_MAX - TRI_WG)
+      throw Error{ASSS_ERR_INVALID_ARG, "the padded incomplete factor has 2^31 entries or more"};
+  }
+  const int32_t pad_col = L.rows[0];  // a row of level 0: solved before any level reads it
+  std::vector<int32_t> ecol(total + TRI_WG, pad_col);
+  std::vector<double> eval(total + TRI_WG, 0.0);
+  for (int32_t l = 0; l < nlev; ++l) {
+    const int64_t nslots = (int64_t)(L.ptr[l + 1] - L.ptr[l]) * lpr[l];
+    for (int32_t e = L.ptr[l]; e < L.ptr[l + 1]; ++e) {
+      const int32_t i = L.rows[e];
+      const int64_t r_local = e - L.ptr[l];
+      int64_t k = 0;
+      for (int64_t q = T.ptr[i]; q < T.ptr[i + 1]; ++q) {
+        if (T.col[q] == i) {
+          dinv[e] = T.val[q];
+          continue;
+        }
+        const int64_t j = k % lpr[l], t = k / lpr[l];
+        const int64_t idx = lbase[l] + t * nslots + r_local * lpr[l] + j;
+        ecol[idx] = T.col[q];
+        eval[idx] = T.val[q];
+        ++k;
+      }
+      if (dinv[e] == 0.0) throw Error{ASSS_ERR_INTERNAL, "the scaled incomplete factor has a zero diagonal entry"};
+    }
+  }
+  // the diagonal is stored inverted (FP64, rounded once; the FP32 copy is the
+  // FP32 inverse of the FP32 diagonal)
+  std::vector<float> eval32(eval.begin(), eval.end()), dinv32(n);
+  for (int64_t e = 0; e < n; ++e) {
+    dinv32[e] = 1.0f / (float)dinv[e];
+    dinv[e] = 1.0 / dinv[e];
   }
   const int32_t* dlp = ar.upload(L.ptr, s);
   const int32_t* dlpr = ar.upload(lpr, s);
+  const int32_t* dlw = ar.upload(lw, s);
+  const int32_t* dlb = ar.upload(lbase, s);
   const int32_t* drow = ar.upload(L.rows, s);
-  const int32_t* dptr = ar.upload(eptr, s);
-  const int32_t* dcol = ar.upload(col, s);
-  std::vector<float> val32(val.begin(), val.end()), diag32(diag.begin(), diag.end());
+  const int32_t* dcol = ar.upload(ecol, s);
   d64.n = d32.n = (int32_t)n;
   d64.nlev = d32.nlev = nlev;
+  d64.wave = d32.wave = wave;
   d64.lev_ptr = d32.lev_ptr = dlp;
   d64.lev_lpr = d32.lev_lpr = dlpr;
+  d64.lev_w = d32.lev_w = dlw;
+  d64.lev_base = d32.lev_base = dlb;
   d64.row = d32.row = drow;
-  d64.eptr = d32.eptr = dptr;
-  d64.col = d32.col = dcol;
-  d64.val = ar.upload(val, s);
-  d64.diag = ar.upload(diag, s);
-  d32.val = ar.upload(val32, s);
-  d32.diag = ar.upload(diag32, s);
+  d64.ecol = d32.ecol = dcol;
+  d64.eval = ar.upload(eval, s);
+  d64.dinv = ar.upload(dinv, s);
+  d32.eval = ar.upload(eval32, s);
+  d32.dinv = ar.upload(dinv32, s);
 }
 
 template <typename T>
@@ -135,7 +171,7 @@ void ildl_setup(asss_handle_s* h, const Csr& Ahat, hipStream_t s) {
   il.d_mp = h->ar.upload(mp, s);
   il.d_drp = h->ar.upload(drp, s);
   il.d_ones = h->ar.upload(std::vector<double>(n, 1.0), s);
-  for (int b = 0; b < 3; ++b) {
+  for (int b = 0; b < 4; ++b) {
     il.t64[b] = h->ar.alloc<double>(n);
     il.t32[b] = h->ar.alloc<float>(n);
   }

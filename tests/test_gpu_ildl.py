@@ -211,17 +211,26 @@ def test_inner_mrs_fixed_steps(case, fp32):
     else:
         # ||J_bar|| ~ 190 here: the Lanczos basis of the short recurrence
         # loses orthogonality, and the oracle's own 30-step iterate moves by
-        # 6e-3 when v moves by 1e-15; what is unique is the minimal-residual
-        # property, so the true residuals are compared
+        # 6e-3 (its residual by 1 %) when v moves by 1e-15.  What is fixed is
+        # the minimal residual over the Krylov space, computed here with a
+        # twice-orthogonalised basis: neither side can go below it, and the
+        # library's residual must stay within 5 % of the oracle's (FP64) or
+        # 30 % (FP32 triangular solves, kappa(Lcal) ~ 550)
         Sb = np.eye(case.n) + st.prec.jbar(np.eye(case.n))
         rg = np.linalg.norm(v - Sb @ _np(y)) / np.linalg.norm(v)
         ro = np.linalg.norm(v - Sb @ yo) / np.linalg.norm(v)
-        if fp32:
-            # FP32 triangular solves with kappa(Lcal) ~ 550 around ||J_hat||:
-            # the residual stays within 30 % of the FP64 optimum
-            assert ro * 0.98 <= rg <= 1.3 * ro
-        else:
-            assert abs(rg - ro) <= 0.02 * ro
+        basis = [v / np.linalg.norm(v)]
+        for _ in range(29):
+            w = Sb @ basis[-1]
+            for _pass in range(2):
+                for q in basis:
+                    w = w - q * (q @ w)
+            basis.append(w / np.linalg.norm(w))
+        V = np.array(basis).T
+        c, *_ = np.linalg.lstsq(Sb @ V, v, rcond=None)
+        rmin = np.linalg.norm(v - Sb @ V @ c) / np.linalg.norm(v)
+        assert rg >= rmin * (1 - 1e-9) and ro >= rmin * (1 - 1e-9)
+        assert rg <= (1.3 if fp32 else 1.05) * ro
 
 
 def test_preconditioner_and_transpose(case):
