@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
         for src in ("host_setup.cpp", "ildl_host.cpp"):
             o = os.path.join(tmp, src.replace(".cpp", ".o"))
             jobs.append(([gxx, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], o))
-        for src in ("kernels.hip", "ildl.hip", "ildl_setup.hip", "asss.hip", "batch.hip"):
+        for src in ("kernels.hip", "ildl.hip", "ildl_setup.hip", "outer.hip", "asss.hip", "batch.hip"):
             o = os.path.join(tmp, src.replace(".hip", ".o"))
             jobs.append(([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], o))
         # the translation units compile independently: run them side by side

@@ -44,11 +44,12 @@ namespace {
 thread_local std::string g_err = "";
 
 // layout of the small device/pinned scalar buffers (doubles)
-// d_small / h_small layout: [0, 2048) Arnoldi scratch, 512 doubles per lockstep
-// column (the Gram-Schmidt coefficients of the first pass and the new norm at
-// +0, those of a second pass at +256; restart_m <= 250), SM_T the SMW
-// coefficients, SM_Y the cycle's least-squares solution.
-constexpr int SM_COL = 512, SM_PASS2 = 256, SM_T = 2048, SM_Y = 3072, SM_SIZE = 4096;
+// d_small layout: [0, 2048) Arnoldi scratch, 512 doubles per lockstep column
+// (the Gram-Schmidt coefficients of the first pass and the new norm at +0,
+// those of a second pass at +256; restart_m <= 250), SM_T the SMW
+// coefficients.  h_small: the Hessenberg step's flags of column c at
+// c * SM_COL, the inner state's head at SM_HSTATE, other read-backs at 0.
+constexpr int SM_COL = 512, SM_PASS2 = 256, SM_T = 2048, SM_HSTATE = 3584, SM_SIZE = 4096;
 static_assert(4 * SM_COL <= SM_T, "Arnoldi scratch of four columns");
 
 }  // namespace
@@ -257,60 +258,99 @@ MrsLaunch make_launch(asss_handle_s* h, int nr, int sign, bool one_col) {
 
 // Inner mrs solve of nc <= NR right-hand sides (columns of rhs / out with
 // leading dimension n; NR = 4: App. B's simultaneous form, one matrix pass per
-// step for all columns, shared stop rule).
+// step for all columns, shared stop rule), in three parts so that a caller can
+// put more work on the stream before it waits: start() enqueues the start and
+// a chunk of steps sized from the previous solve (steps after the end return
+// at once) and copies the state's head to host scratch; settle(), after the
+// caller's synchronization, reads it and returns true when the solve was done,
+// else enqueues more steps (sized from the observed contraction rate) and a
+// new copy; finish() enqueues the output.
+template <typename T, int NR = 1>
+struct MrsJob {
+  asss_handle_s* h;
+  const DSkew<T>* J;
+  const T* Q;
+  MrsBufs<T>* mb;
+  double* out;
+  int nc;
+  double tol;
+  int maxit, fixed;
+  hipStream_t s;
+  MrsLaunch L{};
+  int its = 0, chunk = 0, prev_its = 0, polls = 0;
+  double prev_rel = 1.0;
+
+  // expect >= 0: the caller's estimate of the steps; the chunk then takes a
+  // margin (a step launched after the end costs a few microseconds, a chunk
+  // that falls short costs the caller a second round trip)
+  void start(const double* rhs, int sign, int expect = -1) {
+    L = make_launch<T>(h, nc, sign, NR == 1);
+    if (J->nblocks <= 0) throw Error{ASSS_ERR_INTERNAL, "the sliced inner operator is not built for this handle"};
+    if (J->nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
+    mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, *mb, h->d_state, tol, maxit, fixed, h->red, s);
+    if (fixed > 0) chunk = fixed + 1;
+    else if (expect >= 0) chunk = std::max(4, expect + 5 + expect / 4);
+    else chunk = std::max(4, h->last_inner + 1);
+    launch_chunk();
+  }
+  void launch_chunk() {
+    HIPCHK(hipEventRecord(h->ev0, s));
+    for (int c = 0; c < chunk; ++c) mrs_iter<T, NR>(L, *J, Q, *mb, h->d_state, h->red, s);
+    HIPCHK(hipEventRecord(h->ev1, s));
+    HIPCHK(hipMemcpyAsync(h->h_small + SM_HSTATE, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
+  }
+  bool settle() {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->prof_s += 1e-3 * ms;
+    h->prof_launches += chunk;
+    const char* hs = (const char*)(h->h_small + SM_HSTATE);
+    int32_t st_its, st_status;
+    double rel;
+    std::memcpy(&st_its, hs + offsetof(MrsState, its), 4);
+    std::memcpy(&st_status, hs + offsetof(MrsState, status), 4);
+    std::memcpy(&rel, hs + offsetof(MrsState, relres_max), 8);
+    if (st_status == MRS_RUNNING && st_its <= its && polls > 0)
+      throw Error{ASSS_ERR_INTERNAL, "inner mrs made no progress"};
+    if (++polls > 100000) throw Error{ASSS_ERR_INTERNAL, "inner mrs did not finish"};
+    its = st_its;
+    if (st_status == MRS_DONE) {
+      h->last_inner = its;
+      return true;
+    }
+    if (st_status == MRS_CONVERGED) {
+      chunk = 1;  // the final deferred update
+    } else {
+      // estimate the remaining steps from the observed contraction rate
+      int est = 8;
+      if (its > prev_its && rel > 0 && prev_rel > 0 && rel < prev_rel) {
+        const double rate = std::log(rel / prev_rel) / (double)(its - prev_its);
+        const double need = std::log(tol / rel) / rate;
+        est = (int)std::ceil(need) + 1;
+      }
+      const int left = (fixed > 0 ? fixed : maxit) - its + 1;
+      chunk = std::max(2, std::min({est, 64, left}));
+      prev_rel = rel;
+      prev_its = its;
+    }
+    launch_chunk();
+    return false;
+  }
+  void finish() { mrs_output<T, NR>(h->n, nc, *mb, h->d_perm, out, h->n, s); }
+};
+
 template <typename T, int NR = 1>
 int run_mrs(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
             const double* rhs, double* out, int sign, double tol, int maxit, int fixed, hipStream_t s,
             int nc = 1) {
   Range range(NR == 1 ? "asss:inner mrs" : "asss:inner mrs (4 columns)");
-  MrsLaunch L = make_launch<T>(h, nc, sign, NR == 1);
-  if (J.nblocks <= 0) throw Error{ASSS_ERR_INTERNAL, "the sliced inner operator is not built for this handle"};
-  if (J.nblocks > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
-  mrs_init<T, NR>(L, rhs, h->n, h->d_perm, Q, mb, h->d_state, tol, maxit, fixed, h->red, s);
-  int chunk = fixed > 0 ? fixed + 1 : std::max(4, h->last_inner + 1);
-  int its = 0;
-  double prev_rel = 1.0;
-  int prev_its = 0;
-  for (int guard = 0; guard < 100000; ++guard) {
-    HIPCHK(hipEventRecord(h->ev0, s));
-    for (int c = 0; c < chunk; ++c) mrs_iter<T, NR>(L, J, Q, mb, h->d_state, h->red, s);
-    HIPCHK(hipEventRecord(h->ev1, s));
-    HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
+  MrsJob<T, NR> job{h, &J, Q, &mb, out, nc, tol, maxit, fixed, s};
+  job.start(rhs, sign);
+  do {
     HIPCHK(hipStreamSynchronize(s));
-    {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-      h->prof_s += 1e-3 * ms;
-      h->prof_launches += chunk;
-    }
-    int32_t st_its, st_status;
-    double rel;
-    std::memcpy(&st_its, (char*)h->h_small + offsetof(MrsState, its), 4);
-    std::memcpy(&st_status, (char*)h->h_small + offsetof(MrsState, status), 4);
-    std::memcpy(&rel, (char*)h->h_small + offsetof(MrsState, relres_max), 8);
-    if (st_status == MRS_RUNNING && st_its <= its && guard > 0)
-      throw Error{ASSS_ERR_INTERNAL, "inner mrs made no progress"};
-    its = st_its;
-    if (st_status == MRS_DONE) break;
-    if (st_status == MRS_CONVERGED) {
-      mrs_iter<T, NR>(L, J, Q, mb, h->d_state, h->red, s);  // final deferred update
-      break;
-    }
-    // estimate the remaining iterations from the observed contraction rate
-    int est = 8;
-    if (its > prev_its && rel > 0 && prev_rel > 0 && rel < prev_rel) {
-      double rate = std::log(rel / prev_rel) / (double)(its - prev_its);
-      double need = std::log(tol / rel) / rate;
-      est = (int)std::ceil(need) + 1;
-    }
-    int left = (fixed > 0 ? fixed : maxit) - its + 1;
-    chunk = std::max(2, std::min({est, 64, left}));
-    prev_rel = rel;
-    prev_its = its;
-  }
-  mrs_output<T, NR>(h->n, nc, mb, h->d_perm, out, h->n, s);
-  h->last_inner = its;
-  return its;
+  } while (!job.settle());
+  job.finish();
+  return job.its;
 }
 
 template <typename T>
@@ -320,11 +360,12 @@ int run_mrs1(asss_handle_s* h, const DSkew<T>& J, const T* Q, MrsBufs<T>& mb,
 }
 
 // The inner solve with the incomplete LDL^T preconditioner: one launch of the
-// persistent one-workgroup kernel (start, all steps, final update, output).
+// persistent one-workgroup kernel (start, all steps, final update, output),
+// its state's head copied to host scratch; ildl_settle reads it after the
+// caller's synchronization.
 template <typename T>
-int run_ildl_mrs(asss_handle_s* h, const double* rhs, double* out, int sign, double tol, int maxit, int fixed,
+void ildl_launch(asss_handle_s* h, const double* rhs, double* out, int sign, double tol, int maxit, int fixed,
                  hipStream_t s) {
-  Range range("asss:inner mrs (incomplete LDL^T)");
   auto& il = h->il;
   constexpr bool f32 = std::is_same<T, float>::value;
   IldlMrsArgs<T> a;
@@ -348,29 +389,83 @@ int run_ildl_mrs(asss_handle_s* h, const double* rhs, double* out, int sign, dou
   HIPCHK(hipEventRecord(h->ev0, s));
   ildl_mrs<T>(a, s);
   HIPCHK(hipEventRecord(h->ev1, s));
-  HIPCHK(hipMemcpyAsync(h->h_small, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpyAsync(h->h_small + SM_HSTATE, h->d_state, kStateHead, hipMemcpyDeviceToHost, s));
+}
+
+int ildl_settle(asss_handle_s* h) {
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->prof_s += 1e-3 * ms;
   h->prof_launches += 1;
+  const char* hs = (const char*)(h->h_small + SM_HSTATE);
   int32_t st_its, st_status;
-  std::memcpy(&st_its, (char*)h->h_small + offsetof(MrsState, its), 4);
-  std::memcpy(&st_status, (char*)h->h_small + offsetof(MrsState, status), 4);
+  std::memcpy(&st_its, hs + offsetof(MrsState, its), 4);
+  std::memcpy(&st_status, hs + offsetof(MrsState, status), 4);
   if (st_status != MRS_DONE) throw Error{ASSS_ERR_INTERNAL, "inner mrs (incomplete LDL^T) did not finish"};
   h->last_inner = st_its;
   return st_its;
 }
 
+template <typename T>
+int run_ildl_mrs(asss_handle_s* h, const double* rhs, double* out, int sign, double tol, int maxit, int fixed,
+                 hipStream_t s) {
+  Range range("asss:inner mrs (incomplete LDL^T)");
+  ildl_launch<T>(h, rhs, out, sign, tol, maxit, fixed, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return ildl_settle(h);
+}
+
+// The preconditioner's inner solve (sliced mrs in FP64 or FP32, or the
+// incomplete LDL^T kernel, which finishes in its one launch) as a job in the
+// three parts of MrsJob.
+struct InnerJob {
+  int mode = 0;  // 0 / 1: sliced FP64 / FP32; 2 / 3: incomplete LDL^T FP64 / FP32
+  asss_handle_s* h = nullptr;
+  MrsJob<double> d{};
+  MrsJob<float> f{};
+  int ildl_its = 0;
+
+  void start(asss_handle_s* h_, bool fp32, const double* rhs, double* out, int sign, double tol, int maxit,
+             int fixed, hipStream_t s, int expect = -1) {
+    h = h_;
+    if (h->il.on) {
+      mode = fp32 ? 3 : 2;
+      if (fp32) ildl_launch<float>(h, rhs, out, sign, tol, maxit, fixed, s);
+      else ildl_launch<double>(h, rhs, out, sign, tol, maxit, fixed, s);
+    } else if (fp32) {
+      mode = 1;
+      f = MrsJob<float>{h, &h->J32, h->d_Q32, &h->mb32, out, 1, tol, maxit, fixed, s};
+      f.start(rhs, sign, expect);
+    } else {
+      mode = 0;
+      d = MrsJob<double>{h, &h->J64, h->d_Q64, &h->mb64, out, 1, tol, maxit, fixed, s};
+      d.start(rhs, sign, expect);
+    }
+  }
+  bool settle() {
+    if (mode >= 2) {
+      ildl_its = ildl_settle(h);
+      return true;
+    }
+    return mode == 1 ? f.settle() : d.settle();
+  }
+  void finish() {
+    if (mode == 1) f.finish();
+    else if (mode == 0) d.finish();
+  }
+  int its() const { return mode >= 2 ? ildl_its : (mode == 1 ? f.its : d.its); }
+};
+
 int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
                 int maxit, int fixed, hipStream_t s) {
-  if (h->il.on) {
-    if (fp32) return run_ildl_mrs<float>(h, rhs, out, sign, tol, maxit, fixed, s);
-    return run_ildl_mrs<double>(h, rhs, out, sign, tol, maxit, fixed, s);
-  }
-  if (fp32)
-    return run_mrs1<float>(h, h->J32, h->d_Q32, h->mb32, rhs, out, sign, tol, maxit, fixed, s);
-  return run_mrs1<double>(h, h->J64, h->d_Q64, h->mb64, rhs, out, sign, tol, maxit, fixed, s);
+  Range range(h->il.on ? "asss:inner mrs (incomplete LDL^T)" : "asss:inner mrs");
+  InnerJob job;
+  job.start(h, fp32, rhs, out, sign, tol, maxit, fixed, s);
+  do {
+    HIPCHK(hipStreamSynchronize(s));
+  } while (!job.settle());
+  job.finish();
+  return job.its();
 }
 
 // z <- z - X (C^-1 Sigma) (U_bar^T z): the low-rank part of eq. smw (inverse-free form)
@@ -422,18 +517,20 @@ void ensure_multi(asss_handle_s* h, int m, bool fp32) {
   }
 }
 
-// z = P^-T v = S_bar^-T (v - U_bar Sigma^T C^-T X^T v)
+// The low-rank part of z = P^-T v = S_bar^-T (v - U_bar Sigma^T C^-T X^T v),
+// ahead of the inner solve: returns the inner system's right-hand side.
+const double* prec_pre_T(asss_handle_s* h, const double* v, hipStream_t s) {
+  if (h->kr == 0) return v;
+  double* t = h->d_small + SM_T;
+  gemm_tn<double, double>(h->n, h->kr, h->d_X, h->n, v, 1, t, h->d_Ma, h->red, 3, s);
+  axpby(h->n, 1.0, v, 0.0, h->tmp, s);
+  gemv_acc(h->n, h->kr, h->d_Ubar, h->n, t, -1.0, h->tmp, s);
+  return h->tmp;
+}
+
 int prec_apply_T(asss_handle_s* h, bool fp32, const double* v, double* z, const asss_solve_opts_t& o,
                  hipStream_t s) {
-  const double* rhs = v;
-  if (h->kr > 0) {
-    double* t = h->d_small + SM_T;
-    gemm_tn<double, double>(h->n, h->kr, h->d_X, h->n, v, 1, t, h->d_Ma, h->red, 3, s);
-    axpby(h->n, 1.0, v, 0.0, h->tmp, s);
-    gemv_acc(h->n, h->kr, h->d_Ubar, h->n, t, -1.0, h->tmp, s);
-    rhs = h->tmp;
-  }
-  return inner_solve(h, fp32, rhs, z, -1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
+  return inner_solve(h, fp32, prec_pre_T(h, v, s), z, -1, o.inner_tol, o.inner_maxit, o.fixed_inner_steps, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -886,8 +983,11 @@ bool b_is_finite(asss_handle_s* h, const double* b, hipStream_t s) {
 
 // One column of flexible GMRES(m) on the scaled system, with the stopping rule
 // of the oracle, as a state machine: the caller applies the preconditioner to
-// v_next() into z_next() and calls after_prec(); the column restarts and
-// finishes by itself.  Several columns can so share one preconditioner call.
+// v_next() into z_next() and calls after_prec() (or step() does both); the
+// column restarts and finishes by itself.  Several columns can so share one
+// preconditioner call.  The Hessenberg matrix, its Givens rotations, the
+// residual estimate and the stopping test live on the device (outer.hip, one
+// workspace per column); the host reads back a few flags per Arnoldi step.
 struct FgmresCol {
   asss_handle_s* h = nullptr;
   bool adjoint = false;
@@ -898,10 +998,13 @@ struct FgmresCol {
   int64_t n = 0;
   int m = 1;
   double *V = nullptr, *Z = nullptr, *bchk = nullptr, *xchk = nullptr, *rv = nullptr;
-  std::vector<double> H, cs, sn, g, y;
+  double* W = nullptr;        // Hessenberg workspace (device)
   double bn = 0.0, bcn = 0.0, thr = 0.0, t0 = 0.0;
-  int slot = 0;  // Arnoldi scratch: d_small / h_small + slot * SM_COL
+  double gabs = 0.0;          // |g_j|, the residual estimate after the last step
+  int slot = 0;  // Arnoldi scratch: d_small + slot * SM_COL; flags: h_small + slot * SM_COL
   int last_its = 0;
+  int recent[4] = {0, 0, 0, 0};  // inner steps of the last four outer steps
+  int nrecent = 0;
   int j = 0;
   bool first = true, done = false, implicit_ok = false;
   asss_info_t inf{};
@@ -913,14 +1016,17 @@ struct FgmresCol {
   }
   const double* v_next() const { return V + (int64_t)j * n; }
   double* z_next() { return Z + (int64_t)j * n; }
+  const double* flags() const { return h->h_small + slot * SM_COL; }
 
   void begin(asss_handle_s* h_, bool adj, const double* b_, double* x_, const asss_solve_opts_t& o_,
              double* V_, double* Z_, double* bchk_, double* xchk_, double* rv_, hipStream_t s_) {
     h = h_; adjoint = adj; b = b_; x = x_; o = o_; s = s_;
     V = V_; Z = Z_; bchk = bchk_; xchk = xchk_; rv = rv_;
+    W = h->d_hess + (int64_t)slot * HESS_SLOT;
     t0 = now_s();
     n = h->n;
     m = std::max(1, o.restart_m);
+    if (m > HESS_MMAX) throw Error{ASSS_ERR_INVALID_ARG, "restart_m above 250"};
     inf = asss_info_t{};
     inf.k_eff = h->k_eff;
     inf.rank_r = h->r;
@@ -938,11 +1044,6 @@ struct FgmresCol {
     bcn = std::sqrt(dot_host(h, n, bchk, bchk, s));
     thr = o.tol * bcn;
     HIPCHK(hipMemsetAsync(xchk, 0, n * sizeof(double), s));
-    H.assign((size_t)(m + 1) * m, 0.0);
-    cs.assign(m, 0.0);
-    sn.assign(m, 0.0);
-    g.assign(m + 1, 0.0);
-    y.assign(m, 0.0);
     first = true;
     start_cycle();
   }
@@ -958,89 +1059,104 @@ struct FgmresCol {
     first = false;
     const double beta = std::sqrt(dot_host(h, n, rv, rv, s));
     inf.cycles++;
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
     j = 0;
+    gabs = beta;
     implicit_ok = beta <= thr;
     if (beta > 0) {
+      hess_reset(W, beta, s);
       scale(n, 1.0 / beta, rv, V, s);
     } else {
       end_cycle();
     }
   }
 
-  // Arnoldi step j with z_j = Z[:, j] just written by the preconditioner.
-  // Arnoldi step after the preconditioner application z_j, in two halves so
-  // that lockstep columns share one host round trip: arnoldi_enqueue puts
-  // w = A_chk z_j (straight into V[:, j+1]), the classical Gram-Schmidt
-  // coefficients V^T w and the updated norm on the stream and copies the j + 3
-  // values to this column's host scratch; arnoldi_finish (stream synchronized)
-  // takes them, runs a second pass when the norm dropped below 1/sqrt(10) of
-  // its value (DGKS), and updates the Givens QR and the residual estimate.
-  void arnoldi_enqueue(int its) {
+  void count_inner(int its) {
+    recent[nrecent++ & 3] = its;
     last_its = its;
     inf.inner_its_total += its;
     inf.inner_its_max = std::max(inf.inner_its_max, its);
+  }
+
+  // Arnoldi step j after the preconditioner application z_j, in two halves so
+  // that lockstep columns share one host round trip: arnoldi_enqueue puts
+  // w = A_chk z_j (straight into V[:, j+1]), the classical Gram-Schmidt
+  // coefficients V^T w with the updated norm, and the Hessenberg step on the
+  // stream, and copies the step's flags to this column's host scratch;
+  // arnoldi_finish (stream synchronized) reads them, runs a second
+  // Gram-Schmidt pass when the norm dropped below 1/sqrt(10) of its value
+  // (DGKS), normalizes the new vector and ends the cycle when the residual
+  // estimate passed the test.  Enqueueing again recomputes the same step.
+  void arnoldi_enqueue() {
     double* hbuf = h->d_small + slot * SM_COL;
     double* vn = V + (int64_t)(j + 1) * n;
     op(Z + (int64_t)j * n, vn);
     gemm_tn<double, double>(n, j + 2, V, n, vn, 1, hbuf, nullptr, h->red, 4, s);
     gemv_acc_norm(n, j + 1, V, n, hbuf, -1.0, vn, hbuf + j + 2, h->red, 5, s);
-    HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL, hbuf, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+    hess_step(W, hbuf, nullptr, j, m, 0, thr, s);
+    HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL, hess_out(W), HESS_OUT * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
   }
 
   void after_prec(int its) {
     Range range("asss:outer step");  // the whole Arnoldi step, GPU work and host round trip
-    arnoldi_enqueue(its);
+    count_inner(its);
+    arnoldi_enqueue();
     HIPCHK(hipStreamSynchronize(s));
+    arnoldi_finish();
+  }
+
+  // One outer step of a single column with one host synchronization in the
+  // usual case: the inner solve (a chunk of steps sized from the previous
+  // solve), its output, the low-rank correction and the Arnoldi step go on
+  // the stream together; only when the inner solve needed more steps than
+  // the chunk does the host wait for it and enqueue the rest of the step
+  // again.
+  void step(bool fp32) {
+    Range range("asss:outer step (inner solve, Arnoldi step, Hessenberg update)");
+    const double* v = v_next();
+    double* z = z_next();
+    int expect = h->last_inner;
+    if (nrecent > 0) expect = *std::max_element(recent, recent + std::min(nrecent, 4));
+    InnerJob in;
+    in.start(h, fp32, adjoint ? prec_pre_T(h, v, s) : v, z, adjoint ? -1 : +1, o.inner_tol, o.inner_maxit,
+             o.fixed_inner_steps, s, expect);
+    in.finish();
+    if (!adjoint) smw_correct(h, z, s);
+    arnoldi_enqueue();
+    HIPCHK(hipStreamSynchronize(s));
+    if (!in.settle()) {
+      do {
+        HIPCHK(hipStreamSynchronize(s));
+      } while (!in.settle());
+      in.finish();
+      if (!adjoint) smw_correct(h, z, s);
+      arnoldi_enqueue();
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    count_inner(in.its());
     arnoldi_finish();
   }
 
   void arnoldi_finish() {
     double* hbuf = h->d_small + slot * SM_COL;
-    const double* hh = h->h_small + slot * SM_COL;
     double* vn = V + (int64_t)(j + 1) * n;
-    const double wn2 = hh[j + 1];
-    double hn2 = hh[j + 2];
-    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
-    if (hn2 < 0.1 * wn2) {
+    if (flags()[2] != 0.0) {
       double* h2 = hbuf + SM_PASS2;
       gemm_tn<double, double>(n, j + 1, V, n, vn, 1, h2, nullptr, h->red, 4, s);
       gemv_acc_norm(n, j + 1, V, n, h2, -1.0, vn, h2 + j + 1, h->red, 5, s);
-      HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL + SM_PASS2, h2, (j + 2) * sizeof(double),
+      hess_step(W, hbuf, h2, j, m, 1, thr, s);
+      HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL, hess_out(W), HESS_OUT * sizeof(double),
                             hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      const double* hh2 = h->h_small + slot * SM_COL + SM_PASS2;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hh2[i];
-      hn2 = hh2[j + 1];
       inf.reorth++;
     }
-    const double hn = std::sqrt(hn2);
-    H[(size_t)(j + 1) * m + j] = hn;
+    const double hn = flags()[1];
+    gabs = flags()[0];
+    implicit_ok = flags()[3] != 0.0;
     if (hn != 0.0) scale(n, 1.0 / hn, vn, vn, s);
-    for (int i = 0; i < j; ++i) {
-      const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-      H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-      H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-    }
-    const double rr = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
-    if (rr == 0.0) {
-      cs[j] = 1.0;
-      sn[j] = 0.0;
-    } else {
-      cs[j] = H[(size_t)j * m + j] / rr;
-      sn[j] = H[(size_t)(j + 1) * m + j] / rr;
-    }
-    H[(size_t)j * m + j] = rr;
-    H[(size_t)(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
     inf.outer_its++;
-    implicit_ok = std::fabs(g[j + 1]) <= thr;
     if (h->opts.verbose)
-      std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, last_its,
-                   std::fabs(g[j + 1]) / bcn);
+      std::fprintf(stderr, "[asss] outer %d inner %d implicit %.3e\n", inf.outer_its, last_its, gabs / bcn);
     ++j;
     if (implicit_ok || hn == 0.0 || inf.outer_its >= o.max_outer || j == m) end_cycle();
   }
@@ -1049,15 +1165,10 @@ struct FgmresCol {
   void end_cycle() {
     const int j_used = j;
     if (j_used > 0) {
-      for (int i = j_used - 1; i >= 0; --i) {
-        double acc = g[i];
-        for (int l = i + 1; l < j_used; ++l) acc -= H[(size_t)i * m + l] * y[l];
-        y[i] = acc / H[(size_t)i * m + i];
-      }
-      HIPCHK(hipMemcpyAsync(h->d_small + SM_Y, y.data(), j_used * sizeof(double), hipMemcpyHostToDevice, s));
-      gemv_acc(n, j_used, Z, n, h->d_small + SM_Y, 1.0, xchk, s);
+      hess_solve(W, j_used, m, s);
+      gemv_acc(n, j_used, Z, n, hess_y(W), 1.0, xchk, s);
     }
-    inf.relres_implicit = std::fabs(g[j_used]) / bcn;
+    inf.relres_implicit = gabs / bcn;
     back_transform(h, adjoint, xchk, x, s);
     if (!adjoint) spmv(h->dA, x, rv, nullptr, nullptr, 1, b, s);   // r = b - A x
     else spmv(h->dAt, x, rv, nullptr, nullptr, 1, b, s);           // r = g - A^T lambda
@@ -1098,11 +1209,7 @@ asss_status_t fgmres(asss_handle_s* h, bool adjoint, const double* b, double* x,
   h->prof_launches = 0;
   FgmresCol c;
   c.begin(h, adjoint, b, x, o, h->V, h->Z, h->bchk, h->xchk, h->rv, s);
-  while (!c.done) {
-    const int its = adjoint ? prec_apply_T(h, fp32, c.v_next(), c.z_next(), o, s)
-                            : prec_apply(h, fp32, c.v_next(), c.z_next(), o, s);
-    c.after_prec(its);
-  }
+  while (!c.done) c.step(fp32);
   return c.finish(info);
 }
 
@@ -1151,7 +1258,8 @@ asss_status_t fgmres_block(asss_handle_s* h, int nc, const double* const* B, dou
       double* z = c.z_next();
       HIPCHK(hipMemcpyAsync(z, h->pout + (int64_t)i * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       smw_correct(h, z, s);
-      c.arnoldi_enqueue(its);
+      c.count_inner(its);
+      c.arnoldi_enqueue();
     }
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < na; ++i) cols[act[i]].arnoldi_finish();
@@ -1574,6 +1682,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->red.tickets = h->ar.alloc<unsigned>(16);
     HIPCHK(hipMemsetAsync(h->red.tickets, 0, 16 * sizeof(unsigned), s));
     h->d_small = h->ar.alloc<double>(SM_SIZE);
+    h->d_hess = h->ar.alloc<double>((int64_t)NRMAX * HESS_SLOT);
     h->d_flag = h->ar.alloc<int>(1);
     HIPCHK(hipHostMalloc((void**)&h->h_small, SM_SIZE * sizeof(double), hipHostMallocDefault));
     h->d_state = h->ar.alloc<MrsState>(1);

@@ -18,6 +18,7 @@
 #include "ildl_host.hpp"
 #include "ildl_kernels.hpp"
 #include "kernels.hpp"
+#include "outer_kernels.hpp"
 
 namespace asss {
 namespace host {
@@ -178,6 +179,7 @@ struct asss_handle_s {
   MrsState* d_state = nullptr;
   Reducer red;
   double* d_small = nullptr;  // SM_SIZE doubles of scalars (layout above)
+  double* d_hess = nullptr;   // NRMAX Hessenberg workspaces of HESS_SLOT doubles
   int* d_flag = nullptr;
   double* h_small = nullptr;  // pinned
   // outer workspace
