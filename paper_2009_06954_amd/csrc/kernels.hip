@@ -789,6 +789,64 @@ __global__ __launch_bounds__(WG) void k_mrs_init(MrsLaunch L, const double* __re
         if (l < k) acc[1 + l] += q0[l] * (double)(T)b0 + q1[l] * (double)(T)b1;
     }
   }
+  if constexpr (NR == 1 && sizeof(T) == 4 && KF > 0) {
+    // one FP32 column: a pair of adjacent rows per thread and round, with
+    // 8-byte loads and stores (the basis from its sliced copy, where rows 2t
+    // and 2t + 1 of a slot are adjacent and slices are padded with zeros);
+    // the start is bound by the number of memory instructions per row, which
+    // this halves.  Needs 8-byte aligned buffers and permutation (checked
+    // here, else the row loop below runs).
+    const uintptr_t mis = ((uintptr_t)buf.w[0] | (uintptr_t)buf.w[1] | (uintptr_t)buf.w[2] |
+                           (uintptr_t)buf.p[0] | (uintptr_t)buf.p[1] | (uintptr_t)buf.x | (uintptr_t)perm |
+                           (uintptr_t)L.Qs) & 7u;
+    if (mis == 0 && L.Qs != nullptr && L.kq == k) {
+      const float* __restrict__ Qs = (const float*)L.Qs;
+      const int64_t np = (n + 1) >> 1;
+      for (int64_t pi = i0; pi < np; pi += stride) {
+        const int64_t i = 2 * pi;
+        const bool two = i + 1 < n;
+        int64_t s0 = i, s1 = i + 1;
+        if (perm) {
+          if (two) {
+            const int2 pp = *reinterpret_cast<const int2*>(perm + i);
+            s0 = pp.x;
+            s1 = pp.y;
+          } else {
+            s0 = perm[i];
+          }
+        }
+        float2 q[KF];
+        const int64_t qb = (i >> 6) * (int64_t)(k * 64) + (i & 63);
+#pragma unroll
+        for (int l = 0; l < KF; ++l)
+          if (l < k) q[l] = *reinterpret_cast<const float2*>(Qs + qb + l * 64);
+        const double b0 = L.nr > 0 ? rhs[s0] : 0.0;
+        const double b1 = (L.nr > 0 && two) ? rhs[s1] : 0.0;
+        const float f0 = (float)b0, f1 = (float)b1;
+        if (two) {
+          const float2 z = make_float2(0.f, 0.f);
+          *reinterpret_cast<float2*>(buf.w[1] + i) = make_float2(f0, f1);
+          *reinterpret_cast<float2*>(buf.w[0] + i) = z;
+          *reinterpret_cast<float2*>(buf.w[2] + i) = z;
+          *reinterpret_cast<float2*>(buf.p[0] + i) = z;
+          *reinterpret_cast<float2*>(buf.p[1] + i) = z;
+          *reinterpret_cast<float2*>(buf.x + i) = z;
+        } else {
+          buf.w[1][i] = f0;
+          buf.w[0][i] = 0.f;
+          buf.w[2][i] = 0.f;
+          buf.p[0][i] = 0.f;
+          buf.p[1][i] = 0.f;
+          buf.x[i] = 0.f;
+        }
+        acc[0] += b0 * b0 + b1 * b1;
+#pragma unroll
+        for (int l = 0; l < KF; ++l)
+          if (l < k) acc[1 + l] += (double)q[l].x * (double)f0 + (double)q[l].y * (double)f1;
+      }
+      i0 = n;
+    }
+  }
   for (int64_t i = i0; i < n; i += stride) {
     double b[NR];
     const int64_t src = perm ? (int64_t)perm[i] : i;
