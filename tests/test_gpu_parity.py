@@ -257,6 +257,48 @@ def test_solve_trajectory_parity(cfg0):
     assert _rel(_np(x), xo) <= 1e-10
 
 
+@pytest.mark.parametrize("restart_m", [1, 3, 250])
+def test_solve_trajectory_restart_lengths(cfg0, restart_m):
+    """P2 at the extremes of the restart length (the Hessenberg matrix, its
+    rotations, the residual estimate and the stop test run on the device):
+    fixed inner steps, same outer, cycle, second-pass and inner counts as the
+    oracle, the same implicit residual at the end within 1e-6 of its value,
+    x to 1e-10."""
+    p = cfg0
+    kw = dict(tol=1e-8, fixed_inner_steps=30, restart_m=restart_m, max_outer=400)
+    xo, io = O.solve(p.st, p.w.b, O.SolveOptions(**kw))
+    x, info = p.h.solve(_cuda(p.w.b), **kw)
+    print(f"[restart {restart_m}] outer {info['outer_its']} / {io['outer_its']} cycles {info['cycles']} / "
+          f"{io['cycles']} implicit {info['relres_implicit']:.3e} / {io['relres_implicit']:.3e}", flush=True)
+    assert info["status"] == "OK" and io["converged"]
+    for key in ("outer_its", "cycles", "reorth", "inner_its_total"):
+        assert info[key] == io[key], key
+    assert abs(info["relres_implicit"] - io["relres_implicit"]) <= 1e-6 * io["relres_implicit"]
+    assert _rel(_np(x), xo) <= 1e-10
+
+
+def test_full_cycle_of_250_steps():
+    """One whole FGMRES(250) cycle that does not converge (a stand-in matrix,
+    k = 0, one inner step per outer step): the device back substitution runs
+    over all 250 columns.  On the oracle, perturbing b by 1e-14 moves this
+    cycle's x by 3e-14, so the bounds below leave room for the two sides'
+    own least-squares S (1e-12 apart) and nothing else."""
+    w = W.paper_like(3000, 20000, seed=0)
+    p = Pair(w.A, k=0)
+    kw = dict(tol=1e-10, fixed_inner_steps=1, restart_m=250, max_outer=250)
+    xo, io = O.solve(p.st, w.b, O.SolveOptions(**kw))
+    x, info = p.h.solve(_cuda(w.b), **kw)
+    print(f"[cycle 250] implicit {info['relres_implicit']:.6e} / {io['relres_implicit']:.6e} "
+          f"true {info['relres_true']:.6e} / {io['relres_true']:.6e}", flush=True)
+    assert info["status"] == "NOT_CONVERGED" and not io["converged"]
+    for key in ("outer_its", "cycles", "reorth", "inner_its_total"):
+        assert info[key] == io[key], key
+    assert info["outer_its"] == 250 and info["cycles"] == 1
+    assert abs(info["relres_implicit"] / io["relres_implicit"] - 1.0) <= 1e-9
+    assert abs(info["relres_true"] / io["relres_true"] - 1.0) <= 1e-9
+    assert _rel(_np(x), xo) <= 1e-10
+
+
 def test_solve_default_inner(cfg0):
     p = cfg0
     xo, io = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-8))
