@@ -956,7 +956,7 @@ template <typename T, int NR, int KF, bool STAGE, typename TQ>
 __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T>& J, const MrsBufs<T>& buf,
                                                MrsState* st, double* partials, unsigned* ticket,
                                                int64_t row0, int nrow, int g, int ng, double* acc_lds,
-                                               T* w_lds) {
+                                               T* w_lds, bool pairs = false) {
   constexpr int NV = (KF + 1) * NR;
   __shared__ double lds[(WG / 64) * NV];
   __shared__ double res[NV];
@@ -1037,7 +1037,62 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   const T sgn = (T)L.sign;
-  for (int il = threadIdx.x; il < nrow; il += WG) {
+  int il_start = threadIdx.x;
+  if constexpr (NR == 1 && sizeof(T) == 4 && sizeof(TQ) == 4 && KF > 0) {
+    // one FP32 column: a pair of adjacent rows per thread, 8-byte loads and
+    // stores of the vectors and of the basis (rows 2t, 2t + 1 of a slot are
+    // adjacent in the sliced copy, whose slices are padded with zeros), the
+    // same arithmetic per row; the update is bound by memory instructions
+    // per row, which this halves.  Needs 8-byte aligned vectors and an even
+    // first row (checked; else the row loop below runs).
+    const uintptr_t mis = ((uintptr_t)wold | (uintptr_t)wnew | (uintptr_t)pb | (uintptr_t)x |
+                           (uintptr_t)L.Qs | (uintptr_t)(row0 & 1)) & 7u;
+    if (pairs && mis == 0) {
+      for (int il = 2 * (int)threadIdx.x; il < nrow; il += 2 * WG) {
+        const int64_t i = row0 + il;
+        const bool two = il + 1 < nrow;
+        const float2 wo = two ? *reinterpret_cast<const float2*>(wold + i) : make_float2(wold[i], 0.f);
+        const float u0 = (T)acc_lds[il] * inv_nu[0];
+        const float u1 = two ? (T)acc_lds[il + 1] * inv_nu[0] : 0.f;
+        const float qo0 = wo.x * inv_nu_old[0], qo1 = wo.y * inv_nu_old[0];
+        const TQ* __restrict__ qs = reinterpret_cast<const TQ*>(L.Qs) + (i >> 6) * (int64_t)(L.kq * 64) + (i & 63);
+        float2 qrow[KF];
+        float d0 = 0.f, d1 = 0.f;
+#pragma unroll
+        for (int l = 0; l < KF; ++l) {
+          float2 q = make_float2(0.f, 0.f);
+          if (l < k) q = two ? *reinterpret_cast<const float2*>(qs + l * 64) : make_float2(qs[l * 64], 0.f);
+          qrow[l] = q;
+          d0 += q.x * cv[0][l];
+          d1 += q.y * cv[0][l];
+        }
+        const float qn0 = sgn * (u0 - d0) + beta_prev[0] * qo0;
+        const float qn1 = sgn * (u1 - d1) + beta_prev[0] * qo1;
+        if (two) *reinterpret_cast<float2*>(wnew + i) = make_float2(qn0, qn1);
+        else wnew[i] = qn0;
+        acc[0] += (double)qn0 * (double)qn0 + (double)qn1 * (double)qn1;
+#pragma unroll
+        for (int l = 0; l < KF; ++l)
+          acc[1 + l] += (double)qrow[l].x * (double)qn0 + (double)qrow[l].y * (double)qn1;
+        if (pend) {
+          const float2 pv = two ? *reinterpret_cast<const float2*>(pb + i) : make_float2(pb[i], 0.f);
+          const float2 xv = two ? *reinterpret_cast<const float2*>(x + i) : make_float2(x[i], 0.f);
+          const float p0 = (qo0 - pend_delta[0] * pv.x) * inv_pend_theta[0];
+          const float p1 = (qo1 - pend_delta[0] * pv.y) * inv_pend_theta[0];
+          const float x0 = xv.x + pend_coef[0] * p0, x1 = xv.y + pend_coef[0] * p1;
+          if (two) {
+            *reinterpret_cast<float2*>(pb + i) = make_float2(p0, p1);
+            *reinterpret_cast<float2*>(x + i) = make_float2(x0, x1);
+          } else {
+            pb[i] = p0;
+            x[i] = x0;
+          }
+        }
+      }
+      il_start = nrow;
+    }
+  }
+  for (int il = il_start; il < nrow; il += WG) {
     const int64_t i = row0 + il;
     T defl[NR];
 #pragma unroll
@@ -1102,7 +1157,7 @@ __global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, L.n - row0);
   mrs_iter_block<T, NR, KF, STAGE, TQ>(L, J, buf, st, partials, ticket, row0, nrow, blockIdx.x, gridDim.x,
-                                       acc_lds, w_lds);
+                                       acc_lds, w_lds, true);
 }
 
 // The batched inner step: one launch advances the inner solves of every
