@@ -15,9 +15,11 @@
 //   * Gram-Schmidt, the SMW term and the norms are segmented products: row
 //     blocks accumulate partial sums, and the last block of each (system,
 //     column) adds them in a fixed order.
-// The host keeps each column's Hessenberg matrix, Givens rotations and
-// stopping decisions (the same rules as the one-system solve) and meets the
-// device once per outer step for all columns together.
+// Each column's Hessenberg matrix, Givens rotations, residual estimate and
+// stopping test are updated on the device, one wavefront per column (the
+// kernels of the one-system solve, outer.hip); the host reads their flags and
+// meets the device once per outer step for all columns together (twice when
+// a column needs a second Gram-Schmidt pass).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -379,6 +381,9 @@ struct Plan {
   int ngy = 0;
   double *d_h = nullptr, *d_h2 = nullptr, *d_n1 = nullptr, *d_n2 = nullptr, *d_t = nullptr, *d_t2 = nullptr,
          *d_f = nullptr, *d_y = nullptr;
+  // Hessenberg workspaces of the columns (hess_slot(m) doubles each), their
+  // read-back values, stopping thresholds and cycle starts
+  double *d_hess = nullptr, *d_hout = nullptr, *d_thr = nullptr, *d_beta = nullptr;
   int32_t *d_jv = nullptr, *d_cnt = nullptr, *d_cnt2 = nullptr, *d_done = nullptr;
   double* h_pin = nullptr;  // pinned host scratch for read-backs
   size_t h_pin_size = 0;
@@ -633,6 +638,10 @@ Plan* build_plan(const std::vector<asss_handle_t>& hs, bool fp32, int m, hipStre
   P->d_t2 = ar.alloc<double>(ncol * krm);
   P->d_f = ar.alloc<double>(ncol);
   P->d_y = ar.alloc<double>(ncol * std::max(1, m));
+  P->d_hess = ar.alloc<double>(ncol * hess_slot(std::max(1, m)));
+  P->d_hout = ar.alloc<double>(ncol * HESS_OUT);
+  P->d_thr = ar.alloc<double>(ncol);
+  P->d_beta = ar.alloc<double>(ncol);
   P->d_jv = ar.alloc<int32_t>(ncol);
   P->d_cnt = ar.alloc<int32_t>(ncol);
   P->d_cnt2 = ar.alloc<int32_t>(ncol);
@@ -729,13 +738,15 @@ std::vector<int> inner_solve(Plan& P, double tol, int maxit, hipStream_t s, doub
   return its;
 }
 
-// One column of flexible GMRES on the host side: the Hessenberg matrix, the
-// Givens rotations and the stopping rule of the one-system solve.
+// Host side of one column of flexible GMRES: its position in the cycle,
+// norms, stopping threshold and counters.  The Hessenberg matrix, the Givens
+// rotations, the residual estimate and its test live on the device
+// (outer.hip, one workspace per column).
 struct Col {
   bool active = false, done = false, implicit_ok = false, end = false;
   int j = 0, m = 1;
   double bn = 0, bcn = 0, thr = 0;
-  std::vector<double> H, cs, sn, g, y;
+  double gabs = 0;  // |g_j|, the residual estimate after the last step
   asss_info_t inf{};
   asss_status_t status = ASSS_NOT_CONVERGED;
 };
@@ -793,7 +804,7 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
   HIPCHK(hipMemsetAsync(P.xc, 0, vec * sizeof(double), s));
   HIPCHK(hipMemsetAsync(P.x, 0, vec * sizeof(double), s));
   sync();
-  std::vector<double> f(ncol, 0.0);
+  std::vector<double> f(ncol, 0.0), betas(ncol, -1.0);
   for (int sidx = 0; sidx < ns; ++sidx)
     for (int c = 0; c < NC; ++c) {
       Col& C = cols[sidx * NC + c];
@@ -815,13 +826,9 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
       }
       C.m = m;
       C.thr = o.tol * C.bcn;
-      C.H.assign((size_t)(m + 1) * m, 0.0);
-      C.cs.assign(m, 0.0);
-      C.sn.assign(m, 0.0);
-      C.g.assign(m + 1, 0.0);
-      C.y.assign(m, 0.0);
       // first cycle: r = b_chk, beta = ||b_chk||
-      C.g[0] = C.bcn;
+      C.gabs = C.bcn;
+      betas[sidx * NC + c] = C.bcn;
       C.j = 0;
       C.inf.cycles = 1;
       C.implicit_ok = C.bcn <= C.thr;
@@ -831,6 +838,8 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
     }
   up_i(P.d_jv, jv);
   up_d(P.d_f, f);
+  up_d(P.d_beta, betas);
+  hess_reset_batched(P.d_hess, m, ncol, P.d_beta, s);
   hipLaunchKernelGGL(k_seg_move, gb, dim3(WG), 0, s, sg, P.V, P.bc, vec, P.d_jv, P.d_f, 0);
   double kern_s = 0.0;
   int launches = 0;
@@ -838,23 +847,15 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
   // the end of a cycle for the columns with C.end set: x_chk += Z y,
   // back-transform, true residual; then finish or restart
   auto end_cycles = [&]() {
-    std::vector<double> Y((size_t)ncol * m, 0.0);
     for (int q = 0; q < ncol; ++q) {
       Col& C = cols[q];
       cnt[q] = 0;
       if (!C.end) continue;
-      const int ju = C.j;
-      for (int i = ju - 1; i >= 0; --i) {
-        double acc = C.g[i];
-        for (int l = i + 1; l < ju; ++l) acc -= C.H[(size_t)i * m + l] * C.y[l];
-        C.y[i] = acc / C.H[(size_t)i * m + i];
-      }
-      for (int l = 0; l < ju; ++l) Y[(size_t)q * m + l] = C.y[l];
-      cnt[q] = ju;
-      C.inf.relres_implicit = std::fabs(C.g[ju]) / C.bcn;
+      cnt[q] = C.j;
+      C.inf.relres_implicit = C.gabs / C.bcn;
     }
-    up_d(P.d_y, Y);
     up_i(P.d_cnt, cnt);
+    hess_solve_batched(P.d_hess, m, m, ncol, P.d_cnt, P.d_y, s);
     hipLaunchKernelGGL(k_seg_update, gb, dim3(WG), 0, s, sg, P.xc, P.Z, vec, N, P.d_y, m, P.d_cnt, 1.0,
                        (double*)nullptr, P.d_part, P.d_tick);
     // x = D_c S Omega x_chk, r = b - A x
@@ -900,16 +901,15 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
     norms(P.wc, P.d_n1);
     HIPCHK(hipMemcpyAsync(hp, P.d_n1, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
     sync();
-    std::vector<double> ff(ncol, 0.0);
+    std::vector<double> ff(ncol, 0.0), rb(ncol, -1.0);
     std::vector<int32_t> mv(ncol, -1);
     for (int q = 0; q < ncol; ++q) {
       if (rj[q] < 0) continue;
       Col& C = cols[q];
       const double beta = std::sqrt(hp[q]);
       C.inf.cycles++;
-      std::fill(C.H.begin(), C.H.end(), 0.0);
-      std::fill(C.g.begin(), C.g.end(), 0.0);
-      C.g[0] = beta;
+      C.gabs = beta;
+      rb[q] = beta;
       C.j = 0;
       C.implicit_ok = beta <= C.thr;
       if (beta > 0) {
@@ -921,6 +921,8 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
     }
     up_i(P.d_cnt, mv);
     up_d(P.d_f, ff);
+    up_d(P.d_beta, rb);
+    hess_reset_batched(P.d_hess, m, ncol, P.d_beta, s);
     hipLaunchKernelGGL(k_seg_move, gb, dim3(WG), 0, s, sg, P.V, P.wc, vec, P.d_cnt, P.d_f, 0);
   };
   for (int step = 0;; ++step) {
@@ -965,22 +967,23 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
     norms(P.wc, P.d_n1);
     hipLaunchKernelGGL(k_seg_update, gb, dim3(WG), 0, s, sg, P.wc, P.V, vec, N, P.d_h, ldh, P.d_cnt2, -1.0, P.d_n2,
                        P.d_part, P.d_tick);
-    double* hh = hp;
-    double* hw = hp + (size_t)ncol * ldh;
-    double* hn = hw + ncol;
-    HIPCHK(hipMemcpyAsync(hh, P.d_h, (size_t)ncol * ldh * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hw, P.d_n1, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hn, P.d_n2, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+    // the Hessenberg step of every active column on the device: the column
+    // is taken from this pass unless its norm fell below 1/sqrt(10) of
+    // ||w|| (DGKS), which only flags a second pass
+    std::vector<double> thrv(ncol, 0.0);
+    for (int q = 0; q < ncol; ++q) thrv[q] = cols[q].thr;
+    up_d(P.d_thr, thrv);
+    hess_step_batched(P.d_hess, m, m, ncol, P.d_jv, P.d_cnt2, 0, P.d_h, nullptr, ldh, P.d_n1, P.d_n2, P.d_thr,
+                      P.d_hout, s);
+    HIPCHK(hipMemcpyAsync(hp, P.d_hout, (size_t)ncol * HESS_OUT * sizeof(double), hipMemcpyDeviceToHost, s));
     sync();
-    // DGKS: a second pass where the new norm fell below 1/sqrt(10) of ||w||
     std::vector<int32_t> re(ncol, 0);
     bool any_re = false;
     for (int q = 0; q < ncol; ++q)
-      if (jv[q] >= 0 && hn[q] < 0.1 * hw[q]) {
+      if (jv[q] >= 0 && hp[(size_t)q * HESS_OUT + 2] != 0.0) {
         re[q] = cnt2[q];
         any_re = true;
       }
-    std::vector<double> h2((size_t)ncol * ldh, 0.0), hn2(hn, hn + ncol);
     if (any_re) {
       up_i(P.d_cnt2, re);
       const int ngr = std::max(1, (*std::max_element(re.begin(), re.end()) + NL - 1) / NL);
@@ -988,18 +991,11 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
                          P.d_cnt2, P.d_h2, ldh, P.d_part, P.d_tick, ngr);
       hipLaunchKernelGGL(k_seg_update, gb, dim3(WG), 0, s, sg, P.wc, P.V, vec, N, P.d_h2, ldh, P.d_cnt2, -1.0, P.d_n2,
                          P.d_part, P.d_tick);
-      double* h2p = hn + ncol;
-      double* hn2p = h2p + (size_t)ncol * ldh;
-      HIPCHK(hipMemcpyAsync(h2p, P.d_h2, (size_t)ncol * ldh * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hn2p, P.d_n2, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+      hess_step_batched(P.d_hess, m, m, ncol, P.d_jv, P.d_cnt2, 1, P.d_h, P.d_h2, ldh, P.d_n1, P.d_n2, P.d_thr,
+                        P.d_hout, s);
+      HIPCHK(hipMemcpyAsync(hp, P.d_hout, (size_t)ncol * HESS_OUT * sizeof(double), hipMemcpyDeviceToHost, s));
       sync();
-      for (int q = 0; q < ncol; ++q)
-        if (re[q]) {
-          for (int l = 0; l < re[q]; ++l) h2[(size_t)q * ldh + l] = h2p[(size_t)q * ldh + l];
-          hn2[q] = hn2p[q];
-        }
     }
-    // Hessenberg column, Givens rotation, residual estimate, stopping rule
     std::vector<int32_t> nj(ncol, -1);
     std::vector<double> ff(ncol, 0.0);
     bool any_end = false;
@@ -1010,29 +1006,12 @@ asss_status_t solve(Plan& P, const double* const* B, double* const* X, const int
       const int sys = q / NC;
       C.inf.inner_its_total += its[sys];
       C.inf.inner_its_max = std::max(C.inf.inner_its_max, its[sys]);
-      for (int i = 0; i <= j; ++i) C.H[(size_t)i * m + j] = hh[(size_t)q * ldh + i] + h2[(size_t)q * ldh + i];
       if (re[q]) C.inf.reorth++;
-      const double hnv = std::sqrt(std::max(0.0, hn2[q]));
-      C.H[(size_t)(j + 1) * m + j] = hnv;
-      for (int i = 0; i < j; ++i) {
-        const double a = C.H[(size_t)i * m + j], bb = C.H[(size_t)(i + 1) * m + j];
-        C.H[(size_t)i * m + j] = C.cs[i] * a + C.sn[i] * bb;
-        C.H[(size_t)(i + 1) * m + j] = -C.sn[i] * a + C.cs[i] * bb;
-      }
-      const double rr = std::hypot(C.H[(size_t)j * m + j], C.H[(size_t)(j + 1) * m + j]);
-      if (rr == 0.0) {
-        C.cs[j] = 1.0;
-        C.sn[j] = 0.0;
-      } else {
-        C.cs[j] = C.H[(size_t)j * m + j] / rr;
-        C.sn[j] = C.H[(size_t)(j + 1) * m + j] / rr;
-      }
-      C.H[(size_t)j * m + j] = rr;
-      C.H[(size_t)(j + 1) * m + j] = 0.0;
-      C.g[j + 1] = -C.sn[j] * C.g[j];
-      C.g[j] = C.cs[j] * C.g[j];
+      const double* ho = hp + (size_t)q * HESS_OUT;
+      const double hnv = ho[1];
+      C.gabs = ho[0];
       C.inf.outer_its++;
-      C.implicit_ok = std::fabs(C.g[j + 1]) <= C.thr;
+      C.implicit_ok = ho[3] != 0.0;
       C.j = j + 1;
       if (hnv != 0.0) {
         nj[q] = C.j;

@@ -3,8 +3,9 @@
 // its QR factorization, the rotated right-hand side whose last entry is the
 // residual estimate, the stopping test on it, and at the end of a cycle the
 // small triangular solve for the combination of the preconditioned vectors.
-// The work is O(j) per step (j <= 250) and sequential: one thread does it, so
-// the result does not depend on timing.
+// The work is O(j) per step (j <= 250) and sequential: one wavefront per
+// column, and the rotation chain in one lane, so the result does not depend
+// on timing.
 #include <hip/hip_runtime.h>
 
 #include "outer_kernels.hpp"
@@ -13,53 +14,41 @@ namespace asss {
 
 namespace {
 
-// Workspace of one column (doubles): H row-major (m+1) x m at 0 (leading
-// dimension m), then cs, sn, g, gp (MMAX + 1), y, out.
-constexpr int OFF_CS = (HESS_MMAX + 1) * HESS_MMAX;
-constexpr int OFF_SN = OFF_CS + HESS_MMAX;
-constexpr int OFF_G = OFF_SN + HESS_MMAX;
-constexpr int OFF_GP = OFF_G + HESS_MMAX;
-constexpr int OFF_Y = OFF_GP + HESS_MMAX + 1;
-constexpr int OFF_OUT = OFF_Y + HESS_MMAX;
-static_assert(OFF_OUT + HESS_OUT <= HESS_SLOT, "Hessenberg workspace");
+// Offsets (doubles) in a column's workspace for restart lengths up to cap.
+struct Lay {
+  int cap;
+  __host__ __device__ int64_t cs() const { return (int64_t)(cap + 1) * cap; }
+  __host__ __device__ int64_t sn() const { return cs() + cap; }
+  __host__ __device__ int64_t g() const { return sn() + cap; }
+  __host__ __device__ int64_t gp() const { return g() + cap; }
+  __host__ __device__ int64_t y() const { return gp() + cap + 1; }
+  __host__ __device__ int64_t out() const { return y() + cap; }
+};
+static_assert(hess_slot(HESS_MMAX) == (int64_t)(HESS_MMAX + 1) * HESS_MMAX + 5 * HESS_MMAX + 1 + HESS_OUT,
+              "workspace size");
 
-__global__ void k_hess_reset(double* W, double beta) {
+__device__ void reset_column(double* W, const Lay& L, double beta, double* out) {
   const int t = threadIdx.x;
-  if (t == 0) W[OFF_GP] = beta;
-  if (t < HESS_OUT) W[OFF_OUT + t] = 0.0;
+  if (t == 0) W[L.gp()] = beta;
+  if (t < HESS_OUT) out[t] = 0.0;
 }
 
 // gp[j] is the entry j of the right-hand side before step j's rotation, so
 // the step reads only values no later step of the cycle writes and can be
-// repeated.  Mode 0 with ||w'||^2 < 0.1 ||w||^2 (the vector kept less than
-// 1/sqrt(10) of its norm in the first pass) only flags the second pass.
-// One wavefront: the lanes stage the column and the earlier rotations in
-// LDS, lane 0 applies the rotations (a chain of dependent FMAs whose LDS
-// loads do not depend on it), the lanes write the column back.
-__global__ void __launch_bounds__(64) k_hess_step(double* W, const double* h1, const double* h2, int j, int m,
-                                                   int mode, double thr) {
-  __shared__ double col[HESS_MMAX + 1], c_s[HESS_MMAX], s_s[HESS_MMAX];
+// repeated.  The caller's lanes have put the new column (j + 1 values) in
+// col; the lanes stage the earlier rotations in LDS, lane 0 applies them (a
+// chain of dependent FMAs whose LDS loads do not depend on it) and the new
+// one, and the lanes write the column back.  One wavefront per column.
+__device__ void rotate_column(double* W, const Lay& L, int j, int m, double hn2, double thr, double* col,
+                              double* c_s, double* s_s, double* out) {
   const int t = threadIdx.x;
-  double* out = W + OFF_OUT;
-  double hn2;
-  if (mode == 0) {
-    hn2 = h1[j + 2];
-    if (hn2 < 0.1 * h1[j + 1]) {
-      if (t == 0) out[2] = 1.0;
-      return;
-    }
-    for (int i = t; i <= j; i += 64) col[i] = h1[i];
-  } else {
-    for (int i = t; i <= j; i += 64) col[i] = h1[i] + h2[i];
-    hn2 = h2[j + 1];
-  }
   for (int i = t; i < j; i += 64) {
-    c_s[i] = W[OFF_CS + i];
-    s_s[i] = W[OFF_SN + i];
+    c_s[i] = W[L.cs() + i];
+    s_s[i] = W[L.sn() + i];
   }
   __syncthreads();
   if (t == 0) {
-    const double hn = sqrt(hn2);
+    const double hn = sqrt(fmax(hn2, 0.0));
     double a = col[0];
     for (int i = 0; i < j; ++i) {  // the rotations of the earlier columns
       const double b = col[i + 1];
@@ -72,36 +61,53 @@ __global__ void __launch_bounds__(64) k_hess_step(double* W, const double* h1, c
       c = a / rr;
       sv = hn / rr;
     }
-    W[OFF_CS + j] = c;
-    W[OFF_SN + j] = sv;
+    W[L.cs() + j] = c;
+    W[L.sn() + j] = sv;
     col[j] = rr;
-    const double gj = W[OFF_GP + j];
-    W[OFF_G + j] = c * gj;
+    const double gj = W[L.gp() + j];
+    W[L.g() + j] = c * gj;
     const double gn = -sv * gj;
-    W[OFF_GP + j + 1] = gn;
+    W[L.gp() + j + 1] = gn;
     out[0] = fabs(gn);
     out[1] = hn;
     out[2] = 0.0;
     out[3] = fabs(gn) <= thr ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int i = t; i <= j; i += 64) W[i * m + j] = col[i];
-  if (t == 0) W[(j + 1) * m + j] = 0.0;
+  for (int i = t; i <= j; i += 64) W[(int64_t)i * m + j] = col[i];
+  if (t == 0) W[(int64_t)(j + 1) * m + j] = 0.0;
+}
+
+// Mode 0 with ||w'||^2 < 0.1 ||w||^2 (the vector kept less than 1/sqrt(10)
+// of its norm in the first pass) only flags the second pass.
+__device__ void step_column(double* W, const Lay& L, int j, int m, int mode, const double* h1, const double* h2,
+                            double wn2, double hn2, double thr, double* out) {
+  __shared__ double col[HESS_MMAX + 1], c_s[HESS_MMAX], s_s[HESS_MMAX];
+  const int t = threadIdx.x;
+  if (mode == 0) {
+    if (hn2 < 0.1 * wn2) {
+      if (t == 0) out[2] = 1.0;
+      return;
+    }
+    for (int i = t; i <= j; i += 64) col[i] = h1[i];
+  } else {
+    for (int i = t; i <= j; i += 64) col[i] = h1[i] + h2[i];
+  }
+  rotate_column(W, L, j, m, hn2, thr, col, c_s, s_s, out);
 }
 
 // Back substitution by columns in one wavefront: lane l keeps the entries
 // g_i with i = l (mod 64) in registers; for i = jused-1 down to 0 the owner
 // forms y_i, broadcasts it, and every lane removes R_{:,i} y_i from its
 // entries above i.
-__global__ void __launch_bounds__(64) k_hess_solve(double* W, int jused, int m) {
+__device__ void solve_column(const double* W, const Lay& L, int jused, int m, double* y) {
   constexpr int PER = (HESS_MMAX + 63) / 64;
   const int t = threadIdx.x;
-  const double* H = W;
   double r[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int i = t + 64 * q;
-    r[q] = i < jused ? W[OFF_G + i] : 0.0;
+    r[q] = i < jused ? W[L.g() + i] : 0.0;
   }
   for (int i = jused - 1; i >= 0; --i) {
     const int owner = i & 63, q_i = i >> 6;
@@ -109,22 +115,72 @@ __global__ void __launch_bounds__(64) k_hess_solve(double* W, int jused, int m) 
 #pragma unroll
     for (int q = 0; q < PER; ++q)
       if (q == q_i) mine = r[q];
-    double yi = mine / H[i * m + i];
+    double yi = mine / W[(int64_t)i * m + i];
     yi = __shfl(yi, owner, 64);
-    if (t == owner) W[OFF_Y + i] = yi;
+    if (t == owner) y[i] = yi;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int l = t + 64 * q;
-      if (l < i) r[q] -= H[l * m + i] * yi;
+      if (l < i) r[q] -= W[(int64_t)l * m + i] * yi;
     }
   }
-  if (t == 0) W[OFF_OUT + 4] = fabs(W[OFF_GP + jused]);
+}
+
+__global__ void __launch_bounds__(64) k_hess_reset(double* W, double beta) {
+  const Lay L{HESS_MMAX};
+  reset_column(W, L, beta, W + L.out());
+}
+
+// h1: j + 1 coefficients, ||w||^2 at h1[j + 1], the squared norm after the
+// pass at h1[j + 2]; h2 (mode 1): j + 1 coefficients, the squared norm after
+// the second pass at h2[j + 1].
+__global__ void __launch_bounds__(64) k_hess_step(double* W, const double* h1, const double* h2, int j, int m,
+                                                   int mode, double thr) {
+  const Lay L{HESS_MMAX};
+  const double wn2 = h1[j + 1];
+  const double hn2 = mode == 0 ? h1[j + 2] : h2[j + 1];
+  step_column(W, L, j, m, mode, h1, h2, wn2, hn2, thr, W + L.out());
+}
+
+__global__ void __launch_bounds__(64) k_hess_solve(double* W, int jused, int m) {
+  const Lay L{HESS_MMAX};
+  solve_column(W, L, jused, m, W + L.y());
+}
+
+__global__ void __launch_bounds__(64) k_hess_reset_batched(double* W, int cap, const double* beta) {
+  const int q = blockIdx.x;
+  const double b = beta[q];
+  if (b < 0.0) return;
+  const Lay L{cap};
+  double* Wq = W + (int64_t)q * hess_slot(cap);
+  reset_column(Wq, L, b, Wq + L.out());
+}
+
+__global__ void __launch_bounds__(64) k_hess_step_batched(double* W, int cap, int m, const int32_t* jv,
+                                                           const int32_t* sel, int mode, const double* h1,
+                                                           const double* h2, int ldh, const double* wn2,
+                                                           const double* hn2, const double* thr, double* out) {
+  const int q = blockIdx.x;
+  const int j = jv[q];
+  if (j < 0 || (mode == 1 && sel[q] == 0)) return;
+  const Lay L{cap};
+  step_column(W + (int64_t)q * hess_slot(cap), L, j, m, mode, h1 + (int64_t)q * ldh,
+              mode == 1 ? h2 + (int64_t)q * ldh : nullptr, wn2[q], hn2[q], thr[q], out + (int64_t)q * HESS_OUT);
+}
+
+__global__ void __launch_bounds__(64) k_hess_solve_batched(double* W, int cap, int m, const int32_t* jused,
+                                                            double* y) {
+  const int q = blockIdx.x;
+  const int ju = jused[q];
+  if (ju <= 0) return;
+  const Lay L{cap};
+  solve_column(W + (int64_t)q * hess_slot(cap), L, ju, m, y + (int64_t)q * m);
 }
 
 }  // namespace
 
-double* hess_out(double* W) { return W + OFF_OUT; }
-double* hess_y(double* W) { return W + OFF_Y; }
+double* hess_out(double* W) { return W + Lay{HESS_MMAX}.out(); }
+double* hess_y(double* W) { return W + Lay{HESS_MMAX}.y(); }
 
 void hess_reset(double* W, double beta, hipStream_t s) {
   hipLaunchKernelGGL(k_hess_reset, dim3(1), dim3(64), 0, s, W, beta);
@@ -136,6 +192,22 @@ void hess_step(double* W, const double* h1, const double* h2, int j, int m, int 
 
 void hess_solve(double* W, int jused, int m, hipStream_t s) {
   hipLaunchKernelGGL(k_hess_solve, dim3(1), dim3(64), 0, s, W, jused, m);
+}
+
+void hess_reset_batched(double* W, int cap, int ncol, const double* beta, hipStream_t s) {
+  if (ncol > 0) hipLaunchKernelGGL(k_hess_reset_batched, dim3(ncol), dim3(64), 0, s, W, cap, beta);
+}
+
+void hess_step_batched(double* W, int cap, int m, int ncol, const int32_t* jv, const int32_t* sel, int mode,
+                       const double* h1, const double* h2, int ldh, const double* wn2, const double* hn2,
+                       const double* thr, double* out, hipStream_t s) {
+  if (ncol > 0)
+    hipLaunchKernelGGL(k_hess_step_batched, dim3(ncol), dim3(64), 0, s, W, cap, m, jv, sel, mode, h1, h2, ldh, wn2,
+                       hn2, thr, out);
+}
+
+void hess_solve_batched(double* W, int cap, int m, int ncol, const int32_t* jused, double* y, hipStream_t s) {
+  if (ncol > 0) hipLaunchKernelGGL(k_hess_solve_batched, dim3(ncol), dim3(64), 0, s, W, cap, m, jused, y);
 }
 
 }  // namespace asss

@@ -1,21 +1,26 @@
 // Device side of the Hessenberg least-squares problem of flexible GMRES
 // (definitions in outer.hip).  Each outer column owns a workspace of
-// HESS_SLOT doubles in device memory; restart lengths up to HESS_MMAX.
+// hess_slot(cap) doubles in device memory for restart lengths m <= cap:
+// H ((m+1) x m, leading dimension m), the rotations cs and sn, the rotated
+// right-hand side g, its entries before rotation gp, the cycle's solution y
+// and HESS_OUT values read back by the host.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace asss {
 
 constexpr int HESS_MMAX = 250;
-// H ((m+1) x m), cs, sn, g (rotated), gp (before rotation), y, out
-constexpr int HESS_SLOT = (HESS_MMAX + 1) * HESS_MMAX + 5 * HESS_MMAX + 16;
+constexpr int HESS_OUT = 8;
+constexpr int64_t hess_slot(int cap) { return (int64_t)(cap + 1) * cap + 5 * (int64_t)cap + 1 + HESS_OUT; }
+constexpr int64_t HESS_SLOT = hess_slot(HESS_MMAX);
 
 // out[0] = |g_{j+1}| after step j (the residual estimate of the scaled
 // system), out[1] = h_{j+1,j}, out[2] = 1 when step j needs a second
-// Gram-Schmidt pass (nothing else was done), out[3] = 1 when out[0] <= thr,
-// out[4] = |g_jused| after hess_solve.
-constexpr int HESS_OUT = 8;
+// Gram-Schmidt pass (nothing else was done), out[3] = 1 when out[0] <= thr.
+// Single column (cap = HESS_MMAX): out lies in the workspace.
 double* hess_out(double* W);
 // the combination y of the preconditioned vectors, written by hess_solve
 double* hess_y(double* W);
@@ -23,12 +28,24 @@ double* hess_y(double* W);
 // Start of a cycle: g = beta e_1.
 void hess_reset(double* W, double beta, hipStream_t s);
 // Step j: the Hessenberg column from the Gram-Schmidt coefficients h1 (j + 1
-// values, then ||w||^2 and the norm after the pass) and, in mode 1, h2 (j + 1
-// values of the second pass, then the norm after it); earlier rotations, the
-// new rotation and the residual estimate; thr: the stopping threshold of the
-// estimate.  Repeating a step with the same inputs gives the same result.
+// values, then ||w||^2 and the squared norm after the pass) and, in mode 1,
+// h2 (j + 1 values of the second pass, then the squared norm after it);
+// earlier rotations, the new rotation, the residual estimate and the test
+// against thr.  Repeating a step with the same inputs gives the same result.
 void hess_step(double* W, const double* h1, const double* h2, int j, int m, int mode, double thr, hipStream_t s);
 // End of a cycle: y = R^-1 g over the first jused columns.
 void hess_solve(double* W, int jused, int m, hipStream_t s);
+
+// The same for ncol columns at once (workspace of column q at W + q
+// hess_slot(cap), one wavefront per column).  reset: columns with beta[q] >= 0.
+// step: columns with jv[q] >= 0 (and sel[q] != 0 in mode 1); coefficients
+// of column q at h1 + q ldh (h2 + q ldh), ||w||^2 in wn2[q], the squared
+// norm after the pass in hn2[q], threshold thr[q]; out + q HESS_OUT as above.
+// solve: columns with jused[q] > 0, y of column q at y + q m.
+void hess_reset_batched(double* W, int cap, int ncol, const double* beta, hipStream_t s);
+void hess_step_batched(double* W, int cap, int m, int ncol, const int32_t* jv, const int32_t* sel, int mode,
+                       const double* h1, const double* h2, int ldh, const double* wn2, const double* hn2,
+                       const double* thr, double* out, hipStream_t s);
+void hess_solve_batched(double* W, int cap, int m, int ncol, const int32_t* jused, double* y, hipStream_t s);
 
 }  // namespace asss
