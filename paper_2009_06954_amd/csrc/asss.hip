@@ -111,7 +111,24 @@ DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32
 // One sliced layout of J_tilde on the device, in both precisions (the index
 // arrays are shared), with the list of its buffers so that it can be replaced.
 
-SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s) {
+// Workgroup size of the one-column FP32 inner step for nb row blocks: the
+// caller's choice, else 512 when nb blocks fill whole rounds of 2 resident
+// workgroups per compute unit clearly better (by more than the ~4 % a
+// 512-thread workgroup costs where both fill whole rounds) than of 4.
+int pick_step_threads(int opt, int nb) {
+  if (opt == 256 || opt == 512) return opt;
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (cus <= 0 || nb <= 0) return WG;
+  auto fill = [&](int slots) {
+    const double r = (double)nb / slots;
+    return r / std::ceil(r);
+  };
+  return fill(2 * cus) > fill(4 * cus) + 0.05 ? 2 * WG : WG;
+}
+
+SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s, int step_threads) {
   SkewLayout L;
   auto keep = [&](const void* p) { if (p) L.bufs.push_back(p); };
   const int32_t* aw = ar.upload(sell.a_width, s);
@@ -133,6 +150,7 @@ SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s) {
     keep(p);
   L.J64 = upload_sell<double>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase, adoff);
   L.J32 = upload_sell<float>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase, adoff);
+  L.J32.threads = pick_step_threads(step_threads, L.J32.nblocks);
   for (const void* p : {(const void*)L.J64.a_val, (const void*)L.J64.b_val, (const void*)L.J32.a_val,
                         (const void*)L.J32.b_val})
     keep(p);
@@ -602,7 +620,7 @@ void tune_row_block(asss_handle_s* h, const Csr& Jup, const std::vector<int>& ca
     } catch (const HostError&) {
       continue;  // a forced column form that does not fit this row-block size
     }
-    SkewLayout cand = upload_layout(h->ar, sell, s);
+    SkewLayout cand = upload_layout(h->ar, sell, s, h->opts.step_threads);
     HIPCHK(hipStreamSynchronize(s));
     const double t = time_layout(h, cand, fp32, s);
     h->tuned.push_back({R, 1e6 * t});
@@ -1589,6 +1607,8 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
       throw Error{ASSS_ERR_INVALID_ARG, "row_block must be a multiple of 64 and <= 4096"};
     if (o.autotune < 0 || o.autotune > 1) throw Error{ASSS_ERR_INVALID_ARG, "autotune must be 0 or 1"};
     if (o.skew_form < 0 || o.skew_form > 3) throw Error{ASSS_ERR_INVALID_ARG, "skew_form must be 0, 1, 2 or 3"};
+    if (o.step_threads != 0 && o.step_threads != 256 && o.step_threads != 512)
+      throw Error{ASSS_ERR_INVALID_ARG, "step_threads must be 0, 256 or 512"};
     if (o.precond != ASSS_PRECOND_DIAG && o.precond != ASSS_PRECOND_ILDL)
       throw Error{ASSS_ERR_INVALID_ARG, "precond must be ASSS_PRECOND_DIAG or ASSS_PRECOND_ILDL"};
     if (o.precond == ASSS_PRECOND_ILDL) {
@@ -1776,7 +1796,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->d_om = h->ar.upload(h->Omega, s);
     h->d_dc = h->ar.upload(h->Dc, s);
     if (!ildl) {
-      SkewLayout lay = upload_layout(h->ar, sell, s);
+      SkewLayout lay = upload_layout(h->ar, sell, s, h->opts.step_threads);
       h->narrow_b = lay.narrow;
       h->skew_form = lay.form;
       h->J64 = lay.J64;
@@ -1861,6 +1881,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->ildl_droptol = 0.0;
   o->ildl_fill = HUGE_VAL;
   o->ildl_pivoting = 1;
+  o->step_threads = 0;
 }
 
 void asss_default_solve_opts(asss_solve_opts_t* o) {
@@ -2372,6 +2393,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
       i.ildl_nnz_l = h->il.F.L.nnz();
       i.ildl_dropped = h->il.F.dropped;
     }
+    i.step_threads = h->J32.threads > 0 ? h->J32.threads : WG;
     *out = i;
     return ASSS_OK;
   });

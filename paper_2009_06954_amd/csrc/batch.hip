@@ -536,7 +536,7 @@ Plan* build_plan(const std::vector<asss_handle_t>& hs, bool fp32, int m, hipStre
       }
     }
     SkewSell sell = pack_skew_sell(Jc, kRowBlock, SKEW_AUTO);
-    SkewLayout lay = upload_layout(ar, sell, s);
+    SkewLayout lay = upload_layout(ar, sell, s, 0);
     P->J64 = lay.J64;
     P->J32 = lay.J32;
   }

@@ -109,7 +109,7 @@ struct SkewLayout {
   int narrow = 0;
   int form = SKEW_WIDE;
 };
-SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s);
+SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s, int step_threads);
 
 }  // namespace host
 }  // namespace asss

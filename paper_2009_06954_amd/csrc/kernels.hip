@@ -16,11 +16,11 @@ namespace asss {
 // Reductions
 // ---------------------------------------------------------------------------
 
-// Reduce NV per-thread values over the workgroup; results in res[0..NV).
-// Fixed order (wave butterflies, then waves 0..3), so the result does not
-// depend on timing.
-template <int NV>
-__device__ __forceinline__ void wg_reduce(double (&v)[NV], double* lds /* [WG/64 * NV] */,
+// Reduce NV per-thread values over the workgroup of NT threads; results in
+// res[0..NV).  Fixed order (wave butterflies, then waves in order), so the
+// result does not depend on timing.
+template <int NV, int NT = WG>
+__device__ __forceinline__ void wg_reduce(double (&v)[NV], double* lds /* [NT/64 * NV] */,
                                           double* res /* [NV] */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -29,10 +29,10 @@ __device__ __forceinline__ void wg_reduce(double (&v)[NV], double* lds /* [WG/64
     if (lane == 0) lds[wave * NV + j] = s;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < NV; j += WG) {
+  for (int j = threadIdx.x; j < NV; j += NT) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < WG / 64; ++w) s += lds[w * NV + j];
+    for (int w = 0; w < NT / 64; ++w) s += lds[w * NV + j];
     res[j] = s;
   }
   __syncthreads();
@@ -78,9 +78,9 @@ __device__ __forceinline__ void publish_partials(double* partials, const double*
 }
 
 // The same for block g of ng blocks (a system's blocks in a batched launch).
-template <int NV>
+template <int NV, int NT = WG>
 __device__ __forceinline__ void publish_partials_at(double* partials, const double* res, int g, int ng) {
-  for (int j = threadIdx.x; j < NV; j += WG) store_partial(partials + (int64_t)j * ng + g, res[j]);
+  for (int j = threadIdx.x; j < NV; j += NT) store_partial(partials + (int64_t)j * ng + g, res[j]);
 }
 
 // In the last workgroup: res[j] = sum over groups g of partials[j * ngroups + g].
@@ -89,7 +89,7 @@ __device__ __forceinline__ void publish_partials_at(double* partials, const doub
 // on timing.  The atomic loads stay in program order, so all loads of a batch
 // of B groups are written before any of their sums: one memory round trip per
 // batch instead of one per value.
-template <int NV>
+template <int NV, int NT = WG>
 __device__ __forceinline__ void final_reduce(const double* partials, int ngroups, double* lds,
                                              double* res) {
   constexpr int B = NV <= 20 ? 2 : 1;
@@ -97,25 +97,25 @@ __device__ __forceinline__ void final_reduce(const double* partials, int ngroups
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
   int g = threadIdx.x;
-  for (; g + (B - 1) * WG < ngroups; g += B * WG) {
+  for (; g + (B - 1) * NT < ngroups; g += B * NT) {
     double v[B][NV];
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
-      for (int j = 0; j < NV; ++j) v[b][j] = load_partial(partials + (int64_t)j * ngroups + g + b * WG);
+      for (int j = 0; j < NV; ++j) v[b][j] = load_partial(partials + (int64_t)j * ngroups + g + b * NT);
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
       for (int j = 0; j < NV; ++j) acc[j] += v[b][j];
   }
-  for (; g < ngroups; g += WG) {
+  for (; g < ngroups; g += NT) {
     double v[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = load_partial(partials + (int64_t)j * ngroups + g);
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] += v[j];
   }
-  wg_reduce<NV>(acc, lds, res);
+  wg_reduce<NV, NT>(acc, lds, res);
 }
 
 // sum over g = g0, g0 + step, ... < ng of P[g * stride + o], eight independent
@@ -270,7 +270,7 @@ __device__ __forceinline__ int xcd_block() {
 // base, 3 = offset slots (no per-entry columns: every lane of a slot reads
 // column row + d; padding lanes, whose value is 0, are clamped into the block
 // for part a and into [0, n) for part b).
-template <typename T, int NR, bool STAGE, int FORM>
+template <typename T, int NR, bool STAGE, int FORM, int NT = WG>
 __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t row0, int nrow,
                                                      const T* __restrict__ wg, const T* w_lds,
                                                      double* acc_lds) {
@@ -283,7 +283,7 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
   // 138 -> 124 us on the 128^3 workload).
   constexpr int P = (NR == 1) ? 2 : 1;
   constexpr int U = (NR == 1) ? 4 : 8;
-  constexpr int NW = WG / 64;
+  constexpr int NW = NT / 64;
   constexpr bool NARROW = FORM == 2, SLOTS = FORM == 3;
   // the wave index is uniform: said so, the slice metadata below comes in
   // through scalar loads instead of a vector round trip per slice
@@ -396,16 +396,16 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
 }
 
 // The column form is fixed per matrix: one uniform branch per launch.
-template <typename T, int NR, bool STAGE>
+template <typename T, int NR, bool STAGE, int NT = WG>
 __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
                                                 const T* __restrict__ wg, const T* w_lds,
                                                 double* acc_lds) {
   if (J.form == 3)
-    skew_block_pass_form<T, NR, STAGE, 3>(J, row0, nrow, wg, w_lds, acc_lds);
+    skew_block_pass_form<T, NR, STAGE, 3, NT>(J, row0, nrow, wg, w_lds, acc_lds);
   else if (J.form == 2)
-    skew_block_pass_form<T, NR, STAGE, 2>(J, row0, nrow, wg, w_lds, acc_lds);
+    skew_block_pass_form<T, NR, STAGE, 2, NT>(J, row0, nrow, wg, w_lds, acc_lds);
   else
-    skew_block_pass_form<T, NR, STAGE, 1>(J, row0, nrow, wg, w_lds, acc_lds);
+    skew_block_pass_form<T, NR, STAGE, 1, NT>(J, row0, nrow, wg, w_lds, acc_lds);
 }
 
 template <typename T>
@@ -952,13 +952,13 @@ __global__ __launch_bounds__(WG) void k_mrs_init_batched(MrsBatch B, int R, cons
 // block g at j * ng + g) and whose last block, found with `ticket`, runs the
 // scalar recurrence.  Shared by the one-system kernel (one block per
 // workgroup) and the batched work-queue kernel (blocks of many systems).
-template <typename T, int NR, int KF, bool STAGE, typename TQ>
+template <typename T, int NR, int KF, bool STAGE, typename TQ, int NT = WG>
 __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T>& J, const MrsBufs<T>& buf,
                                                MrsState* st, double* partials, unsigned* ticket,
                                                int64_t row0, int nrow, int g, int ng, double* acc_lds,
                                                T* w_lds, bool pairs = false) {
   constexpr int NV = (KF + 1) * NR;
-  __shared__ double lds[(WG / 64) * NV];
+  __shared__ double lds[(NT / 64) * NV];
   __shared__ double res[NV];
   // The state was written by the previous launch and is not written before
   // the end of this one: every thread reads it with uniform (scalar) loads, so
@@ -1007,7 +1007,7 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
   if (status == MRS_CONVERGED) {
     // last deferred update: p_T and x += g_T c_T p_T
     if (pend) {
-      for (int il = threadIdx.x; il < nrow; il += WG) {
+      for (int il = threadIdx.x; il < nrow; il += NT) {
         const int64_t i = row0 + il;
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
@@ -1024,13 +1024,13 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
   }
 
   // operator pass: acc_lds = J_tilde w_t on this block
-  for (int r = threadIdx.x; r < nrow * NR; r += WG) {
+  for (int r = threadIdx.x; r < nrow * NR; r += NT) {
     acc_lds[r] = 0.0;
     if (STAGE) w_lds[r] = wcur[row0 * NR + r];
   }
   mrs_tail_store<T, NR, KF>(tail, tail_r, k);  // status is MRS_RUNNING here
   __syncthreads();
-  skew_block_pass<T, NR, STAGE>(J, row0, nrow, wcur, w_lds, acc_lds);
+  skew_block_pass<T, NR, STAGE, NT>(J, row0, nrow, wcur, w_lds, acc_lds);
   __syncthreads();
 
   double acc[NV];
@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
     const uintptr_t mis = ((uintptr_t)wold | (uintptr_t)wnew | (uintptr_t)pb | (uintptr_t)x |
                            (uintptr_t)L.Qs | (uintptr_t)(row0 & 1)) & 7u;
     if (pairs && mis == 0) {
-      for (int il = 2 * (int)threadIdx.x; il < nrow; il += 2 * WG) {
+      for (int il = 2 * (int)threadIdx.x; il < nrow; il += 2 * NT) {
         const int64_t i = row0 + il;
         const bool two = il + 1 < nrow;
         const float2 wo = two ? *reinterpret_cast<const float2*>(wold + i) : make_float2(wold[i], 0.f);
@@ -1092,7 +1092,7 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
       il_start = nrow;
     }
   }
-  for (int il = il_start; il < nrow; il += WG) {
+  for (int il = il_start; il < nrow; il += NT) {
     const int64_t i = row0 + il;
     T defl[NR];
 #pragma unroll
@@ -1137,27 +1137,36 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
       }
     }
   }
-  wg_reduce<NV>(acc, lds, res);
-  publish_partials_at<NV>(partials, res, g, ng);
+  wg_reduce<NV, NT>(acc, lds, res);
+  publish_partials_at<NV, NT>(partials, res, g, ng);
   if (!arrive_last(ticket, ng)) return;
-  final_reduce<NV>(partials, ng, lds, res);
+  final_reduce<NV, NT>(partials, ng, lds, res);
   mrs_scalar_update<T, NR, KF>(st, res, k, tail, st_fixed, st_maxit, st_tol, t, L.sign);
   reset_ticket(ticket);
 }
 
-// Occupancy target: 4 waves per SIMD (<= 128 VGPRs) so that 4 workgroups of
-// 256 threads are resident per CU (1024 on the chip).
-template <typename T, int NR, int KF, bool STAGE, typename TQ = T>
-__global__ __launch_bounds__(WG, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
+// Occupancy target: 4 waves per SIMD (<= 128 VGPRs), i.e. 16 waves per CU:
+// 4 workgroups of 256 threads or 2 of 512.  The one-column FP32 step can run
+// 512-thread workgroups (J.threads, chosen at setup): each block then takes
+// half the time, and a grid whose blocks fill whole rounds of 512 resident
+// workgroups better than of 1,024 runs faster (this step is latency bound;
+// the 192^3 tiling's 2,304 blocks are 2.25 rounds of 256-thread workgroups,
+// 4.5 of 512-thread ones).
+
+template <typename T, int NR, int KF, bool STAGE, typename TQ = T, int NT = WG>
+__global__ __launch_bounds__(NT, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
+  // the column-state, tail and scalar-update code strides by WG over at most
+  // NR * KMAX words, which NT >= WG threads cover once
+  static_assert(NT % WG == 0 && NR * KMAX <= WG, "workgroup size");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc_lds = reinterpret_cast<double*>(smem_raw);
   T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
   const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, L.n - row0);
-  mrs_iter_block<T, NR, KF, STAGE, TQ>(L, J, buf, st, partials, ticket, row0, nrow, blockIdx.x, gridDim.x,
-                                       acc_lds, w_lds, true);
+  mrs_iter_block<T, NR, KF, STAGE, TQ, NT>(L, J, buf, st, partials, ticket, row0, nrow, blockIdx.x, gridDim.x,
+                                           acc_lds, w_lds, true);
 }
 
 // The batched inner step: one launch advances the inner solves of every
@@ -1246,6 +1255,13 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
     if constexpr (sizeof(T) == 8) {                                                                    \
       if (L.q32) {                                                                                     \
         hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, float>), dim3(J.nblocks), dim3(WG), lds,       \
+                           s, L, J, Q, buf, st, red.partials, red.tickets + 1);                        \
+        break;                                                                                         \
+      }                                                                                                \
+    }                                                                                                  \
+    if constexpr (NR == 1 && sizeof(T) == 4) {                                                         \
+      if (J.threads == 2 * WG) {                                                                       \
+        hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, T, 2 * WG>), dim3(J.nblocks), dim3(2 * WG), lds, \
                            s, L, J, Q, buf, st, red.partials, red.tickets + 1);                        \
         break;                                                                                         \
       }                                                                                                \

@@ -36,6 +36,7 @@ struct DSkew {
   const int32_t* a_doff = nullptr;  // slots: part-a offset d > 0 per slot (a_off / 64 + slot)
   int32_t b_narrow = 0;
   int32_t form = 1;                 // 1: 32-bit part-b columns, 2: 16-bit deltas, 3: offset slots
+  int32_t threads = 0;              // workgroup size of the one-column FP32 inner step (0: 256)
   const T* a_val = nullptr;
   const T* b_val = nullptr;
 };

@@ -312,7 +312,7 @@ def test_mrs_fixed_steps(case, steps):
     assert err <= max(1e-12, 30 * spread)
 
 
-def test_mrs_fp32(case):
+def _mrs_fp32_check(case, h):
     """FP32 inner mrs (30 steps).  Pinned against the oracle's mrs on the
     same data rounded to FP32 (J_tilde and Q_k values) with its basis vectors
     stored in FP32 (arithmetic FP64): the true FP64 residual ||v - (I + J_bar)
@@ -329,16 +329,43 @@ def test_mrs_fp32(case):
     jbar32 = lambda u: jtilde_apply(J32, u) - Q32 @ (Sk @ (Q32.T @ u))
     v = np.random.default_rng(5).standard_normal(case.n)
     ref, _, _ = O.mrs(1.0, jbar32, r32(v), 30, 0.0, fixed_steps=30, storage=np.float32)
-    out, its = case.hs.apply("mrs", _cuda(v), fixed_inner_steps=30, inner_fp32=True)
+    out, its = h.apply("mrs", _cuda(v), fixed_inner_steps=30, inner_fp32=True)
     y = _np(out)
     res = lambda z: np.linalg.norm(v - (z + st.prec.jbar(z))) / np.linalg.norm(v)
     res_gpu, res_ref = res(y), res(ref)
     err = _rel(y, ref)
     spread = _spread(case, lambda: O.mrs(1.0, st.prec.jbar, v, 30, 0.0, fixed_steps=30)[0], u=2.0 ** -24)
-    print(f"[3d] m={case.m} mrs fp32: residual {res_gpu:.4e} vs FP32-storage oracle {res_ref:.4e}; "
+    print(f"[3d] m={case.m} mrs fp32 (step workgroup {h.info()['step_threads']}): residual {res_gpu:.4e} vs FP32-storage oracle {res_ref:.4e}; "
           f"x vs it {err:.2e}, spread at FP32 rounding {spread:.2e}")
     assert abs(res_gpu - res_ref) <= 0.05 * res_ref
     assert err <= max(1e-5, 30 * spread)
+
+
+def test_mrs_fp32(case):
+    _mrs_fp32_check(case, case.hs)
+
+
+@pytest.mark.parametrize("threads", [256, 512])
+def test_fp32_step_workgroup_size(case, threads):
+    """The one-column FP32 step with 256- and 512-thread workgroups, forced
+    (setup option step_threads; the default picks one from the row-block
+    count): 30-step FP32 mrs as above and P3 against the oracle."""
+    asss = _lib()
+    S = case.st.S.tocsr()
+    h = asss.setup(case.A, k=16, s_pattern="abar", reorder="grid", row_block=case.R, s_values=S.data,
+                   q_basis=case.st.Q, q_alpha=case.st.alpha, step_threads=threads)
+    try:
+        assert h.info()["step_threads"] == threads
+        _mrs_fp32_check(case, h)
+        xo, _ = O.solve(case.st, case.w.b, O.SolveOptions(tol=1e-13))
+        x, info = h.solve(case.b, tol=1e-11, restart_m=200, inner_tol=0.2, inner_fp32=True)
+        assert info["status"] == "OK" and info["relres_true"] <= 1e-11
+        assert _rel(_np(x), xo) <= 1e-7
+    finally:
+        h.close()
+    with pytest.raises(asss.AsssError) as e:
+        asss.setup(case.A, k=16, s_pattern="abar", step_threads=384)
+    assert e.value.name == "INVALID_ARG"
 
 
 def test_mrs_tolerance_stop(case):
