@@ -228,11 +228,11 @@ typedef struct {
                               applied to each column before it updates the rest of the matrix */
   int32_t ildl_pivoting;   /* 1 (default): Bunch-Kaufman partial pivoting, alpha = (1 + sqrt 17)/8;
                               0: 1x1 pivots in the natural order */
-  int32_t step_threads;    /* workgroup size of the one-column FP32 inner step: 0 (default)
-                              chooses 512 when its row blocks fill whole rounds of 512 resident
-                              workgroups clearly better than of 1,024 (4 and 2 per compute
-                              unit), else 256; 256 or 512 force it.  Results are the same up to
-                              rounding order; other values: INVALID_ARG */
+  int32_t step_threads;    /* workgroup size of the one-column inner step: 0 (default) chooses
+                              512 in FP64, and in FP32 512 when its row blocks fill whole rounds
+                              of 512 resident workgroups clearly better than of 1,024 (2 and 4
+                              per compute unit), else 256; 256 or 512 force it in both.  Results
+                              are the same up to rounding order; other values: INVALID_ARG */
 } asss_setup_opts_t;
 
 typedef struct {
@@ -423,6 +423,7 @@ typedef struct {
   int64_t ildl_nnz_l;                     /* strictly lower entries of L */
   int64_t ildl_dropped;                   /* entries of L dropped by droptol and fill */
   int32_t step_threads;                   /* workgroup size of the one-column FP32 inner step */
+  int32_t step_threads_fp64;              /* the same for the FP64 inner step */
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);

@@ -126,7 +126,7 @@ class HandleInfo(C.Structure):
                 ("tune_rows", C.c_int32 * 8), ("tune_us", C.c_double * 8), ("tune_s", C.c_double),
                 ("precond", C.c_int32), ("ildl_n2x2", C.c_int32), ("ildl_levels_lower", C.c_int32),
                 ("ildl_levels_upper", C.c_int32), ("ildl_nnz_l", C.c_int64), ("ildl_dropped", C.c_int64),
-                ("step_threads", C.c_int32)]
+                ("step_threads", C.c_int32), ("step_threads_fp64", C.c_int32)]
 
     def to_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -399,8 +399,8 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     precond: "diag" (L = I, D = diag(A_hat)) or "ildl" (incomplete LDL^T of
     M_hat with Bunch-Kaufman pivoting; ildl_droptol, ildl_fill and
     ildl_pivoting as in asss_setup_opts_t; reorder must stay "auto").
-    step_threads: workgroup size of the one-column FP32 inner step (0 =
-    chosen from the row-block count, 256 or 512; asss_setup_opts_t)."""
+    step_threads: workgroup size of the one-column inner step (0 = chosen
+    per precision, 256 or 512 in both; asss_setup_opts_t)."""
     lib = load()
     n, rp, ci, va = _csr_arrays(A, canonicalize)
     csr = CsrT(n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)

@@ -111,12 +111,14 @@ DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32
 // One sliced layout of J_tilde on the device, in both precisions (the index
 // arrays are shared), with the list of its buffers so that it can be replaced.
 
-// Workgroup size of the one-column FP32 inner step for nb row blocks: the
-// caller's choice, else 512 when nb blocks fill whole rounds of 2 resident
-// workgroups per compute unit clearly better (by more than the ~4 % a
-// 512-thread workgroup costs where both fill whole rounds) than of 4.
-int pick_step_threads(int opt, int nb) {
+// Workgroup size of the one-column inner step for nb row blocks: the
+// caller's choice; else 512 in FP64 (1-2 % faster at 128^3 and 192^3), and in
+// FP32 512 when nb blocks fill whole rounds of 2 resident workgroups per
+// compute unit clearly better (by more than the ~4 % a 512-thread workgroup
+// costs where both fill whole rounds) than of 4.
+int pick_step_threads(int opt, int nb, bool fp32) {
   if (opt == 256 || opt == 512) return opt;
+  if (!fp32) return 2 * WG;
   int dev = 0, cus = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -150,7 +152,8 @@ SkewLayout upload_layout(DevArena& ar, const SkewSell& sell, hipStream_t s, int 
     keep(p);
   L.J64 = upload_sell<double>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase, adoff);
   L.J32 = upload_sell<float>(ar, sell, s, aw, bw, ao, bo, ac, bc, bcd, bbase, adoff);
-  L.J32.threads = pick_step_threads(step_threads, L.J32.nblocks);
+  L.J64.threads = pick_step_threads(step_threads, L.J64.nblocks, false);
+  L.J32.threads = pick_step_threads(step_threads, L.J32.nblocks, true);
   for (const void* p : {(const void*)L.J64.a_val, (const void*)L.J64.b_val, (const void*)L.J32.a_val,
                         (const void*)L.J32.b_val})
     keep(p);
@@ -2394,6 +2397,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
       i.ildl_dropped = h->il.F.dropped;
     }
     i.step_threads = h->J32.threads > 0 ? h->J32.threads : WG;
+    i.step_threads_fp64 = h->J64.threads > 0 ? h->J64.threads : WG;
     *out = i;
     return ASSS_OK;
   });

@@ -996,8 +996,8 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
   const double st_tol = st->tol;
   if (status == MRS_DONE) return;
   __shared__ MrsTail<NR, KF> tail;
-  MrsTailRegs<NR, KF> tail_r;
-  if (status == MRS_RUNNING) mrs_tail_load<T, NR, KF>(tail_r, st, L);
+  MrsTailRegs<NR, KF, NT> tail_r;
+  if (status == MRS_RUNNING) mrs_tail_load<T, NR, KF, NT>(tail_r, st, L);
   const T* __restrict__ wcur = buf.w[t % 3];
   const T* __restrict__ wold = buf.w[(t + 2) % 3];
   T* __restrict__ wnew = buf.w[(t + 1) % 3];
@@ -1028,7 +1028,7 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
     acc_lds[r] = 0.0;
     if (STAGE) w_lds[r] = wcur[row0 * NR + r];
   }
-  mrs_tail_store<T, NR, KF>(tail, tail_r, k);  // status is MRS_RUNNING here
+  mrs_tail_store<T, NR, KF, NT>(tail, tail_r, k);  // status is MRS_RUNNING here
   __syncthreads();
   skew_block_pass<T, NR, STAGE, NT>(J, row0, nrow, wcur, w_lds, acc_lds);
   __syncthreads();
@@ -1146,19 +1146,20 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
 }
 
 // Occupancy target: 4 waves per SIMD (<= 128 VGPRs), i.e. 16 waves per CU:
-// 4 workgroups of 256 threads or 2 of 512.  The one-column FP32 step can run
+// 4 workgroups of 256 threads or 2 of 512.  The one-column step can run
 // 512-thread workgroups (J.threads, chosen at setup): each block then takes
-// half the time, and a grid whose blocks fill whole rounds of 512 resident
-// workgroups better than of 1,024 runs faster (this step is latency bound;
-// the 192^3 tiling's 2,304 blocks are 2.25 rounds of 256-thread workgroups,
-// 4.5 of 512-thread ones).
+// half the time.  The FP32 step, latency bound, gains where its blocks fill
+// whole rounds of 512 resident workgroups better than of 1,024 (the 192^3
+// tiling's 2,304 blocks are 2.25 rounds of 256-thread workgroups, 4.5 of
+// 512-thread ones) and loses a little where both fill them; the FP64 step
+// gains a little at both 128^3 and 192^3.
 
 template <typename T, int NR, int KF, bool STAGE, typename TQ = T, int NT = WG>
 __global__ __launch_bounds__(NT, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
-  // the column-state, tail and scalar-update code strides by WG over at most
-  // NR * KMAX words, which NT >= WG threads cover once
+  // the scalar-update code strides by WG over at most NR * KMAX words, which
+  // NT >= WG threads cover once
   static_assert(NT % WG == 0 && NR * KMAX <= WG, "workgroup size");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc_lds = reinterpret_cast<double*>(smem_raw);
@@ -1259,7 +1260,7 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
         break;                                                                                         \
       }                                                                                                \
     }                                                                                                  \
-    if constexpr (NR == 1 && sizeof(T) == 4) {                                                         \
+    if constexpr (NR == 1) {                                                                           \
       if (J.threads == 2 * WG) {                                                                       \
         hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, T, 2 * WG>), dim3(J.nblocks), dim3(2 * WG), lds, \
                            s, L, J, Q, buf, st, red.partials, red.tickets + 1);                        \

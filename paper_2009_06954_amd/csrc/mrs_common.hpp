@@ -67,22 +67,23 @@ struct MrsTail {
   double gram[KF1 * KF1];
 };
 
-// The tail's values in registers: every thread loads at most one column-state
-// word, one c, one alpha and NG Gram entries.  Loaded at the start of a launch
-// and written to LDS after the block's w is staged, so that these loads
-// overlap the staging loads instead of adding round trips of their own.
-template <int NR, int KF>
+// The tail's values in registers: every thread of the NT-thread workgroup
+// loads at most one column-state word, one c, one alpha and NG Gram entries.
+// Loaded at the start of a launch and written to LDS after the block's w is
+// staged, so that these loads overlap the staging loads instead of adding
+// round trips of their own.
+template <int NR, int KF, int NT = WG>
 struct MrsTailRegs {
   static constexpr int NC = NR * (int)sizeof(MrsCol) / 8;
   static constexpr int KF1 = KF > 0 ? KF : 1;
-  static constexpr int NG = (KF1 * KF1 + WG - 1) / WG;
-  static_assert(NC <= WG && NR * KF1 <= WG && KF1 <= WG, "one tail word per thread");
+  static constexpr int NG = (KF1 * KF1 + NT - 1) / NT;
+  static_assert(NC <= NT && NR * KF1 <= NT && KF1 <= NT, "one tail word per thread");
   double col, cvt, alpha, gram[NG];
 };
 
-template <typename T, int NR, int KF>
-__device__ __forceinline__ void mrs_tail_load(MrsTailRegs<NR, KF>& r, const MrsState* st, const MrsLaunch& L) {
-  using R = MrsTailRegs<NR, KF>;
+template <typename T, int NR, int KF, int NT = WG>
+__device__ __forceinline__ void mrs_tail_load(MrsTailRegs<NR, KF, NT>& r, const MrsState* st, const MrsLaunch& L) {
+  using R = MrsTailRegs<NR, KF, NT>;
   const int e = threadIdx.x, k = L.k;
   r.col = e < R::NC ? reinterpret_cast<const double*>(st->col)[e] : 0.0;
   r.cvt = r.alpha = 0.0;
@@ -94,14 +95,14 @@ __device__ __forceinline__ void mrs_tail_load(MrsTailRegs<NR, KF>& r, const MrsS
       if (e < NR * k) r.cvt = st->cvec[(e / k) * KMAX + e % k];  // rounded to T at the store
 #pragma unroll
       for (int u = 0; u < R::NG; ++u)
-        if (e + u * WG < k * k) r.gram[u] = L.gram[e + u * WG];
+        if (e + u * NT < k * k) r.gram[u] = L.gram[e + u * NT];
     }
   }
 }
 
-template <typename T, int NR, int KF>
-__device__ __forceinline__ void mrs_tail_store(MrsTail<NR, KF>& tl, const MrsTailRegs<NR, KF>& r, int k) {
-  using R = MrsTailRegs<NR, KF>;
+template <typename T, int NR, int KF, int NT = WG>
+__device__ __forceinline__ void mrs_tail_store(MrsTail<NR, KF>& tl, const MrsTailRegs<NR, KF, NT>& r, int k) {
+  using R = MrsTailRegs<NR, KF, NT>;
   const int e = threadIdx.x;
   if (e < R::NC) reinterpret_cast<double*>(tl.col)[e] = r.col;
   if (KF > 0 && k > 0) {
@@ -110,7 +111,7 @@ __device__ __forceinline__ void mrs_tail_store(MrsTail<NR, KF>& tl, const MrsTai
       if (e < NR * k) tl.cvt[e / k][e % k] = (double)(T)r.cvt;
 #pragma unroll
       for (int u = 0; u < R::NG; ++u)
-        if (e + u * WG < k * k) tl.gram[e + u * WG] = r.gram[u];
+        if (e + u * NT < k * k) tl.gram[e + u * NT] = r.gram[u];
     }
   }
 }

@@ -346,18 +346,27 @@ def test_mrs_fp32(case):
 
 
 @pytest.mark.parametrize("threads", [256, 512])
-def test_fp32_step_workgroup_size(case, threads):
-    """The one-column FP32 step with 256- and 512-thread workgroups, forced
-    (setup option step_threads; the default picks one from the row-block
-    count): 30-step FP32 mrs as above and P3 against the oracle."""
+def test_step_workgroup_size(case, threads):
+    """The one-column inner step with 256- and 512-thread workgroups, forced
+    for both precisions (setup option step_threads; the default picks per
+    precision): 30-step FP64 mrs as in test_mrs_fixed_steps, 30-step FP32 mrs
+    as in test_mrs_fp32, P1 and P3 against the oracle."""
     asss = _lib()
     S = case.st.S.tocsr()
     h = asss.setup(case.A, k=16, s_pattern="abar", reorder="grid", row_block=case.R, s_values=S.data,
                    q_basis=case.st.Q, q_alpha=case.st.alpha, step_threads=threads)
     try:
-        assert h.info()["step_threads"] == threads
+        info = h.info()
+        assert info["step_threads"] == threads and info["step_threads_fp64"] == threads
+        v = np.random.default_rng(5).standard_normal(case.n)
+        f = lambda: O.mrs(1.0, case.st.prec.jbar, v, 30, 0.0, fixed_steps=30)[0]
+        out, its = h.apply("mrs", _cuda(v), fixed_inner_steps=30)
+        assert its == 30
+        assert _rel(_np(out), f()) <= max(1e-12, 30 * _spread(case, f))
         _mrs_fp32_check(case, h)
         xo, _ = O.solve(case.st, case.w.b, O.SolveOptions(tol=1e-13))
+        x, info = h.solve(case.b, tol=1e-13)
+        assert info["status"] == "OK" and _rel(_np(x), xo) <= 1e-10
         x, info = h.solve(case.b, tol=1e-11, restart_m=200, inner_tol=0.2, inner_fp32=True)
         assert info["status"] == "OK" and info["relres_true"] <= 1e-11
         assert _rel(_np(x), xo) <= 1e-7
@@ -366,6 +375,8 @@ def test_fp32_step_workgroup_size(case, threads):
     with pytest.raises(asss.AsssError) as e:
         asss.setup(case.A, k=16, s_pattern="abar", step_threads=384)
     assert e.value.name == "INVALID_ARG"
+    # the default: 512 in FP64
+    assert case.hs.info()["step_threads_fp64"] == 512
 
 
 def test_mrs_tolerance_stop(case):
