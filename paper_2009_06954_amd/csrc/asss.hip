@@ -1003,10 +1003,11 @@ bool b_is_finite(asss_handle_s* h, const double* b, hipStream_t s) {
 }
 
 // One column of flexible GMRES(m) on the scaled system, with the stopping rule
-// of the oracle, as a state machine: the caller applies the preconditioner to
-// v_next() into z_next() and calls after_prec() (or step() does both); the
-// column restarts and finishes by itself.  Several columns can so share one
-// preconditioner call.  The Hessenberg matrix, its Givens rotations, the
+// of the oracle, as a state machine: step() runs one outer step of a single
+// column; lockstep columns instead apply the preconditioner to v_next() into
+// z_next() together, then each calls count_inner() and arnoldi_enqueue(),
+// and after one shared wait arnoldi_finish().  A column restarts and finishes
+// by itself.  The Hessenberg matrix, its Givens rotations, the
 // residual estimate and the stopping test live on the device (outer.hip, one
 // workspace per column); the host reads back a few flags per Arnoldi step.
 struct FgmresCol {
@@ -1116,14 +1117,6 @@ struct FgmresCol {
     hess_step(W, hbuf, nullptr, j, m, 0, thr, s);
     HIPCHK(hipMemcpyAsync(h->h_small + slot * SM_COL, hess_out(W), HESS_OUT * sizeof(double),
                           hipMemcpyDeviceToHost, s));
-  }
-
-  void after_prec(int its) {
-    Range range("asss:outer step");  // the whole Arnoldi step, GPU work and host round trip
-    count_inner(its);
-    arnoldi_enqueue();
-    HIPCHK(hipStreamSynchronize(s));
-    arnoldi_finish();
   }
 
   // One outer step of a single column with one host synchronization in the
