@@ -536,7 +536,8 @@ def main():
                    "k": args.k, "s_pattern": "abar", "tol": args.tol,
                    "outer": f"fgmres({args.restart})" if args.outer == "fgmres" else "tfqmr",
                    "inner_tol": args.inner_tol, "row_block": hi["row_block"],
-                   "inner_order": order_name, "deflation": args.deflation},
+                   "inner_order": order_name, "deflation": args.deflation,
+                   "step_threads": {"fp64": hi.get("step_threads_fp64"), "fp32": hi.get("step_threads")}},
         "roofline": roofline(inf64, 8, args.deflation),
         "solve": {"outer_its": inf64[-1]["outer_its"], "inner_its": inf64[-1]["inner_its_total"],
                   "reorth_passes": inf64[-1]["reorth"],

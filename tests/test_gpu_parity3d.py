@@ -375,8 +375,13 @@ def test_step_workgroup_size(case, threads):
     with pytest.raises(asss.AsssError) as e:
         asss.setup(case.A, k=16, s_pattern="abar", step_threads=384)
     assert e.value.name == "INVALID_ARG"
-    # the default: 512 in FP64
-    assert case.hs.info()["step_threads_fp64"] == 512
+    # the defaults: 512 in FP64; in FP32 512 when the blocks fill whole rounds of
+    # 2 workgroups per compute unit better, by more than 0.05, than of 4
+    info = case.hs.info()
+    assert info["step_threads_fp64"] == 512
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    fill = lambda slots: (info["nblocks"] / slots) / np.ceil(info["nblocks"] / slots)
+    assert info["step_threads"] == (512 if fill(2 * cus) > fill(4 * cus) + 0.05 else 256)
 
 
 def test_mrs_tolerance_stop(case):
