@@ -299,6 +299,42 @@ def test_full_cycle_of_250_steps():
     assert _rel(_np(x), xo) <= 1e-10
 
 
+@pytest.fixture(scope="module")
+def k20():
+    """The paper's default k = 20 (more than 16 vectors: the widest deflation
+    form of the one-column inner step, up to 32 basis vectors)."""
+    w = W.config(0)
+    A = O.validate_csr(w.A)
+    st = O.setup(A, O.SetupOptions(k=20))
+    return w, A, st
+
+
+@pytest.mark.parametrize("threads", [256, 512])
+def test_k20_inner_step(k20, threads):
+    """k = 20 with 256- and 512-thread workgroups, on the oracle's S and
+    Lanczos basis (20 unreorthogonalised Lanczos steps amplify rounding, so
+    the two sides' own bases differ by more than the kernels do): 30-step mrs
+    in FP64 (1e-12) and FP32 (1e-5) and P1 against the oracle."""
+    asss = _lib()
+    w, A, st = k20
+    S = st.S.tocsr()
+    h = asss.setup(A, k=20, step_threads=threads, s_values=S.data, q_basis=st.Q, q_alpha=st.alpha)
+    try:
+        info = h.info()
+        assert info["k_eff"] == 20 and info["step_threads_fp64"] == threads and info["step_threads"] == threads
+        v = np.random.default_rng(8).standard_normal(A.shape[0])
+        ref, _, _ = O.mrs(1.0, st.prec.jbar, v, 30, 0.0, fixed_steps=30)
+        out, its = h.apply("mrs", _cuda(v), fixed_inner_steps=30)
+        assert its == 30 and _rel(_np(out), ref) <= 1e-12
+        out, _ = h.apply("mrs", _cuda(v), fixed_inner_steps=30, inner_fp32=True)
+        assert _rel(_np(out), ref) <= 1e-5
+        xo, _ = O.solve(st, w.b, O.SolveOptions(tol=1e-13))
+        x, inf = h.solve(_cuda(w.b), tol=1e-13)
+        assert inf["status"] == "OK" and _rel(_np(x), xo) <= 1e-10
+    finally:
+        h.close()
+
+
 def test_solve_default_inner(cfg0):
     p = cfg0
     xo, io = O.solve(p.st, p.w.b, O.SolveOptions(tol=1e-8))
