@@ -283,10 +283,12 @@ def ildl_bench(args, asss, torch, np, W):
     ildl(1e-2) as in the paper's experiments) against the diagonal reading on
     implicit-Euler grids (the 45 x 45 grid of the small parity workload and a
     100 x 100 one), S tridiagonal, k = 8, tol 1e-8, FGMRES(64), inner
-    tolerance 1e-2; FP64.  Each inner step of the ILDL path is two
-    level-scheduled triangular solves in one workgroup, so its time is the
-    chain of levels: reported per level as well.  The oracle's ILDL solve of
-    the 45 x 45 grid is timed beside it."""
+    tolerance 1e-2; FP64.  The ILDL path runs both ways: with J_tilde formed
+    at setup ("ildl", the default at these sizes: the inner step is the fused
+    sliced kernel on the explicit operator) and with two level-scheduled
+    triangular solves in one workgroup per inner step ("ildl_levels", whose
+    time is the chain of levels: reported per level as well).  The oracle's
+    ILDL solve of the 45 x 45 grid is timed beside it."""
     import oracle as O
     from oracle.ildl import IldlOptions
     out = {"metric": "time-to-1e-8 rel. residual with the incomplete LDL^T preconditioner", "unit": "s",
@@ -296,7 +298,9 @@ def ildl_bench(args, asss, torch, np, W):
         w = W.implicit_euler_grid(m=m, h=0.1, cfg=0)
         b = torch.from_numpy(w.b).cuda()
         rec = {"workload": f"implicit_euler_{m}x{m}_h0.1", "n": int(w.A.shape[0]), "k": 8, "s_pattern": "tridiag"}
-        for name, skw in (("ildl", dict(precond="ildl", ildl_droptol=1e-2)), ("diag", {})):
+        for name, skw in (("ildl", dict(precond="ildl", ildl_droptol=1e-2, ildl_explicit=True)),
+                          ("ildl_levels", dict(precond="ildl", ildl_droptol=1e-2, ildl_explicit=False)),
+                          ("diag", {})):
             t0 = time.perf_counter()
             h = asss.setup(w.A, k=8, s_pattern="tridiag", **skw)
             torch.cuda.synchronize()
@@ -313,7 +317,7 @@ def ildl_bench(args, asss, torch, np, W):
             r = {"solve_s": round(best, 5), "setup_s": round(setup_s, 3), "outer_its": inf["outer_its"],
                  "inner_its": inf["inner_its_total"], "relres_true": inf["relres_true"], "rel_err_vs_xstar": err,
                  "inner_step_us": round(1e6 * inf["inner_kernel_s"] / max(1, inf["inner_its_total"]), 2)}
-            if name == "ildl":
+            if name == "ildl_levels":
                 hi = h.info()
                 lev = hi["ildl_levels_lower"] + hi["ildl_levels_upper"]
                 r.update(levels_lower=hi["ildl_levels_lower"], levels_upper=hi["ildl_levels_upper"],
@@ -322,6 +326,7 @@ def ildl_bench(args, asss, torch, np, W):
             log(f"{rec['workload']} {name}: {r}")
             h.close()
         rec["speedup_ildl_vs_diag"] = round(rec["diag"]["solve_s"] / rec["ildl"]["solve_s"], 3)
+        rec["speedup_explicit_vs_levels"] = round(rec["ildl_levels"]["solve_s"] / rec["ildl"]["solve_s"], 3)
         out["cases"].append(rec)
     out["value"] = out["cases"][0]["ildl"]["solve_s"]
     out["config"] = {"workload": out["cases"][0]["workload"], "precond": "ildl(1e-2)", "outer": "fgmres(64)",

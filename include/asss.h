@@ -228,6 +228,13 @@ typedef struct {
                               applied to each column before it updates the rest of the matrix */
   int32_t ildl_pivoting;   /* 1 (default): Bunch-Kaufman partial pivoting, alpha = (1 + sqrt 17)/8;
                               0: 1x1 pivots in the natural order */
+  int32_t ildl_explicit;   /* with precond = ASSS_PRECOND_ILDL: 1 forms J_tilde = Lcal^-1 J_hat_p
+                              Lcal^-T explicitly at setup (n columns of the two triangular solves
+                              around J_hat_p; it is dense in general, n^2 / 2 stored values) and
+                              runs the inner solve with the fused sliced kernels of the diagonal
+                              reading; 0 applies it as the two level-scheduled triangular solves
+                              in every inner step; -1 (default): 1 when n <= 12288.  The same
+                              operator up to rounding; other values: INVALID_ARG */
   int32_t step_threads;    /* workgroup size of the one-column inner step: 0 (default) chooses
                               512 in FP64, and in FP32 512 when its row blocks fill whole rounds
                               of 512 resident workgroups clearly better than of 1,024 (2 and 4
@@ -424,6 +431,7 @@ typedef struct {
   int64_t ildl_dropped;                   /* entries of L dropped by droptol and fill */
   int32_t step_threads;                   /* workgroup size of the one-column FP32 inner step */
   int32_t step_threads_fp64;              /* the same for the FP64 inner step */
+  int32_t ildl_explicit;                  /* 1: J_tilde of the incomplete LDL^T formed at setup */
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);

@@ -63,7 +63,8 @@ class SetupOpts(C.Structure):
                 ("allocator", C.c_void_p), ("autotune", C.c_int32), ("inner_perm", C.c_void_p),
                 ("skew_form", C.c_int32), ("s_val", C.c_void_p), ("q_basis", C.c_void_p),
                 ("q_alpha", C.c_void_p), ("precond", C.c_int32), ("ildl_droptol", C.c_double),
-                ("ildl_fill", C.c_double), ("ildl_pivoting", C.c_int32), ("step_threads", C.c_int32)]
+                ("ildl_fill", C.c_double), ("ildl_pivoting", C.c_int32), ("ildl_explicit", C.c_int32),
+                ("step_threads", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -126,7 +127,7 @@ class HandleInfo(C.Structure):
                 ("tune_rows", C.c_int32 * 8), ("tune_us", C.c_double * 8), ("tune_s", C.c_double),
                 ("precond", C.c_int32), ("ildl_n2x2", C.c_int32), ("ildl_levels_lower", C.c_int32),
                 ("ildl_levels_upper", C.c_int32), ("ildl_nnz_l", C.c_int64), ("ildl_dropped", C.c_int64),
-                ("step_threads", C.c_int32), ("step_threads_fp64", C.c_int32)]
+                ("step_threads", C.c_int32), ("step_threads_fp64", C.c_int32), ("ildl_explicit", C.c_int32)]
 
     def to_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -373,7 +374,8 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
           x_tol=1e-10, x_maxit=2000, lls_tol=1e-15, lls_maxit=20000, row_block=0, verbose=False,
           stream=None, canonicalize=True, deflation="auto", reorder="auto", allocator=None,
           autotune=False, skew_form="auto", s_values=None, q_basis=None, q_alpha=None, precond="diag",
-          ildl_droptol=0.0, ildl_fill=float("inf"), ildl_pivoting=True, step_threads=0) -> Handle:
+          ildl_droptol=0.0, ildl_fill=float("inf"), ildl_pivoting=True, ildl_explicit="auto",
+          step_threads=0) -> Handle:
     """Preprocess A (scipy CSR or torch sparse CSR on the CPU, float64) on the GPU.
     canonicalize: sum duplicates and sort column indices of a SciPy input first
     (otherwise the library rejects such input with INVALID_CSR).
@@ -398,7 +400,9 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     step; see asss_setup_opts_t.deflation).
     precond: "diag" (L = I, D = diag(A_hat)) or "ildl" (incomplete LDL^T of
     M_hat with Bunch-Kaufman pivoting; ildl_droptol, ildl_fill and
-    ildl_pivoting as in asss_setup_opts_t; reorder must stay "auto").
+    ildl_pivoting as in asss_setup_opts_t; reorder must stay "auto";
+    ildl_explicit: "auto", True (J_tilde formed at setup, inner steps on the
+    sliced kernels) or False (two triangular solves per inner step)).
     step_threads: workgroup size of the one-column inner step (0 = chosen
     per precision, 256 or 512 in both; asss_setup_opts_t)."""
     lib = load()
@@ -421,6 +425,7 @@ def setup(A, gamma=1.0, s_pattern="tridiag", k=20, lanczos_seed=0x2009069540, in
     o.skew_form = SKEW_FORMS[skew_form]
     o.precond = PRECONDS[precond]
     o.ildl_droptol, o.ildl_fill, o.ildl_pivoting = ildl_droptol, ildl_fill, int(bool(ildl_pivoting))
+    o.ildl_explicit = -1 if ildl_explicit == "auto" else int(bool(ildl_explicit))
     o.step_threads = int(step_threads)
     if s_values is not None:
         sv = np.ascontiguousarray(s_values, dtype=np.float64)

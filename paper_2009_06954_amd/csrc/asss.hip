@@ -449,7 +449,7 @@ struct InnerJob {
   void start(asss_handle_s* h_, bool fp32, const double* rhs, double* out, int sign, double tol, int maxit,
              int fixed, hipStream_t s, int expect = -1) {
     h = h_;
-    if (h->il.on) {
+    if (h->il.on && !h->il.explicit_j) {
       mode = fp32 ? 3 : 2;
       if (fp32) ildl_launch<float>(h, rhs, out, sign, tol, maxit, fixed, s);
       else ildl_launch<double>(h, rhs, out, sign, tol, maxit, fixed, s);
@@ -479,7 +479,7 @@ struct InnerJob {
 
 int inner_solve(asss_handle_s* h, bool fp32, const double* rhs, double* out, int sign, double tol,
                 int maxit, int fixed, hipStream_t s) {
-  Range range(h->il.on ? "asss:inner mrs (incomplete LDL^T)" : "asss:inner mrs");
+  Range range(h->il.on && !h->il.explicit_j ? "asss:inner mrs (incomplete LDL^T)" : "asss:inner mrs");
   InnerJob job;
   job.start(h, fp32, rhs, out, sign, tol, maxit, fixed, s);
   do {
@@ -883,7 +883,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
   }
   h->d_X = h->ar.alloc<double>(n * (int64_t)kr);
-  if (h->il.on) {  // X = S_bar^-1 U_bar column by column (one-workgroup inner solves)
+  if (h->il.on && !h->il.explicit_j) {  // X = S_bar^-1 U_bar column by column (one-workgroup inner solves)
     int xits = 0;
     for (int c = 0; c < kr; ++c)
       xits = std::max(xits, run_ildl_mrs<double>(h, h->d_Ubar + (int64_t)c * n, h->d_X + (int64_t)c * n, +1,
@@ -895,7 +895,7 @@ void device_setup(asss_handle_s* h, hipStream_t s) {
     for (int b = 0; b < 3; ++b) mb4.w[b] = tmp.alloc<double>(n * NRMAX);
     for (int b = 0; b < 2; ++b) mb4.p[b] = tmp.alloc<double>(n * NRMAX);
     mb4.x = tmp.alloc<double>(n * NRMAX);
-    const bool use4 = keff <= 16;
+    const bool use4 = keff <= 16 && !h->J64.dense;  // the 4-column step has no explicit form
     int xits = 0;
     for (int c0 = 0; c0 < kr; c0 += (use4 ? NRMAX : 1)) {
       const int nc = use4 ? std::min(NRMAX, kr - c0) : 1;
@@ -1605,6 +1605,8 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     if (o.skew_form < 0 || o.skew_form > 3) throw Error{ASSS_ERR_INVALID_ARG, "skew_form must be 0, 1, 2 or 3"};
     if (o.step_threads != 0 && o.step_threads != 256 && o.step_threads != 512)
       throw Error{ASSS_ERR_INVALID_ARG, "step_threads must be 0, 256 or 512"};
+    if (o.ildl_explicit < -1 || o.ildl_explicit > 1)
+      throw Error{ASSS_ERR_INVALID_ARG, "ildl_explicit must be -1, 0 or 1"};
     if (o.precond != ASSS_PRECOND_DIAG && o.precond != ASSS_PRECOND_ILDL)
       throw Error{ASSS_ERR_INVALID_ARG, "precond must be ASSS_PRECOND_DIAG or ASSS_PRECOND_ILDL"};
     if (o.precond == ASSS_PRECOND_ILDL) {
@@ -1816,6 +1818,7 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
       h->il.opts.fill = o.ildl_fill;
       h->il.opts.pivoting = o.ildl_pivoting != 0;
       ildl_setup(h.get(), Ahat, s);
+      if (o.ildl_explicit == 1 || (o.ildl_explicit < 0 && n <= 12288)) ildl_explicit_jtilde(h.get(), s);
     }
     const double t3 = now_s();
     phase.reset();
@@ -1877,6 +1880,7 @@ void asss_default_setup_opts(asss_setup_opts_t* o) {
   o->ildl_droptol = 0.0;
   o->ildl_fill = HUGE_VAL;
   o->ildl_pivoting = 1;
+  o->ildl_explicit = -1;
   o->step_threads = 0;
 }
 
@@ -2391,6 +2395,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     }
     i.step_threads = h->J32.threads > 0 ? h->J32.threads : WG;
     i.step_threads_fp64 = h->J64.threads > 0 ? h->J64.threads : WG;
+    i.ildl_explicit = h->il.explicit_j ? 1 : 0;
     *out = i;
     return ASSS_OK;
   });

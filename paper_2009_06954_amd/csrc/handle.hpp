@@ -206,6 +206,7 @@ struct asss_handle_s {
   // paper Sec. 3): the scaled system lives in the factorization's positions.
   struct Ildl {
     bool on = false;
+    bool explicit_j = false;  // J_tilde formed at setup: the inner solve runs the sliced kernels
     asss::IldlOpts opts;
     asss::IldlFactor F;     // perm, L, pivot blocks (host copy, for inspection)
     asss::IldlScaled Sc;    // Lcal, U_r, Sigma_r

@@ -236,6 +236,27 @@ __global__ __launch_bounds__(TRI_WG) void k_ildl_sandwich(DTri<T> Lb, DCsr32<T> 
   for (int i = threadIdx.x; i < n; i += TRI_WG) out[i] = (double)y[i];
 }
 
+// Columns j0, j0 + 1, ... of Lcal^-1 M Lcal^-T (M applied to the unit
+// vectors), one workgroup per column, each with four n-vectors of scratch of
+// its own (t0..t3 at scratch + 4 n b): many columns in flight at once.
+template <bool YLDS>
+__global__ __launch_bounds__(TRI_WG) void k_ildl_columns(DTri<double> Lb, DCsr32<double> M, DTri<double> Lf,
+                                                         int64_t j0, double* __restrict__ out, double* scratch) {
+  const int n = Lb.n;
+  const int64_t j = j0 + blockIdx.x;
+  double* t0 = scratch + (int64_t)blockIdx.x * 4 * n;
+  double* t1 = t0 + n;
+  double* t2 = t1 + n;
+  double* t3 = t2 + n;
+  double* y = YLDS ? tri_lds<double>() : t1;
+  for (int i = threadIdx.x; i < n; i += TRI_WG) t0[i] = (i == j) ? 1.0 : 0.0;
+  __syncthreads();
+  trsv_block<double, YLDS>(Lb, t0, y, t3);
+  spmv_block<double>(M, y, t2);
+  trsv_block<double, YLDS>(Lf, t2, y, t3);
+  for (int i = threadIdx.x; i < n; i += TRI_WG) out[j * n + i] = y[i];
+}
+
 template <bool YLDS>
 __global__ __launch_bounds__(TRI_WG) void k_ildl_trsv(DTri<double> F, const double* __restrict__ in,
                                                       double* __restrict__ out, double* __restrict__ bs) {
@@ -259,6 +280,16 @@ template void ildl_sandwich<double>(const DTri<double>&, const DCsr32<double>&, 
                                     const double*, double*, double*, double*, double*, double*, hipStream_t);
 template void ildl_sandwich<float>(const DTri<float>&, const DCsr32<float>&, const DTri<float>&,
                                    const double*, double*, float*, float*, float*, float*, hipStream_t);
+
+void ildl_columns(const DTri<double>& Lb, const DCsr32<double>& M, const DTri<double>& Lf, int64_t j0, int nc,
+                  double* out, double* scratch, hipStream_t s) {
+  if (nc <= 0) return;
+  if (Lb.n <= tri_lds_rows<double>())
+    hipLaunchKernelGGL((k_ildl_columns<true>), dim3(nc), dim3(TRI_WG), (size_t)Lb.n * sizeof(double), s, Lb, M, Lf,
+                       j0, out, scratch);
+  else
+    hipLaunchKernelGGL((k_ildl_columns<false>), dim3(nc), dim3(TRI_WG), 0, s, Lb, M, Lf, j0, out, scratch);
+}
 
 void ildl_trsv(const DTri<double>& F, const double* in, double* out, double* bs, hipStream_t s) {
   if (F.n <= tri_lds_rows<double>())

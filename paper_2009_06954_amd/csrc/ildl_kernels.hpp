@@ -67,6 +67,11 @@ template <typename T>
 void ildl_sandwich(const DTri<T>& Lb, const DCsr32<T>& M, const DTri<T>& Lf, const double* in, double* out,
                    T* t0, T* t1, T* t2, T* t3, hipStream_t s);
 
+// Columns j0 .. j0 + nc - 1 of Lcal^-1 M Lcal^-T in FP64, column j at
+// out + j n, nc workgroups at once; scratch: 4 n nc values.
+void ildl_columns(const DTri<double>& Lb, const DCsr32<double>& M, const DTri<double>& Lf, int64_t j0, int nc,
+                  double* out, double* scratch, hipStream_t s);
+
 // out = F^-1 in (FP64); in and out may not alias; bs: n values of scratch.
 void ildl_trsv(const DTri<double>& F, const double* in, double* out, double* bs, hipStream_t s);
 

@@ -184,5 +184,65 @@ void ildl_setup(asss_handle_s* h, const Csr& Ahat, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
+namespace {
+
+// D[i n + j] = (C[j n + i] - C[i n + j]) / 2 for column-major C (n x n):
+// row-major and exactly skew (fl(a - b) = -fl(b - a)).  Tiles of 32 x 32
+// through LDS so that both the reads and the writes are coalesced.
+__global__ void k_skew_part_rowmajor(int64_t n, const double* __restrict__ C, double* __restrict__ D) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows of 32
+  // tile[a][b] = C[(j0 + a) n + i0 + b] = J[i0 + b][j0 + a]
+  for (int a = ty; a < 32; a += 8) {
+    const int64_t j = j0 + a, i = i0 + tx;
+    tile[a][tx] = (j < n && i < n) ? C[j * n + i] : 0.0;
+  }
+  __syncthreads();
+  // row i = i0 + a, column j = j0 + tx: (C[j n + i] - C[i n + j]) / 2
+  for (int a = ty; a < 32; a += 8) {
+    const int64_t i = i0 + a, j = j0 + tx;
+    if (i < n && j < n) D[i * n + j] = 0.5 * (tile[tx][a] - C[i * n + j]);
+  }
+}
+
+}  // namespace
+
+void ildl_explicit_jtilde(asss_handle_s* h, hipStream_t s) {
+  auto& il = h->il;
+  const int64_t n = h->n;
+  double* C = h->ar.alloc<double>(n * n);
+  // up to 512 columns at a time, one workgroup each
+  const int64_t B = std::min<int64_t>(n, 512);
+  double* scratch = h->ar.alloc<double>(4 * n * B);
+  for (int64_t j0 = 0; j0 < n; j0 += B)
+    ildl_columns(il.Lb64, il.J64, il.Lf64, j0, (int)std::min<int64_t>(B, n - j0), C, scratch, s);
+  double* D64 = h->ar.alloc<double>(n * n);
+  float* D32 = h->ar.alloc<float>(n * n);
+  const unsigned gt = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_skew_part_rowmajor, dim3(gt, gt), dim3(256), 0, s, n, C, D64);
+  cast_d2f(n * n, D64, D32, s);
+  HIPCHK(hipStreamSynchronize(s));
+  h->ar.release(C);
+  h->ar.release(scratch);
+  // row blocks of R rows (a multiple of 8), at most about 512 blocks, one
+  // wave per row within a block
+  const int64_t R = std::max<int64_t>(8, 8 * ((n + 8 * 512 - 1) / (8 * 512)));
+  const int32_t nb = (int32_t)((n + R - 1) / R);
+  if (nb > h->red.max_groups) throw Error{ASSS_ERR_INTERNAL, "more row blocks than reduction slots"};
+  DSkew<double> J64;
+  DSkew<float> J32;
+  J64.n = J32.n = (int32_t)n;
+  J64.R = J32.R = (int32_t)R;
+  J64.nblocks = J32.nblocks = nb;
+  J64.dense = D64;
+  J32.dense = D32;
+  J64.dense_ld = J32.dense_ld = n;
+  h->J64 = J64;
+  h->J32 = J32;
+  h->lay_bufs = {D64, D32};
+  il.explicit_j = true;
+}
+
 }  // namespace host
 }  // namespace asss

@@ -395,6 +395,41 @@ __device__ __forceinline__ void skew_block_pass_form(const DSkew<T>& J, int64_t 
   }
 }
 
+// The explicit (dense) operator: acc_lds[il] = sum_j J[row0 + il][j] w_j for
+// the block's rows, one wave per row (rows round-robin over the waves), the
+// lanes over the columns with coalesced loads of the row, eight loads in
+// flight per lane, a wave sum in a fixed order.
+template <typename T, int NR, int NT>
+__device__ __forceinline__ void dense_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
+                                                 const T* __restrict__ wg, double* acc_lds) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t n = J.n;
+  for (int r = wave; r < nrow; r += NT / 64) {
+    const T* __restrict__ row = J.dense + (row0 + r) * J.dense_ld;
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    int64_t j = lane;
+    for (; j + 7 * 64 < n; j += 8 * 64) {
+      T a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&row[j + u * 64]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] += (double)a[u] * (double)wg[(j + u * 64) * NR + c];
+    }
+    for (; j < n; j += 64)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] += (double)row[j] * (double)wg[j * NR + c];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const double sum = wave_sum(acc[c]);
+      if (lane == 0) acc_lds[r * NR + c] = sum;
+    }
+  }
+}
+
 // The column form is fixed per matrix: one uniform branch per launch.
 template <typename T, int NR, bool STAGE, int NT = WG>
 __device__ __forceinline__ void skew_block_pass(const DSkew<T>& J, int64_t row0, int nrow,
@@ -952,7 +987,7 @@ __global__ __launch_bounds__(WG) void k_mrs_init_batched(MrsBatch B, int R, cons
 // block g at j * ng + g) and whose last block, found with `ticket`, runs the
 // scalar recurrence.  Shared by the one-system kernel (one block per
 // workgroup) and the batched work-queue kernel (blocks of many systems).
-template <typename T, int NR, int KF, bool STAGE, typename TQ, int NT = WG>
+template <typename T, int NR, int KF, bool STAGE, typename TQ, int NT = WG, bool DENSE = false>
 __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T>& J, const MrsBufs<T>& buf,
                                                MrsState* st, double* partials, unsigned* ticket,
                                                int64_t row0, int nrow, int g, int ng, double* acc_lds,
@@ -1030,7 +1065,8 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
   }
   mrs_tail_store<T, NR, KF, NT>(tail, tail_r, k);  // status is MRS_RUNNING here
   __syncthreads();
-  skew_block_pass<T, NR, STAGE, NT>(J, row0, nrow, wcur, w_lds, acc_lds);
+  if constexpr (DENSE) dense_block_pass<T, NR, NT>(J, row0, nrow, wcur, acc_lds);
+  else skew_block_pass<T, NR, STAGE, NT>(J, row0, nrow, wcur, w_lds, acc_lds);
   __syncthreads();
 
   double acc[NV];
@@ -1154,7 +1190,7 @@ __device__ __forceinline__ void mrs_iter_block(const MrsLaunch& L, const DSkew<T
 // 512-thread ones) and loses a little where both fill them; the FP64 step
 // gains a little at both 128^3 and 192^3.
 
-template <typename T, int NR, int KF, bool STAGE, typename TQ = T, int NT = WG>
+template <typename T, int NR, int KF, bool STAGE, typename TQ = T, int NT = WG, bool DENSE = false>
 __global__ __launch_bounds__(NT, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(MrsLaunch L, DSkew<T> J, const T* __restrict__ Q,
                                                  MrsBufs<T> buf, MrsState* st, double* partials,
                                                  unsigned* ticket) {
@@ -1166,8 +1202,8 @@ __global__ __launch_bounds__(NT, (NR == 1 && KF <= 16) ? 4 : 1) void k_mrs_iter(
   T* w_lds = reinterpret_cast<T*>(acc_lds + (size_t)J.R * NR);
   const int64_t row0 = (int64_t)xcd_block<T>() * J.R;
   const int nrow = (int)min((int64_t)J.R, L.n - row0);
-  mrs_iter_block<T, NR, KF, STAGE, TQ, NT>(L, J, buf, st, partials, ticket, row0, nrow, blockIdx.x, gridDim.x,
-                                           acc_lds, w_lds, true);
+  mrs_iter_block<T, NR, KF, STAGE, TQ, NT, DENSE>(L, J, buf, st, partials, ticket, row0, nrow, blockIdx.x,
+                                                  gridDim.x, acc_lds, w_lds, true);
 }
 
 // The batched inner step: one launch advances the inner solves of every
@@ -1261,6 +1297,12 @@ void mrs_iter(const MrsLaunch& L, const DSkew<T>& J, const T* Q, MrsBufs<T>& buf
       }                                                                                                \
     }                                                                                                  \
     if constexpr (NR == 1) {                                                                           \
+      if (J.dense) {                                                                                   \
+        hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, false, T, WG, true>), dim3(J.nblocks), dim3(WG),      \
+                           (size_t)J.R * NR * sizeof(double), s, L, J, Q, buf, st, red.partials,         \
+                           red.tickets + 1);                                                           \
+        break;                                                                                         \
+      }                                                                                                \
       if (J.threads == 2 * WG) {                                                                       \
         hipLaunchKernelGGL((k_mrs_iter<T, NR, KF, STAGE, T, 2 * WG>), dim3(J.nblocks), dim3(2 * WG), lds, \
                            s, L, J, Q, buf, st, red.partials, red.tickets + 1);                        \

@@ -37,6 +37,10 @@ struct DSkew {
   int32_t b_narrow = 0;
   int32_t form = 1;                 // 1: 32-bit part-b columns, 2: 16-bit deltas, 3: offset slots
   int32_t threads = 0;              // workgroup size of the one-column FP32 inner step (0: 256)
+  // explicit form (dense != nullptr): J_tilde row-major, n x n, leading
+  // dimension dense_ld, exactly skew; the block pass is a dense row product
+  const T* dense = nullptr;
+  int64_t dense_ld = 0;
   const T* a_val = nullptr;
   const T* b_val = nullptr;
 };

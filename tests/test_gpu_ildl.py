@@ -88,10 +88,11 @@ CASES = {
 
 
 class Case:
-    def __init__(self, name):
+    def __init__(self, name, explicit):
         asss = _lib()
         build, kw, so, io, self.optol, self.soltol = CASES[name]
         self.name = name
+        self.explicit = explicit
         self.A = O.validate_csr(build())
         self.n = self.A.shape[0]
         print(f"[ildl] {name}: n={self.n} oracle setup", flush=True)
@@ -103,7 +104,7 @@ class Case:
         # dropping threshold; the factorization is then compared on one M_hat
         S = self.st.S.tocsr()
         S.sort_indices()
-        kw = dict(kw, s_values=S.data)
+        kw = dict(kw, s_values=S.data, ildl_explicit=explicit)
         self.h = asss.setup(self.A, precond="ildl", ildl_droptol=io.droptol, ildl_fill=io.fill,
                             ildl_pivoting=io.pivoting, **kw)
         # the same handle with the oracle's deflation basis (positions): the
@@ -114,9 +115,13 @@ class Case:
         self.rng = np.random.default_rng(7)
 
 
-@pytest.fixture(scope="module", params=list(CASES))
+# every case with J_tilde applied as two level-scheduled triangular solves per
+# inner step, and with J_tilde formed at setup (the sliced fused inner step)
+@pytest.fixture(scope="module", params=[(name, ex) for name in CASES for ex in (False, True)],
+                ids=lambda p: f"{p[0]}-{'explicit' if p[1] else 'levels'}")
 def case(request):
-    c = Case(request.param)
+    c = Case(*request.param)
+    assert c.h.info()["ildl_explicit"] == int(c.explicit)
     yield c
     c.h.close()
     c.hq.close()
