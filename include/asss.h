@@ -229,12 +229,14 @@ typedef struct {
   int32_t ildl_pivoting;   /* 1 (default): Bunch-Kaufman partial pivoting, alpha = (1 + sqrt 17)/8;
                               0: 1x1 pivots in the natural order */
   int32_t ildl_explicit;   /* with precond = ASSS_PRECOND_ILDL: 1 forms J_tilde = Lcal^-1 J_hat_p
-                              Lcal^-T explicitly at setup (n columns of the two triangular solves
-                              around J_hat_p; it is dense in general, n^2 / 2 stored values) and
-                              runs the inner solve with the fused sliced kernels of the diagonal
-                              reading; 0 applies it as the two level-scheduled triangular solves
-                              in every inner step; -1 (default): 1 when n <= 12288.  The same
-                              operator up to rounding; other values: INVALID_ARG */
+                              Lcal^-T and the outer operator Lcal^-1 A_hat_p Lcal^-T explicitly at
+                              setup (n columns each of the two triangular solves around J_hat_p,
+                              A_hat_p; dense in general: 3.5 n^2 doubles of device memory), runs
+                              the inner solve with the fused kernel of the diagonal reading on the
+                              dense J_tilde and the outer products as dense row products; 0
+                              applies both as two level-scheduled triangular solves per product;
+                              -1 (default): 1 when n <= 12288.  The same operators up to
+                              rounding; other values: INVALID_ARG */
   int32_t step_threads;    /* workgroup size of the one-column inner step: 0 (default) chooses
                               512 in FP64, and in FP32 512 when its row blocks fill whole rounds
                               of 512 resident workgroups clearly better than of 1,024 (2 and 4

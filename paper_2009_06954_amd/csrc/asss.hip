@@ -191,7 +191,8 @@ double dot_host(asss_handle_s* h, int64_t n, const double* a, const double* b, h
 void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
   if (h->il.on) {
     auto& il = h->il;
-    ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
+    if (il.A_rows) dense_rows(h->n, il.A_rows, z, w, s);
+    else ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
   spmv(h->dS, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
@@ -201,7 +202,8 @@ void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
 void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
   if (h->il.on) {
     auto& il = h->il;
-    ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
+    if (il.AT_rows) dense_rows(h->n, il.AT_rows, z, w, s);
+    else ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
   spmv(h->dAbarT, z, h->t1, nullptr, h->d_om, 0, nullptr, s);

@@ -207,6 +207,8 @@ struct asss_handle_s {
   struct Ildl {
     bool on = false;
     bool explicit_j = false;  // J_tilde formed at setup: the inner solve runs the sliced kernels
+    double* A_rows = nullptr;   // with explicit_j: A_chk = Lcal^-1 A_hat_p Lcal^-T row-major
+    double* AT_rows = nullptr;  // and A_chk^T row-major (A_chk column-major)
     asss::IldlOpts opts;
     asss::IldlFactor F;     // perm, L, pivot blocks (host copy, for inspection)
     asss::IldlScaled Sc;    // Lcal, U_r, Sigma_r

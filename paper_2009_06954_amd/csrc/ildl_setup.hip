@@ -189,6 +189,22 @@ namespace {
 // D[i n + j] = (C[j n + i] - C[i n + j]) / 2 for column-major C (n x n):
 // row-major and exactly skew (fl(a - b) = -fl(b - a)).  Tiles of 32 x 32
 // through LDS so that both the reads and the writes are coalesced.
+// D = C^T (both n x n): tiles of 32 x 32 through LDS.
+__global__ void k_transpose(int64_t n, const double* __restrict__ C, double* __restrict__ D) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int a = ty; a < 32; a += 8) {
+    const int64_t j = j0 + a, i = i0 + tx;
+    tile[a][tx] = (j < n && i < n) ? C[j * n + i] : 0.0;
+  }
+  __syncthreads();
+  for (int a = ty; a < 32; a += 8) {
+    const int64_t i = i0 + a, j = j0 + tx;
+    if (i < n && j < n) D[i * n + j] = tile[tx][a];
+  }
+}
+
 __global__ void k_skew_part_rowmajor(int64_t n, const double* __restrict__ C, double* __restrict__ D) {
   __shared__ double tile[32][33];
   const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
@@ -223,7 +239,16 @@ void ildl_explicit_jtilde(asss_handle_s* h, hipStream_t s) {
   hipLaunchKernelGGL(k_skew_part_rowmajor, dim3(gt, gt), dim3(256), 0, s, n, C, D64);
   cast_d2f(n * n, D64, D32, s);
   HIPCHK(hipStreamSynchronize(s));
-  h->ar.release(C);
+  // the outer operator the same way: A_chk column-major from the columns
+  // (which is A_chk^T row-major) and its transpose (A_chk row-major)
+  double* CA = h->ar.alloc<double>(n * n);
+  for (int64_t j0 = 0; j0 < n; j0 += B)
+    ildl_columns(il.Lb64, il.Ap, il.Lf64, j0, (int)std::min<int64_t>(B, n - j0), CA, scratch, s);
+  double* RA = C;  // the columns of J_tilde are no longer needed
+  hipLaunchKernelGGL(k_transpose, dim3(gt, gt), dim3(256), 0, s, n, CA, RA);
+  HIPCHK(hipStreamSynchronize(s));
+  il.A_rows = RA;
+  il.AT_rows = CA;
   h->ar.release(scratch);
   // row blocks of R rows (a multiple of 8), at most about 512 blocks, one
   // wave per row within a block

@@ -19,7 +19,9 @@ void ildl_setup(asss_handle_s* h, const Csr& Ahat, hipStream_t s);
 // ildl_setup): column j is the two triangular solves around J_hat_p applied
 // to e_j; the stored operator is (C - C^T) / 2 of those columns C, exactly
 // skew, row-major, in FP64 and FP32, with row blocks for the fused inner
-// step (h->J64, h->J32 with dense set).  Sets h->il.explicit_j.
+// step (h->J64, h->J32 with dense set).  The outer operator A_chk = Lcal^-1
+// A_hat_p Lcal^-T likewise, row-major, and its transpose (h->il.A_rows,
+// AT_rows).  Sets h->il.explicit_j.
 void ildl_explicit_jtilde(asss_handle_s* h, hipStream_t s);
 
 }  // namespace host

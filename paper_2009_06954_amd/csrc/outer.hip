@@ -5,7 +5,8 @@
 // small triangular solve for the combination of the preconditioned vectors.
 // The work is O(j) per step (j <= 250) and sequential: one wavefront per
 // column, and the rotation chain in one lane, so the result does not depend
-// on timing.
+// on timing.  Also the dense outer operator of the incomplete LDL^T formed
+// at setup (dense_rows).
 #include <hip/hip_runtime.h>
 
 #include "outer_kernels.hpp"
@@ -177,7 +178,32 @@ __global__ void __launch_bounds__(64) k_hess_solve_batched(double* W, int cap, i
   solve_column(W + (int64_t)q * hess_slot(cap), L, ju, m, y + (int64_t)q * m);
 }
 
+__global__ void __launch_bounds__(256) k_dense_rows(int64_t n, const double* __restrict__ M,
+                                                    const double* __restrict__ x, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  const double* __restrict__ row = M + r * n;
+  double acc = 0.0;
+  int64_t j = lane;
+  for (; j + 7 * 64 < n; j += 8 * 64) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&row[j + u * 64]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += a[u] * x[j + u * 64];
+  }
+  for (; j < n; j += 64) acc += row[j] * x[j];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[r] = acc;
+}
+
 }  // namespace
+
+void dense_rows(int64_t n, const double* M, const double* x, double* y, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_dense_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, M, x, y);
+}
 
 double* hess_out(double* W) { return W + Lay{HESS_MMAX}.out(); }
 double* hess_y(double* W) { return W + Lay{HESS_MMAX}.y(); }

@@ -48,4 +48,8 @@ void hess_step_batched(double* W, int cap, int m, int ncol, const int32_t* jv, c
                        const double* thr, double* out, hipStream_t s);
 void hess_solve_batched(double* W, int cap, int m, int ncol, const int32_t* jused, double* y, hipStream_t s);
 
+// y = M x for a dense row-major n x n matrix M (leading dimension n): one
+// wave per row, coalesced row loads, a fixed summation order.
+void dense_rows(int64_t n, const double* M, const double* x, double* y, hipStream_t s);
+
 }  // namespace asss
