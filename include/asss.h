@@ -263,8 +263,9 @@ typedef struct {
   int32_t batch_engine;    /* asss_solve_batched only: 0 (default) = all systems in one lockstep
                               (rows of all systems concatenated; one persistent work-queue
                               launch per inner step for every system, captured in HIP graph
-                              chunks; segmented outer kernels; one host round trip per outer
-                              step for all columns) when every system qualifies (FGMRES from
+                              chunks; segmented outer kernels; the Hessenberg updates of all
+                              columns on the device; one host round trip per outer step for
+                              all columns) when every system qualifies (FGMRES from
                               zero, no fixed inner steps, <= 4 right-hand sides, k <= 16,
                               k + r <= 256, natural inner order, one device, one inner
                               precision), else per-system workers; 1 = the lockstep engine or
