@@ -235,8 +235,9 @@ typedef struct {
                               the inner solve with the fused kernel of the diagonal reading on the
                               dense J_tilde and the outer products as dense row products; 0
                               applies both as two level-scheduled triangular solves per product;
-                              -1 (default): 1 when n <= 12288.  The same operators up to
-                              rounding; other values: INVALID_ARG */
+                              -1 (default): 1 when n <= 12288 and the device memory holds them
+                              (else 0).  The same operators up to rounding; other values:
+                              INVALID_ARG */
   int32_t step_threads;    /* workgroup size of the one-column inner step: 0 (default) chooses
                               512 in FP64, and in FP32 512 when its row blocks fill whole rounds
                               of 512 resident workgroups clearly better than of 1,024 (2 and 4

@@ -1820,7 +1820,16 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
       h->il.opts.fill = o.ildl_fill;
       h->il.opts.pivoting = o.ildl_pivoting != 0;
       ildl_setup(h.get(), Ahat, s);
-      if (o.ildl_explicit == 1 || (o.ildl_explicit < 0 && n <= 12288)) ildl_explicit_jtilde(h.get(), s);
+      if (o.ildl_explicit == 1) {
+        ildl_explicit_jtilde(h.get(), s);
+      } else if (o.ildl_explicit < 0 && n <= 12288) {
+        try {  // by default: the triangular solves per product when the dense operators do not fit
+          ildl_explicit_jtilde(h.get(), s);
+        } catch (const Error& e) {
+          if (e.code != ASSS_ERR_OOM) throw;
+          (void)hipGetLastError();
+        }
+      }
     }
     const double t3 = now_s();
     phase.reset();

@@ -227,21 +227,30 @@ __global__ void k_skew_part_rowmajor(int64_t n, const double* __restrict__ C, do
 void ildl_explicit_jtilde(asss_handle_s* h, hipStream_t s) {
   auto& il = h->il;
   const int64_t n = h->n;
-  double* C = h->ar.alloc<double>(n * n);
   // up to 512 columns at a time, one workgroup each
   const int64_t B = std::min<int64_t>(n, 512);
-  double* scratch = h->ar.alloc<double>(4 * n * B);
+  // every buffer first, so that a failed allocation leaves nothing behind
+  double *C = nullptr, *scratch = nullptr, *D64 = nullptr, *CA = nullptr;
+  float* D32 = nullptr;
+  try {
+    C = h->ar.alloc<double>(n * n);
+    scratch = h->ar.alloc<double>(4 * n * B);
+    D64 = h->ar.alloc<double>(n * n);
+    D32 = h->ar.alloc<float>(n * n);
+    CA = h->ar.alloc<double>(n * n);
+  } catch (...) {
+    for (void* p : {(void*)C, (void*)scratch, (void*)D64, (void*)D32, (void*)CA})
+      if (p) h->ar.release(p);
+    throw;
+  }
   for (int64_t j0 = 0; j0 < n; j0 += B)
     ildl_columns(il.Lb64, il.J64, il.Lf64, j0, (int)std::min<int64_t>(B, n - j0), C, scratch, s);
-  double* D64 = h->ar.alloc<double>(n * n);
-  float* D32 = h->ar.alloc<float>(n * n);
   const unsigned gt = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL(k_skew_part_rowmajor, dim3(gt, gt), dim3(256), 0, s, n, C, D64);
   cast_d2f(n * n, D64, D32, s);
   HIPCHK(hipStreamSynchronize(s));
   // the outer operator the same way: A_chk column-major from the columns
   // (which is A_chk^T row-major) and its transpose (A_chk row-major)
-  double* CA = h->ar.alloc<double>(n * n);
   for (int64_t j0 = 0; j0 < n; j0 += B)
     ildl_columns(il.Lb64, il.Ap, il.Lf64, j0, (int)std::min<int64_t>(B, n - j0), CA, scratch, s);
   double* RA = C;  // the columns of J_tilde are no longer needed
