@@ -436,6 +436,9 @@ typedef struct {
   int32_t step_threads;                   /* workgroup size of the one-column FP32 inner step */
   int32_t step_threads_fp64;              /* the same for the FP64 inner step */
   int32_t ildl_explicit;                  /* 1: J_tilde of the incomplete LDL^T formed at setup */
+  int32_t outer_ell;                      /* 1: the outer operator's products Abar, S (and their
+                                             transposes) read sliced ELL copies, 64-row slices with
+                                             at most 16 slots (rows that short) */
 } asss_handle_info_t;
 
 asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out);

@@ -127,7 +127,8 @@ class HandleInfo(C.Structure):
                 ("tune_rows", C.c_int32 * 8), ("tune_us", C.c_double * 8), ("tune_s", C.c_double),
                 ("precond", C.c_int32), ("ildl_n2x2", C.c_int32), ("ildl_levels_lower", C.c_int32),
                 ("ildl_levels_upper", C.c_int32), ("ildl_nnz_l", C.c_int64), ("ildl_dropped", C.c_int64),
-                ("step_threads", C.c_int32), ("step_threads_fp64", C.c_int32), ("ildl_explicit", C.c_int32)]
+                ("step_threads", C.c_int32), ("step_threads_fp64", C.c_int32), ("ildl_explicit", C.c_int32),
+                ("outer_ell", C.c_int32)]
 
     def to_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -82,6 +82,82 @@ DCsr upload_csr(DevArena& ar, const Csr& M, hipStream_t s) {
   return d;
 }
 
+// Sliced ELL layout of M (described with DSell); false when a row is longer
+// than SELL_MAXW or M holds no values.
+bool ell_layout(const Csr& M, std::vector<int32_t>& width, std::vector<int64_t>& off, std::vector<int32_t>& col,
+                std::vector<double>& val) {
+  const int64_t n = M.nrows, ns = (n + 63) / 64;
+  if ((int64_t)M.val.size() != M.nnz()) return false;
+  width.assign(ns, 0);
+  off.assign(ns, 0);
+  int64_t total = 0;
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int64_t w = 0;
+    for (int64_t i = sl * 64; i < std::min(n, sl * 64 + 64); ++i) w = std::max(w, M.ptr[i + 1] - M.ptr[i]);
+    if (w > SELL_MAXW) return false;
+    width[sl] = (int32_t)w;
+    off[sl] = total;
+    total += 64 * w;
+  }
+  col.assign(total, 0);
+  val.assign(total, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t sl = i / 64, l = i % 64, b = M.ptr[i], e = M.ptr[i + 1];
+    for (int64_t u = 0; u < width[sl]; ++u) {
+      const int64_t q = off[sl] + 64 * u + l;
+      if (b + u < e) {
+        col[q] = M.col[b + u];
+        val[q] = M.val[b + u];
+      } else if (e > b) {
+        col[q] = M.col[b];
+      }
+    }
+  }
+  return true;
+}
+
+// Device copy in the sliced ELL layout, or none (nrows 0) when M does not fit
+// it or device memory runs out (what was allocated for it is released).
+DSell upload_ell(DevArena& ar, const Csr& M, hipStream_t s) {
+  DSell d;
+  std::vector<int32_t> w, c;
+  std::vector<int64_t> o;
+  std::vector<double> v;
+  if (M.nrows == 0 || !ell_layout(M, w, o, c, v) || v.empty()) return d;
+  void* got[4] = {nullptr, nullptr, nullptr, nullptr};
+  try {
+    int32_t* dw = ar.upload(w, s);
+    got[0] = dw;
+    int64_t* dof = ar.upload(o, s);
+    got[1] = dof;
+    int32_t* dc = ar.upload(c, s);
+    got[2] = dc;
+    double* dv = ar.upload(v, s);
+    got[3] = dv;
+    d.width = dw;
+    d.off = dof;
+    d.col = dc;
+    d.val = dv;
+  } catch (const Error& e) {
+    if (e.code != ASSS_ERR_OOM) throw;
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* p : got)
+      if (p) ar.release(p);
+    return DSell{};
+  }
+  d.nrows = M.nrows;
+  d.entries = (int64_t)v.size();
+  HIPCHK(hipStreamSynchronize(s));  // the host arrays go out of scope
+  return d;
+}
+
+// y = rs o (M (cs o x)), through the sliced ELL copy E when there is one
+void spmv_outer(const DCsr& M, const DSell& E, const double* x, double* y, const double* rs, const double* cs,
+                hipStream_t s) {
+  if (E.nrows > 0) spmv_sell(E, x, y, rs, cs, s);
+  else spmv(M, x, y, rs, cs, 0, nullptr, s);
+}
+
 template <typename T>
 DSkew<T> upload_sell(DevArena& ar, const SkewSell& S, hipStream_t s, const int32_t* aw,
                      const int32_t* bw, const int64_t* ao, const int64_t* bo, const uint16_t* ac,
@@ -195,8 +271,8 @@ void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
     else ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
-  spmv(h->dS, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
-  spmv(h->dAbar, h->t1, w, h->d_om, nullptr, 0, nullptr, s);
+  spmv_outer(h->dS, h->eS, z, h->t1, nullptr, h->d_om, s);
+  spmv_outer(h->dAbar, h->eAbar, h->t1, w, h->d_om, nullptr, s);
 }
 // w = (Omega Abar S Omega)^T z = Omega S^T Abar^T Omega z
 void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
@@ -206,8 +282,8 @@ void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
     else ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
-  spmv(h->dAbarT, z, h->t1, nullptr, h->d_om, 0, nullptr, s);
-  spmv(h->dSt, h->t1, w, h->d_om, nullptr, 0, nullptr, s);
+  spmv_outer(h->dAbarT, h->eAbarT, z, h->t1, nullptr, h->d_om, s);
+  spmv_outer(h->dSt, h->eSt, h->t1, w, h->d_om, nullptr, s);
 }
 
 // Right-hand side of the scaled system: b_chk = Omega P Dr b, or for the
@@ -227,7 +303,7 @@ void rhs_transform(asss_handle_s* h, bool adjoint, const double* b, double* bchk
     return;
   }
   if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, bchk, s);
-  else spmv(h->dSt, b, bchk, h->d_om, h->d_dc, 0, nullptr, s);  // g_chk = Omega S^T (Dc o g)
+  else spmv_outer(h->dSt, h->eSt, b, bchk, h->d_om, h->d_dc, s);  // g_chk = Omega S^T (Dc o g)
 }
 
 // Solution from the scaled one: x = Dc S Omega x_chk, or for the adjoint
@@ -243,7 +319,7 @@ void back_transform(asss_handle_s* h, bool adjoint, const double* xchk, double* 
     else scatter_scale(n, h->d_m, h->d_drp, il.d_ones, h->tmp, x, s);
     return;
   }
-  if (!adjoint) spmv(h->dS, xchk, x, h->d_dc, h->d_om, 0, nullptr, s);
+  if (!adjoint) spmv_outer(h->dS, h->eS, xchk, x, h->d_dc, h->d_om, s);
   else scatter_scale(n, h->d_m, h->d_drp, h->d_om, xchk, x, s);
 }
 
@@ -1788,6 +1864,12 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->dAbarT = upload_csr(h->ar, transpose(Abar), s);
     h->dS = upload_csr(h->ar, h->S, s);
     h->dSt = upload_csr(h->ar, transpose(h->S), s);
+    if (!ildl) {
+      h->eAbar = upload_ell(h->ar, Abar, s);
+      h->eAbarT = upload_ell(h->ar, transpose(Abar), s);
+      h->eS = upload_ell(h->ar, h->S, s);
+      h->eSt = upload_ell(h->ar, transpose(h->S), s);
+    }
     h->d_m = h->ar.upload(h->m, s);
     if (reordered) h->d_perm = h->ar.upload(h->perm, s);
     std::vector<double> drp(n);
@@ -1998,6 +2080,16 @@ asss_status_t asss_update_values(asss_handle_t h, const asss_csr_t* A, void* hip
       if (src[q]->nnz() != dst[q]->nnz) throw Error{ASSS_ERR_INTERNAL, "stored pattern changed"};
       HIPCHK(hipMemcpyAsync(dst[q]->val, src[q]->val.data(), src[q]->nnz() * sizeof(double),
                             hipMemcpyHostToDevice, s));
+    }
+    std::vector<int32_t> ew, ec;
+    std::vector<int64_t> eo;
+    std::vector<double> ev[2];
+    const DSell* edst[2] = {&h->eAbar, &h->eAbarT};
+    for (int q = 0; q < 2; ++q) {
+      if (edst[q]->nrows == 0) continue;
+      if (!ell_layout(*src[2 + q], ew, eo, ec, ev[q]) || (int64_t)ev[q].size() != edst[q]->entries)
+        throw Error{ASSS_ERR_INTERNAL, "stored pattern changed"};
+      HIPCHK(hipMemcpyAsync(edst[q]->val, ev[q].data(), ev[q].size() * sizeof(double), hipMemcpyHostToDevice, s));
     }
     HIPCHK(hipStreamSynchronize(s));  // the host arrays go out of scope
     return ASSS_OK;
@@ -2407,6 +2499,7 @@ asss_status_t asss_get_handle_info(asss_handle_t h, asss_handle_info_t* out) {
     i.step_threads = h->J32.threads > 0 ? h->J32.threads : WG;
     i.step_threads_fp64 = h->J64.threads > 0 ? h->J64.threads : WG;
     i.ildl_explicit = h->il.explicit_j ? 1 : 0;
+    i.outer_ell = h->eAbar.nrows > 0 ? 1 : 0;
     *out = i;
     return ASSS_OK;
   });

@@ -144,6 +144,8 @@ struct asss_handle_s {
   double setup_host_s = 0, setup_device_s = 0;
   // device data
   DCsr dA, dAt, dAbar, dAbarT, dS, dSt;
+  // sliced ELL copies of the outer operator's factors (nrows 0: CSR only)
+  asss::DSell eAbar, eAbarT, eS, eSt;
   Csr Apat;  // pattern of A as stored (explicit zeros dropped), for value updates
   int32_t* d_m = nullptr;
   double *d_drp = nullptr, *d_om = nullptr, *d_dc = nullptr;

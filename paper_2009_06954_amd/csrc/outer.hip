@@ -199,7 +199,42 @@ __global__ void __launch_bounds__(256) k_dense_rows(int64_t n, const double* __r
   if (lane == 0) y[r] = acc;
 }
 
+// One row per thread, a slice per wave: the slot loads of a wave are 64
+// consecutive values (coalesced), all of a row's loads are issued before its
+// gathers, and the row is summed in its CSR order.
+__global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __restrict__ width,
+                                                   const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, const double* __restrict__ x,
+                                                   double* __restrict__ y, const double* __restrict__ rs,
+                                                   const double* __restrict__ cs) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = row >> 6;
+  if (sl * 64 >= n) return;  // the whole wave is past the last slice
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(width[sl]);
+  const int64_t base = off[sl] + lane;
+  int32_t c[SELL_MAXW];
+  double v[SELL_MAXW];
+#pragma unroll
+  for (int u = 0; u < SELL_MAXW; ++u)
+    if (u < w) {
+      c[u] = __builtin_nontemporal_load(&col[base + (int64_t)u * 64]);
+      v[u] = __builtin_nontemporal_load(&val[base + (int64_t)u * 64]);
+    }
+  double sum = 0.0;
+#pragma unroll
+  for (int u = 0; u < SELL_MAXW; ++u)
+    if (u < w) sum += v[u] * (cs ? cs[c[u]] * x[c[u]] : x[c[u]]);
+  if (row < n) y[row] = rs ? rs[row] * sum : sum;
+}
+
 }  // namespace
+
+void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s) {
+  if (M.nrows > 0)
+    hipLaunchKernelGGL(k_spmv_sell, dim3((unsigned)((M.nrows + 255) / 256)), dim3(256), 0, s, M.nrows, M.width,
+                       M.off, M.col, M.val, x, y, rs, cs);
+}
 
 void dense_rows(int64_t n, const double* M, const double* x, double* y, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_dense_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, M, x, y);

@@ -52,4 +52,22 @@ void hess_solve_batched(double* W, int cap, int m, int ncol, const int32_t* juse
 // wave per row, coalesced row loads, a fixed summation order.
 void dense_rows(int64_t n, const double* M, const double* x, double* y, hipStream_t s);
 
+// Sliced ELL copy of a CSR matrix whose rows have at most SELL_MAXW entries:
+// slices of 64 rows (the last one filled up with empty rows), slice s holds
+// width[s] slots (its longest row) at off[s], slot u of row 64 s + l at
+// off[s] + 64 u + l; a row's entries in its CSR order, then padding with value
+// 0 and the column of the row's first entry (column 0 for an empty row).
+constexpr int SELL_MAXW = 16;
+struct DSell {
+  int64_t nrows = 0;  // 0: no copy
+  int64_t entries = 0;  // stored slots, padding included
+  const int32_t* width = nullptr;
+  const int64_t* off = nullptr;
+  const int32_t* col = nullptr;
+  double* val = nullptr;
+};
+// y = rs o (M (cs o x)) (rs, cs may be null), one row per thread; the same
+// products and summation order as the one-row-per-thread CSR kernel.
+void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s);
+
 }  // namespace asss

@@ -184,7 +184,10 @@ def test_skew_operator_ragged_blocks():
 
 
 def test_outer_operators(cfg0):
+    """The outer operator and its transpose (sliced ELL copies of Abar, S and
+    their transposes: the grid rows are short) within rounding of the oracle's."""
     p = cfg0
+    assert p.h.info()["outer_ell"] == 1
     v = np.random.default_rng(2).standard_normal(p.n)
     st = p.st
     aS, aA, om = abs(st.S), abs(st.Abar), st.Omega
@@ -731,10 +734,12 @@ def test_spmv_kernel_shapes(longrow):
     no row has more than 32 entries and lanes per row otherwise.  A has a row
     of 60 entries (lane kernel), A^T and the rows of 20 take the row kernel
     over several rounds; all agree with SciPy within rounding, and the outer
-    operators and the solve with the oracle."""
+    operators (CSR: Abar has rows longer than the sliced ELL copies take) and
+    the solve with the oracle."""
     p = longrow
     L, LT = np.diff(p.A.indptr), np.diff(p.A.T.tocsr().indptr)
     assert L.max() > 32 and LT.max() <= 32 and np.count_nonzero(L > 8) >= 10
+    assert p.h.info()["outer_ell"] == 0
     v = np.random.default_rng(6).standard_normal(p.n)
     aA = abs(p.A)
     out, _ = p.h.apply("A", _cuda(v))
