@@ -82,78 +82,60 @@ DCsr upload_csr(DevArena& ar, const Csr& M, hipStream_t s) {
   return d;
 }
 
-// Sliced ELL layout of M (described with DSell); false when a row is longer
-// than SELL_MAXW or M holds no values.
-bool ell_layout(const Csr& M, std::vector<int32_t>& width, std::vector<int64_t>& off, std::vector<int32_t>& col,
-                std::vector<double>& val) {
+// Sliced ELL copy (layout described with DSell) of the device CSR matrix M,
+// built on the device; none (nrows 0) when a row is longer than SELL_MAXW, M
+// is empty or device memory runs out (what was allocated for it is released).
+DSell ell_from_csr(DevArena& ar, const DCsr& M, hipStream_t s) {
   const int64_t n = M.nrows, ns = (n + 63) / 64;
-  if ((int64_t)M.val.size() != M.nnz()) return false;
-  width.assign(ns, 0);
-  off.assign(ns, 0);
+  if (n == 0 || M.nnz == 0) return DSell{};
+  std::vector<int32_t> w((size_t)ns);
+  std::vector<int64_t> o((size_t)ns);
+  int32_t* dw = nullptr;
+  int64_t* dof = nullptr;
+  int32_t* dc = nullptr;
+  double* dv = nullptr;
+  auto drop = [&]() {
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* p : {(void*)dw, (void*)dof, (void*)dc, (void*)dv})
+      if (p) ar.release(p);
+  };
   int64_t total = 0;
-  for (int64_t sl = 0; sl < ns; ++sl) {
-    int64_t w = 0;
-    for (int64_t i = sl * 64; i < std::min(n, sl * 64 + 64); ++i) w = std::max(w, M.ptr[i + 1] - M.ptr[i]);
-    if (w > SELL_MAXW) return false;
-    width[sl] = (int32_t)w;
-    off[sl] = total;
-    total += 64 * w;
-  }
-  col.assign(total, 0);
-  val.assign(total, 0.0);
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t sl = i / 64, l = i % 64, b = M.ptr[i], e = M.ptr[i + 1];
-    for (int64_t u = 0; u < width[sl]; ++u) {
-      const int64_t q = off[sl] + 64 * u + l;
-      if (b + u < e) {
-        col[q] = M.col[b + u];
-        val[q] = M.val[b + u];
-      } else if (e > b) {
-        col[q] = M.col[b];
-      }
-    }
-  }
-  return true;
-}
-
-// Device copy in the sliced ELL layout, or none (nrows 0) when M does not fit
-// it or device memory runs out (what was allocated for it is released).
-DSell upload_ell(DevArena& ar, const Csr& M, hipStream_t s) {
-  DSell d;
-  std::vector<int32_t> w, c;
-  std::vector<int64_t> o;
-  std::vector<double> v;
-  if (M.nrows == 0 || !ell_layout(M, w, o, c, v) || v.empty()) return d;
-  void* got[4] = {nullptr, nullptr, nullptr, nullptr};
   try {
-    int32_t* dw = ar.upload(w, s);
-    got[0] = dw;
-    int64_t* dof = ar.upload(o, s);
-    got[1] = dof;
-    int32_t* dc = ar.upload(c, s);
-    got[2] = dc;
-    double* dv = ar.upload(v, s);
-    got[3] = dv;
-    d.width = dw;
-    d.off = dof;
-    d.col = dc;
-    d.val = dv;
+    dw = ar.alloc<int32_t>(ns);
+    ell_widths(n, M.ptr, dw, s);
+    HIPCHK(hipMemcpyAsync(w.data(), dw, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t q = 0; q < ns; ++q) {
+      if (w[q] > SELL_MAXW) {
+        drop();
+        return DSell{};
+      }
+      o[q] = total;
+      total += 64 * (int64_t)w[q];
+    }
+    dof = ar.upload(o, s);
+    dc = ar.alloc<int32_t>(total);
+    dv = ar.alloc<double>(total);
+    ell_fill(n, M.ptr, M.col, M.val, dw, dof, dc, dv, s);
   } catch (const Error& e) {
     if (e.code != ASSS_ERR_OOM) throw;
-    HIPCHK(hipStreamSynchronize(s));
-    for (void* p : got)
-      if (p) ar.release(p);
+    drop();
     return DSell{};
   }
-  d.nrows = M.nrows;
-  d.entries = (int64_t)v.size();
-  HIPCHK(hipStreamSynchronize(s));  // the host arrays go out of scope
+  HIPCHK(hipStreamSynchronize(s));  // o goes out of scope
+  DSell d;
+  d.nrows = n;
+  d.entries = total;
+  d.width = dw;
+  d.off = dof;
+  d.col = dc;
+  d.val = dv;
   return d;
 }
 
 // y = rs o (M (cs o x)), through the sliced ELL copy E when there is one
-void spmv_outer(const DCsr& M, const DSell& E, const double* x, double* y, const double* rs, const double* cs,
-                hipStream_t s) {
+void spmv_fast(const DCsr& M, const DSell& E, const double* x, double* y, const double* rs, const double* cs,
+               hipStream_t s) {
   if (E.nrows > 0) spmv_sell(E, x, y, rs, cs, s);
   else spmv(M, x, y, rs, cs, 0, nullptr, s);
 }
@@ -271,8 +253,8 @@ void outer_op(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
     else ildl_sandwich<double>(il.Lb64, il.Ap, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
-  spmv_outer(h->dS, h->eS, z, h->t1, nullptr, h->d_om, s);
-  spmv_outer(h->dAbar, h->eAbar, h->t1, w, h->d_om, nullptr, s);
+  spmv_fast(h->dS, h->eS, z, h->t1, nullptr, h->d_om, s);
+  spmv_fast(h->dAbar, h->eAbar, h->t1, w, h->d_om, nullptr, s);
 }
 // w = (Omega Abar S Omega)^T z = Omega S^T Abar^T Omega z
 void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
@@ -282,8 +264,8 @@ void outer_op_T(asss_handle_s* h, const double* z, double* w, hipStream_t s) {
     else ildl_sandwich<double>(il.Lb64, il.ApT, il.Lf64, z, w, il.t64[0], il.t64[1], il.t64[2], il.t64[3], s);
     return;
   }
-  spmv_outer(h->dAbarT, h->eAbarT, z, h->t1, nullptr, h->d_om, s);
-  spmv_outer(h->dSt, h->eSt, h->t1, w, h->d_om, nullptr, s);
+  spmv_fast(h->dAbarT, h->eAbarT, z, h->t1, nullptr, h->d_om, s);
+  spmv_fast(h->dSt, h->eSt, h->t1, w, h->d_om, nullptr, s);
 }
 
 // Right-hand side of the scaled system: b_chk = Omega P Dr b, or for the
@@ -303,7 +285,7 @@ void rhs_transform(asss_handle_s* h, bool adjoint, const double* b, double* bchk
     return;
   }
   if (!adjoint) gather_scale(n, h->d_m, h->d_drp, h->d_om, b, bchk, s);
-  else spmv_outer(h->dSt, h->eSt, b, bchk, h->d_om, h->d_dc, s);  // g_chk = Omega S^T (Dc o g)
+  else spmv_fast(h->dSt, h->eSt, b, bchk, h->d_om, h->d_dc, s);  // g_chk = Omega S^T (Dc o g)
 }
 
 // Solution from the scaled one: x = Dc S Omega x_chk, or for the adjoint
@@ -319,7 +301,7 @@ void back_transform(asss_handle_s* h, bool adjoint, const double* xchk, double* 
     else scatter_scale(n, h->d_m, h->d_drp, il.d_ones, h->tmp, x, s);
     return;
   }
-  if (!adjoint) spmv_outer(h->dS, h->eS, xchk, x, h->d_dc, h->d_om, s);
+  if (!adjoint) spmv_fast(h->dS, h->eS, xchk, x, h->d_dc, h->d_om, s);
   else scatter_scale(n, h->d_m, h->d_drp, h->d_om, xchk, x, s);
 }
 
@@ -734,6 +716,7 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
   DevArena tmp(h->ar.al);
   const int64_t m = L.B.nrows, nu = L.B.ncols;
   DCsr B = upload_csr(tmp, L.B, s), Bt = upload_csr(tmp, L.Bt, s);
+  const DSell eB = ell_from_csr(tmp, B, s), eBt = ell_from_csr(tmp, Bt, s);
   double* u = tmp.upload(L.rhs, s);
   double* v = tmp.alloc<double>(nu);
   double* w = tmp.alloc<double>(nu);
@@ -746,7 +729,7 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
   std::vector<double> out(nu, 0.0);
   if (beta == 0.0) return out;
   scale(m, 1.0 / beta, u, u, s);
-  spmv(Bt, u, v, nullptr, nullptr, 0, nullptr, s);
+  spmv_fast(Bt, eBt, u, v, nullptr, nullptr, s);
   double alpha = nrm(nu, v);
   if (alpha == 0.0) return out;
   scale(nu, 1.0 / alpha, v, v, s);
@@ -755,12 +738,12 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
   int it = 0;
   double test1 = 1.0, test2 = 1.0;
   for (it = 1; it <= maxit; ++it) {
-    spmv(B, v, y, nullptr, nullptr, 0, nullptr, s);
+    spmv_fast(B, eB, v, y, nullptr, nullptr, s);
     axpby(m, 1.0, y, -alpha, u, s);
     beta = nrm(m, u);
     if (beta > 0) scale(m, 1.0 / beta, u, u, s);
     anorm2 += alpha * alpha + beta * beta;
-    spmv(Bt, u, y, nullptr, nullptr, 0, nullptr, s);
+    spmv_fast(Bt, eBt, u, y, nullptr, nullptr, s);
     axpby(nu, 1.0, y, -beta, v, s);
     alpha = nrm(nu, v);
     if (alpha > 0) scale(nu, 1.0 / alpha, v, v, s);
@@ -1865,10 +1848,10 @@ static asss_status_t setup_impl(const asss_csr_t* A, const asss_setup_opts_t* op
     h->dS = upload_csr(h->ar, h->S, s);
     h->dSt = upload_csr(h->ar, transpose(h->S), s);
     if (!ildl) {
-      h->eAbar = upload_ell(h->ar, Abar, s);
-      h->eAbarT = upload_ell(h->ar, transpose(Abar), s);
-      h->eS = upload_ell(h->ar, h->S, s);
-      h->eSt = upload_ell(h->ar, transpose(h->S), s);
+      h->eAbar = ell_from_csr(h->ar, h->dAbar, s);
+      h->eAbarT = ell_from_csr(h->ar, h->dAbarT, s);
+      h->eS = ell_from_csr(h->ar, h->dS, s);
+      h->eSt = ell_from_csr(h->ar, h->dSt, s);
     }
     h->d_m = h->ar.upload(h->m, s);
     if (reordered) h->d_perm = h->ar.upload(h->perm, s);
@@ -2081,15 +2064,12 @@ asss_status_t asss_update_values(asss_handle_t h, const asss_csr_t* A, void* hip
       HIPCHK(hipMemcpyAsync(dst[q]->val, src[q]->val.data(), src[q]->nnz() * sizeof(double),
                             hipMemcpyHostToDevice, s));
     }
-    std::vector<int32_t> ew, ec;
-    std::vector<int64_t> eo;
-    std::vector<double> ev[2];
+    // the sliced copies from the new CSR values, after their copies on s
     const DSell* edst[2] = {&h->eAbar, &h->eAbarT};
     for (int q = 0; q < 2; ++q) {
-      if (edst[q]->nrows == 0) continue;
-      if (!ell_layout(*src[2 + q], ew, eo, ec, ev[q]) || (int64_t)ev[q].size() != edst[q]->entries)
-        throw Error{ASSS_ERR_INTERNAL, "stored pattern changed"};
-      HIPCHK(hipMemcpyAsync(edst[q]->val, ev[q].data(), ev[q].size() * sizeof(double), hipMemcpyHostToDevice, s));
+      const DSell& E = *edst[q];
+      const DCsr& M = *dst[2 + q];
+      if (E.nrows > 0) ell_fill(M.nrows, M.ptr, M.col, M.val, E.width, E.off, E.col, E.val, s);
     }
     HIPCHK(hipStreamSynchronize(s));  // the host arrays go out of scope
     return ASSS_OK;

@@ -228,7 +228,56 @@ __global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __r
   if (row < n) y[row] = rs ? rs[row] * sum : sum;
 }
 
+// One wave per slice, one lane per row: the row lengths' maximum over the wave.
+__global__ void __launch_bounds__(256) k_ell_widths(int64_t n, const int64_t* __restrict__ ptr,
+                                                    int32_t* __restrict__ width) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = row >> 6;
+  if (sl * 64 >= n) return;  // the whole wave is past the last slice
+  int len = 0;
+  if (row < n) {
+    const int64_t l = ptr[row + 1] - ptr[row];
+    len = l < (int64_t)INT32_MAX ? (int)l : INT32_MAX;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+  if ((threadIdx.x & 63) == 0) width[sl] = len;
+}
+
+// One thread per row of the padded slices: its entries in CSR order, then the
+// padding (value 0, the column of its first entry, column 0 if it has none).
+__global__ void __launch_bounds__(256) k_ell_fill(int64_t n, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                  const int32_t* __restrict__ width,
+                                                  const int64_t* __restrict__ off, int32_t* __restrict__ ecol,
+                                                  double* __restrict__ eval) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = row >> 6;
+  if (sl * 64 >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int w = width[sl];
+  const int64_t b = row < n ? ptr[row] : 0, e = row < n ? ptr[row + 1] : 0;
+  const int32_t pad = e > b ? col[b] : 0;
+  const int64_t base = off[sl] + lane;
+  for (int u = 0; u < w; ++u) {
+    const bool real = b + u < e;
+    ecol[base + (int64_t)u * 64] = real ? col[b + u] : pad;
+    eval[base + (int64_t)u * 64] = real ? val[b + u] : 0.0;
+  }
+}
+
 }  // namespace
+
+void ell_widths(int64_t n, const int64_t* ptr, int32_t* width, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_ell_widths, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ptr, width);
+}
+
+void ell_fill(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int32_t* width,
+              const int64_t* off, int32_t* ecol, double* eval, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_ell_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ptr, col, val, width, off,
+                       ecol, eval);
+}
 
 void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s) {
   if (M.nrows > 0)

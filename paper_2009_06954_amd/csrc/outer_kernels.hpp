@@ -63,11 +63,21 @@ struct DSell {
   int64_t entries = 0;  // stored slots, padding included
   const int32_t* width = nullptr;
   const int64_t* off = nullptr;
-  const int32_t* col = nullptr;
+  int32_t* col = nullptr;
   double* val = nullptr;
 };
 // y = rs o (M (cs o x)) (rs, cs may be null), one row per thread; the same
 // products and summation order as the one-row-per-thread CSR kernel.
 void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s);
+
+// The copy is built on the device from CSR arrays of n rows (ptr n + 1 int64,
+// col int32, val FP64, sorted rows): ell_widths writes the ceil(n / 64) slice
+// widths (each slice's longest row, clamped to INT32_MAX); with width and off
+// in place (off[s] = 64 x the widths before s), ell_fill writes every slot,
+// padding included.  Running ell_fill again after new values of the same
+// pattern refreshes the copy.
+void ell_widths(int64_t n, const int64_t* ptr, int32_t* width, hipStream_t s);
+void ell_fill(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int32_t* width,
+              const int64_t* off, int32_t* ecol, double* eval, hipStream_t s);
 
 }  // namespace asss

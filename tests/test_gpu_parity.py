@@ -759,6 +759,52 @@ def test_spmv_kernel_shapes(longrow):
     assert _rel(_np(x), xo) <= 1e-9
 
 
+def _ragged_rows_matrix(n=1000, seed=11):
+    """Rows of 1 to 16 entries (random count, columns in a 16-wide window about
+    the diagonal, so columns hold at most 16 entries too), diagonally dominant."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        win = [j for j in range(i - 8, i + 8) if 0 <= j < n and j != i]
+        L = int(rng.integers(1, 17))
+        pick = rng.choice(win, size=min(L - 1, len(win)), replace=False)
+        off = rng.uniform(-1.0, 1.0, size=len(pick))
+        rows += [i] * (len(pick) + 1)
+        cols += [i] + pick.tolist()
+        vals += [np.abs(off).sum() + 1.0 + rng.uniform(0.0, 1.0)] + off.tolist()
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    return A
+
+
+@pytest.fixture(scope="module")
+def raggedrows():
+    return Pair(_ragged_rows_matrix(), k=4)
+
+
+def test_outer_operators_ragged_slices(raggedrows):
+    """Sliced ELL copies whose slices mix rows of 1 to 16 entries (padding in
+    every slice) and end in a slice of 40 rows: the outer operator and its
+    transpose within rounding of the oracle's, and the solve."""
+    p = raggedrows
+    L, LT = np.diff(p.A.indptr), np.diff(p.A.T.tocsr().indptr)
+    assert L.min() == 1 and L.max() == 16 and LT.max() <= 16 and p.n % 64 == 40
+    assert p.h.info()["outer_ell"] == 1
+    v = np.random.default_rng(7).standard_normal(p.n)
+    st = p.st
+    aS, aA, om = abs(st.S), abs(st.Abar), st.Omega
+    out, _ = p.h.apply("outer", _cuda(v))
+    _within_rounding(_np(out), st.op(v), om * (aA @ (aS @ (om * np.abs(v)))))
+    out, _ = p.h.apply("outer_t", _cuda(v))
+    _within_rounding(_np(out), st.op_T(v), om * (aS.T @ (aA.T @ (om * np.abs(v)))))
+    b = p.A @ np.ones(p.n)
+    xo, io = O.solve(st, b, O.SolveOptions(tol=1e-12))
+    x, info = p.h.solve(_cuda(b), tol=1e-12)
+    assert io["converged"] and info["status"] == "OK" and info["relres_true"] <= 1e-12
+    assert info["outer_its"] == io["outer_its"]
+    assert _rel(_np(x), xo) <= 1e-10
+
+
 def test_deflation_fp32_basis():
     """deflation = "explicit_fp32_basis": the Lanczos vectors are rounded to FP32
     values at setup and that basis is used everywhere.  The exported basis is
