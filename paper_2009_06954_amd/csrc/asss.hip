@@ -717,6 +717,9 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
   const int64_t m = L.B.nrows, nu = L.B.ncols;
   DCsr B = upload_csr(tmp, L.B, s), Bt = upload_csr(tmp, L.Bt, s);
   const DSell eB = ell_from_csr(tmp, B, s), eBt = ell_from_csr(tmp, Bt, s);
+  // The bidiagonalization vectors are kept unnormalized: u holds beta u_i and
+  // v holds alpha v_i, and each 1/beta, 1/alpha rides on the next product or
+  // update instead of a pass of its own.
   double* u = tmp.upload(L.rhs, s);
   double* v = tmp.alloc<double>(nu);
   double* w = tmp.alloc<double>(nu);
@@ -724,29 +727,36 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
   double* y = tmp.alloc<double>(std::max(m, nu));
   HIPCHK(hipMemsetAsync(x, 0, nu * sizeof(double), s));
   auto nrm = [&](int64_t len, const double* a) { return std::sqrt(dot_host(h, len, a, a, s)); };
+  // io = sa (M in) + sb io
+  auto prod = [&](const DCsr& M, const DSell& E, const double* in, double* io, double sa, double sb) {
+    if (E.nrows > 0) {
+      spmv_sell_acc(E, in, io, sa, sb, s);
+    } else {
+      spmv(M, in, y, nullptr, nullptr, 0, nullptr, s);
+      axpby(M.nrows, sa, y, sb, io, s);
+    }
+  };
   double beta = nrm(m, u);
   const double bnorm = beta;
   std::vector<double> out(nu, 0.0);
   if (beta == 0.0) return out;
-  scale(m, 1.0 / beta, u, u, s);
-  spmv_fast(Bt, eBt, u, v, nullptr, nullptr, s);
+  prod(Bt, eBt, u, v, 1.0 / beta, 0.0);  // alpha_1 v_1 = B^T u_1
   double alpha = nrm(nu, v);
   if (alpha == 0.0) return out;
-  scale(nu, 1.0 / alpha, v, v, s);
-  axpby(nu, 1.0, v, 0.0, w, s);
+  axpby(nu, 1.0 / alpha, v, 0.0, w, s);  // w_1 = v_1
   double phibar = beta, rhobar = alpha, anorm2 = 0.0;
   int it = 0;
   double test1 = 1.0, test2 = 1.0;
   for (it = 1; it <= maxit; ++it) {
-    spmv_fast(B, eB, v, y, nullptr, nullptr, s);
-    axpby(m, 1.0, y, -alpha, u, s);
+    prod(B, eB, v, u, 1.0 / alpha, -alpha / beta);  // beta_{i+1} u_{i+1} = B v_i - alpha_i u_i
     beta = nrm(m, u);
-    if (beta > 0) scale(m, 1.0 / beta, u, u, s);
     anorm2 += alpha * alpha + beta * beta;
-    spmv_fast(Bt, eBt, u, y, nullptr, nullptr, s);
-    axpby(nu, 1.0, y, -beta, v, s);
-    alpha = nrm(nu, v);
-    if (alpha > 0) scale(nu, 1.0 / alpha, v, v, s);
+    if (beta > 0) {
+      prod(Bt, eBt, u, v, 1.0 / beta, -beta / alpha);  // alpha_{i+1} v_{i+1} = B^T u_{i+1} - beta_{i+1} v_i
+      alpha = nrm(nu, v);
+    } else {
+      alpha = 0.0;  // u_{i+1} = 0: the next v is zero and the iteration ends below
+    }
     const double rho = std::hypot(rhobar, beta);
     const double c = rhobar / rho, sn = beta / rho;
     const double theta = sn * alpha;
@@ -754,7 +764,7 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
     const double phi = c * phibar;
     phibar = sn * phibar;
     axpby(nu, phi / rho, w, 1.0, x, s);
-    axpby(nu, 1.0, v, -theta / rho, w, s);
+    if (alpha > 0) axpby(nu, 1.0 / alpha, v, -theta / rho, w, s);  // w = v_{i+1} - (theta / rho) w
     const double anorm = std::sqrt(anorm2);
     const double rnorm = phibar;
     const double arnorm = phibar * alpha * std::fabs(c);

@@ -201,12 +201,13 @@ __global__ void __launch_bounds__(256) k_dense_rows(int64_t n, const double* __r
 
 // One row per thread, a slice per wave: the slot loads of a wave are 64
 // consecutive values (coalesced), all of a row's loads are issued before its
-// gathers, and the row is summed in its CSR order.
+// gathers, and the row is summed in its CSR order.  ACC: y = sa sum + sb y.
+template <bool ACC>
 __global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __restrict__ width,
                                                    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
                                                    const double* __restrict__ val, const double* __restrict__ x,
                                                    double* __restrict__ y, const double* __restrict__ rs,
-                                                   const double* __restrict__ cs) {
+                                                   const double* __restrict__ cs, double sa, double sb) {
   const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t sl = row >> 6;
   if (sl * 64 >= n) return;  // the whole wave is past the last slice
@@ -225,7 +226,10 @@ __global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __r
 #pragma unroll
   for (int u = 0; u < SELL_MAXW; ++u)
     if (u < w) sum += v[u] * (cs ? cs[c[u]] * x[c[u]] : x[c[u]]);
-  if (row < n) y[row] = rs ? rs[row] * sum : sum;
+  if (row < n) {
+    if (ACC) y[row] = sb == 0.0 ? sa * sum : sa * sum + sb * y[row];
+    else y[row] = rs ? rs[row] * sum : sum;
+  }
 }
 
 // One wave per slice, one lane per row: the row lengths' maximum over the wave.
@@ -281,8 +285,14 @@ void ell_fill(int64_t n, const int64_t* ptr, const int32_t* col, const double* v
 
 void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s) {
   if (M.nrows > 0)
-    hipLaunchKernelGGL(k_spmv_sell, dim3((unsigned)((M.nrows + 255) / 256)), dim3(256), 0, s, M.nrows, M.width,
-                       M.off, M.col, M.val, x, y, rs, cs);
+    hipLaunchKernelGGL(k_spmv_sell<false>, dim3((unsigned)((M.nrows + 255) / 256)), dim3(256), 0, s, M.nrows,
+                       M.width, M.off, M.col, M.val, x, y, rs, cs, 1.0, 0.0);
+}
+
+void spmv_sell_acc(const DSell& M, const double* x, double* y, double sa, double sb, hipStream_t s) {
+  if (M.nrows > 0)
+    hipLaunchKernelGGL(k_spmv_sell<true>, dim3((unsigned)((M.nrows + 255) / 256)), dim3(256), 0, s, M.nrows,
+                       M.width, M.off, M.col, M.val, x, y, nullptr, nullptr, sa, sb);
 }
 
 void dense_rows(int64_t n, const double* M, const double* x, double* y, hipStream_t s) {

@@ -69,6 +69,9 @@ struct DSell {
 // y = rs o (M (cs o x)) (rs, cs may be null), one row per thread; the same
 // products and summation order as the one-row-per-thread CSR kernel.
 void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s);
+// y = sa (M x) + sb y (y is not read when sb == 0; x and y must not overlap),
+// the same row sums.
+void spmv_sell_acc(const DSell& M, const double* x, double* y, double sa, double sb, hipStream_t s);
 
 // The copy is built on the device from CSR arrays of n rows (ptr n + 1 int64,
 // col int32, val FP64, sorted rows): ell_widths writes the ceil(n / 64) slice
