@@ -805,6 +805,31 @@ def test_outer_operators_ragged_slices(raggedrows):
     assert _rel(_np(x), xo) <= 1e-10
 
 
+def test_update_values_refreshes_outer_copies():
+    """After asss_update_values the outer operator and its transpose (sliced
+    ELL copies of Abar and Abar^T, filled again on the device) follow the new
+    values: within rounding of Omega Abar' S Omega, Abar' = P Dr A' Dc with the
+    matching, scaling, S and Omega of the setup, which the update keeps."""
+    A = _ragged_rows_matrix()
+    p = Pair(A, k=4)
+    assert p.h.info()["outer_ell"] == 1
+    rng = np.random.default_rng(12)
+    A2 = A.copy()
+    A2.data = A.data * (1.0 + 0.5 * rng.uniform(0.0, 1.0, A.nnz))
+    p.h.update_values(A2)
+    st = p.st
+    Ab2 = O.permute_scale(A2, st.m, st.Dr, st.Dc)
+    assert abs(Ab2 - st.Abar).max() > 0.1
+    v = rng.standard_normal(p.n)
+    aS, aA, om = abs(st.S), abs(Ab2), st.Omega
+    out, _ = p.h.apply("outer", _cuda(v))
+    _within_rounding(_np(out), om * (Ab2 @ (st.S @ (om * v))), om * (aA @ (aS @ (om * np.abs(v)))))
+    out, _ = p.h.apply("outer_t", _cuda(v))
+    _within_rounding(_np(out), om * (st.S.T @ (Ab2.T @ (om * v))), om * (aS.T @ (aA.T @ (om * np.abs(v)))))
+    out, _ = p.h.apply("A", _cuda(v))
+    assert _rel(_np(out), A2 @ v) <= 1e-15
+
+
 def test_deflation_fp32_basis():
     """deflation = "explicit_fp32_basis": the Lanczos vectors are rounded to FP32
     values at setup and that basis is used everywhere.  The exported basis is
