@@ -725,35 +725,38 @@ std::vector<double> lsqr_device(asss_handle_s* h, const LlsSystem& L, double tol
   double* w = tmp.alloc<double>(nu);
   double* x = tmp.alloc<double>(nu);
   double* y = tmp.alloc<double>(std::max(m, nu));
+  double* part = tmp.alloc<double>((std::max(m, nu) + 255) / 256 + 256);
   HIPCHK(hipMemsetAsync(x, 0, nu * sizeof(double), s));
   auto nrm = [&](int64_t len, const double* a) { return std::sqrt(dot_host(h, len, a, a, s)); };
-  // io = sa (M in) + sb io
+  // io = sa (M in) + sb io; returns ||io|| (from the product's epilogue when
+  // it reads the sliced copy)
   auto prod = [&](const DCsr& M, const DSell& E, const double* in, double* io, double sa, double sb) {
     if (E.nrows > 0) {
-      spmv_sell_acc(E, in, io, sa, sb, s);
-    } else {
-      spmv(M, in, y, nullptr, nullptr, 0, nullptr, s);
-      axpby(M.nrows, sa, y, sb, io, s);
+      spmv_sell_acc(E, in, io, sa, sb, part, s);
+      sum_parts((E.nrows + 255) / 256, part, h->d_small, s);
+      HIPCHK(hipMemcpyAsync(h->h_small, h->d_small, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      return std::sqrt(h->h_small[0]);
     }
+    spmv(M, in, y, nullptr, nullptr, 0, nullptr, s);
+    axpby(M.nrows, sa, y, sb, io, s);
+    return nrm(M.nrows, io);
   };
   double beta = nrm(m, u);
   const double bnorm = beta;
   std::vector<double> out(nu, 0.0);
   if (beta == 0.0) return out;
-  prod(Bt, eBt, u, v, 1.0 / beta, 0.0);  // alpha_1 v_1 = B^T u_1
-  double alpha = nrm(nu, v);
+  double alpha = prod(Bt, eBt, u, v, 1.0 / beta, 0.0);  // alpha_1 v_1 = B^T u_1
   if (alpha == 0.0) return out;
   axpby(nu, 1.0 / alpha, v, 0.0, w, s);  // w_1 = v_1
   double phibar = beta, rhobar = alpha, anorm2 = 0.0;
   int it = 0;
   double test1 = 1.0, test2 = 1.0;
   for (it = 1; it <= maxit; ++it) {
-    prod(B, eB, v, u, 1.0 / alpha, -alpha / beta);  // beta_{i+1} u_{i+1} = B v_i - alpha_i u_i
-    beta = nrm(m, u);
+    beta = prod(B, eB, v, u, 1.0 / alpha, -alpha / beta);  // beta_{i+1} u_{i+1} = B v_i - alpha_i u_i
     anorm2 += alpha * alpha + beta * beta;
     if (beta > 0) {
-      prod(Bt, eBt, u, v, 1.0 / beta, -beta / alpha);  // alpha_{i+1} v_{i+1} = B^T u_{i+1} - beta_{i+1} v_i
-      alpha = nrm(nu, v);
+      alpha = prod(Bt, eBt, u, v, 1.0 / beta, -beta / alpha);  // alpha_{i+1} v_{i+1} = B^T u_{i+1} - beta_{i+1} v_i
     } else {
       alpha = 0.0;  // u_{i+1} = 0: the next v is zero and the iteration ends below
     }

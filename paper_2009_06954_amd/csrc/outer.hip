@@ -202,16 +202,10 @@ __global__ void __launch_bounds__(256) k_dense_rows(int64_t n, const double* __r
 // One row per thread, a slice per wave: the slot loads of a wave are 64
 // consecutive values (coalesced), all of a row's loads are issued before its
 // gathers, and the row is summed in its CSR order.  ACC: y = sa sum + sb y.
-template <bool ACC>
-__global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __restrict__ width,
-                                                   const int64_t* __restrict__ off, const int32_t* __restrict__ col,
-                                                   const double* __restrict__ val, const double* __restrict__ x,
-                                                   double* __restrict__ y, const double* __restrict__ rs,
-                                                   const double* __restrict__ cs, double sa, double sb) {
-  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t sl = row >> 6;
-  if (sl * 64 >= n) return;  // the whole wave is past the last slice
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ double sell_row(int64_t sl, int lane, const int32_t* __restrict__ width,
+                                           const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                                           const double* __restrict__ val, const double* __restrict__ x,
+                                           const double* __restrict__ cs) {
   const int w = __builtin_amdgcn_readfirstlane(width[sl]);
   const int64_t base = off[sl] + lane;
   int32_t c[SELL_MAXW];
@@ -226,10 +220,63 @@ __global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __r
 #pragma unroll
   for (int u = 0; u < SELL_MAXW; ++u)
     if (u < w) sum += v[u] * (cs ? cs[c[u]] * x[c[u]] : x[c[u]]);
-  if (row < n) {
-    if (ACC) y[row] = sb == 0.0 ? sa * sum : sa * sum + sb * y[row];
-    else y[row] = rs ? rs[row] * sum : sum;
+  return sum;
+}
+
+// ACC: y = sa sum + sb y, and with part, the block's sum of the new y_i^2 in
+// part[blockIdx.x] (wave sums, then the four waves in a fixed order).
+template <bool ACC>
+__global__ void __launch_bounds__(256) k_spmv_sell(int64_t n, const int32_t* __restrict__ width,
+                                                   const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, const double* __restrict__ x,
+                                                   double* __restrict__ y, const double* __restrict__ rs,
+                                                   const double* __restrict__ cs, double sa, double sb,
+                                                   double* __restrict__ part) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = row >> 6;
+  const int lane = threadIdx.x & 63;
+  if (!ACC) {
+    if (sl * 64 >= n) return;  // the whole wave is past the last slice
+    const double sum = sell_row(sl, lane, width, off, col, val, x, cs);
+    if (row < n) y[row] = rs ? rs[row] * sum : sum;
+    return;
   }
+  double yv = 0.0;
+  if (sl * 64 < n) {
+    const double sum = sell_row(sl, lane, width, off, col, val, x, cs);
+    if (row < n) {
+      yv = sb == 0.0 ? sa * sum : sa * sum + sb * y[row];
+      y[row] = yv;
+    }
+  }
+  if (part) {  // the same for the whole grid: every thread reaches the barrier
+    __shared__ double wsum[4];
+    double q = yv * yv;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) q += __shfl_xor(q, o, 64);
+    if (lane == 0) wsum[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  }
+}
+
+// out[b] = the sum of workgroup b's contiguous share of part[0 .. np): thread
+// t adds its values t, t + 1024, ... of the share in turn, then a fixed tree
+// over the threads.
+__global__ void __launch_bounds__(1024) k_sum_parts(int64_t np, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  __shared__ double red[1024];
+  const int64_t chunk = (np + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < np ? lo + chunk : np;
+  double a = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 1024) a += part[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = 512; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // One wave per slice, one lane per row: the row lengths' maximum over the wave.
@@ -286,13 +333,23 @@ void ell_fill(int64_t n, const int64_t* ptr, const int32_t* col, const double* v
 void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s) {
   if (M.nrows > 0)
     hipLaunchKernelGGL(k_spmv_sell<false>, dim3((unsigned)((M.nrows + 255) / 256)), dim3(256), 0, s, M.nrows,
-                       M.width, M.off, M.col, M.val, x, y, rs, cs, 1.0, 0.0);
+                       M.width, M.off, M.col, M.val, x, y, rs, cs, 1.0, 0.0, nullptr);
 }
 
-void spmv_sell_acc(const DSell& M, const double* x, double* y, double sa, double sb, hipStream_t s) {
+void spmv_sell_acc(const DSell& M, const double* x, double* y, double sa, double sb, double* part, hipStream_t s) {
   if (M.nrows > 0)
     hipLaunchKernelGGL(k_spmv_sell<true>, dim3((unsigned)((M.nrows + 255) / 256)), dim3(256), 0, s, M.nrows,
-                       M.width, M.off, M.col, M.val, x, y, nullptr, nullptr, sa, sb);
+                       M.width, M.off, M.col, M.val, x, y, nullptr, nullptr, sa, sb, part);
+}
+
+void sum_parts(int64_t np, double* part, double* out, hipStream_t s) {
+  constexpr int G = 256;
+  if (np > 4 * 1024) {  // one workgroup alone reads a long part array slowly
+    hipLaunchKernelGGL(k_sum_parts, dim3(G), dim3(1024), 0, s, np, part, part + np);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (int64_t)G, part + np, out);
+  } else {
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, np, part, out);
+  }
 }
 
 void dense_rows(int64_t n, const double* M, const double* x, double* y, hipStream_t s) {

@@ -70,8 +70,13 @@ struct DSell {
 // products and summation order as the one-row-per-thread CSR kernel.
 void spmv_sell(const DSell& M, const double* x, double* y, const double* rs, const double* cs, hipStream_t s);
 // y = sa (M x) + sb y (y is not read when sb == 0; x and y must not overlap),
-// the same row sums.
-void spmv_sell_acc(const DSell& M, const double* x, double* y, double sa, double sb, hipStream_t s);
+// the same row sums.  With part (ceil(nrows / 256) values), part[b] = the sum
+// of the new y_i^2 over rows 256 b .. 256 b + 255; sum_parts then adds the
+// np values of part in a fixed order into out[0] (part must hold np + 256
+// values: the 256 after the np take partial sums).
+void spmv_sell_acc(const DSell& M, const double* x, double* y, double sa, double sb, double* part,
+                   hipStream_t s);
+void sum_parts(int64_t np, double* part, double* out, hipStream_t s);
 
 // The copy is built on the device from CSR arrays of n rows (ptr n + 1 int64,
 // col int32, val FP64, sorted rows): ell_widths writes the ceil(n / 64) slice
