@@ -830,6 +830,46 @@ def test_update_values_refreshes_outer_copies():
     assert _rel(_np(out), A2 @ v) <= 1e-15
 
 
+def _arrow_matrix(n=200, w=24, seed=5):
+    """Tridiagonal plus a first row and column of w entries, diagonally
+    dominant: with the diagonal S pattern the unknown s_00 appears in w
+    least-squares equations, so B^T has a row longer than the sliced copies
+    take while the rows of B hold at most 2 entries."""
+    rng = np.random.default_rng(seed)
+    A = sp.diags([rng.uniform(-1, 1, n - 1), 4.0 + rng.uniform(0, 1, n), rng.uniform(-1, 1, n - 1)],
+                 [-1, 0, 1], format="lil")
+    for i in range(1, w):
+        A[i, 0] = rng.uniform(-1, 1)
+        A[0, i] = rng.uniform(-1, 1)
+    A[0, 0] = float(w)
+    A = A.tocsr()
+    A.sort_indices()
+    return A
+
+
+def test_lsqr_with_long_least_squares_rows():
+    """The device LSQR when B^T has rows of more than 16 entries (its products
+    take the CSR kernels with separate update and norm passes) and B has not
+    (the sliced copy with the update and the norm in the epilogue): S and
+    J_tilde within 1e-12 of the oracle's, and the solve."""
+    A = _arrow_matrix()
+    p = Pair(A, k=4, pattern="diag")
+    lls = O.build_lls(p.st.Abar, O.s_pattern(p.st.Abar, "diag"), 1.0)
+    B = [m for m in lls if sp.issparse(m)][0].tocsr()
+    assert np.diff(B.indptr).max() <= 16 < np.diff(B.T.tocsr().indptr).max()
+    S = p.st.S.tocsr()
+    S.sort_indices()
+    assert np.array_equal(p.h.array("S_rowptr"), S.indptr) and np.array_equal(p.h.array("S_colind"), S.indices)
+    assert _rel(p.h.array("S_val"), S.data) <= 1e-12
+    assert np.array_equal(p.h.array("J_colind"), p.st.Jup.indices)
+    assert _rel(p.h.array("J_val"), p.st.Jup.data) <= 1e-12
+    b = A @ np.ones(p.n)
+    xo, io = O.solve(p.st, b, O.SolveOptions(tol=1e-12))
+    x, info = p.h.solve(_cuda(b), tol=1e-12)
+    assert io["converged"] and info["status"] == "OK" and info["relres_true"] <= 1e-12
+    assert _rel(_np(x), xo) <= 1e-10
+
+
 def test_deflation_fp32_basis():
     """deflation = "explicit_fp32_basis": the Lanczos vectors are rounded to FP32
     values at setup and that basis is used everywhere.  The exported basis is
